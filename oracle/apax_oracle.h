@@ -1,0 +1,107 @@
+/*
+ * apax_oracle.h -- plain single-threaded CPU reference for the APAX numerical
+ * encoder, decoder and profiler (A. Wegener, "Universal Numerical Encoder and
+ * Profiler ...", arXiv 1303.4994).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can check the GPU library
+ * against an independent, obviously-correct implementation.  It shares no
+ * source, header, table or helper with the GPU path, and the GPU path never
+ * loads it.
+ *
+ * Every array pointer here is HOST memory owned by the caller.  Integer
+ * return values: 0 on success, a negative ORC_E_* code otherwise.
+ *
+ * The bitstream format this oracle writes is the reading of the paper frozen
+ * in the project design notes (block header, JEE tokens, BFPE payload,
+ * 64-byte stream header, block-length index); the comments in
+ * apax_oracle.c cite the paper section each step follows.
+ */
+#ifndef APAX_ORACLE_H
+#define APAX_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_I8 = 1, ORC_I16 = 2, ORC_I32 = 3, ORC_F32 = 4, ORC_F64 = 5 };
+enum { ORC_LOSSLESS = 0, ORC_FIXED_RATE = 1, ORC_FIXED_QUALITY = 2 };
+enum {
+  ORC_OK = 0,
+  ORC_E_INVALID = -1,
+  ORC_E_UNSUPPORTED = -2,
+  ORC_E_CAPACITY = -3,
+  ORC_E_CORRUPT = -4,
+  ORC_E_NONFINITE = -5
+};
+#define ORC_NEAR_TIE 1u
+#define ORC_NCURVE 17
+
+typedef struct {
+  uint32_t size;        /* sizeof(orc_params) */
+  uint32_t dtype;       /* ORC_I8 .. ORC_F64 */
+  uint32_t ndim;        /* 1..3 */
+  uint32_t mode;        /* ORC_LOSSLESS, ORC_FIXED_RATE, ORC_FIXED_QUALITY */
+  uint64_t dims[3];     /* slow -> fast, first ndim entries used */
+  uint32_t brick[3];    /* slow -> fast, first ndim entries used */
+  uint32_t stream_mask; /* bit s allows stream s; 0 = every stream of ndim */
+  double rate;          /* fixed-rate: input bits per encoded bit */
+  double target_corr;   /* fixed-quality: correlation target */
+  int32_t code;         /* gain code (fixed-rate start code / fixed-quality code) */
+  uint32_t reserved;
+} orc_params;
+
+typedef struct {
+  double r, one_minus_r, snr_db, rms_pct, rms_db;
+  double mean_x, mean_y, mean_d, std_x, std_y, std_d, max_abs_d;
+  double sxx, syy, sdd, sds, sum_x, sum_y, sum_d;
+  double ratio;
+  uint64_t n, enc_bytes;
+} orc_metrics;
+
+typedef struct {
+  int32_t code;
+  int32_t pad;
+  double ratio;
+  double r;
+} orc_curve_point;
+
+typedef struct {
+  uint32_t size;
+  int32_t code;          /* recommended gain code (c* or c_p); 0 for lossless */
+  uint32_t stream_mask;  /* pruned stream mask recommended to the encoder */
+  uint32_t flags;        /* ORC_NEAR_TIE */
+  int32_t c_floor, c_cap;/* whole-array bracket */
+  uint32_t n_sub;        /* number of subsample blocks */
+  uint32_t n_probes;     /* bisection probes taken */
+  orc_curve_point curve[ORC_NCURVE];
+  orc_metrics m;
+} orc_profile_result;
+
+/* whole-array calls */
+int orc_encode_bound(const orc_params* p, uint64_t* bound);
+int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint64_t* nbytes);
+int orc_decode(const void* in, uint64_t nbytes, void* y, uint64_t cap_bytes);
+int orc_stream_info(const void* in, uint64_t nbytes, orc_params* p);
+int orc_profile(const void* x, const orc_params* p, orc_profile_result* res);
+
+/* pieces exposed for pins and for sampled comparisons at full size */
+double orc_gain(int32_t c);
+double orc_inv_gain_mantissa(int32_t f);
+int orc_block_bracket(const void* x, const orc_params* p, int64_t j, double* M,
+                      int32_t* c_floor, int32_t* c_cap);
+int orc_encode_block(const void* x, const orc_params* p, int64_t j, uint32_t* words,
+                     int32_t cap_words, int32_t* nwords, int32_t* stream, int32_t* cj,
+                     int32_t* used_bits);
+int orc_stream_values(const int64_t* a, const uint32_t* brick, int32_t W, int32_t s,
+                      int64_t* v);
+int orc_group_eps(const int64_t* v, int32_t G, int32_t W, int32_t* eps);
+int orc_jee_tokens(const int32_t* eps, int32_t G, uint8_t* nibbles, int32_t* n_nibbles);
+int orc_stats(const double* x, const double* y, uint64_t n, orc_metrics* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,232 @@
+"""ctypes binding of the CPU oracle (test infrastructure only).
+
+Everything here works on host numpy arrays.  Parameters are plain dicts:
+    {"mode": "lossless" | "fixed_rate" | "fixed_quality",
+     "brick": (..), "stream_mask": 0, "rate": 4.0, "target_corr": 0.99999,
+     "code": 0}
+The array's dtype and shape give the dtype and dims.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+I8, I16, I32, F32, F64 = 1, 2, 3, 4, 5
+LOSSLESS, FIXED_RATE, FIXED_QUALITY = 0, 1, 2
+E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE = -1, -2, -3, -4, -5
+NEAR_TIE = 1
+NCURVE = 17
+
+DTYPES = {np.dtype(np.int8): I8, np.dtype(np.int16): I16, np.dtype(np.int32): I32,
+          np.dtype(np.float32): F32, np.dtype(np.float64): F64}
+NP_OF = {v: k for k, v in DTYPES.items()}
+MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: oracle error {code}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32),
+                ("mode", C.c_uint32), ("dims", C.c_uint64 * 3), ("brick", C.c_uint32 * 3),
+                ("stream_mask", C.c_uint32), ("rate", C.c_double),
+                ("target_corr", C.c_double), ("code", C.c_int32), ("reserved", C.c_uint32)]
+
+
+class Metrics(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "r", "one_minus_r", "snr_db", "rms_pct", "rms_db", "mean_x", "mean_y", "mean_d",
+        "std_x", "std_y", "std_d", "max_abs_d", "sxx", "syy", "sdd", "sds", "sum_x",
+        "sum_y", "sum_d", "ratio")] + [("n", C.c_uint64), ("enc_bytes", C.c_uint64)]
+
+
+class CurvePoint(C.Structure):
+    _fields_ = [("code", C.c_int32), ("pad", C.c_int32), ("ratio", C.c_double),
+                ("r", C.c_double)]
+
+
+class ProfileResult(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("code", C.c_int32), ("stream_mask", C.c_uint32),
+                ("flags", C.c_uint32), ("c_floor", C.c_int32), ("c_cap", C.c_int32),
+                ("n_sub", C.c_uint32), ("n_probes", C.c_uint32),
+                ("curve", CurvePoint * NCURVE), ("m", Metrics)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = C.CDLL(path)
+        vp, P = C.c_void_p, C.POINTER
+        L.orc_encode_bound.argtypes = [P(Params), P(C.c_uint64)]
+        L.orc_encode.argtypes = [vp, P(Params), vp, C.c_uint64, P(C.c_uint64)]
+        L.orc_decode.argtypes = [vp, C.c_uint64, vp, C.c_uint64]
+        L.orc_stream_info.argtypes = [vp, C.c_uint64, P(Params)]
+        L.orc_profile.argtypes = [vp, P(Params), P(ProfileResult)]
+        L.orc_gain.argtypes = [C.c_int32]
+        L.orc_gain.restype = C.c_double
+        L.orc_inv_gain_mantissa.argtypes = [C.c_int32]
+        L.orc_inv_gain_mantissa.restype = C.c_double
+        L.orc_block_bracket.argtypes = [vp, P(Params), C.c_int64, P(C.c_double),
+                                        P(C.c_int32), P(C.c_int32)]
+        L.orc_encode_block.argtypes = [vp, P(Params), C.c_int64, vp, C.c_int32,
+                                       P(C.c_int32), P(C.c_int32), P(C.c_int32),
+                                       P(C.c_int32)]
+        L.orc_stream_values.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
+        L.orc_group_eps.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.orc_jee_tokens.argtypes = [vp, C.c_int32, vp, P(C.c_int32)]
+        L.orc_stats.argtypes = [vp, vp, C.c_uint64, P(Metrics)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(x_or_dtype, shape, params) -> Params:
+    dt = np.dtype(x_or_dtype)
+    p = Params()
+    p.size = C.sizeof(Params)
+    p.dtype = DTYPES[dt]
+    p.ndim = len(shape)
+    for i, d in enumerate(shape):
+        p.dims[i] = int(d)
+    brick = params.get("brick", (256,) if len(shape) == 1 else None)
+    for i, b in enumerate(brick):
+        p.brick[i] = int(b)
+    p.mode = MODES[params.get("mode", "lossless")]
+    p.stream_mask = int(params.get("stream_mask", 0))
+    p.rate = float(params.get("rate", 0.0))
+    p.target_corr = float(params.get("target_corr", 0.99999))
+    p.code = int(params.get("code", 0))
+    return p
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(rc, what)
+
+
+def encode_bound(dtype, shape, params) -> int:
+    p = make_params(dtype, shape, params)
+    b = C.c_uint64()
+    _check(lib().orc_encode_bound(C.byref(p), C.byref(b)), "encode_bound")
+    return b.value
+
+
+def encode(x: np.ndarray, params) -> np.ndarray:
+    x = np.ascontiguousarray(x)
+    p = make_params(x.dtype, x.shape, params)
+    b = C.c_uint64()
+    _check(lib().orc_encode_bound(C.byref(p), C.byref(b)), "encode_bound")
+    out = np.zeros(b.value, np.uint8)
+    nb = C.c_uint64()
+    _check(lib().orc_encode(_ptr(x), C.byref(p), _ptr(out), b.value, C.byref(nb)), "encode")
+    return out[: nb.value].copy()
+
+
+def stream_info(buf: np.ndarray) -> Params:
+    buf = np.ascontiguousarray(buf, np.uint8)
+    p = Params()
+    _check(lib().orc_stream_info(_ptr(buf), buf.size, C.byref(p)), "stream_info")
+    return p
+
+
+def decode(buf: np.ndarray) -> np.ndarray:
+    buf = np.ascontiguousarray(buf, np.uint8)
+    p = stream_info(buf)
+    shape = tuple(int(p.dims[i]) for i in range(p.ndim))
+    y = np.zeros(shape, NP_OF[p.dtype])
+    _check(lib().orc_decode(_ptr(buf), buf.size, _ptr(y), y.nbytes), "decode")
+    return y
+
+
+def decode_rc(buf: np.ndarray, y: np.ndarray) -> int:
+    buf = np.ascontiguousarray(buf, np.uint8)
+    return lib().orc_decode(_ptr(buf), buf.size, _ptr(y), y.nbytes)
+
+
+def profile(x: np.ndarray, params) -> ProfileResult:
+    x = np.ascontiguousarray(x)
+    p = make_params(x.dtype, x.shape, dict(params, code=0))
+    r = ProfileResult()
+    _check(lib().orc_profile(_ptr(x), C.byref(p), C.byref(r)), "profile")
+    return r
+
+
+def profile_dict(r: ProfileResult) -> dict:
+    m = {f: getattr(r.m, f) for f, _ in Metrics._fields_}
+    return {"code": r.code, "stream_mask": r.stream_mask, "flags": r.flags,
+            "c_floor": r.c_floor, "c_cap": r.c_cap, "n_sub": r.n_sub, "n_probes": r.n_probes,
+            "curve": [(r.curve[i].code, r.curve[i].ratio, r.curve[i].r) for i in range(NCURVE)],
+            "metrics": m}
+
+
+def gain(c: int) -> float:
+    return lib().orc_gain(int(c))
+
+
+def inv_gain_mantissa(f: int) -> float:
+    return lib().orc_inv_gain_mantissa(int(f))
+
+
+def block_bracket(x: np.ndarray, params, j: int):
+    x = np.ascontiguousarray(x)
+    p = make_params(x.dtype, x.shape, params)
+    M, cf, cc = C.c_double(), C.c_int32(), C.c_int32()
+    _check(lib().orc_block_bracket(_ptr(x), C.byref(p), int(j), C.byref(M), C.byref(cf),
+                                   C.byref(cc)), "block_bracket")
+    return M.value, cf.value, cc.value
+
+
+def encode_block(x: np.ndarray, params, j: int, cap_words: int = 20000):
+    x = np.ascontiguousarray(x)
+    p = make_params(x.dtype, x.shape, params)
+    w = np.zeros(cap_words, np.uint32)
+    nw, st, cj, ub = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().orc_encode_block(_ptr(x), C.byref(p), int(j), _ptr(w), cap_words,
+                                  C.byref(nw), C.byref(st), C.byref(cj), C.byref(ub)),
+           "encode_block")
+    return w[: nw.value].copy(), st.value, cj.value, ub.value
+
+
+def stream_values(a: np.ndarray, brick, W: int, s: int) -> np.ndarray:
+    a = np.ascontiguousarray(a, np.int64).ravel()
+    b = np.ones(3, np.uint32)
+    b[3 - len(brick):] = brick
+    v = np.zeros_like(a)
+    _check(lib().orc_stream_values(_ptr(a), _ptr(b), int(W), int(s), _ptr(v)), "stream_values")
+    return v
+
+
+def group_eps(v: np.ndarray, W: int) -> np.ndarray:
+    v = np.ascontiguousarray(v, np.int64).ravel()
+    G = v.size // 4
+    e = np.zeros(G, np.int32)
+    _check(lib().orc_group_eps(_ptr(v), G, int(W), _ptr(e)), "group_eps")
+    return e
+
+
+def jee_tokens(eps) -> list:
+    e = np.ascontiguousarray(eps, np.int32)
+    nib = np.zeros(2 * max(e.size, 1), np.uint8)
+    n = C.c_int32()
+    _check(lib().orc_jee_tokens(_ptr(e), e.size, _ptr(nib), C.byref(n)), "jee_tokens")
+    return [int(t) for t in nib[: n.value]]
+
+
+def stats(x: np.ndarray, y: np.ndarray) -> dict:
+    x = np.ascontiguousarray(x, np.float64).ravel()
+    y = np.ascontiguousarray(y, np.float64).ravel()
+    m = Metrics()
+    _check(lib().orc_stats(_ptr(x), _ptr(y), x.size, C.byref(m)), "stats")
+    return {f: getattr(m, f) for f, _ in Metrics._fields_}
