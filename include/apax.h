@@ -1,0 +1,157 @@
+/*
+ * apax.h -- C ABI of libapax.so, the MI355X (gfx950) implementation of the
+ * APAX numerical encoder, decoder and profiler (A. Wegener, arXiv 1303.4994).
+ *
+ * What the calls compute (paper sections):
+ *   apax_profile  Sec. 4  profiler: recommended operating point (gain code) for a
+ *                         correlation target (fixed quality) or a rate (fixed
+ *                         rate), the rate-correlation curve (Window 1) and the
+ *                         time-domain summary metrics (Window 2: r, SNR, RMS
+ *                         residual in % and dB, means, standard deviations).
+ *   apax_encode   Sec. 6  encoder: per-block attenuation, redundancy removal
+ *                         (derivative streams, Sec. 5), block floating point with
+ *                         one exponent per 4 samples, joint exponent encoding
+ *                         (JEE) of exponent differences, 4-byte (ints) / 6-byte
+ *                         (floats) block headers.
+ *   apax_decode   Sec. 1/6 decoder: the inverse of every encoder stage.
+ * The bit-level format (token codes, header fields, bit order, container) is
+ * not given in the paper; the library implements the reading documented with
+ * the project (LSB-first 32-bit words, [header][tokens][payload] per block,
+ * 64-byte stream header, uint16 block-length index).
+ *
+ * Conventions for every call
+ *   - Array, stream and workspace pointers are DEVICE pointers allocated and
+ *     owned by the caller (hipMalloc / torch).  Result structs of
+ *     apax_profile are HOST memory owned by the caller.
+ *   - Work is enqueued on the caller's stream; apax_encode/apax_decode return
+ *     before the GPU finishes.  apax_profile and apax_status synchronize the
+ *     stream.
+ *   - Return value: APAX_OK (0) or a negative APAX_E_* code.  Errors found on
+ *     the host (bad parameters, too-small buffers) return before anything is
+ *     enqueued.  Errors found on the device (non-finite input, corrupt
+ *     stream) are recorded in a status word inside the workspace; read them
+ *     with apax_status after the call completes.
+ *   - Calls that share one workspace must not overlap in time.
+ *   - Input arrays are C-contiguous (row-major, dims[ndim-1] fastest).
+ */
+#ifndef APAX_H
+#define APAX_H
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* dtypes (the integer and float types of the paper's Table 2) */
+enum { APAX_I8 = 1, APAX_I16 = 2, APAX_I32 = 3, APAX_F32 = 4, APAX_F64 = 5 };
+/* modes: lossless (integers only, unit gain), fixed rate (per-block word
+ * budget, Sec. 6 "compressed packet size"), fixed quality (correlation target) */
+enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2 };
+enum {
+  APAX_OK = 0,
+  APAX_E_INVALID = -1,     /* bad parameters */
+  APAX_E_UNSUPPORTED = -2, /* valid request this build does not implement (lossless floats) */
+  APAX_E_CAPACITY = -3,    /* output or workspace buffer too small */
+  APAX_E_CORRUPT = -4,     /* stream fails validation */
+  APAX_E_NONFINITE = -5,   /* NaN or Inf in the input */
+  APAX_E_HIP = -6,         /* HIP runtime error */
+  APAX_E_INTERNAL = -7     /* device-side safety limit hit (should not happen) */
+};
+#define APAX_NEAR_TIE 1u /* profile: a bisection probe was within 1e-11 of the target */
+#define APAX_NCURVE 17
+
+typedef struct apax_params {
+  uint32_t size;        /* = sizeof(apax_params) */
+  uint32_t dtype;       /* APAX_I8 .. APAX_F64 */
+  uint32_t ndim;        /* 1..3 */
+  uint32_t mode;        /* APAX_LOSSLESS / APAX_FIXED_RATE / APAX_FIXED_QUALITY */
+  uint64_t dims[3];     /* array extent, slow -> fast; first ndim entries used */
+  uint32_t brick[3];    /* block (brick) extent, slow -> fast; product B in
+                           [64, 16384], B % 4 == 0 (Sec. 6), brick[ndim-1] % 4 == 0 */
+  uint32_t stream_mask; /* bit s allows stream s (0 samples, 1 dx, 2 dx dx, 3 dy,
+                           4 dz, 5 dx dy, 6 dx dy dz, 7 verbatim); 0 = all of ndim.
+                           Variable modes always add streams 0 and 7; fixed rate
+                           adds 0 and never uses 7. */
+  double rate;          /* fixed rate: input bits per encoded bit (e.g. 4.0) */
+  double target_corr;   /* fixed quality (profile): correlation target, e.g. 0.99999 */
+  int32_t code;         /* gain code g(c) = (16+f) 2^(k-4), c = 16k+f: fixed-rate
+                           start code / fixed-quality code (from apax_profile);
+                           ignored in lossless mode.  ints: [-512, 0];
+                           floats: [-17120, 16383] */
+  uint32_t reserved;    /* 0 */
+} apax_params;
+
+typedef struct apax_metrics {
+  double r, one_minus_r;   /* Sec. 4 correlation (uncentered, as printed) */
+  double snr_db;           /* 10 log10(sum x^2 / sum d^2), d = x - y */
+  double rms_pct, rms_db;  /* RMS residual relative to RMS(x), in % and dB */
+  double mean_x, mean_y, mean_d, std_x, std_y, std_d, max_abs_d;
+  double sxx, syy, sdd, sds, sum_x, sum_y, sum_d; /* the sums behind the above */
+  double ratio;            /* input bytes / encoded bytes (whole stream) */
+  uint64_t n, enc_bytes;
+} apax_metrics;
+
+typedef struct apax_curve_point {
+  int32_t code;
+  int32_t pad;
+  double ratio;
+  double r;
+} apax_curve_point;
+
+typedef struct apax_profile_result {
+  uint32_t size;          /* = sizeof(apax_profile_result) */
+  int32_t code;           /* recommended code (c* fixed quality, c_p fixed rate, 0 lossless) */
+  uint32_t stream_mask;   /* recommended (pruned) stream mask */
+  uint32_t flags;         /* APAX_NEAR_TIE */
+  int32_t c_floor, c_cap; /* whole-array code bracket */
+  uint32_t n_sub;         /* subsample blocks (j % 16 == 0, or all if < 1024 blocks) */
+  uint32_t n_probes;      /* bisection probes */
+  apax_curve_point curve[APAX_NCURVE]; /* rate-correlation curve, Sec. 4 Window 1 */
+  apax_metrics m;         /* metrics at the recommended point, full array */
+} apax_profile_result;
+
+/* Upper bound of the encoded stream size in bytes (exact for fixed rate). */
+int apax_encode_bound(const apax_params* p, uint64_t* bytes);
+
+/* Workspace bytes needed by apax_profile / apax_encode / apax_decode for p
+ * (the maximum over the three calls). */
+int apax_workspace_size(const apax_params* p, uint64_t* bytes);
+
+/* Sec. 4 profiler.  d_x: input array (p->dtype, p->dims).  Synchronous:
+ * fills *h_out on return.  p->code is ignored. */
+int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* h_out,
+                 void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Sec. 6 encoder.  Writes the whole stream (header, index, blocks) to
+ * d_stream (cap bytes, >= apax_encode_bound) and its byte length to
+ * *d_nbytes (device uint64).  Asynchronous.  Non-finite input sets
+ * APAX_E_NONFINITE in the workspace status. */
+int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
+                uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Decoder.  h_hdr: host copy of the first 64 bytes of the stream (the
+ * parameters are taken from it; apax_stream_info parses it); d_stream: the
+ * whole stream on the device, nbytes long; d_y: output array (cap bytes).
+ * Asynchronous.  A malformed stream sets APAX_E_CORRUPT in the workspace
+ * status (output then unspecified). */
+int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* d_y,
+                uint64_t cap, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Parse a 64-byte stream header (host memory) into parameters. */
+int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out);
+
+/* Clear the workspace status word (enqueued on stream). */
+int apax_status_clear(void* d_ws, hipStream_t stream);
+
+/* Synchronize stream and return the workspace status (APAX_OK or the first
+ * device-side error of the calls since the last clear). */
+int apax_status(const void* d_ws, hipStream_t stream);
+
+const char* apax_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

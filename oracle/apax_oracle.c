@@ -1178,6 +1178,35 @@ int orc_profile(const void* x, const orc_params* p, orc_profile_result* res) {
 /* ------------------------------------------------------------------------ */
 /* pieces exposed for pins */
 
+/* r over the full array with every block at clamp(code) (the fixed-quality
+ * predicate of the profiler's bisection) */
+int orc_corr_at(const void* x, const orc_params* p, int32_t code, double* r) {
+  geom g;
+  orc_params q = *p;
+  q.code = 0;
+  q.mode = ORC_FIXED_QUALITY;
+  int e = setup_geom(&q, &g);
+  if (e) return e;
+  scratch s;
+  int* cf = malloc(sizeof(int) * (size_t)(g.nblocks ? g.nblocks : 1));
+  int* cc = malloc(sizeof(int) * (size_t)(g.nblocks ? g.nblocks : 1));
+  if (scratch_alloc(&s, g.B) || !cf || !cc) {
+    scratch_free(&s); free(cf); free(cc);
+    return ORC_E_INVALID;
+  }
+  for (int64_t j = 0; j < g.nblocks; j++) {
+    double M;
+    gather(&g, x, j, &s, &M);
+    bracket(&g, M, &cf[j], &cc[j]);
+  }
+  pctx P = {&g, x, &s, cf, cc};
+  *r = r_full(&P, code, NULL);
+  scratch_free(&s);
+  free(cf);
+  free(cc);
+  return ORC_OK;
+}
+
 int orc_block_bracket(const void* x, const orc_params* p, int64_t j, double* M, int32_t* c_floor,
                       int32_t* c_cap) {
   geom g;

@@ -100,6 +100,7 @@ int orc_stream_values(const int64_t* a, const uint32_t* brick, int32_t W, int32_
 int orc_group_eps(const int64_t* v, int32_t G, int32_t W, int32_t* eps);
 int orc_jee_tokens(const int32_t* eps, int32_t G, uint8_t* nibbles, int32_t* n_nibbles);
 int orc_stats(const double* x, const double* y, uint64_t n, orc_metrics* m);
+int orc_corr_at(const void* x, const orc_params* p, int32_t code, double* r);
 
 #ifdef __cplusplus
 }

@@ -84,6 +84,7 @@ def lib():
         L.orc_group_eps.argtypes = [vp, C.c_int32, C.c_int32, vp]
         L.orc_jee_tokens.argtypes = [vp, C.c_int32, vp, P(C.c_int32)]
         L.orc_stats.argtypes = [vp, vp, C.c_uint64, P(Metrics)]
+        L.orc_corr_at.argtypes = [vp, P(Params), C.c_int32, P(C.c_double)]
         _lib = L
     return _lib
 
@@ -230,3 +231,11 @@ def stats(x: np.ndarray, y: np.ndarray) -> dict:
     m = Metrics()
     _check(lib().orc_stats(_ptr(x), _ptr(y), x.size, C.byref(m)), "stats")
     return {f: getattr(m, f) for f, _ in Metrics._fields_}
+
+
+def corr_at(x: np.ndarray, params, code: int) -> float:
+    x = np.ascontiguousarray(x)
+    p = make_params(x.dtype, x.shape, dict(params, code=0))
+    r = C.c_double()
+    _check(lib().orc_corr_at(_ptr(x), C.byref(p), int(code), C.byref(r)), "corr_at")
+    return r.value

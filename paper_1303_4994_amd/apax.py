@@ -1,0 +1,242 @@
+"""Python binding of libapax.so (argument marshalling only).
+
+Names follow the C ABI in include/apax.h.  Arrays are torch tensors on the
+GPU; every call runs on the current torch stream unless one is given.  The
+compute runs in the HIP library: if libapax.so is missing this module raises
+at import time -- there is no CPU fallback.
+
+Parameters are dicts:
+    {"mode": "lossless" | "fixed_rate" | "fixed_quality",
+     "brick": (..), "stream_mask": 0, "rate": 4.0, "target_corr": 0.99999,
+     "code": 0}
+dtype and dims come from the tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import struct
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapax.so")
+
+I8, I16, I32, F32, F64 = 1, 2, 3, 4, 5
+LOSSLESS, FIXED_RATE, FIXED_QUALITY = 0, 1, 2
+OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE, E_HIP, E_INTERNAL = \
+    0, -1, -2, -3, -4, -5, -6, -7
+NEAR_TIE = 1
+NCURVE = 17
+
+_DT = {torch.int8: I8, torch.int16: I16, torch.int32: I32, torch.float32: F32,
+       torch.float64: F64}
+_TORCH_OF = {v: k for k, v in _DT.items()}
+_MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY}
+
+
+class ApaxError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {code} ({_errstr(code)})")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32),
+                ("mode", C.c_uint32), ("dims", C.c_uint64 * 3), ("brick", C.c_uint32 * 3),
+                ("stream_mask", C.c_uint32), ("rate", C.c_double),
+                ("target_corr", C.c_double), ("code", C.c_int32), ("reserved", C.c_uint32)]
+
+
+class Metrics(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "r", "one_minus_r", "snr_db", "rms_pct", "rms_db", "mean_x", "mean_y", "mean_d",
+        "std_x", "std_y", "std_d", "max_abs_d", "sxx", "syy", "sdd", "sds", "sum_x",
+        "sum_y", "sum_d", "ratio")] + [("n", C.c_uint64), ("enc_bytes", C.c_uint64)]
+
+
+class CurvePoint(C.Structure):
+    _fields_ = [("code", C.c_int32), ("pad", C.c_int32), ("ratio", C.c_double),
+                ("r", C.c_double)]
+
+
+class ProfileResult(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("code", C.c_int32), ("stream_mask", C.c_uint32),
+                ("flags", C.c_uint32), ("c_floor", C.c_int32), ("c_cap", C.c_int32),
+                ("n_sub", C.c_uint32), ("n_probes", C.c_uint32),
+                ("curve", CurvePoint * NCURVE), ("m", Metrics)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, P, u64 = C.c_void_p, C.POINTER, C.c_uint64
+    L.apax_encode_bound.argtypes = [P(Params), P(u64)]
+    L.apax_workspace_size.argtypes = [P(Params), P(u64)]
+    L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
+    L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
+    L.apax_decode.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp]
+    L.apax_stream_info.argtypes = [vp, u64, P(Params)]
+    L.apax_status_clear.argtypes = [vp, vp]
+    L.apax_status.argtypes = [vp, vp]
+    L.apax_strerror.argtypes = [C.c_int]
+    L.apax_strerror.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _errstr(code):
+    return lib.apax_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ApaxError(rc, what)
+
+
+def make_params(dtype: torch.dtype, shape, params: dict) -> Params:
+    p = Params()
+    p.size = C.sizeof(Params)
+    p.dtype = _DT[dtype]
+    p.ndim = len(shape)
+    for i, d in enumerate(shape):
+        p.dims[i] = int(d)
+    brick = params.get("brick", (256,) if len(shape) == 1 else None)
+    if brick is None or len(brick) != len(shape):
+        raise ApaxError(E_INVALID, "brick must have one extent per dimension")
+    for i, b in enumerate(brick):
+        p.brick[i] = int(b)
+    p.mode = _MODES[params.get("mode", "lossless")]
+    p.stream_mask = int(params.get("stream_mask", 0))
+    p.rate = float(params.get("rate", 0.0))
+    p.target_corr = float(params.get("target_corr", 0.99999))
+    p.code = int(params.get("code", 0))
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() else C.c_void_p(0)
+
+
+def apax_encode_bound(dtype, shape, params) -> int:
+    p = make_params(dtype, shape, params)
+    b = C.c_uint64()
+    _check(lib.apax_encode_bound(C.byref(p), C.byref(b)), "apax_encode_bound")
+    return b.value
+
+
+def apax_workspace_size(dtype, shape, params) -> int:
+    p = make_params(dtype, shape, params)
+    b = C.c_uint64()
+    _check(lib.apax_workspace_size(C.byref(p), C.byref(b)), "apax_workspace_size")
+    return b.value
+
+
+def workspace(dtype, shape, params, device="cuda") -> torch.Tensor:
+    n = apax_workspace_size(dtype, shape, params)
+    return torch.empty(max(n, 16), dtype=torch.uint8, device=device)
+
+
+def apax_status_clear(ws: torch.Tensor, stream=None):
+    _check(lib.apax_status_clear(_dev_ptr(ws), _stream_ptr(stream)), "apax_status_clear")
+
+
+def apax_status(ws: torch.Tensor, stream=None) -> int:
+    return lib.apax_status(_dev_ptr(ws), _stream_ptr(stream))
+
+
+def apax_profile(x: torch.Tensor, params: dict, ws: torch.Tensor | None = None, stream=None) -> dict:
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    if ws is None:
+        ws = workspace(x.dtype, tuple(x.shape), params, x.device)
+    r = ProfileResult()
+    _check(lib.apax_profile(_dev_ptr(x), C.byref(p), C.byref(r), _dev_ptr(ws), ws.numel(),
+                            _stream_ptr(stream)), "apax_profile")
+    return profile_dict(r)
+
+
+def profile_dict(r: ProfileResult) -> dict:
+    m = {f: getattr(r.m, f) for f, _ in Metrics._fields_}
+    return {"code": r.code, "stream_mask": r.stream_mask, "flags": r.flags,
+            "c_floor": r.c_floor, "c_cap": r.c_cap, "n_sub": r.n_sub, "n_probes": r.n_probes,
+            "curve": [(r.curve[i].code, r.curve[i].ratio, r.curve[i].r) for i in range(NCURVE)],
+            "metrics": m}
+
+
+def apax_encode(x: torch.Tensor, params: dict, out: torch.Tensor | None = None,
+                nbytes: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                stream=None, clear_status: bool = True):
+    """Encode x; returns (stream buffer, device int64 tensor holding the byte length)."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), params)
+    bound = C.c_uint64()
+    _check(lib.apax_encode_bound(C.byref(p), C.byref(bound)), "apax_encode_bound")
+    if out is None:
+        out = torch.empty(max(bound.value, 64), dtype=torch.uint8, device=x.device)
+    if nbytes is None:
+        nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
+    if ws is None:
+        ws = workspace(x.dtype, tuple(x.shape), params, x.device)
+    sp = _stream_ptr(stream)
+    if clear_status:
+        _check(lib.apax_status_clear(_dev_ptr(ws), sp), "apax_status_clear")
+    _check(lib.apax_encode(_dev_ptr(x), C.byref(p), _dev_ptr(out), out.numel(),
+                           _dev_ptr(nbytes), _dev_ptr(ws), ws.numel(), sp), "apax_encode")
+    return out, nbytes
+
+
+def apax_stream_info(hdr: bytes) -> dict:
+    b = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
+    p = Params()
+    _check(lib.apax_stream_info(C.cast(b, C.c_void_p), 64, C.byref(p)), "apax_stream_info")
+    names = {v: k for k, v in _MODES.items()}
+    return {"dtype": _TORCH_OF[p.dtype], "shape": tuple(int(p.dims[i]) for i in range(p.ndim)),
+            "mode": names[p.mode], "brick": tuple(int(p.brick[i]) for i in range(p.ndim)),
+            "stream_mask": p.stream_mask, "rate": p.rate, "code": p.code}
+
+
+def stream_nbytes(hdr: bytes) -> int:
+    info = apax_stream_info(hdr)
+    payload_words = struct.unpack_from("<Q", hdr, 56)[0]
+    nb = struct.unpack_from("<Q", hdr, 48)[0]
+    if info["mode"] == "fixed_rate":
+        area = 64
+    else:
+        o = 64 + (2 * nb + 7) // 8 * 8 + 8 * ((nb + 63) // 64)
+        area = (o + 15) // 16 * 16
+    return area + 4 * payload_words
+
+
+def apax_decode(stream_buf: torch.Tensor, nbytes: int | None = None, hdr: bytes | None = None,
+                y: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None,
+                clear_status: bool = True) -> torch.Tensor:
+    assert stream_buf.is_cuda
+    if hdr is None:
+        hdr = bytes(stream_buf[:64].cpu().numpy().tobytes())
+    info = apax_stream_info(hdr)
+    if nbytes is None:
+        nbytes = stream_nbytes(hdr)
+    params = {"mode": info["mode"], "brick": info["brick"], "rate": info["rate"],
+              "code": info["code"], "target_corr": 0.5}
+    if y is None:
+        y = torch.empty(info["shape"], dtype=info["dtype"], device=stream_buf.device)
+    if ws is None:
+        ws = workspace(info["dtype"], info["shape"], params, stream_buf.device)
+    sp = _stream_ptr(stream)
+    hb = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
+    if clear_status:
+        _check(lib.apax_status_clear(_dev_ptr(ws), sp), "apax_status_clear")
+    _check(lib.apax_decode(C.cast(hb, C.c_void_p), _dev_ptr(stream_buf), int(nbytes), _dev_ptr(y),
+                           y.numel() * y.element_size(), _dev_ptr(ws), ws.numel(), sp),
+           "apax_decode")
+    return y

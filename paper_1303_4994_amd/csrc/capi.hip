@@ -1,0 +1,682 @@
+// capi.hip -- host side of libapax: parameter validation, stream container
+// layout, workspace layout, kernel launches and the profiler's control loop.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "apax.h"
+#include "kernels.h"
+
+using namespace apax;
+
+namespace {
+
+constexpr uint32_t MAGIC = 0x58415041u;  // "APAX"
+constexpr uint32_t ND_ALLOWED[4] = {0u, 0x87u, 0xAFu, 0xFFu};
+
+struct HG {
+  Geo g;
+  int dtype, mode, ndim, esz, W, H;
+  bool isint;
+  uint64_t nsamples;
+};
+
+int floordiv16(int c) { return c >> 4; }
+
+double host_gain(int c) { return ldexp((double)(16 + (c & 15)), floordiv16(c) - 4); }
+
+// Largest code in [cmin, cmax] with fl64(M * g(c)) <= lim (monotone in c).
+int host_largest(double M, double lim, int cmin, int cmax) {
+  if (M * host_gain(cmax) <= lim) return cmax;
+  int lo = cmin, hi = cmax;
+  while (hi - lo > 1) {
+    int mid = lo + ((hi - lo) >> 1);
+    if (M * host_gain(mid) <= lim) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Validation of apax_params (the rules of include/apax.h).  forced_budget >= 0
+// takes the fixed-rate budget from a stream header instead of the rate.
+int setup(const apax_params* p, HG& h, int forced_budget = -1) {
+  memset(&h, 0, sizeof(h));
+  if (!p || p->size != sizeof(apax_params)) return APAX_E_INVALID;
+  if (p->dtype < APAX_I8 || p->dtype > APAX_F64) return APAX_E_INVALID;
+  if (p->ndim < 1 || p->ndim > 3) return APAX_E_INVALID;
+  if (p->mode > APAX_FIXED_QUALITY) return APAX_E_INVALID;
+  static const int ESZ[6] = {0, 1, 2, 4, 4, 8};
+  static const int WQ[6] = {0, 8, 16, 32, 32, 32};
+  h.dtype = (int)p->dtype;
+  h.mode = (int)p->mode;
+  h.ndim = (int)p->ndim;
+  h.esz = ESZ[h.dtype];
+  h.W = WQ[h.dtype];
+  h.isint = h.dtype <= APAX_I32;
+  h.H = h.isint ? 32 : 48;
+  if (h.mode == APAX_LOSSLESS && !h.isint) return APAX_E_UNSUPPORTED;
+  int64_t n[3] = {1, 1, 1}, b[3] = {1, 1, 1};
+  int off = 3 - h.ndim;
+  int64_t B = 1;
+  for (int i = 0; i < h.ndim; i++) {
+    if (p->brick[i] < 1 || p->brick[i] > 16384) return APAX_E_INVALID;
+    if (p->dims[i] > (1ull << 40)) return APAX_E_INVALID;
+    n[off + i] = (int64_t)p->dims[i];
+    b[off + i] = p->brick[i];
+    B *= p->brick[i];
+  }
+  if (B < 64 || B > 16384 || B % 4 != 0 || b[2] % 4 != 0) return APAX_E_INVALID;
+  Geo& g = h.g;
+  for (int i = 0; i < 3; i++) { g.n[i] = n[i]; g.b[i] = (int32_t)b[i]; }
+  g.B = (int32_t)B;
+  g.G = (int32_t)(B / 4);
+  g.rowq = g.b[2] / 4;
+  g.plane = g.b[1] * g.rowq;
+  int64_t nb[3];
+  g.nblocks = 1;
+  for (int i = 0; i < 3; i++) {
+    nb[i] = (n[i] + b[i] - 1) / b[i];
+    g.nblocks *= nb[i];
+  }
+  g.nbx = nb[2] ? nb[2] : 1;
+  g.nby = nb[1] ? nb[1] : 1;
+  if (g.nblocks > (int64_t)0x7FFFFFFF) return APAX_E_UNSUPPORTED;
+  h.nsamples = (uint64_t)(n[0] * n[1] * n[2]);
+  uint32_t allowed = ND_ALLOWED[h.ndim];
+  uint32_t m = p->stream_mask ? p->stream_mask : allowed;
+  if (m & ~allowed) return APAX_E_INVALID;
+  m = h.mode == APAX_FIXED_RATE ? ((m | 1u) & 0x7Fu) : (m | 0x81u);
+  g.mask = m;
+  g.mode = h.mode;
+  g.cmin = h.isint ? -512 : -17120;
+  g.cmax = h.isint ? 0 : 16383;
+  g.code = 0;
+  if (h.mode != APAX_LOSSLESS) {
+    if (p->code < g.cmin || p->code > g.cmax) return APAX_E_INVALID;
+    g.code = p->code;
+  }
+  g.maxw = (h.H + g.B * h.W + 31) / 32;
+  g.ldsw = (h.H + 8 * (g.G - 1) + g.B * h.W + 31) / 32 + 2;
+  g.budget = 0;
+  if (h.mode == APAX_FIXED_RATE) {
+    double words;
+    if (forced_budget >= 0) {
+      words = forced_budget;
+    } else {
+      if (!(p->rate > 0.0) || !isfinite(p->rate)) return APAX_E_INVALID;
+      words = floor((double)g.B * 8.0 * h.esz / (p->rate * 32.0));
+    }
+    int min_words = (h.H + 4 * (g.G / 2) + 31) / 32;
+    if (words < min_words || words > 65535.0) return APAX_E_INVALID;
+    g.budget = (int32_t)words;
+  }
+  if (h.mode == APAX_FIXED_QUALITY && forced_budget < 0) {
+    if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
+  }
+  if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not in this build
+  return APAX_OK;
+}
+
+uint64_t lens_bytes(const HG& h) { return ((uint64_t)h.g.nblocks * 2 + 7) / 8 * 8; }
+uint64_t sbo_count(const HG& h) { return ((uint64_t)h.g.nblocks + 63) / 64; }
+
+uint64_t area_offset(const HG& h) {
+  if (h.mode == APAX_FIXED_RATE) return 64;
+  uint64_t o = 64 + lens_bytes(h) + 8 * sbo_count(h);
+  return (o + 15) / 16 * 16;
+}
+
+uint64_t bound_of(const HG& h) {
+  uint64_t per = h.g.budget ? (uint64_t)h.g.budget : (uint64_t)h.g.maxw;
+  return area_offset(h) + 4 * per * (uint64_t)h.g.nblocks;
+}
+
+void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
+  uint8_t b[64];
+  memset(b, 0, sizeof(b));
+  auto put16 = [&](int o, uint16_t v) { memcpy(b + o, &v, 2); };
+  auto put32 = [&](int o, uint32_t v) { memcpy(b + o, &v, 4); };
+  auto put64 = [&](int o, uint64_t v) { memcpy(b + o, &v, 8); };
+  put32(0, MAGIC);
+  put16(4, 1);
+  b[6] = (uint8_t)h.dtype;
+  b[7] = (uint8_t)h.mode;
+  b[8] = (uint8_t)h.ndim;
+  b[9] = (uint8_t)h.g.mask;
+  put16(10, (uint16_t)h.g.budget);
+  put32(12, (uint32_t)h.g.code);
+  for (int i = 0; i < 3; i++) put64(16 + 8 * i, i < h.ndim ? p->dims[i] : 0);
+  for (int i = 0; i < 3; i++) put16(40 + 2 * i, (uint16_t)(i < h.ndim ? p->brick[i] : 0));
+  put64(48, (uint64_t)h.g.nblocks);
+  put64(56, h.mode == APAX_FIXED_RATE ? (uint64_t)h.g.budget * (uint64_t)h.g.nblocks : 0);
+  memcpy(hdr, b, 64);
+}
+
+// ---- workspace layout
+constexpr uint64_t WS_STATUS = 0, WS_TICKET = 4, WS_MAXBITS = 16, WS_FITS = 64, WS_HIST = 160,
+                   WS_WORDS = 256, WS_FINAL = 512, WS_CTRL = 2048;
+
+uint64_t tiles_enc(const HG& h) { return (uint64_t)encode_tiles(h.g); }
+
+uint64_t partial_floats(const HG& h) {
+  int64_t sub = h.g.nblocks >= 1024 ? (h.g.nblocks + 15) / 16 : h.g.nblocks;
+  uint64_t a = (uint64_t)prof_tiles(h.g, h.g.nblocks);
+  uint64_t b = (uint64_t)MAXCODES * (uint64_t)prof_tiles(h.g, sub);
+  return std::max(a, b) * NSUM * 2;
+}
+
+uint64_t ws_need(const HG& h) {
+  return WS_CTRL + ((8 * tiles_enc(h) + 255) / 256) * 256 + 4 * partial_floats(h);
+}
+
+uint64_t* tile_state_ptr(void* ws) { return (uint64_t*)((uint8_t*)ws + WS_CTRL); }
+float* partials_ptr(void* ws, const HG& h) {
+  return (float*)((uint8_t*)ws + WS_CTRL + ((8 * tiles_enc(h) + 255) / 256) * 256);
+}
+
+int hip_err(hipError_t e) { return e == hipSuccess ? APAX_OK : APAX_E_HIP; }
+
+__global__ void k_clear(uint32_t* p, int nwords) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+__global__ void k_header_only(uint32_t* out, uint64_t* d_nbytes, uint64_t nbytes, uint32_t h0,
+                              uint32_t h1, uint32_t h2, uint32_t h3, uint32_t h4, uint32_t h5,
+                              uint32_t h6, uint32_t h7, uint32_t h8, uint32_t h9, uint32_t h10,
+                              uint32_t h11, uint32_t h12, uint32_t h13, uint32_t h14,
+                              uint32_t h15) {
+  if (threadIdx.x == 0) {
+    uint32_t h[16] = {h0, h1, h2, h3, h4, h5, h6, h7, h8, h9, h10, h11, h12, h13, h14, h15};
+    for (int i = 0; i < 16; i++) out[i] = h[i];
+    *d_nbytes = nbytes;
+  }
+}
+
+// r from the four sums, cancellation-free form of the printed formula (Sec. 4)
+void r_of(double sxx, double syy, double sdd, double sds, double& r, double& omr) {
+  if (sxx == 0.0 && syy == 0.0) { r = 1.0; omr = 0.0; return; }
+  if (sxx == 0.0 || syy == 0.0) { r = 0.0; omr = 1.0; return; }
+  double nx = sqrt(sxx), ny = sqrt(syy);
+  double dn = sds / (nx + ny);
+  omr = (sdd - dn * dn) / (2.0 * nx * ny);
+  r = 1.0 - omr;
+}
+
+// valid samples in block j
+uint64_t block_valid(const HG& h, int64_t j) {
+  const Geo& g = h.g;
+  int64_t bx = j % g.nbx, t = j / g.nbx, by = t % g.nby, bz = t / g.nby;
+  int64_t ex = std::min<int64_t>(g.b[2], g.n[2] - bx * g.b[2]);
+  int64_t ey = std::min<int64_t>(g.b[1], g.n[1] - by * g.b[1]);
+  int64_t ez = std::min<int64_t>(g.b[0], g.n[0] - bz * g.b[0]);
+  return (uint64_t)(ex * ey * ez);
+}
+
+struct ProfRun {
+  const HG& h;
+  const void* x;
+  void* ws;
+  hipStream_t s;
+  int escale;
+  int64_t sub_stride, sub_n;
+
+  uint8_t* ctrl() const { return (uint8_t*)ws; }
+
+  int clear_ctrl() {
+    hipLaunchKernelGGL(k_clear, dim3(2), dim3(256), 0, s, (uint32_t*)ws, (int)(WS_FINAL / 4));
+    return hip_err(hipGetLastError());
+  }
+
+  ProfArgs args(int op, int rule, uint32_t mask, bool sub) const {
+    ProfArgs A;
+    memset(&A, 0, sizeof(A));
+    A.x = x;
+    A.g = h.g;
+    A.op = op;
+    A.rule = rule;
+    A.mask = mask;
+    A.jstride = sub ? sub_stride : 1;
+    A.nbe = sub ? sub_n : h.g.nblocks;
+    A.partials = partials_ptr(ws, h);
+    A.words = (unsigned long long*)(ctrl() + WS_WORDS);
+    A.fits = (unsigned int*)(ctrl() + WS_FITS);
+    A.hist = (unsigned int*)(ctrl() + WS_HIST);
+    A.maxbits = (unsigned long long*)(ctrl() + WS_MAXBITS);
+    A.status = (uint32_t*)(ctrl() + WS_STATUS);
+    A.escale = escale;
+    A.ncodes = 1;
+    return A;
+  }
+
+  int run(ProfArgs& A, bool finalize) {
+    int e = clear_ctrl();
+    if (e) return e;
+    e = hip_err(launch_profile(h.dtype, h.ndim, A, s));
+    if (e) return e;
+    if (finalize) {
+      e = hip_err(launch_finalize(A.partials, A.ntiles, A.ncodes, (double*)(ctrl() + WS_FINAL), s));
+      if (e) return e;
+    }
+    return APAX_OK;
+  }
+
+  int read(void* dst, uint64_t off, size_t n) {
+    if (hipMemcpyAsync(dst, ctrl() + off, n, hipMemcpyDeviceToHost, s) != hipSuccess) return APAX_E_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return APAX_E_HIP;
+    uint32_t st = 0;
+    if (hipMemcpy(&st, ctrl() + WS_STATUS, 4, hipMemcpyDeviceToHost) != hipSuccess) return APAX_E_HIP;
+    if (st & ST_NONFINITE) return APAX_E_NONFINITE;
+    if (st & ST_INTERNAL) return APAX_E_INTERNAL;
+    return APAX_OK;
+  }
+
+  // sums of one code (already finalised), unscaled
+  void sums(const double* f, int ci, double out[NSUM]) const {
+    for (int i = 0; i < NSUM; i++) {
+      bool sq = i >= S_XX;
+      out[i] = ldexp(f[ci * NSUM + i], sq ? 2 * escale : escale);
+    }
+  }
+};
+
+}  // namespace
+
+// ======================================================================== C ABI
+
+extern "C" {
+
+const char* apax_strerror(int code) {
+  switch (code) {
+    case APAX_OK: return "ok";
+    case APAX_E_INVALID: return "invalid parameters";
+    case APAX_E_UNSUPPORTED: return "unsupported parameters";
+    case APAX_E_CAPACITY: return "buffer too small";
+    case APAX_E_CORRUPT: return "corrupt stream";
+    case APAX_E_NONFINITE: return "non-finite input";
+    case APAX_E_HIP: return "HIP runtime error";
+    case APAX_E_INTERNAL: return "device safety limit";
+    default: return "unknown error";
+  }
+}
+
+int apax_encode_bound(const apax_params* p, uint64_t* bytes) {
+  HG h;
+  int e = setup(p, h);
+  if (e) return e;
+  *bytes = bound_of(h);
+  return APAX_OK;
+}
+
+int apax_workspace_size(const apax_params* p, uint64_t* bytes) {
+  apax_params q = *p;
+  q.code = 0;
+  HG h;
+  int e = setup(&q, h);
+  if (e) return e;
+  *bytes = ws_need(h);
+  return APAX_OK;
+}
+
+int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
+  if (!h_hdr || n < 64 || !out) return APAX_E_CORRUPT;
+  const uint8_t* b = (const uint8_t*)h_hdr;
+  uint32_t magic;
+  uint16_t ver, budget, rsv, brick[3];
+  int32_t code;
+  uint64_t dims[3], nblocks;
+  memcpy(&magic, b, 4);
+  memcpy(&ver, b + 4, 2);
+  memcpy(&budget, b + 10, 2);
+  memcpy(&code, b + 12, 4);
+  memcpy(dims, b + 16, 24);
+  memcpy(brick, b + 40, 6);
+  memcpy(&rsv, b + 46, 2);
+  memcpy(&nblocks, b + 48, 8);
+  if (magic != MAGIC || ver != 1 || rsv != 0) return APAX_E_CORRUPT;
+  apax_params p;
+  memset(&p, 0, sizeof(p));
+  p.size = sizeof(p);
+  p.dtype = b[6];
+  p.mode = b[7];
+  p.ndim = b[8];
+  p.stream_mask = b[9];
+  p.code = code;
+  if (p.ndim < 1 || p.ndim > 3) return APAX_E_CORRUPT;
+  for (int i = 0; i < 3; i++) {
+    if (i < (int)p.ndim) { p.dims[i] = dims[i]; p.brick[i] = brick[i]; }
+    else if (dims[i] || brick[i]) return APAX_E_CORRUPT;
+  }
+  p.target_corr = 0.5;
+  if (p.mode == APAX_FIXED_RATE) {
+    if (budget == 0) return APAX_E_CORRUPT;
+  } else if (budget != 0) {
+    return APAX_E_CORRUPT;
+  }
+  HG h;
+  if (setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1) != APAX_OK) return APAX_E_CORRUPT;
+  if (h.g.mask != p.stream_mask || (uint64_t)h.g.nblocks != nblocks) return APAX_E_CORRUPT;
+  if (p.mode == APAX_FIXED_RATE) {
+    uint32_t B = 1;
+    for (int i = 0; i < (int)p.ndim; i++) B *= p.brick[i];
+    p.rate = (double)B * 8.0 * h.esz / (32.0 * (double)budget);
+  }
+  *out = p;
+  return APAX_OK;
+}
+
+int apax_status_clear(void* d_ws, hipStream_t stream) {
+  if (!d_ws) return APAX_E_INVALID;
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, 1);
+  return hip_err(hipGetLastError());
+}
+
+int apax_status(const void* d_ws, hipStream_t stream) {
+  if (!d_ws) return APAX_E_INVALID;
+  uint32_t st = 0;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  if (hipMemcpy(&st, d_ws, 4, hipMemcpyDeviceToHost) != hipSuccess) return APAX_E_HIP;
+  if (st & ST_NONFINITE) return APAX_E_NONFINITE;
+  if (st & ST_CORRUPT) return APAX_E_CORRUPT;
+  if (st & ST_INTERNAL) return APAX_E_INTERNAL;
+  return APAX_OK;
+}
+
+int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
+                uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  HG h;
+  int e = setup(p, h);
+  if (e) return e;
+  if (!d_stream || !d_nbytes || !d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
+  if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
+  if (cap < bound_of(h)) return APAX_E_CAPACITY;
+  if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
+  EncArgs A;
+  memset(&A, 0, sizeof(A));
+  A.g = h.g;
+  A.x = d_x;
+  A.out_base = (uint8_t*)d_stream;
+  A.area = area_offset(h);
+  A.out_words = (uint32_t*)((uint8_t*)d_stream + A.area);
+  A.lens = (uint16_t*)((uint8_t*)d_stream + 64);
+  A.sbo = (uint64_t*)((uint8_t*)d_stream + 64 + lens_bytes(h));
+  A.d_nbytes = d_nbytes;
+  A.status = (uint32_t*)((uint8_t*)d_ws + WS_STATUS);
+  A.ticket = (uint32_t*)((uint8_t*)d_ws + WS_TICKET);
+  A.tile_state = tile_state_ptr(d_ws);
+  make_header(p, h, A.hdr);
+  if (h.mode != APAX_FIXED_RATE) {
+    A.zpad[0] = (uint64_t)(64 + 2 * (uint64_t)h.g.nblocks);
+    A.zpad[1] = (uint64_t)(64 + lens_bytes(h));
+    A.zpad[2] = (uint64_t)(64 + lens_bytes(h) + 8 * sbo_count(h));
+    A.zpad[3] = A.area;
+  }
+  if (h.g.nblocks == 0) {
+    const uint32_t* q = A.hdr;
+    hipLaunchKernelGGL(k_header_only, dim3(1), dim3(64), 0, stream, (uint32_t*)d_stream, d_nbytes,
+                       A.area, q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10],
+                       q[11], q[12], q[13], q[14], q[15]);
+    return hip_err(hipGetLastError());
+  }
+  return hip_err(launch_encode(h.dtype, h.ndim, A, stream));
+}
+
+int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* d_y, uint64_t cap,
+                void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  apax_params p;
+  int e = apax_stream_info(h_hdr, 64, &p);
+  if (e) return e;
+  uint16_t budget;
+  memcpy(&budget, (const uint8_t*)h_hdr + 10, 2);
+  HG h;
+  e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1);
+  if (e) return e == APAX_E_UNSUPPORTED ? e : APAX_E_CORRUPT;
+  if (!d_stream || !d_ws || (!d_y && h.nsamples)) return APAX_E_INVALID;
+  if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
+  if (cap < h.nsamples * (uint64_t)h.esz) return APAX_E_CAPACITY;
+  if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
+  uint64_t pw;
+  memcpy(&pw, (const uint8_t*)h_hdr + 56, 8);
+  uint64_t area = area_offset(h);
+  if (h.mode == APAX_FIXED_RATE && pw != (uint64_t)h.g.budget * (uint64_t)h.g.nblocks) return APAX_E_CORRUPT;
+  if (nbytes < area || (nbytes - area) / 4 < pw) return APAX_E_CORRUPT;
+  DecArgs A;
+  memset(&A, 0, sizeof(A));
+  A.g = h.g;
+  A.in = (const uint8_t*)d_stream;
+  A.words = (const uint32_t*)((const uint8_t*)d_stream + area);
+  A.lens = (const uint16_t*)((const uint8_t*)d_stream + 64);
+  A.sbo = (const uint64_t*)((const uint8_t*)d_stream + 64 + lens_bytes(h));
+  A.y = d_y;
+  A.status = (uint32_t*)((uint8_t*)d_ws + WS_STATUS);
+  A.payload_words = pw;
+  memcpy(A.hdr, h_hdr, 64);
+  return hip_err(launch_decode(h.dtype, h.ndim, A, stream));
+}
+
+int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out, void* d_ws,
+                 uint64_t ws_bytes, hipStream_t stream) {
+  if (!p || !out) return APAX_E_INVALID;
+  apax_params q = *p;
+  q.code = 0;
+  HG h;
+  int e = setup(&q, h);
+  if (e) return e;
+  if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
+  if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
+  if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
+  memset(out, 0, sizeof(*out));
+  out->size = sizeof(*out);
+  const Geo& g = h.g;
+  ProfRun R{h, d_x, d_ws, stream, 0, 1, 0};
+  R.sub_stride = g.nblocks >= 1024 ? 16 : 1;
+  R.sub_n = (g.nblocks + R.sub_stride - 1) / R.sub_stride;
+  out->n_sub = (uint32_t)R.sub_n;
+
+  // 1. max |x| over the array
+  double Mall = 0.0;
+  if (g.nblocks) {
+    ProfArgs A = R.args(P_MAX, R_LOSSLESS, g.mask, false);
+    if ((e = R.run(A, false))) return e;
+    uint64_t mb = 0;
+    if ((e = R.read(&mb, WS_MAXBITS, 8))) return e;
+    memcpy(&Mall, &mb, 8);
+  }
+  int CF = host_largest(Mall, 0.5, g.cmin, g.cmax);
+  int CC = h.isint ? 0 : host_largest(Mall, 2147483647.0, g.cmin, g.cmax);
+  out->c_floor = CF;
+  out->c_cap = CC;
+  int ex = 0;
+  if (Mall > 0) frexp(Mall, &ex);
+  R.escale = ex;
+
+  auto stats_at = [&](int rule, uint32_t mask, const int* codes, int ncodes, bool sub,
+                      std::vector<double>& sums, std::vector<uint64_t>& words, double* maxd) -> int {
+    ProfArgs A = R.args(P_STATS, rule, mask, sub);
+    A.ncodes = ncodes;
+    for (int i = 0; i < ncodes; i++) A.codes[i] = codes[i];
+    int e2 = R.run(A, true);
+    if (e2) return e2;
+    std::vector<double> f(ncodes * NSUM);
+    std::vector<unsigned long long> w(ncodes);
+    if ((e2 = R.read(w.data(), WS_WORDS, 8 * ncodes))) return e2;
+    if ((e2 = R.read(f.data(), WS_FINAL, 8 * NSUM * ncodes))) return e2;
+    sums.assign(ncodes * NSUM, 0.0);
+    for (int ci = 0; ci < ncodes; ci++) R.sums(f.data(), ci, &sums[ci * NSUM]);
+    words.assign(w.begin(), w.end());
+    if (maxd) {
+      uint64_t mb;
+      if ((e2 = R.read(&mb, WS_MAXBITS + 8, 8))) return e2;
+      memcpy(maxd, &mb, 8);
+    }
+    return APAX_OK;
+  };
+  auto fits_at = [&](int rule, uint32_t mask, int code, bool sub, unsigned& fits,
+                     unsigned hist[8]) -> int {
+    ProfArgs A = R.args(P_FITS, rule, mask, sub);
+    A.codes[0] = code;
+    int e2 = R.run(A, false);
+    if (e2) return e2;
+    if ((e2 = R.read(&fits, WS_FITS, 4))) return e2;
+    return R.read(hist, WS_HIST, 32);
+  };
+
+  // 2. operating point
+  int code = 0;
+  const int rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
+  if (g.nblocks && h.mode == APAX_FIXED_QUALITY) {
+    const double rt = p->target_corr;
+    std::vector<double> S;
+    std::vector<uint64_t> Wd;
+    auto r_at = [&](int c, double& r) -> int {
+      int e2 = stats_at(R_QUALITY, g.mask, &c, 1, false, S, Wd, nullptr);
+      if (e2) return e2;
+      double omr;
+      r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
+      out->n_probes++;
+      if (fabs(r - rt) < 1e-11) out->flags |= APAX_NEAR_TIE;
+      return APAX_OK;
+    };
+    if (CF >= CC) {
+      code = CC;
+    } else {
+      double r;
+      if ((e = r_at(CC, r))) return e;
+      if (!(r >= rt)) {
+        code = CC;
+      } else {
+        int lo = CF, hi = CC;
+        while (hi - lo > 1) {
+          int mid = lo + ((hi - lo) >> 1);
+          if ((e = r_at(mid, r))) return e;
+          if (r >= rt) hi = mid;
+          else lo = mid;
+        }
+        code = hi;
+      }
+    }
+  } else if (g.nblocks && h.mode == APAX_FIXED_RATE) {
+    unsigned need = (unsigned)((9 * (uint64_t)R.sub_n + 9) / 10), fits, hist[8];
+    if (CF >= CC) {
+      code = CC;
+    } else {
+      out->n_probes++;
+      if ((e = fits_at(R_RATE, g.mask & 0x7Fu, CC, true, fits, hist))) return e;
+      if (fits >= need) {
+        code = CC;
+      } else {
+        int lo = CF, hi = CC;
+        while (hi - lo > 1) {
+          int mid = lo + ((hi - lo) >> 1);
+          out->n_probes++;
+          if ((e = fits_at(R_RATE, g.mask & 0x7Fu, mid, true, fits, hist))) return e;
+          if (fits >= need) lo = mid;
+          else hi = mid;
+        }
+        code = lo;
+      }
+    }
+  } else if (h.mode == APAX_FIXED_RATE || h.mode == APAX_FIXED_QUALITY) {
+    code = CC;
+  }
+  out->code = code;
+
+  // 3. stream mask from the subsample histogram at the chosen code
+  uint32_t mask = 0x81u;
+  if (g.nblocks) {
+    unsigned fits, hist[8];
+    uint32_t m = h.mode == APAX_FIXED_RATE ? (g.mask & 0x7Fu) : g.mask;
+    if ((e = fits_at(rule, m, code, true, fits, hist))) return e;
+    uint64_t thresh = ((uint64_t)R.sub_n + 99) / 100;
+    if (thresh < 1) thresh = 1;
+    for (int t = 0; t < 8; t++)
+      if (hist[t] >= thresh) mask |= 1u << t;
+  }
+  mask &= (g.mask | 0x81u);
+  out->stream_mask = mask;
+
+  // 4. rate-correlation curve on the subsample
+  {
+    int codes[MAXCODES];
+    for (int t = 0; t < APAX_NCURVE; t++) {
+      int ct = code + 4 * (t - APAX_NCURVE / 2);
+      codes[t] = ct < g.cmin ? g.cmin : (ct > g.cmax ? g.cmax : ct);
+    }
+    double in_bits = 0.0;
+    for (int64_t jj = 0; jj < R.sub_n; jj++) in_bits += (double)block_valid(h, jj * R.sub_stride);
+    in_bits *= 8.0 * h.esz;
+    std::vector<double> S;
+    std::vector<uint64_t> Wd;
+    if (g.nblocks) {
+      if ((e = stats_at(R_QUALITY, mask | 0x81u, codes, APAX_NCURVE, true, S, Wd, nullptr))) return e;
+    }
+    for (int t = 0; t < APAX_NCURVE; t++) {
+      out->curve[t].code = codes[t];
+      double r = 1.0, omr = 0.0;
+      double ob = 0.0;
+      if (g.nblocks) {
+        r_of(S[t * NSUM + S_XX], S[t * NSUM + S_YY], S[t * NSUM + S_DD], S[t * NSUM + S_DS], r, omr);
+        ob = 32.0 * (double)Wd[t];
+      }
+      out->curve[t].ratio = ob > 0 ? in_bits / ob : 0.0;
+      out->curve[t].r = r;
+    }
+  }
+
+  // 5. metrics at the operating point, full array
+  {
+    apax_metrics& m = out->m;
+    uint32_t mm = h.mode == APAX_FIXED_RATE ? ((mask & 0x7Fu) | 1u) : (mask | 0x81u);
+    std::vector<double> S(NSUM, 0.0);
+    std::vector<uint64_t> Wd(1, 0);
+    double maxd = 0.0;
+    if (g.nblocks) {
+      if ((e = stats_at(rule, mm, &code, 1, false, S, Wd, &maxd))) return e;
+    }
+    m.n = h.nsamples;
+    m.sum_x = S[S_X];
+    m.sum_y = S[S_Y];
+    m.sum_d = S[S_D];
+    m.sxx = S[S_XX];
+    m.syy = S[S_YY];
+    m.sdd = S[S_DD];
+    m.sds = S[S_DS];
+    m.max_abs_d = maxd;
+    r_of(m.sxx, m.syy, m.sdd, m.sds, m.r, m.one_minus_r);
+    if (m.sdd == 0.0) { m.snr_db = INFINITY; m.rms_pct = 0.0; m.rms_db = -INFINITY; }
+    else if (m.sxx == 0.0) { m.snr_db = -INFINITY; m.rms_pct = INFINITY; m.rms_db = INFINITY; }
+    else {
+      m.snr_db = 10.0 * log10(m.sxx / m.sdd);
+      m.rms_pct = 100.0 * sqrt(m.sdd / m.sxx);
+      m.rms_db = -m.snr_db;
+    }
+    double nn = (double)(m.n ? m.n : 1);
+    m.mean_x = m.sum_x / nn;
+    m.mean_y = m.sum_y / nn;
+    m.mean_d = m.sum_d / nn;
+    m.enc_bytes = area_offset(h) + 4 * (h.mode == APAX_FIXED_RATE
+                                            ? (uint64_t)g.budget * (uint64_t)g.nblocks
+                                            : Wd[0]);
+    m.ratio = m.enc_bytes ? (double)(h.nsamples * (uint64_t)h.esz) / (double)m.enc_bytes : 0.0;
+    if (g.nblocks) {
+      ProfArgs A = R.args(P_CENTER, rule, mm, false);
+      A.codes[0] = code;
+      A.mean_x = m.mean_x;
+      A.mean_y = m.mean_y;
+      A.mean_d = m.mean_d;
+      if ((e = R.run(A, true))) return e;
+      double f[NSUM];
+      if ((e = R.read(f, WS_FINAL, 8 * NSUM))) return e;
+      double c[NSUM];
+      R.sums(f, 0, c);
+      m.std_x = sqrt(c[S_CXX] / nn);
+      m.std_y = sqrt(c[S_CYY] / nn);
+      m.std_d = sqrt(c[S_CDD] / nn);
+    }
+  }
+  return APAX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// codec.h -- device building blocks of the APAX codec for gfx950 (wave64).
+//
+// One 64-lane wavefront works on 64/LPB blocks at once ("segments" of LPB
+// lanes); lane gi of a segment owns group gi (4 consecutive samples along x,
+// Sec. 6 "groups of N = 4") of its block, so a block of B <= 256 samples is
+// held in registers as one value per group and lane.  Cross-lane data moves
+// with ds_bpermute shuffles inside a segment, per-block decisions are made on
+// 64-bit ballot masks with scalar bit arithmetic (JEE token counts), and
+// block sizes / bit offsets come from segmented wave reductions and scans.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace apax {
+
+enum { DT_I8 = 1, DT_I16 = 2, DT_I32 = 3, DT_F32 = 4, DT_F64 = 5 };
+enum { M_LOSSLESS = 0, M_RATE = 1, M_QUALITY = 2 };
+enum : uint32_t { ST_NONFINITE = 1u, ST_CORRUPT = 2u, ST_INTERNAL = 4u };
+
+template <typename T> struct Traits;
+template <> struct Traits<int8_t> { static constexpr int W = 8, H = 32; static constexpr bool isint = true; };
+template <> struct Traits<int16_t> { static constexpr int W = 16, H = 32; static constexpr bool isint = true; };
+template <> struct Traits<int32_t> { static constexpr int W = 32, H = 32; static constexpr bool isint = true; };
+template <> struct Traits<float> { static constexpr int W = 32, H = 48; static constexpr bool isint = false; };
+template <> struct Traits<double> { static constexpr int W = 32, H = 48; static constexpr bool isint = false; };
+
+// Geometry of one array, passed by value to every kernel.
+struct Geo {
+  int64_t n[3];     // extent z, y, x (leading 1s below 3-d)
+  int64_t nbx, nby; // bricks along x, y
+  int64_t nblocks;
+  int32_t b[3];     // brick z, y, x
+  int32_t B, G;     // samples / groups per block
+  int32_t rowq;     // groups per brick row = b[2] / 4
+  int32_t plane;    // groups per brick plane = b[1] * rowq
+  int32_t mode;
+  uint32_t mask;    // effective stream mask
+  int32_t budget;   // fixed-rate words per block (0 otherwise)
+  int32_t code;     // gain code (fixed-rate start / fixed-quality)
+  int32_t cmin, cmax;
+  int32_t maxw;     // words of the largest variable-size block (verbatim)
+  int32_t ldsw;     // LDS words of one block buffer: worst BFPE encoding + 2
+};
+
+// ------------------------------------------------------------ gain grid
+// Attenuator values (Sec. 6): g(c) = (16 + f) 2^(k-4), c = 16k + f.  An
+// arithmetic shift is floor division by 16 for negative codes as well.
+__device__ __forceinline__ double gain_of(int c) {
+  return ldexp((double)(16 + (c & 15)), (c >> 4) - 4);
+}
+
+// Largest code in [cmin, cmax] with fl64(M * g(c)) <= lim (M * g(cmin) <=
+// lim holds for every finite M).  An estimate from the exponent of lim / M is
+// corrected by exact tests of the predicate (monotone in c).
+__device__ __forceinline__ int largest_code(double M, double lim, int cmin, int cmax) {
+  if (M == 0.0) return cmax;
+  double q = lim / M;
+  int c;
+  if (!(q < 1.0e300)) {
+    c = cmax;
+  } else {
+    int e;
+    double m = frexp(q, &e);           // q = m 2^e, m in [0.5, 1)
+    int f = (int)((2.0 * m - 1.0) * 16.0);
+    c = 16 * (e - 1) + f;
+  }
+  c = c > cmax ? cmax : (c < cmin ? cmin : c);
+  while (c < cmax && M * gain_of(c + 1) <= lim) c++;
+  while (c > cmin && !(M * gain_of(c) <= lim)) c--;
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ void bracket(double M, int cmin, int cmax, int& cf, int& cc) {
+  cc = Traits<T>::isint ? 0 : largest_code(M, 2147483647.0, cmin, cmax);
+  cf = largest_code(M, 0.5, cmin, cmax);
+}
+
+__device__ __forceinline__ int clampc(int c, int lo, int hi) { return c < lo ? lo : (c > hi ? hi : c); }
+
+// Quantizer: a = rint(fl64(x) * g), round half to even, binary64.
+__device__ __forceinline__ int32_t quant(double x, double g) {
+  return (int32_t)__builtin_rint(x * g);
+}
+
+// Dequantizer: y = ldexp(fl64(a * R[f]), -k), R[f] = 16 / (16 + f).
+__device__ __forceinline__ double dequant(int32_t a, int c) {
+  double R = 16.0 / (double)(16 + (c & 15));
+  return ldexp((double)a * R, -(c >> 4));
+}
+
+template <typename T>
+__device__ __forceinline__ T to_out(double y) {
+  if constexpr (!Traits<T>::isint) {
+    return (T)y;  // binary64 -> binary32 cast rounds to nearest even
+  } else {
+    double r = __builtin_rint(y);
+    constexpr double lo = Traits<T>::W == 8 ? -128.0 : (Traits<T>::W == 16 ? -32768.0 : -2147483648.0);
+    constexpr double hi = Traits<T>::W == 8 ? 127.0 : (Traits<T>::W == 16 ? 32767.0 : 2147483647.0);
+    r = r < lo ? lo : (r > hi ? hi : r);
+    return (T)(int32_t)r;
+  }
+}
+
+// ------------------------------------------------------------ W-bit wrap
+template <int W>
+__device__ __forceinline__ int32_t wrapw(uint32_t v) {
+  if constexpr (W == 32) return (int32_t)v;
+  else return ((int32_t)(v << (32 - W))) >> (32 - W);
+}
+
+// Exponent of a group (minimal two's-complement width, Sec. 6 BFPE): the
+// highest bit where some sample differs from its next-higher bit.  eps
+// saturates at 31; width(31) is 32 bits when W = 32.
+template <int W>
+__device__ __forceinline__ void group_eps(const int32_t v[4], int& eps, int& pw) {
+  uint32_t t = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) t |= (uint32_t)v[k] ^ ((uint32_t)v[k] << 1);
+  int w = t ? 32 - __clz((int)t) : 0;
+  eps = w > 31 ? 31 : w;
+  pw = (W == 32 && w >= 31) ? 32 : w;
+}
+
+// ------------------------------------------------------------ wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <int LPB>
+__device__ __forceinline__ uint64_t seg_bits(int seg) {
+  if constexpr (LPB == 64) return ~0ull;
+  else return ((1ull << LPB) - 1ull) << (LPB * seg);
+}
+
+// value from lane (gi - d) of the same segment (caller masks gi < d)
+template <int LPB>
+__device__ __forceinline__ int32_t up(int32_t v, int d) { return __shfl_up(v, (unsigned)d, LPB); }
+template <int LPB>
+__device__ __forceinline__ int32_t dn(int32_t v, int d) { return __shfl_down(v, (unsigned)d, LPB); }
+
+template <int LPB>
+__device__ __forceinline__ int32_t seg_sum(int32_t v) {
+#pragma unroll
+  for (int o = 1; o < LPB; o <<= 1) v += __shfl_xor(v, o, LPB);
+  return v;
+}
+template <int LPB>
+__device__ __forceinline__ uint32_t seg_max_u(uint32_t v) {
+#pragma unroll
+  for (int o = 1; o < LPB; o <<= 1) {
+    uint32_t t = (uint32_t)__shfl_xor((int)v, o, LPB);
+    v = t > v ? t : v;
+  }
+  return v;
+}
+template <int LPB>
+__device__ __forceinline__ int32_t seg_excl_scan(int32_t v, int gi) {
+  int32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < LPB; o <<= 1) {
+    int32_t t = __shfl_up(inc, (unsigned)o, LPB);
+    if (gi >= o) inc += t;
+  }
+  return inc - v;
+}
+
+// number of set bits of m below this lane, inside this lane's segment
+template <int LPB>
+__device__ __forceinline__ int below_in_seg(uint64_t m, int seg) {
+  int all = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+  if constexpr (LPB == 64) return all;
+  else return all - __popcll(m & ((1ull << (LPB * seg)) - 1ull));
+}
+
+// JEE (Sec. 6), greedy parse as bit arithmetic.  m: positions whose exponent
+// difference is in [-1, 1] (bit 0 of every segment clear, so runs never
+// cross segments).  Inside a maximal run starting at p the greedy parse emits
+// tokens at p, p+2, ... (pairs, plus a single at the end of an odd run).
+// Adding the run-start bit of every run that starts on an even position
+// clears exactly those runs; what survives are the odd-start runs.
+__device__ __forceinline__ uint64_t jee_token_starts(uint64_t m) {
+  const uint64_t E = 0x5555555555555555ull;
+  uint64_t st = m & ~(m << 1);
+  uint64_t rodd = (m + (st & E)) & m;
+  uint64_t reven = m & ~rodd;
+  return (reven & E) | (rodd & ~E);
+}
+
+}  // namespace apax

@@ -1,0 +1,258 @@
+// encode.hip -- APAX encoder kernel (Sec. 6) for gfx950.
+//
+// One workgroup = 4 wavefronts = one tile of 4 * (64/LPB) blocks.  Per block:
+// coalesced loads of its groups, block max -> code bracket, gain choice
+// (lossless: 0; fixed quality: clamp(c*); fixed rate: cap-and-descend
+// search), every candidate stream costed in registers, the cheapest emitted
+// into a zeroed LDS buffer with ds_or (header | JEE tokens | BFPE payload),
+// then copied out with coalesced word stores.  Fixed rate places block j at
+// j * budget words; variable-size modes place blocks with a single-pass
+// decoupled look-back over per-tile word counts (tiles taken in ticket
+// order, so every tile waited on is already resident).
+#include "block.h"
+#include "kernels.h"
+
+namespace apax {
+
+__device__ __forceinline__ void or_bits(uint32_t* buf, int bitpos, uint32_t val, int len) {
+  if (len <= 0) return;
+  int w = bitpos >> 5, sh = bitpos & 31;
+  uint32_t lo = val << sh;
+  if (lo) atomicOr(&buf[w], lo);
+  if (sh && sh + len > 32) {
+    uint32_t hi = val >> (32 - sh);
+    if (hi) atomicOr(&buf[w + 1], hi);
+  }
+}
+
+__device__ __forceinline__ uint32_t low_bits(int32_t v, int n) {
+  return n >= 32 ? (uint32_t)v : ((uint32_t)v & ((1u << n) - 1u));
+}
+
+__global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64_t* tile_state,
+                               int64_t ntiles) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *ticket = 0;
+  for (; i < ntiles; i += (int64_t)gridDim.x * blockDim.x) tile_state[i] = 0;
+  (void)status_unused;
+}
+
+template <typename T, int LPB, int NDIM>
+__global__ __launch_bounds__(256) void k_encode(EncArgs A) {
+  constexpr int BPW = 64 / LPB;
+  constexpr int H = Traits<T>::H;
+  constexpr int W = Traits<T>::W;
+  using B_ = Blk<T, LPB, NDIM>;
+  const Geo& g = A.g;
+  extern __shared__ uint32_t lds[];
+  __shared__ int64_t s_tile;
+  __shared__ uint32_t s_nw[WPG * 4];
+  __shared__ uint64_t s_off[WPG * 4];
+
+  const int wave = threadIdx.x >> 6;
+  const bool variable = g.mode != M_RATE;
+  if (threadIdx.x == 0) s_tile = variable ? (int64_t)atomicAdd(A.ticket, 1u) : (int64_t)blockIdx.x;
+  __syncthreads();
+  const int64_t tile = s_tile;
+
+  B_ b;
+  const int lane = lane_id();
+  b.init(g, (tile * WPG + wave) * BPW + lane / LPB);
+  b.load((const T*)A.x, g);
+  if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
+
+  int c = 0, st = 0;
+  int32_t a[4], v[7][4], sz[8];
+  int eps[7], pw[7];
+  if (g.mode == M_QUALITY) c = clampc(g.code, b.cf, b.cc);
+  else if (g.mode == M_RATE) c = b.rate_search(g, g.mask, g.code, st);
+  b.quantize(c, g.mode == M_LOSSLESS, a);
+  b.sizes(g, g.mask, a, v, eps, pw, sz);
+  int32_t best;
+  if (g.mode != M_RATE) st = B_::argmin(sz, g.mask, best);
+  else best = B_::sel8(sz, st);
+  const int nw = !b.blk_ok ? 0 : (g.mode == M_RATE ? g.budget : ((best + 31) >> 5));
+
+  // ---- emit into this segment's LDS buffer
+  const int seg = b.L.seg, gi = b.L.gi;
+  const int stride = g.ldsw;
+  uint32_t* buf = lds + (wave * BPW + seg) * stride;
+  for (int w = gi; w < stride; w += LPB) buf[w] = 0u;
+  __syncthreads();
+
+  const bool verb = st == 7;
+  int32_t vv[4];
+  int e = 0, p = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) vv[k] = v[0][k];
+  e = eps[0];
+  p = pw[0];
+#pragma unroll
+  for (int t = 1; t < 7; t++) {
+    if (st == t) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) vv[k] = v[t][k];
+      e = eps[t];
+      p = pw[t];
+    }
+  }
+  if (verb) { e = 0; p = 0; }
+
+  const int em1 = up<LPB>(e, 1);
+  const int d = e - em1;
+  const bool pos = b.act && gi >= 1 && !verb;
+  const uint64_t m1 = __ballot(pos && (uint32_t)(d + 1) <= 2u);
+  const uint64_t m2 = __ballot(pos && (uint32_t)(d + 2) <= 4u);
+  const uint64_t vp = __ballot(pos);
+  const uint64_t Tm = jee_token_starts(m1);
+  const uint64_t starts = Tm | (~m1 & vp);
+  const uint64_t ab = ~m2 & vp;
+  const int dnext = dn<LPB>(d, 1);
+  const uint64_t sb = seg_bits<LPB>(seg);
+  const int ntot = __popcll(starts & sb) + __popcll(ab & sb);
+  const int pay0 = H + 4 * ntot;
+  const int pex = seg_excl_scan<LPB>(4 * p, gi);
+  if (b.act) {
+    if ((starts >> lane) & 1) {
+      int nib_off = below_in_seg<LPB>(starts, seg) + below_in_seg<LPB>(ab, seg);
+      bool pair = ((Tm >> lane) & 1) && lane < 63 && ((m1 >> (lane + 1)) & 1);
+      bool isabs = (ab >> lane) & 1;
+      uint32_t tok;
+      int len = 4;
+      if (pair) tok = (uint32_t)(3 * (d + 1) + (dnext + 1));
+      else if (isabs) { tok = (uint32_t)(14 + (e >> 4)) | ((uint32_t)(e & 15) << 4); len = 8; }
+      else tok = (uint32_t)(11 + d);
+      or_bits(buf, H + 4 * nib_off, tok, len);
+    }
+    if (!verb) {
+      int o = pay0 + pex;
+#pragma unroll
+      for (int k = 0; k < 4; k++) or_bits(buf, o + k * p, low_bits(vv[k], p), p);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; k++) or_bits(buf, H + (4 * gi + k) * W, low_bits(a[k], W), W);
+    }
+    if (gi == 0) {
+      uint32_t cm = H == 32 ? 0x3FFu : 0xFFFFu;
+      uint32_t hdr = (uint32_t)st | ((uint32_t)e << 3) | (((uint32_t)c & cm) << 8);
+      or_bits(buf, 0, hdr, 32);
+    }
+  }
+  if (gi == 0) s_nw[wave * BPW + seg] = (uint32_t)nw;
+  __syncthreads();
+
+  // ---- placement
+  if (threadIdx.x == 0) {
+    uint64_t agg = 0;
+    for (int i = 0; i < WPG * BPW; i++) {
+      s_off[i] = agg;
+      agg += s_nw[i];
+    }
+    uint64_t base = 0;
+    if (variable) {
+      const uint64_t FLAG_A = 1ull << 62, FLAG_P = 2ull << 62, VAL = (1ull << 62) - 1;
+      if (tile == 0) {
+        __hip_atomic_store(&A.tile_state[0], FLAG_P | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(&A.tile_state[tile], FLAG_A | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t pidx = tile - 1;
+        uint32_t spins = 0;
+        for (;;) {
+          uint64_t s = __hip_atomic_load(&A.tile_state[pidx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          uint64_t flag = s >> 62;
+          if (flag == 0) {
+            if (++spins > (1u << 26)) {  // safety valve: never hang the GPU
+              atomicOr(A.status, ST_INTERNAL);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          base += s & VAL;
+          if (flag == 2) break;
+          --pidx;
+        }
+        __hip_atomic_store(&A.tile_state[tile], FLAG_P | (base + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (tile == A.ntiles - 1) {
+        uint64_t total = base + agg;
+        *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
+        *A.d_nbytes = A.area + 4 * total;
+      }
+    } else {
+      base = (uint64_t)tile * (WPG * BPW) * (uint64_t)g.budget;
+    }
+    if (tile == 0) {
+      uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
+      for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
+      for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
+      for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
+      if (!variable) {
+        h[14] = A.hdr[14];
+        h[15] = A.hdr[15];
+        *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
+      }
+    }
+    for (int i = 0; i < WPG * BPW; i++) s_off[i] += base;
+  }
+  __syncthreads();
+
+  if (b.blk_ok) {
+    const uint64_t off = s_off[wave * BPW + seg];
+    uint32_t* dst = A.out_words + off;
+    for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
+    if (variable && gi == 0) {
+      A.lens[b.j] = (uint16_t)nw;
+      if ((b.j & 63) == 0) A.sbo[b.j >> 6] = off;
+    }
+  }
+}
+
+// ------------------------------------------------------------ launcher
+template <typename T, int LPB, int NDIM>
+static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
+  constexpr int BPW = 64 / LPB;
+  size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
+  hipLaunchKernelGGL((k_encode<T, LPB, NDIM>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
+  return hipGetLastError();
+}
+
+template <typename T, int NDIM>
+static hipError_t launch_lpb(const EncArgs& A, hipStream_t s) {
+  if (A.g.G <= 16) return launch_t<T, 16, NDIM>(A, s);
+  if (A.g.G <= 32) return launch_t<T, 32, NDIM>(A, s);
+  return launch_t<T, 64, NDIM>(A, s);
+}
+
+template <typename T>
+static hipError_t launch_nd(const EncArgs& A, int ndim, hipStream_t s) {
+  if (ndim == 1) return launch_lpb<T, 1>(A, s);
+  if (ndim == 2) return launch_lpb<T, 2>(A, s);
+  return launch_lpb<T, 3>(A, s);
+}
+
+int64_t encode_tiles(const Geo& g) {
+  int lpb = g.G <= 16 ? 16 : (g.G <= 32 ? 32 : 64);
+  int64_t per = (int64_t)WPG * (64 / lpb);
+  return (g.nblocks + per - 1) / per;
+}
+
+hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s) {
+  A.ntiles = encode_tiles(A.g);
+  if (A.ntiles == 0) return hipSuccess;
+  if (A.g.mode != M_RATE) {
+    int64_t nb = (A.ntiles + 255) / 256;
+    unsigned grid = (unsigned)(nb > 1024 ? 1024 : (nb < 1 ? 1 : nb));
+    hipLaunchKernelGGL(k_encode_reset, dim3(grid), dim3(256), 0, s, A.ticket, A.status,
+                       A.tile_state, A.ntiles);
+  }
+  switch (dtype) {
+    case DT_I8: return launch_nd<int8_t>(A, ndim, s);
+    case DT_I16: return launch_nd<int16_t>(A, ndim, s);
+    case DT_I32: return launch_nd<int32_t>(A, ndim, s);
+    case DT_F32: return launch_nd<float>(A, ndim, s);
+    default: return launch_nd<double>(A, ndim, s);
+  }
+}
+
+}  // namespace apax

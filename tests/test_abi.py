@@ -1,0 +1,86 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the public
+header declares, and its host-side logic (validation, bounds, stream-header
+parsing) agrees with the oracle.  No GPU call is made here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1303_4994_amd import apax
+    return apax
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "apax.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(apax_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(A):
+    names = declared_functions()
+    assert {"apax_profile", "apax_encode", "apax_decode"} <= set(names)
+    lib = C.CDLL(A.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+VALIDATION = [
+    (np.int16, (1000,), {"mode": "lossless", "brick": (64,)}),
+    (np.int16, (1000,), {"mode": "lossless", "brick": (60,)}),
+    (np.int16, (1000,), {"mode": "lossless", "brick": (66,)}),
+    (np.float32, (1000,), {"mode": "lossless", "brick": (64,)}),
+    (np.float32, (64, 64), {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}),
+    (np.float32, (64, 64), {"mode": "fixed_rate", "brick": (16, 16), "rate": 100.0}),
+    (np.float32, (64, 64), {"mode": "fixed_rate", "brick": (16, 16), "rate": 0.0}),
+    (np.float64, (8, 8, 8), {"mode": "fixed_quality", "brick": (4, 4, 8), "code": 16384}),
+    (np.float64, (8, 8, 8), {"mode": "fixed_quality", "brick": (4, 4, 8), "code": 16383}),
+    (np.int32, (8, 8, 8), {"mode": "fixed_quality", "brick": (4, 4, 8), "code": 1}),
+    (np.int32, (8, 8, 8), {"mode": "fixed_quality", "brick": (4, 4, 8), "code": -512}),
+    (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x10}),
+    (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x28}),
+    (np.int8, (8, 64), {"mode": "lossless", "brick": (32, 2)}),
+]
+
+
+@pytest.mark.parametrize("dt,shape,params", VALIDATION)
+def test_validation_and_bound_match_oracle(A, dt, shape, params):
+    import torch
+    tdt = {np.int8: torch.int8, np.int16: torch.int16, np.int32: torch.int32,
+           np.float32: torch.float32, np.float64: torch.float64}[dt]
+    try:
+        ob = O.encode_bound(dt, shape, params)
+        oe = 0
+    except O.OracleError as e:
+        oe = e.code
+    try:
+        gb = A.apax_encode_bound(tdt, shape, params)
+        ge = 0
+    except A.ApaxError as e:
+        ge = e.code
+    assert ge == oe
+    if oe == 0:
+        assert gb == ob
+
+
+def test_stream_info_parses_oracle_streams(A):
+    x = np.arange(3000, dtype=np.int16).reshape(30, 100) // 3
+    for params in ({"mode": "lossless", "brick": (4, 16)},
+                   {"mode": "fixed_rate", "brick": (4, 16), "rate": 3.0, "code": -20}):
+        s = O.encode(x, params)
+        info = A.apax_stream_info(bytes(s[:64]))
+        assert info["shape"] == x.shape and info["brick"] == params["brick"]
+        assert info["mode"] == params["mode"]
+        assert A.stream_nbytes(bytes(s[:64])) == len(s)
+    bad = bytearray(s[:64])
+    bad[0] ^= 1
+    with pytest.raises(A.ApaxError):
+        A.apax_stream_info(bytes(bad))
