@@ -14,7 +14,10 @@ SOURCES = ["capi.hip", "encode.hip", "decode.hip", "profile.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function"]
+         "-munsafe-fp-atomics", "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function",
+         # keep DPP lane moves as separate v_mov_b32_dpp: folding a wave_shr
+         # move into a subtract-reverse gave negated results on gfx950
+         "-mllvm", "-amdgpu-dpp-combine=false"]
 
 
 def _compile(src):

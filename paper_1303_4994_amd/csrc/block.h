@@ -4,7 +4,9 @@
 // block j.  For a given gain code it quantizes its 4 samples, forms every
 // candidate derivative stream (Sec. 5 / Sec. 6 redundancy remover), the group
 // exponent of each stream, and the block size of each stream: header + JEE
-// tokens (bit arithmetic on ballots) + BFPE payload (segmented wave sum).
+// tokens (bit arithmetic on ballots, scalar unit) + BFPE payload (DPP
+// segmented scans, two streams packed per 32-bit lane value).  x-neighbours
+// move with DPP wave shifts; y/z-neighbours through a per-wave LDS exchange.
 #pragma once
 #include "codec.h"
 
@@ -99,6 +101,11 @@ __device__ __forceinline__ void load4(const T* __restrict__ x, int64_t idx, int 
   }
 }
 
+// Costs of the candidate streams of one evaluation (segment-uniform values).
+struct Costs {
+  int32_t sz[8];   // bits per stream (0x7FFFFFFF if not allowed)
+};
+
 // Per-lane state of a block held by a wave segment.
 template <typename T, int LPB, int NDIM>
 struct Blk {
@@ -106,6 +113,7 @@ struct Blk {
   static constexpr int H = Traits<T>::H;
   static constexpr bool ISINT = Traits<T>::isint;
   static constexpr uint32_t NDMASK = NDIM == 1 ? 0x07u : (NDIM == 2 ? 0x2Fu : 0x7Fu);
+  static constexpr int BIG = 0x7FFFFFFF;
 
   LaneMap<LPB> L;
   int64_t j;
@@ -117,13 +125,15 @@ struct Blk {
   int cf, cc;    // code bracket (segment-uniform)
   bool nonfinite;
   uint64_t vpos; // ballot: lanes with a JEE position (1 <= gi < G)
+  uint4* xch;    // per-wave LDS exchange (64 entries), used for NDIM >= 2
 
-  __device__ __forceinline__ void init(const Geo& g, int64_t j_) {
+  __device__ __forceinline__ void init(const Geo& g, int64_t j_, uint4* xch_) {
     L = lane_map<LPB>(g);
     j = j_;
     blk_ok = j < g.nblocks;
     act = blk_ok && L.gi < g.G;
     vpos = __ballot(act && L.gi >= 1);
+    xch = xch_;
   }
 
   __device__ __forceinline__ int64_t load(const T* __restrict__ x, const Geo& g) {
@@ -132,22 +142,44 @@ struct Blk {
     nvalid = 0;
     if (act) idx = group_index<NDIM, LPB>(g, L, j, nvalid);
     load4<T>(x, idx, nvalid, v);
-    double m = 0.0;
     bool nf = false;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       xd[k] = (double)v[k];
       if constexpr (!ISINT) nf |= !__builtin_isfinite(xd[k]);
-      double ax = __builtin_fabs(xd[k]);
-      m = ax > m ? ax : m;  // NaN never wins
     }
-#pragma unroll
-    for (int o = 1; o < LPB; o <<= 1) {
-      double t = __shfl_xor(m, o, LPB);
-      m = t > m ? t : m;
-    }
-    M = m;
     nonfinite = nf;
+    // block max |x|: reduce the magnitude bit patterns (monotone in value)
+    if constexpr (sizeof(T) <= 4) {
+      uint32_t key = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        uint32_t kk;
+        if constexpr (ISINT) {
+          int32_t iv = (int32_t)v[k];
+          kk = iv < 0 ? (uint32_t)(-(int64_t)iv) : (uint32_t)iv;
+        } else {
+          kk = __builtin_bit_cast(uint32_t, (float)v[k]) & 0x7FFFFFFFu;
+          if (kk > 0x7F800000u) kk = 0;  // NaN never wins
+        }
+        key = kk > key ? kk : key;
+      }
+      key = seg_last<LPB>(seg_scan_max<LPB>(key), L.seg);
+      if constexpr (ISINT) M = (double)key;
+      else M = (double)__builtin_bit_cast(float, key);
+    } else {
+      uint64_t key = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        uint64_t kk = __builtin_bit_cast(uint64_t, xd[k]) & 0x7FFFFFFFFFFFFFFFull;
+        if (kk > 0x7FF0000000000000ull) kk = 0;
+        key = kk > key ? kk : key;
+      }
+      uint32_t hi = seg_last<LPB>(seg_scan_max<LPB>((uint32_t)(key >> 32)), L.seg);
+      uint32_t lo = (uint32_t)(key >> 32) == hi ? (uint32_t)key : 0u;
+      lo = seg_last<LPB>(seg_scan_max<LPB>(lo), L.seg);
+      M = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    }
     bracket<T>(M, g.cmin, g.cmax, cf, cc);
     return idx;
   }
@@ -164,10 +196,10 @@ struct Blk {
     }
   }
 
-  // candidate streams 0..6 (only those of NDIM are formed)
+  // candidate streams 0..6 (only those of NDIM are formed), mod 2^W, 0 past the edge
   __device__ __forceinline__ void streams(const Geo& g, const int32_t a[4], int32_t v[7][4]) const {
     uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
-    uint32_t p3 = (uint32_t)up<LPB>(a[3], 1), p2 = (uint32_t)up<LPB>(a[2], 1);
+    uint32_t p3 = shr1(A[3]), p2 = shr1(A[2]);
     if (!L.hx) { p3 = 0; p2 = 0; }
     uint32_t d[4] = {A[0] - p3, A[1] - A[0], A[2] - A[1], A[3] - A[2]};
     uint32_t dp = p3 - p2;
@@ -181,13 +213,17 @@ struct Blk {
 #pragma unroll
     for (int k = 0; k < 4; k++) { s[3][k] = 0; s[4][k] = 0; s[5][k] = 0; s[6][k] = 0; }
     if constexpr (NDIM >= 2) {
+      const int lane = L.lane;
+      xch[lane] = make_uint4(A[0], A[1], A[2], A[3]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint4 q = xch[L.hy ? lane - g.rowq : lane];
+      uint32_t Q[4] = {q.x, q.y, q.z, q.w};
       uint32_t f[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        uint32_t q = (uint32_t)up<LPB>(a[k], g.rowq);
-        f[k] = A[k] - (L.hy ? q : 0u);
-      }
-      uint32_t fp = (uint32_t)up<LPB>((int32_t)f[3], 1);
+      for (int k = 0; k < 4; k++) f[k] = A[k] - (L.hy ? Q[k] : 0u);
+      uint32_t fp = shr1(f[3]);
       if (!L.hx) fp = 0;
 #pragma unroll
       for (int k = 0; k < 4; k++) s[3][k] = f[k];
@@ -195,27 +231,28 @@ struct Blk {
       s[5][1] = f[1] - f[0];
       s[5][2] = f[2] - f[1];
       s[5][3] = f[3] - f[2];
-    }
-    if constexpr (NDIM == 3) {
-      uint32_t h[4], u[4];
+      if constexpr (NDIM == 3) {
+        uint4 r = xch[L.hz ? lane - g.plane : lane];
+        uint4 rq = xch[(L.hz && L.hy) ? lane - g.plane - g.rowq : lane];
+        uint32_t Rr[4] = {r.x, r.y, r.z, r.w}, RQ[4] = {rq.x, rq.y, rq.z, rq.w};
+        uint32_t h[4], u[4];
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        uint32_t r = (uint32_t)up<LPB>(a[k], g.plane);
-        h[k] = A[k] - (L.hz ? r : 0u);
+        for (int k = 0; k < 4; k++) {
+          h[k] = A[k] - (L.hz ? Rr[k] : 0u);
+          // dz dy a = a - a(y-1) - a(z-1) + a(y-1, z-1)
+          u[k] = h[k] - (L.hy ? Q[k] : 0u) + ((L.hz && L.hy) ? RQ[k] : 0u);
+        }
+        uint32_t upv = shr1(u[3]);
+        if (!L.hx) upv = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) s[4][k] = h[k];
+        s[6][0] = u[0] - upv;
+        s[6][1] = u[1] - u[0];
+        s[6][2] = u[2] - u[1];
+        s[6][3] = u[3] - u[2];
       }
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        uint32_t q = (uint32_t)up<LPB>((int32_t)h[k], g.rowq);
-        u[k] = h[k] - (L.hy ? q : 0u);
-      }
-      uint32_t upv = (uint32_t)up<LPB>((int32_t)u[3], 1);
-      if (!L.hx) upv = 0;
-#pragma unroll
-      for (int k = 0; k < 4; k++) s[4][k] = h[k];
-      s[6][0] = u[0] - upv;
-      s[6][1] = u[1] - u[0];
-      s[6][2] = u[2] - u[1];
-      s[6][3] = u[3] - u[2];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
     for (int t = 0; t < 7; t++)
@@ -223,9 +260,9 @@ struct Blk {
       for (int k = 0; k < 4; k++) v[t][k] = valid(k) ? wrapw<W>(s[t][k]) : 0;
   }
 
-  // JEE token nibbles of one stream for this lane's block (segment-uniform)
-  __device__ __forceinline__ int token_nibbles(int eps, int G) const {
-    int em1 = up<LPB>(eps, 1);
+  // JEE token nibbles of one stream for each segment's block (value of this lane's segment)
+  __device__ __forceinline__ int token_nibbles(int eps) const {
+    int em1 = (int)shr1((uint32_t)eps);
     int d = eps - em1;
     bool pos = act && L.gi >= 1;
     uint64_t m1 = __ballot(pos && (uint32_t)(d + 1) <= 2u);
@@ -233,93 +270,126 @@ struct Blk {
     uint64_t Tm = jee_token_starts(m1);
     uint64_t starts = Tm | (~m1 & vpos);
     uint64_t ab = ~m2 & vpos;
-    uint64_t sb = seg_bits<LPB>(L.seg);
-    return __popcll(starts & sb) + __popcll(ab & sb);
+    return seg_popc<LPB>(starts, L.seg) + seg_popc<LPB>(ab, L.seg);
   }
 
-  // sizes (bits) of every allowed stream at the current quantization; keeps
-  // the stream values, exponents and payload widths
+  // sizes (bits) of every allowed stream; also the stream values, exponents
+  // and payload widths (zero for lanes without a group)
   __device__ __forceinline__ void sizes(const Geo& g, uint32_t mask, const int32_t a[4],
-                                        int32_t v[7][4], int eps[7], int pw[7], int32_t sz[8]) const {
+                                        int32_t v[7][4], int eps[7], int pw[7], Costs& C) const {
     streams(g, a, v);
 #pragma unroll
     for (int t = 0; t < 7; t++) {
-      sz[t] = 0x7FFFFFFF;
       eps[t] = 0;
       pw[t] = 0;
-      if (!((NDMASK >> t) & 1)) continue;
-      group_eps<W>(v[t], eps[t], pw[t]);
-      if (!act) { eps[t] = 0; pw[t] = 0; }
-      if (!((mask >> t) & 1)) continue;  // mask is wave-uniform
-      int nib = token_nibbles(eps[t], g.G);
-      int pay = seg_sum<LPB>(4 * pw[t]);
-      sz[t] = H + 4 * nib + pay;
+      if ((NDMASK >> t) & 1) {
+        group_eps<W>(v[t], eps[t], pw[t]);
+        if (!act) { eps[t] = 0; pw[t] = 0; }
+      }
     }
-    sz[7] = ((mask >> 7) & 1) ? H + g.B * W : 0x7FFFFFFF;
+    // payload: two streams per 32-bit scan (each segment total <= 64 * 32)
+    uint32_t pay[8];
+#pragma unroll
+    for (int t = 0; t < 7; t += 2) {
+      uint32_t pk = (uint32_t)pw[t] | (t + 1 < 7 ? ((uint32_t)pw[t + 1] << 16) : 0u);
+      bool need = (((NDMASK & mask) >> t) & 1) || (t + 1 < 7 && (((NDMASK & mask) >> (t + 1)) & 1));
+      uint32_t tot = 0;
+      if (need) tot = seg_last<LPB>(seg_scan_add<LPB>(pk), L.seg);
+      pay[t] = tot & 0xFFFFu;
+      pay[t + 1] = tot >> 16;
+    }
+#pragma unroll
+    for (int t = 0; t < 7; t++) {
+      C.sz[t] = BIG;
+      if (!(((NDMASK & mask) >> t) & 1)) continue;  // mask is wave-uniform
+      C.sz[t] = H + 4 * token_nibbles(eps[t]) + 4 * (int)pay[t];
+    }
+    C.sz[7] = ((mask >> 7) & 1) ? H + g.B * W : BIG;
+  }
+
+  // size of one stream st (segment-uniform) at the given values
+  __device__ __forceinline__ int size_of(int st, const int32_t v[7][4]) const {
+    int32_t vv[4];
+    select_stream(st, v, vv);
+    int e, p;
+    group_eps<W>(vv, e, p);
+    if (!act) { e = 0; p = 0; }
+    uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)p), L.seg);
+    return H + 4 * token_nibbles(e) + 4 * (int)tot;
+  }
+
+  __device__ __forceinline__ static void select_stream(int st, const int32_t v[7][4], int32_t vv[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      uint32_t r = 0;
+#pragma unroll
+      for (int t = 0; t < 7; t++)
+        if ((NDMASK >> t) & 1) r |= pick(st == t, (uint32_t)v[t][k]);
+      vv[k] = (int32_t)r;
+    }
+  }
+
+  __device__ __forceinline__ static int pick_int(int st, const int x[7]) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int t = 0; t < 7; t++)
+      if ((NDMASK >> t) & 1) r |= pick(st == t, (uint32_t)x[t]);
+    return (int)r;
   }
 
   // lowest-id stream of minimal size among mask
-  __device__ __forceinline__ static int argmin(const int32_t sz[8], uint32_t mask, int32_t& best) {
+  __device__ __forceinline__ static int argmin(const Costs& C, uint32_t mask, int32_t& best) {
     int bs = 0;
-    best = 0x7FFFFFFF;
+    best = BIG;
 #pragma unroll
     for (int t = 0; t < 8; t++)
-      if (((mask >> t) & 1) && sz[t] < best) { best = sz[t]; bs = t; }
+      if (((mask >> t) & 1) && C.sz[t] < best) { best = C.sz[t]; bs = t; }
     return bs;
   }
 
+  __device__ __forceinline__ static int32_t size_sel(const Costs& C, int st) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int t = 0; t < 8; t++) r |= pick(st == t, (uint32_t)C.sz[t]);
+    return (int32_t)r;
+  }
+
   // Fixed-rate per-block gain search (cap and descend; reading of the
-  // adaptive loop, Sec. 6).  Returns the code; st receives the stream chosen
-  // at the start code, kept for the whole search.
-  __device__ int rate_search(const Geo& g, uint32_t mask, int cp, int& st) const {
-    int32_t a[4], v[7][4], sz[8];
-    int eps[7], pw[7];
+  // adaptive loop, Sec. 6), from an evaluation at the start code c0 that
+  // chose stream st.  Returns the final code (c0 when the block fits there).
+  // Probes need only the chosen stream's size.
+  __device__ int rate_search(const Geo& g, int c0, int st, bool need) const {
+    int32_t a[4], v[7][4];
     const int32_t budget_bits = 32 * g.budget;
-    uint32_t m7 = mask & 0x7Fu;
-    int c = clampc(cp, cf, cc);
-    quantize(c, false, a);
-    sizes(g, m7, a, v, eps, pw, sz);
-    int32_t best;
-    st = argmin(sz, m7, best);
-    bool need = act && best > budget_bits;
-    if (!__ballot(need)) return c;
-    int hi = c, lo = c;
-    // descend by octaves (never below c_floor, where everything is 0)
+    int c = c0, hi = c0, lo = c0;
     bool done = !need;
     int guard = 0;
     while (__ballot(!done)) {
       if (++guard > 4096) break;  // unreachable: c_floor always fits a valid budget
       int ct = done ? c : (c - 16 < cf ? cf : c - 16);
       quantize(ct, false, a);
-      sizes(g, m7, a, v, eps, pw, sz);
-      int32_t s_of = sel8(sz, st);
+      streams(g, a, v);
+      int s_of = size_of(st, v);
       if (!done) {
         if (s_of <= budget_bits) { done = true; lo = ct; }
         else { hi = ct; }
         c = ct;
       }
     }
-    if (!need) { lo = c; hi = c; }
+    if (!need) { lo = c0; hi = c0; }
     // bisection between the last fitting (lo) and last failing (hi) code
     while (__ballot(hi - lo > 1)) {
       bool on = hi - lo > 1;
       int mid = lo + ((hi - lo) >> 1);
       quantize(on ? mid : lo, false, a);
-      sizes(g, m7, a, v, eps, pw, sz);
-      int32_t s_of = sel8(sz, st);
+      streams(g, a, v);
+      int s_of = size_of(st, v);
       if (on) {
         if (s_of <= budget_bits) lo = mid;
         else hi = mid;
       }
     }
     return lo;
-  }
-
-  __device__ __forceinline__ static int32_t sel8(const int32_t sz[8], int s) {
-    int32_t r = sz[0];
-#pragma unroll
-    for (int t = 1; t < 8; t++) r = s == t ? sz[t] : r;
-    return r;
   }
 };
 

@@ -98,7 +98,7 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
     g.code = p->code;
   }
   g.maxw = (h.H + g.B * h.W + 31) / 32;
-  g.ldsw = (h.H + 8 * (g.G - 1) + g.B * h.W + 31) / 32 + 2;
+  g.ldsw = ((h.H + 8 * (g.G - 1) + g.B * h.W + 31) / 32 + 2 + 3) / 4 * 4;
   g.budget = 0;
   if (h.mode == APAX_FIXED_RATE) {
     double words;
@@ -161,20 +161,19 @@ constexpr uint64_t WS_STATUS = 0, WS_TICKET = 4, WS_MAXBITS = 16, WS_FITS = 64, 
 uint64_t tiles_enc(const HG& h) { return (uint64_t)encode_tiles(h.g); }
 
 uint64_t partial_floats(const HG& h) {
-  int64_t sub = h.g.nblocks >= 1024 ? (h.g.nblocks + 15) / 16 : h.g.nblocks;
-  uint64_t a = (uint64_t)prof_tiles(h.g, h.g.nblocks);
-  uint64_t b = (uint64_t)MAXCODES * (uint64_t)prof_tiles(h.g, sub);
-  return std::max(a, b) * NSUM * 2;
+  uint64_t w = (uint64_t)prof_wgs(prof_tiles(h.g, h.g.nblocks));
+  return (uint64_t)MAXCODES * std::max<uint64_t>(w, 1) * NSUM * 2;
 }
 
-uint64_t ws_need(const HG& h) {
-  return WS_CTRL + ((8 * tiles_enc(h) + 255) / 256) * 256 + 4 * partial_floats(h);
-}
+uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
+uint64_t ws_tile_off() { return WS_CTRL; }
+uint64_t ws_cj_off(const HG& h) { return WS_CTRL + al256(8 * tiles_enc(h)); }
+uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
+uint64_t ws_need(const HG& h) { return ws_part_off(h) + 4 * partial_floats(h); }
 
-uint64_t* tile_state_ptr(void* ws) { return (uint64_t*)((uint8_t*)ws + WS_CTRL); }
-float* partials_ptr(void* ws, const HG& h) {
-  return (float*)((uint8_t*)ws + WS_CTRL + ((8 * tiles_enc(h) + 255) / 256) * 256);
-}
+uint64_t* tile_state_ptr(void* ws) { return (uint64_t*)((uint8_t*)ws + ws_tile_off()); }
+float* partials_ptr(void* ws, const HG& h) { return (float*)((uint8_t*)ws + ws_part_off(h)); }
+int32_t* cj_ptr(void* ws, const HG& h) { return (int32_t*)((uint8_t*)ws + ws_cj_off(h)); }
 
 int hip_err(hipError_t e) { return e == hipSuccess ? APAX_OK : APAX_E_HIP; }
 
@@ -222,13 +221,9 @@ struct ProfRun {
   hipStream_t s;
   int escale;
   int64_t sub_stride, sub_n;
+  alignas(16) uint8_t hc[WS_CTRL];  // host copy of the control block after a run
 
   uint8_t* ctrl() const { return (uint8_t*)ws; }
-
-  int clear_ctrl() {
-    hipLaunchKernelGGL(k_clear, dim3(2), dim3(256), 0, s, (uint32_t*)ws, (int)(WS_FINAL / 4));
-    return hip_err(hipGetLastError());
-  }
 
   ProfArgs args(int op, int rule, uint32_t mask, bool sub) const {
     ProfArgs A;
@@ -241,6 +236,7 @@ struct ProfRun {
     A.jstride = sub ? sub_stride : 1;
     A.nbe = sub ? sub_n : h.g.nblocks;
     A.partials = partials_ptr(ws, h);
+    A.cj = cj_ptr(ws, h);
     A.words = (unsigned long long*)(ctrl() + WS_WORDS);
     A.fits = (unsigned int*)(ctrl() + WS_FITS);
     A.hist = (unsigned int*)(ctrl() + WS_HIST);
@@ -248,39 +244,54 @@ struct ProfRun {
     A.status = (uint32_t*)(ctrl() + WS_STATUS);
     A.escale = escale;
     A.ncodes = 1;
+    A.hist_code = -1;
     return A;
   }
 
+  // clear the counters, launch, reduce, copy the control block back (one sync)
   int run(ProfArgs& A, bool finalize) {
-    int e = clear_ctrl();
-    if (e) return e;
-    e = hip_err(launch_profile(h.dtype, h.ndim, A, s));
+    hipLaunchKernelGGL(k_clear, dim3(2), dim3(256), 0, s, (uint32_t*)ws, (int)(WS_FINAL / 4));
+    if (hipGetLastError() != hipSuccess) return APAX_E_HIP;
+    int e = hip_err(launch_profile(h.dtype, h.ndim, A, s));
     if (e) return e;
     if (finalize) {
-      e = hip_err(launch_finalize(A.partials, A.ntiles, A.ncodes, (double*)(ctrl() + WS_FINAL), s));
+      e = hip_err(launch_finalize(A.partials, A.nwg, A.ncodes, (double*)(ctrl() + WS_FINAL), s));
       if (e) return e;
     }
-    return APAX_OK;
-  }
-
-  int read(void* dst, uint64_t off, size_t n) {
-    if (hipMemcpyAsync(dst, ctrl() + off, n, hipMemcpyDeviceToHost, s) != hipSuccess) return APAX_E_HIP;
+    if (hipMemcpyAsync(hc, ctrl(), WS_CTRL, hipMemcpyDeviceToHost, s) != hipSuccess) return APAX_E_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return APAX_E_HIP;
-    uint32_t st = 0;
-    if (hipMemcpy(&st, ctrl() + WS_STATUS, 4, hipMemcpyDeviceToHost) != hipSuccess) return APAX_E_HIP;
+    uint32_t st;
+    memcpy(&st, hc + WS_STATUS, 4);
     if (st & ST_NONFINITE) return APAX_E_NONFINITE;
     if (st & ST_INTERNAL) return APAX_E_INTERNAL;
     return APAX_OK;
   }
 
-  // sums of one code (already finalised), unscaled
-  void sums(const double* f, int ci, double out[NSUM]) const {
+  unsigned fits(int ci) const { unsigned v; memcpy(&v, hc + WS_FITS + 4 * ci, 4); return v; }
+  unsigned hist(int t) const { unsigned v; memcpy(&v, hc + WS_HIST + 4 * t, 4); return v; }
+  uint64_t words(int ci) const { uint64_t v; memcpy(&v, hc + WS_WORDS + 8 * ci, 8); return v; }
+  double maxbits(int i) const { double v; memcpy(&v, hc + WS_MAXBITS + 8 * i, 8); return v; }
+
+  // sums of one code, unscaled
+  void sums(int ci, double out[NSUM]) const {
     for (int i = 0; i < NSUM; i++) {
+      double f;
+      memcpy(&f, hc + WS_FINAL + 8 * (ci * NSUM + i), 8);
       bool sq = i >= S_XX;
-      out[i] = ldexp(f[ci * NSUM + i], sq ? 2 * escale : escale);
+      out[i] = ldexp(f, sq ? 2 * escale : escale);
     }
   }
 };
+
+// Codes the bisection (mid = lo + ((hi - lo) >> 1)) may probe in its next
+// `depth` steps from (lo, hi): the nodes of its decision tree.
+void bisect_tree(int lo, int hi, int depth, std::vector<int>& out) {
+  if (depth == 0 || hi - lo <= 1) return;
+  int mid = lo + ((hi - lo) >> 1);
+  out.push_back(mid);
+  bisect_tree(lo, mid, depth - 1, out);
+  bisect_tree(mid, hi, depth - 1, out);
+}
 
 }  // namespace
 
@@ -470,113 +481,100 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   memset(out, 0, sizeof(*out));
   out->size = sizeof(*out);
   const Geo& g = h.g;
-  ProfRun R{h, d_x, d_ws, stream, 0, 1, 0};
+  ProfRun R{h, d_x, d_ws, stream, 0, 1, 0, {}};
   R.sub_stride = g.nblocks >= 1024 ? 16 : 1;
   R.sub_n = (g.nblocks + R.sub_stride - 1) / R.sub_stride;
   out->n_sub = (uint32_t)R.sub_n;
+  const int rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
 
-  // 1. max |x| over the array
+  // 1. max |x| over the array -> whole-array bracket, statistics scale
   double Mall = 0.0;
   if (g.nblocks) {
     ProfArgs A = R.args(P_MAX, R_LOSSLESS, g.mask, false);
     if ((e = R.run(A, false))) return e;
-    uint64_t mb = 0;
-    if ((e = R.read(&mb, WS_MAXBITS, 8))) return e;
-    memcpy(&Mall, &mb, 8);
+    Mall = R.maxbits(0);
   }
-  int CF = host_largest(Mall, 0.5, g.cmin, g.cmax);
-  int CC = h.isint ? 0 : host_largest(Mall, 2147483647.0, g.cmin, g.cmax);
+  const int CF = host_largest(Mall, 0.5, g.cmin, g.cmax);
+  const int CC = h.isint ? 0 : host_largest(Mall, 2147483647.0, g.cmin, g.cmax);
   out->c_floor = CF;
   out->c_cap = CC;
   int ex = 0;
   if (Mall > 0) frexp(Mall, &ex);
   R.escale = ex;
 
-  auto stats_at = [&](int rule, uint32_t mask, const int* codes, int ncodes, bool sub,
-                      std::vector<double>& sums, std::vector<uint64_t>& words, double* maxd) -> int {
-    ProfArgs A = R.args(P_STATS, rule, mask, sub);
-    A.ncodes = ncodes;
-    for (int i = 0; i < ncodes; i++) A.codes[i] = codes[i];
-    int e2 = R.run(A, true);
-    if (e2) return e2;
-    std::vector<double> f(ncodes * NSUM);
-    std::vector<unsigned long long> w(ncodes);
-    if ((e2 = R.read(w.data(), WS_WORDS, 8 * ncodes))) return e2;
-    if ((e2 = R.read(f.data(), WS_FINAL, 8 * NSUM * ncodes))) return e2;
-    sums.assign(ncodes * NSUM, 0.0);
-    for (int ci = 0; ci < ncodes; ci++) R.sums(f.data(), ci, &sums[ci * NSUM]);
-    words.assign(w.begin(), w.end());
-    if (maxd) {
-      uint64_t mb;
-      if ((e2 = R.read(&mb, WS_MAXBITS + 8, 8))) return e2;
-      memcpy(maxd, &mb, 8);
-    }
-    return APAX_OK;
-  };
-  auto fits_at = [&](int rule, uint32_t mask, int code, bool sub, unsigned& fits,
-                     unsigned hist[8]) -> int {
-    ProfArgs A = R.args(P_FITS, rule, mask, sub);
-    A.codes[0] = code;
-    int e2 = R.run(A, false);
-    if (e2) return e2;
-    if ((e2 = R.read(&fits, WS_FITS, 4))) return e2;
-    return R.read(hist, WS_HIST, 32);
-  };
-
-  // 2. operating point
+  // 2. operating point: bisection; each launch evaluates the whole decision
+  //    tree of the next steps (one code per grid row), the host walks it
   int code = 0;
-  const int rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
-  if (g.nblocks && h.mode == APAX_FIXED_QUALITY) {
+  if (g.nblocks && CF < CC && (h.mode == APAX_FIXED_RATE || h.mode == APAX_FIXED_QUALITY)) {
+    const bool fr = h.mode == APAX_FIXED_RATE;
     const double rt = p->target_corr;
-    std::vector<double> S;
-    std::vector<uint64_t> Wd;
-    auto r_at = [&](int c, double& r) -> int {
-      int e2 = stats_at(R_QUALITY, g.mask, &c, 1, false, S, Wd, nullptr);
+    const unsigned need = (unsigned)((9 * (uint64_t)R.sub_n + 9) / 10);
+    // fixed quality re-reads the full array per code: shallower trees when
+    // the array does not stay in the 256 MB last-level cache
+    const uint64_t in_bytes = h.nsamples * (uint64_t)h.esz;
+    const int depth = fr ? 4 : (in_bytes <= (96ull << 20) ? 4 : 2);
+    std::vector<char> near;
+    auto probe = [&](const std::vector<int>& codes, std::vector<char>& pred) -> int {
+      ProfArgs A = fr ? R.args(P_FITS, R_RATE, g.mask & 0x7Fu, true)
+                      : R.args(P_STATS, R_QUALITY, g.mask, false);
+      A.ncodes = (int)codes.size();
+      for (size_t i = 0; i < codes.size(); i++) A.codes[i] = codes[i];
+      int e2 = R.run(A, !fr);
       if (e2) return e2;
-      double omr;
-      r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
-      out->n_probes++;
-      if (fabs(r - rt) < 1e-11) out->flags |= APAX_NEAR_TIE;
+      pred.assign(codes.size(), 0);
+      near.assign(codes.size(), 0);
+      for (size_t i = 0; i < codes.size(); i++) {
+        if (fr) {
+          pred[i] = R.fits((int)i) >= need;
+        } else {
+          double S[NSUM], r, omr;
+          R.sums((int)i, S);
+          r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
+          near[i] = fabs(r - rt) < 1e-11;
+          pred[i] = r >= rt;
+        }
+      }
       return APAX_OK;
     };
-    if (CF >= CC) {
-      code = CC;
+    int lo = CF, hi = CC;
+    std::vector<int> codes{CC};
+    bisect_tree(lo, hi, depth, codes);
+    std::vector<char> pred;
+    if ((e = probe(codes, pred))) return e;
+    out->n_probes++;
+    if (near[0]) out->flags |= APAX_NEAR_TIE;
+    bool top = pred[0];
+    if (fr ? top : !top) {
+      code = CC;  // fixed rate: everything fits at the cap; fixed quality: target unreachable
     } else {
-      double r;
-      if ((e = r_at(CC, r))) return e;
-      if (!(r >= rt)) {
-        code = CC;
-      } else {
-        int lo = CF, hi = CC;
+      for (;;) {
+        // walk the evaluated tree
+        size_t k = 1;
+        bool walked = false;
         while (hi - lo > 1) {
           int mid = lo + ((hi - lo) >> 1);
-          if ((e = r_at(mid, r))) return e;
-          if (r >= rt) hi = mid;
-          else lo = mid;
-        }
-        code = hi;
-      }
-    }
-  } else if (g.nblocks && h.mode == APAX_FIXED_RATE) {
-    unsigned need = (unsigned)((9 * (uint64_t)R.sub_n + 9) / 10), fits, hist[8];
-    if (CF >= CC) {
-      code = CC;
-    } else {
-      out->n_probes++;
-      if ((e = fits_at(R_RATE, g.mask & 0x7Fu, CC, true, fits, hist))) return e;
-      if (fits >= need) {
-        code = CC;
-      } else {
-        int lo = CF, hi = CC;
-        while (hi - lo > 1) {
-          int mid = lo + ((hi - lo) >> 1);
+          while (k < codes.size() && codes[k] != mid) k++;
+          if (k >= codes.size()) break;
+          walked = true;
           out->n_probes++;
-          if ((e = fits_at(R_RATE, g.mask & 0x7Fu, mid, true, fits, hist))) return e;
-          if (fits >= need) lo = mid;
-          else hi = mid;
+          if (near[k]) out->flags |= APAX_NEAR_TIE;
+          bool pm = pred[k];
+          // fixed rate keeps the largest fitting code, fixed quality the
+          // smallest code reaching the target
+          if (fr) { if (pm) lo = mid; else hi = mid; }
+          else { if (pm) hi = mid; else lo = mid; }
         }
-        code = lo;
+        if (hi - lo <= 1) break;
+        (void)walked;
+        codes.clear();
+        bisect_tree(lo, hi, depth, codes);
+        if ((e = probe(codes, pred))) return e;
+        // probe() filled pred for codes starting at index 0
+        codes.insert(codes.begin(), INT32_MIN);
+        pred.insert(pred.begin(), 0);
+        near.insert(near.begin(), 0);
       }
+      code = fr ? lo : hi;
     }
   } else if (h.mode == APAX_FIXED_RATE || h.mode == APAX_FIXED_QUALITY) {
     code = CC;
@@ -586,18 +584,20 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   // 3. stream mask from the subsample histogram at the chosen code
   uint32_t mask = 0x81u;
   if (g.nblocks) {
-    unsigned fits, hist[8];
     uint32_t m = h.mode == APAX_FIXED_RATE ? (g.mask & 0x7Fu) : g.mask;
-    if ((e = fits_at(rule, m, code, true, fits, hist))) return e;
+    ProfArgs A = R.args(P_FITS, rule, m, true);
+    A.codes[0] = code;
+    A.hist_code = 0;
+    if ((e = R.run(A, false))) return e;
     uint64_t thresh = ((uint64_t)R.sub_n + 99) / 100;
     if (thresh < 1) thresh = 1;
     for (int t = 0; t < 8; t++)
-      if (hist[t] >= thresh) mask |= 1u << t;
+      if (R.hist(t) >= thresh) mask |= 1u << t;
   }
   mask &= (g.mask | 0x81u);
   out->stream_mask = mask;
 
-  // 4. rate-correlation curve on the subsample
+  // 4. rate-correlation curve on the subsample (17 codes in one launch)
   {
     int codes[MAXCODES];
     for (int t = 0; t < APAX_NCURVE; t++) {
@@ -607,33 +607,42 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     double in_bits = 0.0;
     for (int64_t jj = 0; jj < R.sub_n; jj++) in_bits += (double)block_valid(h, jj * R.sub_stride);
     in_bits *= 8.0 * h.esz;
-    std::vector<double> S;
-    std::vector<uint64_t> Wd;
     if (g.nblocks) {
-      if ((e = stats_at(R_QUALITY, mask | 0x81u, codes, APAX_NCURVE, true, S, Wd, nullptr))) return e;
+      ProfArgs A = R.args(P_STATS, R_QUALITY, mask | 0x81u, true);
+      A.ncodes = APAX_NCURVE;
+      for (int t = 0; t < APAX_NCURVE; t++) A.codes[t] = codes[t];
+      if ((e = R.run(A, true))) return e;
     }
     for (int t = 0; t < APAX_NCURVE; t++) {
       out->curve[t].code = codes[t];
-      double r = 1.0, omr = 0.0;
-      double ob = 0.0;
+      double r = 1.0, omr = 0.0, ob = 0.0;
       if (g.nblocks) {
-        r_of(S[t * NSUM + S_XX], S[t * NSUM + S_YY], S[t * NSUM + S_DD], S[t * NSUM + S_DS], r, omr);
-        ob = 32.0 * (double)Wd[t];
+        double S[NSUM];
+        R.sums(t, S);
+        r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
+        ob = 32.0 * (double)R.words(t);
       }
       out->curve[t].ratio = ob > 0 ? in_bits / ob : 0.0;
       out->curve[t].r = r;
     }
   }
 
-  // 5. metrics at the operating point, full array
+  // 5. metrics at the operating point, full array (two passes: sums, then
+  //    centred sums for the population standard deviations)
   {
     apax_metrics& m = out->m;
     uint32_t mm = h.mode == APAX_FIXED_RATE ? ((mask & 0x7Fu) | 1u) : (mask | 0x81u);
-    std::vector<double> S(NSUM, 0.0);
-    std::vector<uint64_t> Wd(1, 0);
+    double S[NSUM] = {0};
+    uint64_t W0 = 0;
     double maxd = 0.0;
     if (g.nblocks) {
-      if ((e = stats_at(rule, mm, &code, 1, false, S, Wd, &maxd))) return e;
+      ProfArgs A = R.args(P_STATS, rule, mm, false);
+      A.codes[0] = code;
+      A.store_cj = 1;
+      if ((e = R.run(A, true))) return e;
+      R.sums(0, S);
+      W0 = R.words(0);
+      maxd = R.maxbits(1);
     }
     m.n = h.nsamples;
     m.sum_x = S[S_X];
@@ -658,7 +667,7 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     m.mean_d = m.sum_d / nn;
     m.enc_bytes = area_offset(h) + 4 * (h.mode == APAX_FIXED_RATE
                                             ? (uint64_t)g.budget * (uint64_t)g.nblocks
-                                            : Wd[0]);
+                                            : W0);
     m.ratio = m.enc_bytes ? (double)(h.nsamples * (uint64_t)h.esz) / (double)m.enc_bytes : 0.0;
     if (g.nblocks) {
       ProfArgs A = R.args(P_CENTER, rule, mm, false);
@@ -667,10 +676,8 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
       A.mean_y = m.mean_y;
       A.mean_d = m.mean_d;
       if ((e = R.run(A, true))) return e;
-      double f[NSUM];
-      if ((e = R.read(f, WS_FINAL, 8 * NSUM))) return e;
       double c[NSUM];
-      R.sums(f, 0, c);
+      R.sums(0, c);
       m.std_x = sqrt(c[S_CXX] / nn);
       m.std_y = sqrt(c[S_CYY] / nn);
       m.std_d = sqrt(c[S_CDD] / nn);

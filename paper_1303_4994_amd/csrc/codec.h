@@ -70,10 +70,23 @@ __device__ __forceinline__ int largest_code(double M, double lim, int cmin, int 
   return c;
 }
 
+// c_floor = largest code with fl64(M g) <= 1/2; c_cap = largest code with
+// fl64(M g) <= 2^31 - 1 (ints: 0).  Scaling by 2^32 (512 codes) is exact, so
+// c_cap is c_floor + 512 or, when the product lands in (2^31 - 1, 2^31],
+// one code less.
 template <typename T>
 __device__ __forceinline__ void bracket(double M, int cmin, int cmax, int& cf, int& cc) {
-  cc = Traits<T>::isint ? 0 : largest_code(M, 2147483647.0, cmin, cmax);
   cf = largest_code(M, 0.5, cmin, cmax);
+  if constexpr (Traits<T>::isint) {
+    cc = 0;
+  } else {
+    if (cf + 512 >= cmax) {
+      cc = (cf + 511 >= cmax || M * gain_of(cmax) <= 2147483647.0) ? cmax : cmax - 1;
+      if (!(M * gain_of(cc) <= 2147483647.0)) cc = largest_code(M, 2147483647.0, cmin, cmax);
+    } else {
+      cc = M * gain_of(cf + 512) <= 2147483647.0 ? cf + 512 : cf + 511;
+    }
+  }
 }
 
 __device__ __forceinline__ int clampc(int c, int lo, int hi) { return c < lo ? lo : (c > hi ? hi : c); }
@@ -124,6 +137,80 @@ __device__ __forceinline__ void group_eps(const int32_t v[4], int& eps, int& pw)
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// DPP lane moves (wave64, GFX9 controls): lane l receives lane l-1 / l+1
+// (0 at the wave edge).  Segment edges are masked by the callers.
+__device__ __forceinline__ uint32_t shr1(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t shl1(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, true);
+}
+template <int K>
+__device__ __forceinline__ uint32_t row_shr(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + K, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t bcast15(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+}
+__device__ __forceinline__ uint32_t bcast31(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+}
+
+// inclusive scan (sum mod 2^32) inside segments of LPB lanes
+template <int LPB>
+__device__ __forceinline__ uint32_t seg_scan_add(uint32_t v) {
+  v += row_shr<1>(v);
+  v += row_shr<2>(v);
+  v += row_shr<4>(v);
+  v += row_shr<8>(v);
+  if constexpr (LPB >= 32) v += bcast15(v);
+  if constexpr (LPB == 64) v += bcast31(v);
+  return v;
+}
+template <int LPB>
+__device__ __forceinline__ uint32_t seg_scan_max(uint32_t v) {
+  v = max(v, row_shr<1>(v));
+  v = max(v, row_shr<2>(v));
+  v = max(v, row_shr<4>(v));
+  v = max(v, row_shr<8>(v));
+  if constexpr (LPB >= 32) v = max(v, bcast15(v));
+  if constexpr (LPB == 64) v = max(v, bcast31(v));
+  return v;
+}
+// value of the last lane of this lane's segment (after an inclusive scan)
+template <int LPB>
+__device__ __forceinline__ uint32_t seg_last(uint32_t v, int seg) {
+  if constexpr (LPB == 64) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+  } else if constexpr (LPB == 32) {
+    uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return seg ? b : a;
+  } else {
+    uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+    uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+    uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+    uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    return seg == 0 ? a : (seg == 1 ? b : (seg == 2 ? c : d));
+  }
+}
+// per-segment popcount of a wave mask, as a value of this lane's segment
+template <int LPB>
+__device__ __forceinline__ int seg_popc(uint64_t m, int seg) {
+  if constexpr (LPB == 64) {
+    return __popcll(m);
+  } else if constexpr (LPB == 32) {
+    int a = __popc((uint32_t)m), b = __popc((uint32_t)(m >> 32));
+    return seg ? b : a;
+  } else {
+    int a = __popc((uint32_t)m & 0xFFFFu), b = __popc((uint32_t)(m >> 16) & 0xFFFFu);
+    int c = __popc((uint32_t)(m >> 32) & 0xFFFFu), d = __popc((uint32_t)(m >> 48));
+    return seg == 0 ? a : (seg == 1 ? b : (seg == 2 ? c : d));
+  }
+}
+// x when sel, else 0, without a select over memory
+__device__ __forceinline__ uint32_t pick(bool sel, uint32_t x) { return x & (0u - (uint32_t)sel); }
 
 template <int LPB>
 __device__ __forceinline__ uint64_t seg_bits(int seg) {

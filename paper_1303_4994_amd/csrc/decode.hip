@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs A) {
   constexpr int W = Traits<T>::W;
   constexpr int MAXEPS = W == 32 ? 31 : W;
   const Geo& g = A.g;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int32_t s_info[WPG * 64];
   __shared__ int32_t s_end[WPG * 4];
 

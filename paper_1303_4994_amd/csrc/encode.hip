@@ -44,10 +44,11 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs A) {
   constexpr int W = Traits<T>::W;
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ int64_t s_tile;
   __shared__ uint32_t s_nw[WPG * 4];
   __shared__ uint64_t s_off[WPG * 4];
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
 
   const int wave = threadIdx.x >> 6;
   const bool variable = g.mode != M_RATE;
@@ -57,48 +58,50 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs A) {
 
   B_ b;
   const int lane = lane_id();
-  b.init(g, (tile * WPG + wave) * BPW + lane / LPB);
+  b.init(g, (tile * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
   b.load((const T*)A.x, g);
   if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
 
+  // ---- operating point and stream
   int c = 0, st = 0;
-  int32_t a[4], v[7][4], sz[8];
+  int32_t a[4], v[7][4];
   int eps[7], pw[7];
-  if (g.mode == M_QUALITY) c = clampc(g.code, b.cf, b.cc);
-  else if (g.mode == M_RATE) c = b.rate_search(g, g.mask, g.code, st);
-  b.quantize(c, g.mode == M_LOSSLESS, a);
-  b.sizes(g, g.mask, a, v, eps, pw, sz);
+  Costs C;
   int32_t best;
-  if (g.mode != M_RATE) st = B_::argmin(sz, g.mask, best);
-  else best = B_::sel8(sz, st);
+  if (g.mode == M_QUALITY) c = clampc(g.code, b.cf, b.cc);
+  else if (g.mode == M_RATE) c = clampc(g.code, b.cf, b.cc);
+  const uint32_t emask = g.mode == M_RATE ? (g.mask & 0x7Fu) : g.mask;
+  b.quantize(c, g.mode == M_LOSSLESS, a);
+  b.sizes(g, emask, a, v, eps, pw, C);
+  st = B_::argmin(C, emask, best);
+  if (g.mode == M_RATE) {
+    const bool need = b.act && best > 32 * g.budget;
+    if (__ballot(need)) {
+      // some block of this wave does not fit at its start code: search, then
+      // re-evaluate every block of the wave at its final code
+      c = b.rate_search(g, c, st, need);
+      b.quantize(c, false, a);
+      b.sizes(g, emask, a, v, eps, pw, C);
+      best = B_::size_sel(C, st);
+    }
+  }
   const int nw = !b.blk_ok ? 0 : (g.mode == M_RATE ? g.budget : ((best + 31) >> 5));
 
   // ---- emit into this segment's LDS buffer
   const int seg = b.L.seg, gi = b.L.gi;
   const int stride = g.ldsw;
   uint32_t* buf = lds + (wave * BPW + seg) * stride;
-  for (int w = gi; w < stride; w += LPB) buf[w] = 0u;
+  for (int w = 4 * gi; w < stride; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
   const bool verb = st == 7;
   int32_t vv[4];
-  int e = 0, p = 0;
-#pragma unroll
-  for (int k = 0; k < 4; k++) vv[k] = v[0][k];
-  e = eps[0];
-  p = pw[0];
-#pragma unroll
-  for (int t = 1; t < 7; t++) {
-    if (st == t) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) vv[k] = v[t][k];
-      e = eps[t];
-      p = pw[t];
-    }
-  }
+  B_::select_stream(st, v, vv);
+  int e = B_::pick_int(st, eps);
+  int p = B_::pick_int(st, pw);
   if (verb) { e = 0; p = 0; }
 
-  const int em1 = up<LPB>(e, 1);
+  const int em1 = (int)shr1((uint32_t)e);
   const int d = e - em1;
   const bool pos = b.act && gi >= 1 && !verb;
   const uint64_t m1 = __ballot(pos && (uint32_t)(d + 1) <= 2u);
@@ -107,11 +110,10 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs A) {
   const uint64_t Tm = jee_token_starts(m1);
   const uint64_t starts = Tm | (~m1 & vp);
   const uint64_t ab = ~m2 & vp;
-  const int dnext = dn<LPB>(d, 1);
-  const uint64_t sb = seg_bits<LPB>(seg);
-  const int ntot = __popcll(starts & sb) + __popcll(ab & sb);
+  const int dnext = (int)shl1((uint32_t)d);
+  const int ntot = seg_popc<LPB>(starts, seg) + seg_popc<LPB>(ab, seg);
   const int pay0 = H + 4 * ntot;
-  const int pex = seg_excl_scan<LPB>(4 * p, gi);
+  const int pex = (int)seg_scan_add<LPB>((uint32_t)(4 * p)) - 4 * p;
   if (b.act) {
     if ((starts >> lane) & 1) {
       int nib_off = below_in_seg<LPB>(starts, seg) + below_in_seg<LPB>(ab, seg);
@@ -125,9 +127,28 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs A) {
       or_bits(buf, H + 4 * nib_off, tok, len);
     }
     if (!verb) {
-      int o = pay0 + pex;
+      // the group's 4 fields are contiguous: pack them into 128 bits, then
+      // OR the (up to 5) words they touch
+      if (p > 0) {
+        uint64_t m = p >= 32 ? 0xFFFFFFFFull : ((1ull << p) - 1ull);
+        uint64_t lo = ((uint64_t)(uint32_t)vv[0] & m) | (((uint64_t)(uint32_t)vv[1] & m) << p);
+        uint64_t hi = ((uint64_t)(uint32_t)vv[2] & m) | (((uint64_t)(uint32_t)vv[3] & m) << p);
+        int s2 = 2 * p;  // 2..64
+        uint64_t f0 = s2 >= 64 ? lo : (lo | (hi << s2));
+        uint64_t f1 = s2 >= 64 ? hi : (hi >> (64 - s2));
+        int o = pay0 + pex;
+        int w0 = o >> 5, sh = o & 31;
+        uint32_t wd[5];
+        wd[0] = (uint32_t)(f0 << sh);
+        wd[1] = (uint32_t)((f0 << sh) >> 32);
+        wd[2] = (uint32_t)((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0));
+        wd[3] = (uint32_t)(((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0)) >> 32);
+        wd[4] = sh ? (uint32_t)(f1 >> (64 - sh)) : 0u;
+        const int nwd = (sh + 4 * p + 31) >> 5;
 #pragma unroll
-      for (int k = 0; k < 4; k++) or_bits(buf, o + k * p, low_bits(vv[k], p), p);
+        for (int i = 0; i < 5; i++)
+          if (i < nwd && wd[i]) atomicOr(&buf[w0 + i], wd[i]);
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < 4; k++) or_bits(buf, H + (4 * gi + k) * W, low_bits(a[k], W), W);

@@ -46,7 +46,8 @@ constexpr int MAXCODES = 17;
 
 struct ProfArgs {
   const void* x;
-  float* partials;            // [ncodes][ntiles][NSUM][2]
+  float* partials;            // [ncodes][nwg][NSUM][2]
+  int32_t* cj;                // per-block codes (fixed rate): written by P_STATS, read by P_CENTER
   unsigned long long* words;  // [ncodes] total block words
   unsigned int* fits;         // [ncodes]
   unsigned int* hist;         // [8]
@@ -54,8 +55,10 @@ struct ProfArgs {
   uint32_t* status;
   int64_t jstride;            // 1 (full array) or 16 (subsample)
   int64_t nbe;                // blocks visited
-  int64_t ntiles;
+  int64_t ntiles;             // tiles of blocks to visit
+  int64_t nwg;                // persistent workgroups per code
   int op, rule;
+  int store_cj, hist_code;    // P_STATS: store per-block codes; P_FITS: code index histogrammed
   uint32_t mask;
   int ncodes;
   int escale;                 // sums are scaled by 2^-escale (linear) or 2^-2escale (squares)
@@ -68,6 +71,7 @@ int64_t encode_tiles(const Geo& g);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
+int64_t prof_wgs(int64_t ntiles);
 hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s);
 hipError_t launch_finalize(const float* partials, int64_t ntiles, int ncodes, double* out,
                            hipStream_t s);
