@@ -154,20 +154,17 @@ void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
   memcpy(hdr, b, 64);
 }
 
-// ---- workspace layout
-constexpr uint64_t WS_STATUS = 0, WS_TICKET = 4, WS_MAXBITS = 16, WS_FITS = 64, WS_HIST = 160,
-                   WS_WORDS = 256, WS_FINAL = 512, WS_CTRL = 2048;
-
+// ---- workspace layout: [PState][tile states][per-block codes][partials]
+uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 uint64_t tiles_enc(const HG& h) { return (uint64_t)encode_tiles(h.g); }
 
 uint64_t partial_floats(const HG& h) {
-  uint64_t w = (uint64_t)prof_wgs(prof_tiles(h.g, h.g.nblocks));
+  uint64_t w = (uint64_t)prof_wgs(prof_tiles(h.g, h.g.nblocks), 1);
   return (uint64_t)MAXCODES * std::max<uint64_t>(w, 1) * NSUM * 2;
 }
 
-uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
-uint64_t ws_tile_off() { return WS_CTRL; }
-uint64_t ws_cj_off(const HG& h) { return WS_CTRL + al256(8 * tiles_enc(h)); }
+uint64_t ws_tile_off() { return al256(sizeof(PState)); }
+uint64_t ws_cj_off(const HG& h) { return ws_tile_off() + al256(8 * tiles_enc(h)); }
 uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
 uint64_t ws_need(const HG& h) { return ws_part_off(h) + 4 * partial_floats(h); }
 
@@ -212,85 +209,6 @@ uint64_t block_valid(const HG& h, int64_t j) {
   int64_t ey = std::min<int64_t>(g.b[1], g.n[1] - by * g.b[1]);
   int64_t ez = std::min<int64_t>(g.b[0], g.n[0] - bz * g.b[0]);
   return (uint64_t)(ex * ey * ez);
-}
-
-struct ProfRun {
-  const HG& h;
-  const void* x;
-  void* ws;
-  hipStream_t s;
-  int escale;
-  int64_t sub_stride, sub_n;
-  alignas(16) uint8_t hc[WS_CTRL];  // host copy of the control block after a run
-
-  uint8_t* ctrl() const { return (uint8_t*)ws; }
-
-  ProfArgs args(int op, int rule, uint32_t mask, bool sub) const {
-    ProfArgs A;
-    memset(&A, 0, sizeof(A));
-    A.x = x;
-    A.g = h.g;
-    A.op = op;
-    A.rule = rule;
-    A.mask = mask;
-    A.jstride = sub ? sub_stride : 1;
-    A.nbe = sub ? sub_n : h.g.nblocks;
-    A.partials = partials_ptr(ws, h);
-    A.cj = cj_ptr(ws, h);
-    A.words = (unsigned long long*)(ctrl() + WS_WORDS);
-    A.fits = (unsigned int*)(ctrl() + WS_FITS);
-    A.hist = (unsigned int*)(ctrl() + WS_HIST);
-    A.maxbits = (unsigned long long*)(ctrl() + WS_MAXBITS);
-    A.status = (uint32_t*)(ctrl() + WS_STATUS);
-    A.escale = escale;
-    A.ncodes = 1;
-    A.hist_code = -1;
-    return A;
-  }
-
-  // clear the counters, launch, reduce, copy the control block back (one sync)
-  int run(ProfArgs& A, bool finalize) {
-    hipLaunchKernelGGL(k_clear, dim3(2), dim3(256), 0, s, (uint32_t*)ws, (int)(WS_FINAL / 4));
-    if (hipGetLastError() != hipSuccess) return APAX_E_HIP;
-    int e = hip_err(launch_profile(h.dtype, h.ndim, A, s));
-    if (e) return e;
-    if (finalize) {
-      e = hip_err(launch_finalize(A.partials, A.nwg, A.ncodes, (double*)(ctrl() + WS_FINAL), s));
-      if (e) return e;
-    }
-    if (hipMemcpyAsync(hc, ctrl(), WS_CTRL, hipMemcpyDeviceToHost, s) != hipSuccess) return APAX_E_HIP;
-    if (hipStreamSynchronize(s) != hipSuccess) return APAX_E_HIP;
-    uint32_t st;
-    memcpy(&st, hc + WS_STATUS, 4);
-    if (st & ST_NONFINITE) return APAX_E_NONFINITE;
-    if (st & ST_INTERNAL) return APAX_E_INTERNAL;
-    return APAX_OK;
-  }
-
-  unsigned fits(int ci) const { unsigned v; memcpy(&v, hc + WS_FITS + 4 * ci, 4); return v; }
-  unsigned hist(int t) const { unsigned v; memcpy(&v, hc + WS_HIST + 4 * t, 4); return v; }
-  uint64_t words(int ci) const { uint64_t v; memcpy(&v, hc + WS_WORDS + 8 * ci, 8); return v; }
-  double maxbits(int i) const { double v; memcpy(&v, hc + WS_MAXBITS + 8 * i, 8); return v; }
-
-  // sums of one code, unscaled
-  void sums(int ci, double out[NSUM]) const {
-    for (int i = 0; i < NSUM; i++) {
-      double f;
-      memcpy(&f, hc + WS_FINAL + 8 * (ci * NSUM + i), 8);
-      bool sq = i >= S_XX;
-      out[i] = ldexp(f, sq ? 2 * escale : escale);
-    }
-  }
-};
-
-// Codes the bisection (mid = lo + ((hi - lo) >> 1)) may probe in its next
-// `depth` steps from (lo, hi): the nodes of its decision tree.
-void bisect_tree(int lo, int hi, int depth, std::vector<int>& out) {
-  if (depth == 0 || hi - lo <= 1) return;
-  int mid = lo + ((hi - lo) >> 1);
-  out.push_back(mid);
-  bisect_tree(lo, mid, depth - 1, out);
-  bisect_tree(mid, hi, depth - 1, out);
 }
 
 }  // namespace
@@ -414,8 +332,8 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
   A.lens = (uint16_t*)((uint8_t*)d_stream + 64);
   A.sbo = (uint64_t*)((uint8_t*)d_stream + 64 + lens_bytes(h));
   A.d_nbytes = d_nbytes;
-  A.status = (uint32_t*)((uint8_t*)d_ws + WS_STATUS);
-  A.ticket = (uint32_t*)((uint8_t*)d_ws + WS_TICKET);
+  A.status = &((PState*)d_ws)->status;
+  A.ticket = &((PState*)d_ws)->ticket;
   A.tile_state = tile_state_ptr(d_ws);
   make_header(p, h, A.hdr);
   if (h.mode != APAX_FIXED_RATE) {
@@ -461,7 +379,7 @@ int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* 
   A.lens = (const uint16_t*)((const uint8_t*)d_stream + 64);
   A.sbo = (const uint64_t*)((const uint8_t*)d_stream + 64 + lens_bytes(h));
   A.y = d_y;
-  A.status = (uint32_t*)((uint8_t*)d_ws + WS_STATUS);
+  A.status = &((PState*)d_ws)->status;
   A.payload_words = pw;
   memcpy(A.hdr, h_hdr, 64);
   return hip_err(launch_decode(h.dtype, h.ndim, A, stream));
@@ -481,207 +399,142 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   memset(out, 0, sizeof(*out));
   out->size = sizeof(*out);
   const Geo& g = h.g;
-  ProfRun R{h, d_x, d_ws, stream, 0, 1, 0, {}};
-  R.sub_stride = g.nblocks >= 1024 ? 16 : 1;
-  R.sub_n = (g.nblocks + R.sub_stride - 1) / R.sub_stride;
-  out->n_sub = (uint32_t)R.sub_n;
+  PState* st = (PState*)d_ws;
+  const int64_t sub_stride = g.nblocks >= 1024 ? 16 : 1;
+  const int64_t sub_n = (g.nblocks + sub_stride - 1) / sub_stride;
+  out->n_sub = (uint32_t)sub_n;
   const int rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
+  const bool fr = h.mode == APAX_FIXED_RATE;
+  const uint64_t in_bytes = h.nsamples * (uint64_t)h.esz;
+  // bisection batches: each probe launch evaluates the decision tree of the
+  // next `depth` steps; fixed quality re-reads the whole array per code, so
+  // it evaluates one code per launch once the array outgrows the last-level cache
+  const int depth = fr ? 3 : (in_bytes <= (96ull << 20) ? 3 : 1);
+  const int nbatch = (16 + depth - 1) / depth;
+  const int tree_n = (1 << depth) - 1 + 1;
 
-  // 1. max |x| over the array -> whole-array bracket, statistics scale
-  double Mall = 0.0;
+  CtlArgs C;
+  memset(&C, 0, sizeof(C));
+  C.st = st;
+  C.mode = h.mode;
+  C.isint = h.isint;
+  C.depth = depth;
+  C.cmin = g.cmin;
+  C.cmax = g.cmax;
+  C.mask_user = g.mask;
+  C.nsub = (uint64_t)sub_n;
+  C.nsamples = h.nsamples;
+  C.target = p->target_corr;
+  auto ctl = [&](int step) { C.step = step; return hip_err(launch_ctl(C, stream)); };
+  auto args = [&](int op, int rl, int mask_sel, bool sub, int maxcodes) {
+    ProfArgs A;
+    memset(&A, 0, sizeof(A));
+    A.x = d_x;
+    A.st = st;
+    A.g = g;
+    A.op = op;
+    A.rule = rl;
+    A.mask_sel = mask_sel;
+    A.jstride = sub ? sub_stride : 1;
+    A.nbe = sub ? sub_n : g.nblocks;
+    A.maxcodes = maxcodes;
+    A.partials = partials_ptr(d_ws, h);
+    A.cj = cj_ptr(d_ws, h);
+    return A;
+  };
+  auto run = [&](ProfArgs A, bool fin) -> int {
+    int e2 = hip_err(launch_profile(h.dtype, h.ndim, A, stream));
+    if (e2) return e2;
+    if (fin) e2 = hip_err(launch_finalize(A.partials, A.nwg, A.maxcodes, st, stream));
+    return e2;
+  };
+
+  // whole profile, asynchronously: clear, max |x|, bisection batches,
+  // histogram -> mask, curve, metrics, centred metrics; then one read-back
+  hipLaunchKernelGGL(k_clear, dim3((unsigned)((sizeof(PState) / 4 + 255) / 256)), dim3(256), 0,
+                     stream, (uint32_t*)st, (int)(sizeof(PState) / 4));
+  if ((e = hip_err(hipGetLastError()))) return e;
+  if ((e = hip_err(launch_pmax(h.dtype, d_x, h.nsamples, st, stream)))) return e;
+  if ((e = ctl(C_INIT))) return e;
   if (g.nblocks) {
-    ProfArgs A = R.args(P_MAX, R_LOSSLESS, g.mask, false);
-    if ((e = R.run(A, false))) return e;
-    Mall = R.maxbits(0);
-  }
-  const int CF = host_largest(Mall, 0.5, g.cmin, g.cmax);
-  const int CC = h.isint ? 0 : host_largest(Mall, 2147483647.0, g.cmin, g.cmax);
-  out->c_floor = CF;
-  out->c_cap = CC;
-  int ex = 0;
-  if (Mall > 0) frexp(Mall, &ex);
-  R.escale = ex;
-
-  // 2. operating point: bisection; each launch evaluates the whole decision
-  //    tree of the next steps (one code per grid row), the host walks it
-  int code = 0;
-  if (g.nblocks && CF < CC && (h.mode == APAX_FIXED_RATE || h.mode == APAX_FIXED_QUALITY)) {
-    const bool fr = h.mode == APAX_FIXED_RATE;
-    const double rt = p->target_corr;
-    const unsigned need = (unsigned)((9 * (uint64_t)R.sub_n + 9) / 10);
-    // fixed quality re-reads the full array per code: shallower trees when
-    // the array does not stay in the 256 MB last-level cache
-    const uint64_t in_bytes = h.nsamples * (uint64_t)h.esz;
-    const int depth = fr ? 4 : (in_bytes <= (96ull << 20) ? 4 : 2);
-    std::vector<char> near;
-    auto probe = [&](const std::vector<int>& codes, std::vector<char>& pred) -> int {
-      ProfArgs A = fr ? R.args(P_FITS, R_RATE, g.mask & 0x7Fu, true)
-                      : R.args(P_STATS, R_QUALITY, g.mask, false);
-      A.ncodes = (int)codes.size();
-      for (size_t i = 0; i < codes.size(); i++) A.codes[i] = codes[i];
-      int e2 = R.run(A, !fr);
-      if (e2) return e2;
-      pred.assign(codes.size(), 0);
-      near.assign(codes.size(), 0);
-      for (size_t i = 0; i < codes.size(); i++) {
-        if (fr) {
-          pred[i] = R.fits((int)i) >= need;
-        } else {
-          double S[NSUM], r, omr;
-          R.sums((int)i, S);
-          r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
-          near[i] = fabs(r - rt) < 1e-11;
-          pred[i] = r >= rt;
-        }
-      }
-      return APAX_OK;
-    };
-    int lo = CF, hi = CC;
-    std::vector<int> codes{CC};
-    bisect_tree(lo, hi, depth, codes);
-    std::vector<char> pred;
-    if ((e = probe(codes, pred))) return e;
-    out->n_probes++;
-    if (near[0]) out->flags |= APAX_NEAR_TIE;
-    bool top = pred[0];
-    if (fr ? top : !top) {
-      code = CC;  // fixed rate: everything fits at the cap; fixed quality: target unreachable
-    } else {
-      for (;;) {
-        // walk the evaluated tree
-        size_t k = 1;
-        bool walked = false;
-        while (hi - lo > 1) {
-          int mid = lo + ((hi - lo) >> 1);
-          while (k < codes.size() && codes[k] != mid) k++;
-          if (k >= codes.size()) break;
-          walked = true;
-          out->n_probes++;
-          if (near[k]) out->flags |= APAX_NEAR_TIE;
-          bool pm = pred[k];
-          // fixed rate keeps the largest fitting code, fixed quality the
-          // smallest code reaching the target
-          if (fr) { if (pm) lo = mid; else hi = mid; }
-          else { if (pm) hi = mid; else lo = mid; }
-        }
-        if (hi - lo <= 1) break;
-        (void)walked;
-        codes.clear();
-        bisect_tree(lo, hi, depth, codes);
-        if ((e = probe(codes, pred))) return e;
-        // probe() filled pred for codes starting at index 0
-        codes.insert(codes.begin(), INT32_MIN);
-        pred.insert(pred.begin(), 0);
-        near.insert(near.begin(), 0);
-      }
-      code = fr ? lo : hi;
+    for (int b = 0; b < nbatch && (fr || h.mode == APAX_FIXED_QUALITY); b++) {
+      if (fr) { if ((e = run(args(P_FITS, R_RATE, 0, true, tree_n), false))) return e; }
+      else { if ((e = run(args(P_STATS, R_QUALITY, 0, false, tree_n), true))) return e; }
+      if ((e = ctl(C_DECIDE))) return e;
     }
-  } else if (h.mode == APAX_FIXED_RATE || h.mode == APAX_FIXED_QUALITY) {
-    code = CC;
+    if ((e = ctl(C_MASK))) return e;
+    ProfArgs H = args(P_FITS, rule, 0, true, 1);
+    H.hist = 1;
+    if ((e = run(H, false))) return e;
+    if ((e = ctl(C_CURVE))) return e;
+    if ((e = run(args(P_STATS, R_QUALITY, 1, true, NCURVE), true))) return e;
+    if ((e = ctl(C_METRICS))) return e;
+    ProfArgs Mx = args(P_STATS, rule, 2, false, 1);
+    Mx.store_cj = 1;
+    if ((e = run(Mx, true))) return e;
+    if ((e = ctl(C_MEANS))) return e;
+    if ((e = run(args(P_CENTER, rule, 2, false, 1), true))) return e;
+  } else {
+    if ((e = ctl(C_MASK))) return e;
+    if ((e = ctl(C_CURVE))) return e;
   }
-  out->code = code;
+  PState hs;
+  if (hipMemcpyAsync(&hs, st, sizeof(PState), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  if (hs.status & ST_NONFINITE) return APAX_E_NONFINITE;
+  if (hs.status & ST_INTERNAL) return APAX_E_INTERNAL;
 
-  // 3. stream mask from the subsample histogram at the chosen code
-  uint32_t mask = 0x81u;
+  out->c_floor = hs.cf;
+  out->c_cap = hs.cc;
+  out->code = hs.code;
+  out->flags = (uint32_t)hs.flags;
+  out->n_probes = (uint32_t)hs.n_probes;
+  out->stream_mask = hs.mask_out;
+  const int es = hs.escale;
+  auto unscale = [&](double v, int i) { return ldexp(v, i >= S_XX ? 2 * es : es); };
+  double in_bits = 0.0;
+  for (int64_t jj = 0; jj < sub_n; jj++) in_bits += (double)block_valid(h, jj * sub_stride);
+  in_bits *= 8.0 * h.esz;
+  for (int t = 0; t < APAX_NCURVE; t++) {
+    out->curve[t].code = hs.curve_codes[t];
+    double r = 1.0, omr = 0.0, ob = 0.0;
+    if (g.nblocks) {
+      r_of(hs.curve_sums[t][0], hs.curve_sums[t][1], hs.curve_sums[t][2], hs.curve_sums[t][3], r, omr);
+      ob = 32.0 * (double)hs.curve_words[t];
+    }
+    out->curve[t].ratio = ob > 0 ? in_bits / ob : 0.0;
+    out->curve[t].r = r;
+  }
+  apax_metrics& m = out->m;
+  m.n = h.nsamples;
   if (g.nblocks) {
-    uint32_t m = h.mode == APAX_FIXED_RATE ? (g.mask & 0x7Fu) : g.mask;
-    ProfArgs A = R.args(P_FITS, rule, m, true);
-    A.codes[0] = code;
-    A.hist_code = 0;
-    if ((e = R.run(A, false))) return e;
-    uint64_t thresh = ((uint64_t)R.sub_n + 99) / 100;
-    if (thresh < 1) thresh = 1;
-    for (int t = 0; t < 8; t++)
-      if (R.hist(t) >= thresh) mask |= 1u << t;
+    m.sum_x = unscale(hs.msums[S_X], S_X);
+    m.sum_y = unscale(hs.msums[S_Y], S_Y);
+    m.sum_d = unscale(hs.msums[S_D], S_D);
+    m.sxx = unscale(hs.msums[S_XX], S_XX);
+    m.syy = unscale(hs.msums[S_YY], S_YY);
+    m.sdd = unscale(hs.msums[S_DD], S_DD);
+    m.sds = unscale(hs.msums[S_DS], S_DS);
+    memcpy(&m.max_abs_d, &hs.maxbits[1], 8);
   }
-  mask &= (g.mask | 0x81u);
-  out->stream_mask = mask;
-
-  // 4. rate-correlation curve on the subsample (17 codes in one launch)
-  {
-    int codes[MAXCODES];
-    for (int t = 0; t < APAX_NCURVE; t++) {
-      int ct = code + 4 * (t - APAX_NCURVE / 2);
-      codes[t] = ct < g.cmin ? g.cmin : (ct > g.cmax ? g.cmax : ct);
-    }
-    double in_bits = 0.0;
-    for (int64_t jj = 0; jj < R.sub_n; jj++) in_bits += (double)block_valid(h, jj * R.sub_stride);
-    in_bits *= 8.0 * h.esz;
-    if (g.nblocks) {
-      ProfArgs A = R.args(P_STATS, R_QUALITY, mask | 0x81u, true);
-      A.ncodes = APAX_NCURVE;
-      for (int t = 0; t < APAX_NCURVE; t++) A.codes[t] = codes[t];
-      if ((e = R.run(A, true))) return e;
-    }
-    for (int t = 0; t < APAX_NCURVE; t++) {
-      out->curve[t].code = codes[t];
-      double r = 1.0, omr = 0.0, ob = 0.0;
-      if (g.nblocks) {
-        double S[NSUM];
-        R.sums(t, S);
-        r_of(S[S_XX], S[S_YY], S[S_DD], S[S_DS], r, omr);
-        ob = 32.0 * (double)R.words(t);
-      }
-      out->curve[t].ratio = ob > 0 ? in_bits / ob : 0.0;
-      out->curve[t].r = r;
-    }
+  r_of(m.sxx, m.syy, m.sdd, m.sds, m.r, m.one_minus_r);
+  if (m.sdd == 0.0) { m.snr_db = INFINITY; m.rms_pct = 0.0; m.rms_db = -INFINITY; }
+  else if (m.sxx == 0.0) { m.snr_db = -INFINITY; m.rms_pct = INFINITY; m.rms_db = INFINITY; }
+  else {
+    m.snr_db = 10.0 * log10(m.sxx / m.sdd);
+    m.rms_pct = 100.0 * sqrt(m.sdd / m.sxx);
+    m.rms_db = -m.snr_db;
   }
-
-  // 5. metrics at the operating point, full array (two passes: sums, then
-  //    centred sums for the population standard deviations)
-  {
-    apax_metrics& m = out->m;
-    uint32_t mm = h.mode == APAX_FIXED_RATE ? ((mask & 0x7Fu) | 1u) : (mask | 0x81u);
-    double S[NSUM] = {0};
-    uint64_t W0 = 0;
-    double maxd = 0.0;
-    if (g.nblocks) {
-      ProfArgs A = R.args(P_STATS, rule, mm, false);
-      A.codes[0] = code;
-      A.store_cj = 1;
-      if ((e = R.run(A, true))) return e;
-      R.sums(0, S);
-      W0 = R.words(0);
-      maxd = R.maxbits(1);
-    }
-    m.n = h.nsamples;
-    m.sum_x = S[S_X];
-    m.sum_y = S[S_Y];
-    m.sum_d = S[S_D];
-    m.sxx = S[S_XX];
-    m.syy = S[S_YY];
-    m.sdd = S[S_DD];
-    m.sds = S[S_DS];
-    m.max_abs_d = maxd;
-    r_of(m.sxx, m.syy, m.sdd, m.sds, m.r, m.one_minus_r);
-    if (m.sdd == 0.0) { m.snr_db = INFINITY; m.rms_pct = 0.0; m.rms_db = -INFINITY; }
-    else if (m.sxx == 0.0) { m.snr_db = -INFINITY; m.rms_pct = INFINITY; m.rms_db = INFINITY; }
-    else {
-      m.snr_db = 10.0 * log10(m.sxx / m.sdd);
-      m.rms_pct = 100.0 * sqrt(m.sdd / m.sxx);
-      m.rms_db = -m.snr_db;
-    }
-    double nn = (double)(m.n ? m.n : 1);
-    m.mean_x = m.sum_x / nn;
-    m.mean_y = m.sum_y / nn;
-    m.mean_d = m.sum_d / nn;
-    m.enc_bytes = area_offset(h) + 4 * (h.mode == APAX_FIXED_RATE
-                                            ? (uint64_t)g.budget * (uint64_t)g.nblocks
-                                            : W0);
-    m.ratio = m.enc_bytes ? (double)(h.nsamples * (uint64_t)h.esz) / (double)m.enc_bytes : 0.0;
-    if (g.nblocks) {
-      ProfArgs A = R.args(P_CENTER, rule, mm, false);
-      A.codes[0] = code;
-      A.mean_x = m.mean_x;
-      A.mean_y = m.mean_y;
-      A.mean_d = m.mean_d;
-      if ((e = R.run(A, true))) return e;
-      double c[NSUM];
-      R.sums(0, c);
-      m.std_x = sqrt(c[S_CXX] / nn);
-      m.std_y = sqrt(c[S_CYY] / nn);
-      m.std_d = sqrt(c[S_CDD] / nn);
-    }
+  double nn = (double)(m.n ? m.n : 1);
+  m.mean_x = m.sum_x / nn;
+  m.mean_y = m.sum_y / nn;
+  m.mean_d = m.sum_d / nn;
+  m.enc_bytes = area_offset(h) + 4 * (fr ? (uint64_t)g.budget * (uint64_t)g.nblocks : hs.mwords);
+  m.ratio = m.enc_bytes ? (double)(h.nsamples * (uint64_t)h.esz) / (double)m.enc_bytes : 0.0;
+  if (g.nblocks) {
+    m.std_x = sqrt(unscale(hs.sums[0][S_CXX], S_CXX) / nn);
+    m.std_y = sqrt(unscale(hs.sums[0][S_CYY], S_CYY) / nn);
+    m.std_d = sqrt(unscale(hs.sums[0][S_CDD], S_CDD) / nn);
   }
   return APAX_OK;
 }

@@ -39,41 +39,74 @@ struct DecArgs {
   Geo g;
 };
 
-enum { P_MAX = 0, P_STATS = 1, P_FITS = 2, P_CENTER = 3 };
+enum { P_STATS = 1, P_FITS = 2, P_CENTER = 3 };
 enum { R_LOSSLESS = 0, R_RATE = 1, R_QUALITY = 2 };
 enum { S_X = 0, S_Y, S_D, S_XX, S_YY, S_DD, S_DS, S_CXX, S_CYY, S_CDD, NSUM };
 constexpr int MAXCODES = 17;
+constexpr int NCURVE = 17;
+
+// Device-resident profiler state (start of the workspace).  The control
+// kernel (one thread) makes every decision of the profile on the device --
+// bracket, bisection walk, stream mask, curve codes, means -- so a whole
+// profile is one asynchronous launch sequence and one read-back.
+struct PState {
+  uint32_t status;          // device-side error bits (shared with encode/decode)
+  uint32_t ticket;          // encode: dynamic tile ticket
+  uint64_t maxbits[2];      // max|x|, max|d| (binary64 bits, non-negative)
+  int32_t cf, cc, escale, code;      // whole-array bracket, statistics scale, result code
+  int32_t lo, hi, done, n_probes;    // bisection state
+  int32_t flags, ncodes, first, pad0;
+  uint32_t mask_probe, mask_out, need, pad1;
+  int32_t codes[MAXCODES];  // codes evaluated by the next probe launch
+  int32_t probe[MAXCODES];  // codes of the last probe launch (tree order)
+  uint32_t fits[MAXCODES];
+  uint32_t hist[8];
+  uint64_t words[MAXCODES];
+  double mean[3];
+  double sums[MAXCODES][NSUM];        // finalize output of the last stats launch
+  double curve_sums[NCURVE][4];       // Sxx, Syy, Sdd, Sds of the curve codes
+  uint64_t curve_words[NCURVE];
+  int32_t curve_codes[NCURVE];
+  int32_t pad2;
+  double msums[NSUM];                 // metrics at the operating point
+  uint64_t mwords;
+};
 
 struct ProfArgs {
   const void* x;
-  float* partials;            // [ncodes][nwg][NSUM][2]
+  PState* st;
+  float* partials;            // [MAXCODES][nwg][NSUM][2]
   int32_t* cj;                // per-block codes (fixed rate): written by P_STATS, read by P_CENTER
-  unsigned long long* words;  // [ncodes] total block words
-  unsigned int* fits;         // [ncodes]
-  unsigned int* hist;         // [8]
-  unsigned long long* maxbits;// [0] max|x|, [1] max|d| (binary64 bits, non-negative)
-  uint32_t* status;
   int64_t jstride;            // 1 (full array) or 16 (subsample)
   int64_t nbe;                // blocks visited
   int64_t ntiles;             // tiles of blocks to visit
   int64_t nwg;                // persistent workgroups per code
   int op, rule;
-  int store_cj, hist_code;    // P_STATS: store per-block codes; P_FITS: code index histogrammed
-  uint32_t mask;
-  int ncodes;
-  int escale;                 // sums are scaled by 2^-escale (linear) or 2^-2escale (squares)
-  int codes[MAXCODES];
-  double mean_x, mean_y, mean_d;
+  int maxcodes;               // grid rows launched (rows >= st->ncodes exit)
+  int store_cj, hist;         // P_STATS: store per-block codes; P_FITS: histogram streams
+  int mask_sel;               // 0 st->mask_probe, 1 st->mask_out (+0x81), 2 metrics mask
   Geo g;
+};
+
+// control steps of the profile
+enum { C_INIT = 0, C_DECIDE = 1, C_MASK = 2, C_CURVE = 3, C_METRICS = 4, C_MEANS = 5 };
+struct CtlArgs {
+  PState* st;
+  int step, mode, isint, depth, cmin, cmax;
+  uint32_t mask_user;         // effective user stream mask
+  uint64_t nsub, nsamples;
+  double target;
 };
 
 int64_t encode_tiles(const Geo& g);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
-int64_t prof_wgs(int64_t ntiles);
+int64_t prof_wgs(int64_t ntiles, int ncodes);
 hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s);
-hipError_t launch_finalize(const float* partials, int64_t ntiles, int ncodes, double* out,
+hipError_t launch_finalize(const float* partials, int64_t nwg, int maxcodes, PState* st,
                            hipStream_t s);
+hipError_t launch_pmax(int dtype, const void* x, uint64_t n, PState* st, hipStream_t s);
+hipError_t launch_ctl(const CtlArgs& C, hipStream_t s);
 
 }  // namespace apax

@@ -42,40 +42,87 @@ __device__ __forceinline__ FF ff_shfl_xor(FF a, int o) {
   return {__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
 }
 
+// ---------------------------------------------------------------- max |x|
+// Streaming pass: max |x| as magnitude bit patterns (monotone in value) and
+// the non-finite flag, 16-byte loads, one atomic per wave.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pmax(const T* __restrict__ x, uint64_t n, PState* st) {
+  constexpr int PER = 16 / sizeof(T);
+  const uint64_t nvec = (((uintptr_t)x) & 15) == 0 ? n / PER : 0;
+  uint64_t key = 0;
+  bool nf = false;
+  auto take = [&](T v) {
+    uint64_t k;
+    if constexpr (Traits<T>::isint) {
+      int64_t iv = (int64_t)v;
+      k = (uint64_t)(iv < 0 ? -iv : iv);
+    } else if constexpr (sizeof(T) == 4) {
+      k = __builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu;
+      nf |= k >= 0x7F800000u;
+      k = (uint64_t)__builtin_bit_cast(uint64_t, (double)__builtin_bit_cast(float, (uint32_t)k));
+    } else {
+      k = __builtin_bit_cast(uint64_t, v) & 0x7FFFFFFFFFFFFFFFull;
+      nf |= k >= 0x7FF0000000000000ull;
+    }
+    if constexpr (Traits<T>::isint) k = __builtin_bit_cast(uint64_t, (double)k);
+    bool bad = false;
+    if constexpr (!Traits<T>::isint) bad = nf;
+    key = (!bad && k > key) ? k : key;
+  };
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+    uint4 u = reinterpret_cast<const uint4*>(x)[i];
+    T v[PER];
+    __builtin_memcpy(v, &u, 16);
+#pragma unroll
+    for (int k = 0; k < PER; k++) take(v[k]);
+  }
+  for (uint64_t i = nvec * PER + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    take(x[i]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t t = (uint64_t)__shfl_xor((unsigned long long)key, o, 64);
+    key = t > key ? t : key;
+  }
+  if (__ballot(nf) && lane_id() == 0) atomicOr(&st->status, ST_NONFINITE);
+  if (lane_id() == 0 && key) atomicMax((unsigned long long*)&st->maxbits[0], (unsigned long long)key);
+}
+
+// ---------------------------------------------------------------- block passes
 template <typename T, int LPB, int NDIM>
 __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   constexpr int BPW = 64 / LPB;
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
+  PState* st = A.st;
   __shared__ float s_red[WPG][NSUM][2];
   __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
 
+  const int ci = blockIdx.y;
+  if (ci >= st->ncodes) return;  // uniform per workgroup
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
-  const int ci = blockIdx.y;
-  int code = 0;
-#pragma unroll
-  for (int t = 0; t < MAXCODES; t++) code |= (int)pick(ci == t, (uint32_t)A.codes[t]);
-  const double s1 = ldexp(1.0, -A.escale);
-  const double s2 = ldexp(1.0, -2 * A.escale);
+  const int code = st->codes[ci];
+  const int escale = st->escale;
+  uint32_t mask;
+  if (A.mask_sel == 0) mask = st->mask_probe;
+  else if (A.mask_sel == 1) mask = st->mask_out | 0x81u;
+  else mask = A.rule == R_RATE ? ((st->mask_out & 0x7Fu) | 1u) : (st->mask_out | 0x81u);
+  const double s1 = ldexp(1.0, -escale);
+  const double s2 = ldexp(1.0, -2 * escale);
+  const double mx = st->mean[0], my = st->mean[1], md = st->mean[2];
   FF acc[NSUM];
 #pragma unroll
   for (int i = 0; i < NSUM; i++) acc[i] = {0.f, 0.f};
-  double dmax = 0.0, xmax = 0.0;
+  double dmax = 0.0;
   uint32_t nfit = 0;
   unsigned long long wsum = 0;
-  bool nonfinite = false;
 
   for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += A.nwg) {
     const int64_t jj = (tile * WPG + wave) * BPW + lane / LPB;
     B_ b;
     b.init(g, jj < A.nbe ? jj * A.jstride : g.nblocks, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
     b.load((const T*)A.x, g);
-    nonfinite |= b.act && b.nonfinite;
-    if (A.op == P_MAX) {
-      xmax = b.act && b.M > xmax ? b.M : xmax;
-      continue;
-    }
     int32_t a[4], v[7][4];
     int eps[7], pw[7];
     Costs C;
@@ -84,11 +131,11 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       // argmin over the mask at the clamped code: fit test + stream histogram
       int c = A.rule == R_LOSSLESS ? 0 : clampc(code, b.cf, b.cc);
       b.quantize(c, A.rule == R_LOSSLESS, a);
-      b.sizes(g, A.mask, a, v, eps, pw, C);
-      int st = B_::argmin(C, A.mask, best);
+      b.sizes(g, mask, a, v, eps, pw, C);
+      int s_ = B_::argmin(C, mask, best);
       if (b.blk_ok && b.L.gi == 0) {
         if (best <= 32 * g.budget) nfit++;
-        if (ci == A.hist_code) atomicAdd(&A.hist[st], 1u);
+        if (A.hist) atomicAdd(&st->hist[s_], 1u);
       }
       continue;
     }
@@ -101,12 +148,12 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
         c = b.blk_ok ? A.cj[b.j] : 0;
       } else {
         c = clampc(code, b.cf, b.cc);
-        const uint32_t m7 = A.mask & 0x7Fu;
+        const uint32_t m7 = mask & 0x7Fu;
         b.quantize(c, false, a);
         b.sizes(g, m7, a, v, eps, pw, C);
-        int st = B_::argmin(C, m7, best);
+        int s_ = B_::argmin(C, m7, best);
         bool need = b.act && best > 32 * g.budget;
-        if (__ballot(need)) c = b.rate_search(g, c, st, need);
+        if (__ballot(need)) c = b.rate_search(g, c, s_, need);
         if (A.store_cj && b.blk_ok && b.L.gi == 0) A.cj[b.j] = c;
       }
     }
@@ -114,14 +161,19 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     if (A.op == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
-        b.sizes(g, A.mask, a, v, eps, pw, C);
-        B_::argmin(C, A.mask, best);
+        b.sizes(g, mask, a, v, eps, pw, C);
+        B_::argmin(C, mask, best);
         nw = (best + 31) >> 5;
       } else {
         nw = g.budget;
       }
       if (b.blk_ok && b.L.gi == 0) wsum += (unsigned long long)nw;
     }
+    // the group's terms are summed in binary64 first (4 terms, relative error
+    // ~1e-16), then added to the FP32 float-float accumulators
+    double t[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; i++) t[i] = 0.0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (!(b.act && b.valid(k))) continue;
@@ -131,38 +183,37 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       else y = (double)to_out<T>(dequant(a[k], c));
       double d = x - y;
       if (A.op == P_STATS) {
-        acc[S_X] = ff_add(acc[S_X], ff_of(x * s1));
-        acc[S_Y] = ff_add(acc[S_Y], ff_of(y * s1));
-        acc[S_D] = ff_add(acc[S_D], ff_of(d * s1));
-        acc[S_XX] = ff_add(acc[S_XX], ff_of((x * x) * s2));
-        acc[S_YY] = ff_add(acc[S_YY], ff_of((y * y) * s2));
-        acc[S_DD] = ff_add(acc[S_DD], ff_of((d * d) * s2));
-        acc[S_DS] = ff_add(acc[S_DS], ff_of((d * (x + y)) * s2));
+        t[S_X] += x;
+        t[S_Y] += y;
+        t[S_D] += d;
+        t[S_XX] += x * x;
+        t[S_YY] += y * y;
+        t[S_DD] += d * d;
+        t[S_DS] += d * (x + y);
         double ad = __builtin_fabs(d);
         dmax = ad > dmax ? ad : dmax;
       } else {
-        double ex = x - A.mean_x, ey = y - A.mean_y, ed = d - A.mean_d;
-        acc[S_CXX] = ff_add(acc[S_CXX], ff_of((ex * ex) * s2));
-        acc[S_CYY] = ff_add(acc[S_CYY], ff_of((ey * ey) * s2));
-        acc[S_CDD] = ff_add(acc[S_CDD], ff_of((ed * ed) * s2));
+        double ex = x - mx, ey = y - my, ed = d - md;
+        t[S_CXX] += ex * ex;
+        t[S_CYY] += ey * ey;
+        t[S_CDD] += ed * ed;
       }
+    }
+    if (A.op == P_STATS) {
+#pragma unroll
+      for (int i = S_X; i <= S_D; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s1));
+#pragma unroll
+      for (int i = S_XX; i <= S_DS; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s2));
+    } else {
+#pragma unroll
+      for (int i = S_CXX; i < NSUM; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s2));
     }
   }
 
-  if (__ballot(nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
-  if (A.op == P_MAX) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      double t = __shfl_xor(xmax, o, 64);
-      xmax = t > xmax ? t : xmax;
-    }
-    if (lane == 0) atomicMax(&A.maxbits[0], (unsigned long long)__builtin_bit_cast(uint64_t, xmax));
-    return;
-  }
   if (A.op == P_FITS) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) nfit += __shfl_xor(nfit, o, 64);
-    if (lane == 0 && nfit) atomicAdd(&A.fits[ci], nfit);
+    if (lane == 0 && nfit) atomicAdd(&st->fits[ci], nfit);
     return;
   }
   // wave reduction of the sums this op produced
@@ -177,13 +228,13 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   if (A.op == P_STATS) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      double t = __shfl_xor(dmax, o, 64);
-      dmax = t > dmax ? t : dmax;
+      double tt = __shfl_xor(dmax, o, 64);
+      dmax = tt > dmax ? tt : dmax;
       wsum += __shfl_xor(wsum, o, 64);
     }
     if (lane == 0) {
-      atomicMax(&A.maxbits[1], (unsigned long long)__builtin_bit_cast(uint64_t, dmax));
-      if (wsum) atomicAdd(&A.words[ci], wsum);
+      atomicMax((unsigned long long*)&st->maxbits[1], (unsigned long long)__builtin_bit_cast(uint64_t, dmax));
+      if (wsum) atomicAdd((unsigned long long*)&st->words[ci], wsum);
     }
   }
   if (lane == 0) {
@@ -196,19 +247,19 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   __syncthreads();
   if (threadIdx.x < NSUM) {
     int i = threadIdx.x;
-    FF t = {s_red[0][i][0], s_red[0][i][1]};
-    for (int w = 1; w < WPG; w++) t = ff_add(t, FF{s_red[w][i][0], s_red[w][i][1]});
+    FF tt = {s_red[0][i][0], s_red[0][i][1]};
+    for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
     float* p = A.partials + (((int64_t)ci * A.nwg + blockIdx.x) * NSUM + i) * 2;
-    p[0] = t.hi;
-    p[1] = t.lo;
+    p[0] = tt.hi;
+    p[1] = tt.lo;
   }
 }
 
 // Fixed-order reduction of the per-workgroup partials of every code.
-__global__ __launch_bounds__(256) void k_finalize(const float* partials, int64_t nwg,
-                                                  double* out) {
+__global__ __launch_bounds__(256) void k_finalize(const float* partials, int64_t nwg, PState* st) {
   __shared__ float s[256][2];
   const int ci = blockIdx.x / NSUM, i = blockIdx.x % NSUM;
+  if (ci >= st->ncodes) return;
   FF acc = {0.f, 0.f};
   for (int64_t t = threadIdx.x; t < nwg; t += 256) {
     const float* p = partials + ((ci * nwg + t) * NSUM + i) * 2;
@@ -227,7 +278,175 @@ __global__ __launch_bounds__(256) void k_finalize(const float* partials, int64_t
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[ci * NSUM + i] = (double)s[0][0] + (double)s[0][1];
+  if (threadIdx.x == 0) st->sums[ci][i] = (double)s[0][0] + (double)s[0][1];
+}
+
+// ---------------------------------------------------------------- control
+__device__ int ctl_largest(double M, double lim, int cmin, int cmax) {
+  if (M * gain_of(cmax) <= lim) return cmax;
+  int lo = cmin, hi = cmax;
+  while (hi - lo > 1) {
+    int mid = lo + ((hi - lo) >> 1);
+    if (M * gain_of(mid) <= lim) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// pre-order nodes of the bisection decision tree of the next `depth` steps
+__device__ int ctl_tree(int lo, int hi, int depth, int32_t* out, int n) {
+  int slo[8], shi[8], sd[8], sp = 0;
+  slo[0] = lo; shi[0] = hi; sd[0] = depth; sp = 1;
+  while (sp > 0 && n < MAXCODES) {
+    --sp;
+    int l = slo[sp], h = shi[sp], d = sd[sp];
+    if (d == 0 || h - l <= 1) continue;
+    int mid = l + ((h - l) >> 1);
+    out[n++] = mid;
+    // push right first so the left subtree comes next (pre-order)
+    if (sp + 2 <= 8) {
+      slo[sp] = mid; shi[sp] = h; sd[sp] = d - 1; sp++;
+      slo[sp] = l; shi[sp] = mid; sd[sp] = d - 1; sp++;
+    }
+  }
+  return n;
+}
+
+__device__ void r_from(const double* S, double& r) {
+  double sxx = S[S_XX], syy = S[S_YY], sdd = S[S_DD], sds = S[S_DS];
+  if (sxx == 0.0 && syy == 0.0) { r = 1.0; return; }
+  if (sxx == 0.0 || syy == 0.0) { r = 0.0; return; }
+  double nx = sqrt(sxx), ny = sqrt(syy);
+  double dn = sds / (nx + ny);
+  r = 1.0 - (sdd - dn * dn) / (2.0 * nx * ny);
+}
+
+__device__ void ctl_zero(PState* st) {
+  for (int i = 0; i < MAXCODES; i++) { st->fits[i] = 0; st->words[i] = 0; }
+}
+
+__global__ void k_ctl(CtlArgs C) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  PState* st = C.st;
+  const bool fr = C.mode == M_RATE;
+  switch (C.step) {
+    case C_INIT: {
+      double M = __builtin_bit_cast(double, st->maxbits[0]);
+      int CF = ctl_largest(M, 0.5, C.cmin, C.cmax);
+      int CC = C.isint ? 0 : ctl_largest(M, 2147483647.0, C.cmin, C.cmax);
+      int ex = 0;
+      if (M > 0) frexp(M, &ex);
+      st->cf = CF; st->cc = CC; st->escale = ex;
+      st->need = (uint32_t)((9 * C.nsub + 9) / 10);
+      st->mask_probe = fr ? (C.mask_user & 0x7Fu) : C.mask_user;
+      st->flags = 0; st->n_probes = 0;
+      ctl_zero(st);
+      if (C.mode == M_LOSSLESS || (st->status & ST_NONFINITE) || CF >= CC) {
+        st->code = C.mode == M_LOSSLESS ? 0 : CC;
+        st->done = 1; st->ncodes = 0;
+      } else {
+        st->lo = CF; st->hi = CC; st->first = 1; st->done = 0;
+        st->probe[0] = CC;
+        int n = ctl_tree(CF, CC, C.depth, st->probe, 1);
+        for (int i = 0; i < n; i++) st->codes[i] = st->probe[i];
+        st->ncodes = n;
+      }
+      break;
+    }
+    case C_DECIDE: {
+      if (st->done || st->ncodes == 0) { st->ncodes = 0; break; }
+      const int n = st->ncodes;
+      bool pred[MAXCODES], near[MAXCODES];
+      for (int i = 0; i < n; i++) {
+        if (fr) {
+          pred[i] = st->fits[i] >= st->need;
+          near[i] = false;
+        } else {
+          double r;
+          r_from(st->sums[i], r);
+          pred[i] = r >= C.target;
+          near[i] = fabs(r - C.target) < 1e-11;
+        }
+      }
+      int k = 0;
+      if (st->first) {
+        st->first = 0;
+        st->n_probes++;
+        if (near[0]) st->flags |= 1;
+        if (fr ? pred[0] : !pred[0]) {  // all fit at the cap / target unreachable
+          st->code = st->cc; st->done = 1; st->ncodes = 0;
+          break;
+        }
+        k = 1;
+      }
+      int lo = st->lo, hi = st->hi;
+      while (hi - lo > 1) {
+        int mid = lo + ((hi - lo) >> 1);
+        while (k < n && st->probe[k] != mid) k++;
+        if (k >= n) break;
+        st->n_probes++;
+        if (near[k]) st->flags |= 1;
+        if (fr) { if (pred[k]) lo = mid; else hi = mid; }
+        else { if (pred[k]) hi = mid; else lo = mid; }
+      }
+      st->lo = lo; st->hi = hi;
+      ctl_zero(st);
+      if (hi - lo <= 1) {
+        st->code = fr ? lo : hi; st->done = 1; st->ncodes = 0;
+      } else {
+        int m = ctl_tree(lo, hi, C.depth, st->probe, 0);
+        for (int i = 0; i < m; i++) st->codes[i] = st->probe[i];
+        st->ncodes = m;
+      }
+      break;
+    }
+    case C_MASK: {  // histogram launch comes next: probe the chosen code
+      st->codes[0] = st->code; st->ncodes = 1;
+      for (int t = 0; t < 8; t++) st->hist[t] = 0;
+      ctl_zero(st);
+      break;
+    }
+    case C_CURVE: {  // after the histogram: stream mask, then the curve codes
+      uint64_t thresh = (C.nsub + 99) / 100;
+      if (thresh < 1) thresh = 1;
+      uint32_t mask = 0x81u;
+      for (int t = 0; t < 8; t++)
+        if (st->hist[t] >= thresh) mask |= 1u << t;
+      st->mask_out = mask & (C.mask_user | 0x81u);
+      for (int t = 0; t < NCURVE; t++) {
+        int ct = st->code + 4 * (t - NCURVE / 2);
+        ct = ct < C.cmin ? C.cmin : (ct > C.cmax ? C.cmax : ct);
+        st->codes[t] = ct;
+        st->curve_codes[t] = ct;
+      }
+      st->ncodes = NCURVE;
+      ctl_zero(st);
+      break;
+    }
+    case C_METRICS: {  // after the curve: keep it, set up the metrics pass
+      for (int t = 0; t < NCURVE; t++) {
+        st->curve_sums[t][0] = st->sums[t][S_XX];
+        st->curve_sums[t][1] = st->sums[t][S_YY];
+        st->curve_sums[t][2] = st->sums[t][S_DD];
+        st->curve_sums[t][3] = st->sums[t][S_DS];
+        st->curve_words[t] = st->words[t];
+      }
+      st->codes[0] = st->code; st->ncodes = 1;
+      st->maxbits[1] = 0;
+      ctl_zero(st);
+      break;
+    }
+    case C_MEANS: {  // after the metrics pass: keep it, means for the centred pass
+      for (int i = 0; i < NSUM; i++) st->msums[i] = st->sums[0][i];
+      st->mwords = st->words[0];
+      double n = (double)(C.nsamples ? C.nsamples : 1);
+      st->mean[0] = ldexp(st->sums[0][S_X], st->escale) / n;
+      st->mean[1] = ldexp(st->sums[0][S_Y], st->escale) / n;
+      st->mean[2] = ldexp(st->sums[0][S_D], st->escale) / n;
+      st->codes[0] = st->code; st->ncodes = 1;
+      break;
+    }
+  }
 }
 
 int64_t prof_tiles(const Geo& g, int64_t nbe) {
@@ -236,12 +455,15 @@ int64_t prof_tiles(const Geo& g, int64_t nbe) {
   return (nbe + per - 1) / per;
 }
 
-// persistent workgroups per code: enough to fill 256 CUs several times over
-int64_t prof_wgs(int64_t ntiles) { return ntiles < 2048 ? ntiles : 2048; }
+// persistent workgroups per code: about 2048 in flight over all codes
+int64_t prof_wgs(int64_t ntiles, int ncodes) {
+  int64_t w = (2048 + ncodes - 1) / ncodes;
+  return ntiles < w ? ntiles : w;
+}
 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL((k_profile<T, LPB, NDIM>), dim3((unsigned)A.nwg, A.ncodes), dim3(WPG * 64),
+  hipLaunchKernelGGL((k_profile<T, LPB, NDIM>), dim3((unsigned)A.nwg, A.maxcodes), dim3(WPG * 64),
                      0, s, A);
   return hipGetLastError();
 }
@@ -262,7 +484,7 @@ static hipError_t launch_nd(const ProfArgs& A, int ndim, hipStream_t s) {
 
 hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
   A.ntiles = prof_tiles(A.g, A.nbe);
-  A.nwg = prof_wgs(A.ntiles);
+  A.nwg = prof_wgs(A.ntiles, A.maxcodes);
   if (A.ntiles == 0) return hipSuccess;
   switch (dtype) {
     case DT_I8: return launch_nd<int8_t>(A, ndim, s);
@@ -273,11 +495,29 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
   }
 }
 
-hipError_t launch_finalize(const float* partials, int64_t nwg, int ncodes, double* out,
+hipError_t launch_finalize(const float* partials, int64_t nwg, int maxcodes, PState* st,
                            hipStream_t s) {
   if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)(ncodes * NSUM)), dim3(256), 0, s, partials,
-                     nwg, out);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)(maxcodes * NSUM)), dim3(256), 0, s, partials,
+                     nwg, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pmax(int dtype, const void* x, uint64_t n, PState* st, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  unsigned grid = 2048;
+  switch (dtype) {
+    case DT_I8: hipLaunchKernelGGL(k_pmax<int8_t>, dim3(grid), dim3(256), 0, s, (const int8_t*)x, n, st); break;
+    case DT_I16: hipLaunchKernelGGL(k_pmax<int16_t>, dim3(grid), dim3(256), 0, s, (const int16_t*)x, n, st); break;
+    case DT_I32: hipLaunchKernelGGL(k_pmax<int32_t>, dim3(grid), dim3(256), 0, s, (const int32_t*)x, n, st); break;
+    case DT_F32: hipLaunchKernelGGL(k_pmax<float>, dim3(grid), dim3(256), 0, s, (const float*)x, n, st); break;
+    default: hipLaunchKernelGGL(k_pmax<double>, dim3(grid), dim3(256), 0, s, (const double*)x, n, st); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl(const CtlArgs& C, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl, dim3(1), dim3(64), 0, s, C);
   return hipGetLastError();
 }
 
