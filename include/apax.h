@@ -151,6 +151,50 @@ int apax_status(const void* d_ws, hipStream_t stream);
 
 const char* apax_strerror(int code);
 
+/* ------------------------------------------------------------------------
+ * Batches: many arrays (any sizes, dtypes, modes, ndim) encoded or decoded by
+ * one persistent kernel launch per block-shape class (one launch when every
+ * item has the same ndim and a block of 129..256 samples), optionally
+ * replayed as a hipGraph.  Each item's output is byte-identical to a
+ * separate apax_encode / apax_decode call.  Launch geometry (waves per
+ * workgroup, persistent workgroups per CU, tiles taken per work-queue
+ * ticket) never changes any output; an autotuner chooses it. */
+enum { APAX_OP_ENCODE = 0, APAX_OP_DECODE = 1 };
+
+typedef struct apax_batch_item {
+  apax_params p;        /* encode: the array's parameters; decode: ignored (from h_hdr) */
+  const void* d_in;     /* encode: input array; decode: input stream (device) */
+  void* d_out;          /* encode: stream buffer; decode: output array (device) */
+  uint64_t in_bytes;    /* decode: stream length in bytes */
+  uint64_t cap;         /* bytes available at d_out */
+  uint64_t* d_nbytes;   /* encode: device uint64 receiving the stream length */
+  const void* h_hdr;    /* decode: host copy of the stream's 64-byte header */
+} apax_batch_item;
+
+typedef struct apax_tune {
+  uint32_t waves_per_wg;     /* 2, 4 or 8 (0 = 4) */
+  uint32_t wgs_per_cu;       /* persistent workgroups per compute unit (0 = 8) */
+  uint32_t tiles_per_ticket; /* tiles taken per atomic ticket (0 = 1) */
+  uint32_t reserved;
+} apax_tune;
+
+typedef struct apax_batch apax_batch; /* opaque host-side plan */
+
+/* Validate n host-side items and build a plan; *ws_bytes receives the
+ * workspace size the plan needs.  Items are copied; their buffers must stay
+ * valid while the plan is used.  Errors name the first bad item's code. */
+int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const apax_tune* tune,
+                      apax_batch** out, uint64_t* ws_bytes);
+/* Copy the plan's descriptor tables into the workspace (synchronous). */
+int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+/* Enqueue the whole batch (work-queue reset + persistent kernels). */
+int apax_batch_run(apax_batch* b, hipStream_t stream);
+/* Record apax_batch_run into a hipGraph (on a private capture stream). */
+int apax_batch_capture(apax_batch* b);
+/* Replay the captured graph on stream (apax_batch_run if none was captured). */
+int apax_batch_launch(apax_batch* b, hipStream_t stream);
+void apax_batch_destroy(apax_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,20 @@ class ProfileResult(C.Structure):
                 ("curve", CurvePoint * NCURVE), ("m", Metrics)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("p", Params), ("d_in", C.c_void_p), ("d_out", C.c_void_p),
+                ("in_bytes", C.c_uint64), ("cap", C.c_uint64), ("d_nbytes", C.c_void_p),
+                ("h_hdr", C.c_void_p)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("waves_per_wg", C.c_uint32), ("wgs_per_cu", C.c_uint32),
+                ("tiles_per_ticket", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+OP_ENCODE, OP_DECODE = 0, 1
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -80,6 +94,13 @@ def _load():
     L.apax_stream_info.argtypes = [vp, u64, P(Params)]
     L.apax_status_clear.argtypes = [vp, vp]
     L.apax_status.argtypes = [vp, vp]
+    L.apax_batch_create.argtypes = [C.c_int, P(BatchItem), C.c_uint32, P(Tune), P(vp), P(u64)]
+    L.apax_batch_upload.argtypes = [vp, vp, u64, vp]
+    L.apax_batch_run.argtypes = [vp, vp]
+    L.apax_batch_capture.argtypes = [vp]
+    L.apax_batch_launch.argtypes = [vp, vp]
+    L.apax_batch_destroy.argtypes = [vp]
+    L.apax_batch_destroy.restype = None
     L.apax_strerror.argtypes = [C.c_int]
     L.apax_strerror.restype = C.c_char_p
     return L
@@ -240,3 +261,119 @@ def apax_decode(stream_buf: torch.Tensor, nbytes: int | None = None, hdr: bytes 
                            y.numel() * y.element_size(), _dev_ptr(ws), ws.numel(), sp),
            "apax_decode")
     return y
+
+
+# ---------------------------------------------------------------- batches
+
+def apax_batch_create(op: int, items, tune: dict | None = None):
+    """Plan for a list of BatchItem; returns (handle, workspace bytes)."""
+    arr = (BatchItem * max(1, len(items)))(*items)
+    t = Tune()
+    for k, v in (tune or {}).items():
+        setattr(t, k, int(v))
+    h = C.c_void_p()
+    nb = C.c_uint64()
+    _check(lib.apax_batch_create(int(op), arr, len(items), C.byref(t), C.byref(h), C.byref(nb)),
+           "apax_batch_create")
+    return h, nb.value
+
+
+def apax_batch_upload(h, ws: torch.Tensor, stream=None):
+    _check(lib.apax_batch_upload(h, _dev_ptr(ws), ws.numel(), _stream_ptr(stream)),
+           "apax_batch_upload")
+
+
+def apax_batch_run(h, stream=None):
+    _check(lib.apax_batch_run(h, _stream_ptr(stream)), "apax_batch_run")
+
+
+def apax_batch_capture(h):
+    _check(lib.apax_batch_capture(h), "apax_batch_capture")
+
+
+def apax_batch_launch(h, stream=None):
+    _check(lib.apax_batch_launch(h, _stream_ptr(stream)), "apax_batch_launch")
+
+
+def apax_batch_destroy(h):
+    lib.apax_batch_destroy(h)
+
+
+class Batch:
+    """Encode (or decode) many device arrays with one persistent launch.
+
+    encode: Batch.encode([(tensor, params), ...]) -> outputs in .outs /
+            .nbytes (device int64 per item);
+    decode: Batch.decode([(stream_buffer, nbytes, header_bytes), ...]).
+    run() enqueues the batch, capture() records it as a hipGraph, launch()
+    replays it.  tune: dict of Tune fields (launch geometry only)."""
+
+    def __init__(self, op, items, keep, outs, nbytes, tune=None, device="cuda"):
+        self.op = op
+        self._keep = keep
+        self.outs = outs
+        self.nbytes = nbytes
+        self.handle, wsb = apax_batch_create(op, items, tune)
+        self.ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=device)
+        apax_batch_upload(self.handle, self.ws)
+
+    @classmethod
+    def encode(cls, arrays, tune=None, device="cuda"):
+        items, keep, outs = [], [], []
+        nbytes = torch.empty(max(1, len(arrays)), dtype=torch.int64, device=device)
+        for i, (x, params) in enumerate(arrays):
+            assert x.is_cuda and x.is_contiguous()
+            p = make_params(x.dtype, tuple(x.shape), params)
+            bound = apax_encode_bound(x.dtype, tuple(x.shape), params)
+            out = torch.empty(max(bound, 64), dtype=torch.uint8, device=device)
+            it = BatchItem()
+            it.p = p
+            it.d_in = x.data_ptr() if x.numel() else None
+            it.d_out = out.data_ptr()
+            it.cap = out.numel()
+            it.d_nbytes = nbytes.data_ptr() + 8 * i
+            items.append(it)
+            keep.append(x)
+            outs.append(out)
+        return cls(OP_ENCODE, items, keep, outs, nbytes, tune, device)
+
+    @classmethod
+    def decode(cls, streams, tune=None, device="cuda"):
+        items, keep, outs = [], [], []
+        for buf, n, hdr in streams:
+            info = apax_stream_info(hdr)
+            y = torch.empty(info["shape"], dtype=info["dtype"], device=device)
+            hb = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
+            it = BatchItem()
+            it.d_in = buf.data_ptr()
+            it.d_out = y.data_ptr() if y.numel() else None
+            it.in_bytes = int(n)
+            it.cap = y.numel() * y.element_size()
+            it.h_hdr = C.cast(hb, C.c_void_p)
+            items.append(it)
+            keep += [buf, hb]
+            outs.append(y)
+        return cls(OP_DECODE, items, keep, outs, None, tune, device)
+
+    def run(self, stream=None):
+        apax_batch_run(self.handle, stream)
+
+    def capture(self):
+        apax_batch_capture(self.handle)
+
+    def launch(self, stream=None):
+        apax_batch_launch(self.handle, stream)
+
+    def status(self, stream=None) -> int:
+        return apax_status(self.ws, stream)
+
+    def close(self):
+        if self.handle:
+            apax_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

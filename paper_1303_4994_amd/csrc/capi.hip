@@ -211,7 +211,30 @@ uint64_t block_valid(const HG& h, int64_t j) {
   return (uint64_t)(ex * ey * ez);
 }
 
+// ---- batch plans
+struct BatchClass {
+  int lpb, ndim;
+  std::vector<uint32_t> items;  // indices into the plan's items
+  int64_t total_tiles = 0;
+  int maxldsw = 0;
+  uint64_t items_off = 0, starts_off = 0, tstate_off = 0, ticket_off = 0;
+  int grid = 0;
+};
+
 }  // namespace
+
+struct apax_batch {
+  int op = 0;
+  apax_tune tune{};
+  std::vector<apax_batch_item> items;
+  std::vector<HG> geo;
+  std::vector<BatchClass> classes;
+  uint64_t ws_bytes = 0;
+  void* d_ws = nullptr;
+  std::vector<uint8_t> tables;  // host image of [descriptors | starts] of every class
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 // ======================================================================== C ABI
 
@@ -537,6 +560,224 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     m.std_d = sqrt(unscale(hs.sums[0][S_CDD], S_CDD) / nn);
   }
   return APAX_OK;
+}
+
+static int batch_error(int e, uint32_t i) { (void)i; return e; }
+
+int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const apax_tune* tune,
+                      apax_batch** out, uint64_t* ws_bytes) {
+  if (!out || !ws_bytes || (n && !h_items) || (op != APAX_OP_ENCODE && op != APAX_OP_DECODE))
+    return APAX_E_INVALID;
+  *out = nullptr;
+  apax_tune t = tune ? *tune : apax_tune{};
+  if (t.waves_per_wg == 0) t.waves_per_wg = 4;
+  if (t.wgs_per_cu == 0) t.wgs_per_cu = 8;
+  if (t.tiles_per_ticket == 0) t.tiles_per_ticket = 1;
+  if ((t.waves_per_wg != 2 && t.waves_per_wg != 4 && t.waves_per_wg != 8) || t.wgs_per_cu > 64 ||
+      t.tiles_per_ticket > 64)
+    return APAX_E_INVALID;
+  apax_batch* b = new apax_batch();
+  b->op = op;
+  b->tune = t;
+  b->items.assign(h_items, h_items + n);
+  b->geo.resize(n);
+  for (uint32_t i = 0; i < n; i++) {
+    const apax_batch_item& it = h_items[i];
+    HG& h = b->geo[i];
+    int e;
+    if (op == APAX_OP_ENCODE) {
+      if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
+      if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
+        delete b;
+        return batch_error(APAX_E_INVALID, i);
+      }
+      if (it.cap < bound_of(h)) { delete b; return batch_error(APAX_E_CAPACITY, i); }
+    } else {
+      apax_params q;
+      if (!it.h_hdr || (e = apax_stream_info(it.h_hdr, 64, &q))) { delete b; return batch_error(APAX_E_CORRUPT, i); }
+      uint16_t budget;
+      memcpy(&budget, (const uint8_t*)it.h_hdr + 10, 2);
+      if ((e = setup(&q, h, q.mode == APAX_FIXED_RATE ? budget : -1))) { delete b; return batch_error(e, i); }
+      uint64_t pw;
+      memcpy(&pw, (const uint8_t*)it.h_hdr + 56, 8);
+      uint64_t area = area_offset(h);
+      if (!it.d_in || ((uintptr_t)it.d_in & 15) || (!it.d_out && h.nsamples)) { delete b; return batch_error(APAX_E_INVALID, i); }
+      if (it.in_bytes < area || (it.in_bytes - area) / 4 < pw) { delete b; return batch_error(APAX_E_CORRUPT, i); }
+      if (h.mode == APAX_FIXED_RATE && pw != (uint64_t)h.g.budget * (uint64_t)h.g.nblocks) { delete b; return batch_error(APAX_E_CORRUPT, i); }
+      if (it.cap < h.nsamples * (uint64_t)h.esz) { delete b; return batch_error(APAX_E_CAPACITY, i); }
+    }
+    int lpb = lpb_of(h.g);
+    BatchClass* c = nullptr;
+    for (auto& k : b->classes)
+      if (k.lpb == lpb && k.ndim == h.ndim) c = &k;
+    if (!c) {
+      b->classes.push_back(BatchClass{});
+      c = &b->classes.back();
+      c->lpb = lpb;
+      c->ndim = h.ndim;
+    }
+    c->items.push_back(i);
+    c->total_tiles += std::max<int64_t>(1, encode_tiles_wp(h.g, (int)t.waves_per_wg));
+    c->maxldsw = std::max(c->maxldsw, h.g.ldsw);
+  }
+  int dev = 0, ncu = 256;
+  if (hipGetDevice(&dev) == hipSuccess)
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t desc = op == APAX_OP_ENCODE ? sizeof(BatchEnc) : sizeof(BatchDec);
+  uint64_t off = al256(sizeof(PState));
+  uint64_t tab = 0;
+  for (auto& c : b->classes) {
+    c.items_off = tab;
+    tab += al256(desc * c.items.size());
+    c.starts_off = tab;
+    tab += al256(8 * c.items.size());
+  }
+  b->tables.assign(tab, 0);
+  uint64_t tables_off = off;
+  off += tab;
+  for (auto& c : b->classes) {
+    c.ticket_off = off;
+    off += 256;
+    c.tstate_off = off;
+    off += al256(8 * (uint64_t)c.total_tiles);
+    int64_t g = (int64_t)ncu * t.wgs_per_cu;
+    c.grid = (int)std::min<int64_t>(std::max<int64_t>(1, c.total_tiles), g);
+    c.items_off += tables_off;
+    c.starts_off += tables_off;
+  }
+  b->ws_bytes = off;
+  *ws_bytes = off;
+  *out = b;
+  return APAX_OK;
+}
+
+int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!b || !d_ws || ((uintptr_t)d_ws & 255)) return APAX_E_INVALID;
+  if (ws_bytes < b->ws_bytes) return APAX_E_CAPACITY;
+  b->d_ws = d_ws;
+  uint8_t* ws = (uint8_t*)d_ws;
+  const uint64_t tables_off = al256(sizeof(PState));
+  const int wp = (int)b->tune.waves_per_wg;
+  for (auto& c : b->classes) {
+    int64_t start = 0;
+    for (size_t k = 0; k < c.items.size(); k++) {
+      const uint32_t i = c.items[k];
+      const apax_batch_item& it = b->items[i];
+      const HG& h = b->geo[i];
+      int64_t nt = std::max<int64_t>(1, encode_tiles_wp(h.g, wp));
+      uint8_t* dst = b->tables.data() + (c.items_off - tables_off) + k * (b->op == APAX_OP_ENCODE ? sizeof(BatchEnc) : sizeof(BatchDec));
+      if (b->op == APAX_OP_ENCODE) {
+        BatchEnc E;
+        memset(&E, 0, sizeof(E));
+        E.dtype = h.dtype;
+        E.ndim = h.ndim;
+        E.tile_start = start;
+        EncArgs& A = E.a;
+        A.g = h.g;
+        A.x = it.d_in;
+        A.out_base = (uint8_t*)it.d_out;
+        A.area = area_offset(h);
+        A.out_words = (uint32_t*)((uint8_t*)it.d_out + A.area);
+        A.lens = (uint16_t*)((uint8_t*)it.d_out + 64);
+        A.sbo = (uint64_t*)((uint8_t*)it.d_out + 64 + lens_bytes(h));
+        A.d_nbytes = it.d_nbytes;
+        A.status = &((PState*)d_ws)->status;
+        A.ticket = nullptr;
+        A.tile_state = (uint64_t*)(ws + c.tstate_off) + start;
+        A.ntiles = nt;
+        make_header(&it.p, h, A.hdr);
+        if (h.mode != APAX_FIXED_RATE) {
+          A.zpad[0] = 64 + 2 * (uint64_t)h.g.nblocks;
+          A.zpad[1] = 64 + lens_bytes(h);
+          A.zpad[2] = 64 + lens_bytes(h) + 8 * sbo_count(h);
+          A.zpad[3] = A.area;
+        }
+        memcpy(dst, &E, sizeof(E));
+      } else {
+        BatchDec D;
+        memset(&D, 0, sizeof(D));
+        D.dtype = h.dtype;
+        D.ndim = h.ndim;
+        D.tile_start = start;
+        DecArgs& A = D.a;
+        A.g = h.g;
+        uint64_t area = area_offset(h);
+        A.in = (const uint8_t*)it.d_in;
+        A.words = (const uint32_t*)((const uint8_t*)it.d_in + area);
+        A.lens = (const uint16_t*)((const uint8_t*)it.d_in + 64);
+        A.sbo = (const uint64_t*)((const uint8_t*)it.d_in + 64 + lens_bytes(h));
+        A.y = it.d_out;
+        A.status = &((PState*)d_ws)->status;
+        memcpy(&A.payload_words, (const uint8_t*)it.h_hdr + 56, 8);
+        A.ntiles = nt;
+        memcpy(A.hdr, it.h_hdr, 64);
+        memcpy(dst, &D, sizeof(D));
+      }
+      memcpy(b->tables.data() + (c.starts_off - tables_off) + 8 * k, &start, 8);
+      start += nt;
+    }
+  }
+  if (!b->tables.empty() &&
+      hipMemcpyAsync(ws + tables_off, b->tables.data(), b->tables.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return APAX_E_HIP;
+  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, 1);
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  return APAX_OK;
+}
+
+int apax_batch_run(apax_batch* b, hipStream_t stream) {
+  if (!b || !b->d_ws) return APAX_E_INVALID;
+  uint8_t* ws = (uint8_t*)b->d_ws;
+  const int wp = (int)b->tune.waves_per_wg;
+  for (auto& c : b->classes) {
+    BatchArgs B;
+    memset(&B, 0, sizeof(B));
+    B.items = ws + c.items_off;
+    B.starts = (const int64_t*)(ws + c.starts_off);
+    B.ticket = (uint32_t*)(ws + c.ticket_off);
+    B.tile_state = (uint64_t*)(ws + c.tstate_off);
+    B.total_tiles = c.total_tiles;
+    B.n = (uint32_t)c.items.size();
+    B.tiles_per_ticket = b->tune.tiles_per_ticket;
+    int e = hip_err(launch_batch_reset(B.ticket, B.tile_state, b->op == APAX_OP_ENCODE ? c.total_tiles : 0, stream));
+    if (e) return e;
+    size_t lds = (size_t)wp * (64 / c.lpb) * (size_t)c.maxldsw * 4;
+    if (b->op == APAX_OP_ENCODE) e = hip_err(launch_encode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
+    else e = hip_err(launch_decode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
+    if (e) return e;
+  }
+  return APAX_OK;
+}
+
+int apax_batch_capture(apax_batch* b) {
+  if (!b || !b->d_ws) return APAX_E_INVALID;
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return APAX_E_HIP;
+  int e = APAX_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) e = APAX_E_HIP;
+  if (!e) {
+    int e2 = apax_batch_run(b, cs);
+    if (hipStreamEndCapture(cs, &b->graph) != hipSuccess) e2 = APAX_E_HIP;
+    e = e2;
+  }
+  if (!e && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) e = APAX_E_HIP;
+  hipStreamDestroy(cs);
+  return e;
+}
+
+int apax_batch_launch(apax_batch* b, hipStream_t stream) {
+  if (!b) return APAX_E_INVALID;
+  if (!b->exec) return apax_batch_run(b, stream);
+  return hipGraphLaunch(b->exec, stream) == hipSuccess ? APAX_OK : APAX_E_HIP;
+}
+
+void apax_batch_destroy(apax_batch* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  delete b;
 }
 
 }  // extern "C"

@@ -1,369 +1,21 @@
-// decode.hip -- APAX decoder kernel for gfx950.
-//
-// Same lane layout as the encoder: one wave segment per block, lane gi owns
-// group gi.  Per block: offset from the block-length index (superblock offset
-// + segmented sum of up to 63 lengths), block words staged in LDS, header
-// checked, JEE tokens parsed in parallel -- a nibble is the low half of an
-// 8-bit token exactly when it follows an escape nibble that itself starts a
-// token, and inside a run of escape-valued nibbles starts alternate, so the
-// token starts follow from the same run-parity bit arithmetic as on encode;
-// token coverage prefix sums place each exponent difference at its group,
-// a segmented scan rebuilds the exponents, an exclusive scan of payload
-// widths gives every group's bit offset, values are extracted with 64-bit
-// funnel shifts, running sums along x/y/z undo the derivative stream, and
-// the dequantizer restores the samples.
-#include "block.h"
-#include "kernels.h"
+// decode.hip -- single-array APAX decoder kernel for gfx950 (one workgroup
+// per tile; the tile body is in decode_tile.h).
+#include "decode_tile.h"
 
 namespace apax {
 
-// token-start mask of a nibble sequence (lo = first 64 nibbles, hi = next
-// 64); esc marks nibbles with value >= 14.  Returns the "low half" mask.
-__device__ __forceinline__ void low_half_mask(uint64_t elo, uint64_t ehi, uint64_t& llo,
-                                              uint64_t& lhi) {
-  const uint64_t EV = 0x5555555555555555ull;
-  // run starts st = M & ~(M << 1) (128-bit shift)
-  uint64_t shl_lo = elo << 1, shl_hi = (ehi << 1) | (elo >> 63);
-  uint64_t st_lo = elo & ~shl_lo, st_hi = ehi & ~shl_hi;
-  uint64_t t_lo = st_lo & EV, t_hi = st_hi & EV;
-  // M + t, 128-bit
-  uint64_t s_lo = elo + t_lo;
-  uint64_t carry = s_lo < elo ? 1ull : 0ull;
-  uint64_t s_hi = ehi + t_hi + carry;
-  uint64_t rodd_lo = s_lo & elo, rodd_hi = s_hi & ehi;
-  uint64_t rev_lo = elo & ~rodd_lo, rev_hi = ehi & ~rodd_hi;
-  uint64_t se_lo = (rev_lo & EV) | (rodd_lo & ~EV);
-  uint64_t se_hi = (rev_hi & EV) | (rodd_hi & ~EV);
-  llo = se_lo << 1;
-  lhi = (se_hi << 1) | (se_lo >> 63);
-}
-
-template <int LPB>
-__device__ __forceinline__ int32_t seg_shfl(int32_t v, int src) {
-  return __shfl(v, src, LPB);
-}
-
-template <typename T>
-__device__ __forceinline__ void store4(T* __restrict__ y, int64_t idx, int nvalid, const T v[4]) {
-  if (nvalid <= 0) return;
-  T* p = y + idx;
-  bool aligned = (((uintptr_t)p) & (4 * sizeof(T) - 1)) == 0;
-  if (nvalid == 4 && aligned) {
-    if constexpr (sizeof(T) == 4) {
-      uint4 u;
-      u.x = __builtin_bit_cast(uint32_t, v[0]);
-      u.y = __builtin_bit_cast(uint32_t, v[1]);
-      u.z = __builtin_bit_cast(uint32_t, v[2]);
-      u.w = __builtin_bit_cast(uint32_t, v[3]);
-      *reinterpret_cast<uint4*>(p) = u;
-    } else if constexpr (sizeof(T) == 8) {
-      uint64_t w[4];
-#pragma unroll
-      for (int k = 0; k < 4; k++) w[k] = __builtin_bit_cast(uint64_t, v[k]);
-      uint4 u0, u1;
-      u0.x = (uint32_t)w[0]; u0.y = (uint32_t)(w[0] >> 32); u0.z = (uint32_t)w[1]; u0.w = (uint32_t)(w[1] >> 32);
-      u1.x = (uint32_t)w[2]; u1.y = (uint32_t)(w[2] >> 32); u1.z = (uint32_t)w[3]; u1.w = (uint32_t)(w[3] >> 32);
-      uint4* q = reinterpret_cast<uint4*>(p);
-      q[0] = u0;
-      q[1] = u1;
-    } else if constexpr (sizeof(T) == 2) {
-      uint2 u;
-      u.x = (uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16);
-      u.y = (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16);
-      *reinterpret_cast<uint2*>(p) = u;
-    } else {
-      uint32_t u = 0;
-#pragma unroll
-      for (int k = 0; k < 4; k++) u |= (uint32_t)(uint8_t)v[k] << (8 * k);
-      *reinterpret_cast<uint32_t*>(p) = u;
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (k < nvalid) p[k] = v[k];
-  }
-}
-
-template <int LPB>
-__device__ __forceinline__ void sum_x(uint32_t r[4], int xq, int rowq) {
-  r[1] += r[0];
-  r[2] += r[1];
-  r[3] += r[2];
-  uint32_t t = r[3], inc = t;
-#pragma unroll
-  for (int o = 1; o < LPB; o <<= 1) {
-    uint32_t u = (uint32_t)up<LPB>((int32_t)inc, o);
-    if (o < rowq && xq >= o) inc += u;
-  }
-  uint32_t ex = inc - t;
-#pragma unroll
-  for (int k = 0; k < 4; k++) r[k] += ex;
-}
-
-template <int LPB>
-__device__ __forceinline__ void sum_axis(uint32_t r[4], int coord, int extent, int lanestep) {
-#pragma unroll
-  for (int o = 1; o < LPB; o <<= 1) {
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      uint32_t u = (uint32_t)up<LPB>((int32_t)r[k], o * lanestep);
-      if (o < extent && coord >= o) r[k] += u;
-    }
-  }
-}
-
-template <typename T, int LPB, int NDIM>
-__global__ __launch_bounds__(256) void k_decode(DecArgs A) {
-  constexpr int BPW = 64 / LPB;
-  constexpr int H = Traits<T>::H;
-  constexpr int W = Traits<T>::W;
-  constexpr int MAXEPS = W == 32 ? 31 : W;
-  const Geo& g = A.g;
+template <typename T, int LPB, int NDIM, int WP>
+__global__ __launch_bounds__(WP * 64) void k_decode(DecArgs A) {
   extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int32_t s_info[WPG * 64];
-  __shared__ int32_t s_end[WPG * 4];
-
-  const int wave = threadIdx.x >> 6;
-  const int lane = lane_id();
-  const LaneMap<LPB> L = lane_map<LPB>(g);
-  const int seg = L.seg, gi = L.gi;
-  const int64_t j = ((int64_t)blockIdx.x * WPG + wave) * BPW + seg;
-  const bool blk_ok = j < g.nblocks;
-  const bool act = blk_ok && gi < g.G;
-  const bool variable = g.mode != M_RATE;
-  bool bad = false;
-
-  if (blockIdx.x == 0 && threadIdx.x < 16) {
-    const uint32_t* h = reinterpret_cast<const uint32_t*>(A.in);
-    if (h[threadIdx.x] != A.hdr[threadIdx.x]) atomicOr(A.status, ST_CORRUPT);
-  }
-
-  // ---- block offset and length
-  uint64_t off = 0;
-  int len = 0;
-  if (variable) {
-    int64_t jb = (j >> 6) << 6;
-    int acc = 0;
-    if (blk_ok)
-      for (int64_t r = jb + gi; r < j; r += LPB) acc += A.lens[r];
-    acc = seg_sum<LPB>(acc);
-    if (blk_ok) {
-      off = A.sbo[j >> 6] + (uint64_t)acc;
-      len = A.lens[j];
-    }
-  } else if (blk_ok) {
-    off = (uint64_t)j * (uint64_t)g.budget;
-    len = g.budget;
-  }
-  if (blk_ok && (len < 1 || (variable && len > g.maxw) || off + (uint64_t)len > A.payload_words)) {
-    bad = true;
-    len = 0;
-  }
-
-  // ---- stage block words in LDS
-  const int stride = g.ldsw;
-  uint32_t* buf = lds + (wave * BPW + seg) * stride;
-  for (int w = gi; w < stride; w += LPB) buf[w] = w < len ? A.words[off + w] : 0u;
-  // words past the LDS buffer (fixed rate with a budget above any encoding)
-  // can only be padding
-  for (int w = stride + gi; w < len; w += LPB)
-    if (A.words[off + w]) bad = true;
-  if (gi < 64 / BPW) s_info[wave * 64 + seg * LPB + gi] = 0;
-  if (gi == 0) s_end[wave * BPW + seg] = -1;
-  __syncthreads();
-
-  // ---- block header
-  const uint32_t w0 = buf[0], w1 = buf[1];
-  const int st = (int)(w0 & 7u);
-  const int e0 = (int)((w0 >> 3) & 31u);
-  int c;
-  uint32_t rsv;
-  if constexpr (H == 32) {
-    c = ((int32_t)(w0 << 14)) >> 22;
-    rsv = w0 >> 18;
-  } else {
-    c = (int32_t)(int16_t)(uint16_t)((w0 >> 8) & 0xFFFFu);
-    rsv = (w0 >> 24) | (w1 & 0xFFFFu);
-  }
-  const bool verb = st == 7;
-  if (blk_ok) {
-    bad |= rsv != 0u;
-    bad |= !((g.mask >> st) & 1u);
-    bad |= g.mode == M_LOSSLESS ? (c != 0) : (c < g.cmin || c > g.cmax);
-    bad |= 32 * len < H;
-    if (verb) bad |= e0 != 0 || 32 * len < H + g.B * W;
-    else bad |= e0 > MAXEPS;
-  }
-
-  // ---- JEE token parse (nibbles gi and LPB + gi of the token section)
-  auto nib_at = [&](int n) -> int {
-    int bit = H + 4 * n;
-    int w = bit >> 5;
-    if (w >= stride) return 0;
-    return (int)((buf[w] >> (bit & 31)) & 15u);
-  };
-  const bool tk = act && !verb;
-  const int nb0 = nib_at(gi), nb1 = nib_at(LPB + gi);
-  const uint64_t E0 = __ballot(tk && nb0 >= 14), E1 = __ballot(tk && nb1 >= 14);
-  uint64_t slo, shi;
-  if constexpr (LPB == 64) {
-    slo = E0;
-    shi = E1;
-  } else {
-    const uint64_t msk = (1ull << LPB) - 1ull;
-    slo = ((E0 >> (LPB * seg)) & msk) | (((E1 >> (LPB * seg)) & msk) << LPB);
-    shi = 0;
-  }
-  uint64_t llo, lhi;
-  low_half_mask(slo, shi, llo, lhi);
-  bool low0, low1;
-  if constexpr (LPB == 64) {
-    low0 = (llo >> gi) & 1;
-    low1 = (lhi >> gi) & 1;
-  } else {
-    low0 = (llo >> gi) & 1;
-    low1 = (llo >> (LPB + gi)) & 1;
-  }
-  const bool s0 = tk && !low0, s1 = tk && !low1;
-  const uint64_t P0 = __ballot(s0 && nb0 <= 8), Q0 = __ballot(s0 && nb0 >= 9);
-  const uint64_t P1 = __ballot(s1 && nb1 <= 8), Q1 = __ballot(s1 && nb1 >= 9);
-  const uint64_t sbm = seg_bits<LPB>(seg);
-  const int cov0 = 2 * below_in_seg<LPB>(P0, seg) + below_in_seg<LPB>(Q0, seg);
-  const int cov1 = 2 * (__popcll(P0 & sbm) + below_in_seg<LPB>(P1, seg)) +
-                   (__popcll(Q0 & sbm) + below_in_seg<LPB>(Q1, seg));
-  // low nibble following each position
-  const int nxt0_a = dn<LPB>(nb0, 1), nxt0_b = seg_shfl<LPB>(nb1, 0);
-  const int nxt0 = gi < LPB - 1 ? nxt0_a : nxt0_b;
-  const int nxt1 = dn<LPB>(nb1, 1);
-  int32_t* info = s_info + wave * 64 + seg * LPB;
-  const int G = g.G;
-  bool tbad = false;
-  auto place = [&](bool s, int v, int cov, int nxt, int n) {
-    if (!s) return;
-    int g0 = 1 + cov;
-    if (g0 > G - 1) return;
-    int end;
-    if (v <= 8) {
-      if (g0 + 1 > G - 1) { tbad = true; return; }
-      info[g0] = (1 << 8) | ((v / 3 - 1) & 0xFF);
-      info[g0 + 1] = (1 << 8) | ((v % 3 - 1) & 0xFF);
-      end = n + 1;
-      if (g0 + 1 == G - 1) s_end[wave * BPW + seg] = end;
-    } else if (v <= 13) {
-      info[g0] = (1 << 8) | ((v - 11) & 0xFF);
-      end = n + 1;
-      if (g0 == G - 1) s_end[wave * BPW + seg] = end;
-    } else {
-      if (n + 1 >= 2 * LPB) { tbad = true; return; }
-      info[g0] = (2 << 8) | (16 * (v - 14) + nxt);
-      end = n + 2;
-      if (g0 == G - 1) s_end[wave * BPW + seg] = end;
-    }
-  };
-  place(s0, nb0, cov0, nxt0, gi);
-  place(s1, nb1, cov1, (gi < LPB - 1) ? nxt1 : 0, LPB + gi);
-  if (act && gi == 0) info[0] = (2 << 8) | e0;
-  bad |= tbad;
-  __syncthreads();
-
-  // ---- exponents: segmented scan (absolute tokens reset the running sum)
-  int32_t iv = act ? info[gi] : (2 << 8);
-  const int kind = iv >> 8;
-  if (act && !verb && kind == 0) bad = true;
-  int32_t f = kind == 2 ? 1 : 0;
-  int32_t x = kind == 2 ? (iv & 0xFF) : (int32_t)(int8_t)(iv & 0xFF);
-#pragma unroll
-  for (int o = 1; o < LPB; o <<= 1) {
-    int32_t fo = up<LPB>(f, o), xo = up<LPB>(x, o);
-    if (gi >= o && !f) {
-      x += xo;
-      f = fo;
-    }
-  }
-  int eps = x;
-  if (tk && (eps < 0 || eps > MAXEPS)) bad = true;
-  if (!tk) eps = 0;
-  const int pw = (W == 32 && eps == 31) ? 32 : eps;
-  const int tend = s_end[wave * BPW + seg];
-  if (blk_ok && !verb && tend < 0) bad = true;
-  const int pay0 = H + 4 * (tend < 0 ? 0 : tend);
-  const int pex = seg_excl_scan<LPB>(4 * pw, gi);
-  const int total = verb ? (H + g.B * W) : (pay0 + seg_sum<LPB>(4 * pw));
-  if (blk_ok && total > 32 * len) bad = true;
-
-  // ---- extract values
-  uint32_t r[4];
-#pragma unroll
-  for (int k = 0; k < 4; k++) {
-    int width = verb ? W : pw;
-    int bit = verb ? H + (4 * gi + k) * W : pay0 + pex + k * pw;
-    int w = bit >> 5;
-    w = w < 0 ? 0 : (w > stride - 2 ? stride - 2 : w);
-    uint64_t both = ((uint64_t)buf[w + 1] << 32) | buf[w];
-    uint32_t raw = (uint32_t)(both >> (bit & 31));
-    r[k] = width == 0 ? 0u : (width >= 32 ? raw : (uint32_t)(((int32_t)(raw << (32 - width))) >> (32 - width)));
-  }
-  // padding after the last used bit must be zero
-  if (blk_ok && total <= 32 * len) {
-    int wfirst = (total + 31) >> 5;
-    int wlast = len < stride ? len : stride;
-    for (int w = wfirst + gi; w < wlast; w += LPB)
-      if (buf[w]) bad = true;
-    if (gi == 0 && (total & 31) && (buf[total >> 5] >> (total & 31))) bad = true;
-  }
-
-  // ---- undo the derivative stream (running sums, mod 2^W)
-  {
-    uint32_t u[4] = {r[0], r[1], r[2], r[3]};
-    const bool dx1 = st == 1 || st == 2 || st == 5 || st == 6;
-    sum_x<LPB>(u, L.xq, g.rowq);
-#pragma unroll
-    for (int k = 0; k < 4; k++) r[k] = dx1 ? u[k] : r[k];
-#pragma unroll
-    for (int k = 0; k < 4; k++) u[k] = r[k];
-    sum_x<LPB>(u, L.xq, g.rowq);
-#pragma unroll
-    for (int k = 0; k < 4; k++) r[k] = st == 2 ? u[k] : r[k];
-    if constexpr (NDIM >= 2) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) u[k] = r[k];
-      sum_axis<LPB>(u, L.y, g.b[1], g.rowq);
-      const bool dy = st == 3 || st == 5 || st == 6;
-#pragma unroll
-      for (int k = 0; k < 4; k++) r[k] = dy ? u[k] : r[k];
-    }
-    if constexpr (NDIM == 3) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) u[k] = r[k];
-      sum_axis<LPB>(u, L.z, g.b[0], g.plane);
-      const bool dz = st == 4 || st == 6;
-#pragma unroll
-      for (int k = 0; k < 4; k++) r[k] = dz ? u[k] : r[k];
-    }
-  }
-
-  if (__ballot(bad) && lane == 0) atomicOr(A.status, ST_CORRUPT);
-
-  // ---- dequantize and store
-  if (act) {
-    int nvalid = 0;
-    int64_t idx = group_index<NDIM, LPB>(g, L, j, nvalid);
-    T out[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-      int32_t av = wrapw<W>(r[k]);
-      if (g.mode == M_LOSSLESS) out[k] = (T)av;
-      else out[k] = to_out<T>(dequant(av, c));
-    }
-    store4<T>((T*)A.y, idx, nvalid, out);
-  }
+  __shared__ DecShared<WP> sm;
+  decode_tile<T, LPB, NDIM, WP>(A, (int64_t)blockIdx.x, sm, lds);
 }
 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const DecArgs& A, hipStream_t s) {
   constexpr int BPW = 64 / LPB;
   size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
-  hipLaunchKernelGGL((k_decode<T, LPB, NDIM>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
+  hipLaunchKernelGGL((k_decode<T, LPB, NDIM, WPG>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
 }
 

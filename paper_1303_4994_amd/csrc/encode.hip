@@ -1,33 +1,9 @@
-// encode.hip -- APAX encoder kernel (Sec. 6) for gfx950.
-//
-// One workgroup = 4 wavefronts = one tile of 4 * (64/LPB) blocks.  Per block:
-// coalesced loads of its groups, block max -> code bracket, gain choice
-// (lossless: 0; fixed quality: clamp(c*); fixed rate: cap-and-descend
-// search), every candidate stream costed in registers, the cheapest emitted
-// into a zeroed LDS buffer with ds_or (header | JEE tokens | BFPE payload),
-// then copied out with coalesced word stores.  Fixed rate places block j at
-// j * budget words; variable-size modes place blocks with a single-pass
-// decoupled look-back over per-tile word counts (tiles taken in ticket
-// order, so every tile waited on is already resident).
-#include "block.h"
-#include "kernels.h"
+// encode.hip -- single-array APAX encoder kernel for gfx950: one workgroup
+// per tile; variable-size modes take tiles from an atomic ticket so tiles
+// start in order (the look-back in encode_tile.h relies on it).
+#include "encode_tile.h"
 
 namespace apax {
-
-__device__ __forceinline__ void or_bits(uint32_t* buf, int bitpos, uint32_t val, int len) {
-  if (len <= 0) return;
-  int w = bitpos >> 5, sh = bitpos & 31;
-  uint32_t lo = val << sh;
-  if (lo) atomicOr(&buf[w], lo);
-  if (sh && sh + len > 32) {
-    uint32_t hi = val >> (32 - sh);
-    if (hi) atomicOr(&buf[w + 1], hi);
-  }
-}
-
-__device__ __forceinline__ uint32_t low_bits(int32_t v, int n) {
-  return n >= 32 ? (uint32_t)v : ((uint32_t)v & ((1u << n) - 1u));
-}
 
 __global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64_t* tile_state,
                                int64_t ntiles) {
@@ -37,196 +13,14 @@ __global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64
   (void)status_unused;
 }
 
-template <typename T, int LPB, int NDIM>
-__global__ __launch_bounds__(256) void k_encode(EncArgs A) {
-  constexpr int BPW = 64 / LPB;
-  constexpr int H = Traits<T>::H;
-  constexpr int W = Traits<T>::W;
-  using B_ = Blk<T, LPB, NDIM>;
-  const Geo& g = A.g;
+template <typename T, int LPB, int NDIM, int WP>
+__global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
   extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ int64_t s_tile;
-  __shared__ uint32_t s_nw[WPG * 4];
-  __shared__ uint64_t s_off[WPG * 4];
-  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
-
-  const int wave = threadIdx.x >> 6;
-  const bool variable = g.mode != M_RATE;
-  if (threadIdx.x == 0) s_tile = variable ? (int64_t)atomicAdd(A.ticket, 1u) : (int64_t)blockIdx.x;
+  __shared__ EncShared<WP> sm;
+  if (threadIdx.x == 0)
+    sm.tile = A.g.mode != M_RATE ? (int64_t)atomicAdd(A.ticket, 1u) : (int64_t)blockIdx.x;
   __syncthreads();
-  const int64_t tile = s_tile;
-
-  B_ b;
-  const int lane = lane_id();
-  b.init(g, (tile * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
-  b.load((const T*)A.x, g);
-  if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
-
-  // ---- operating point and stream
-  int c = 0, st = 0;
-  int32_t a[4], v[7][4];
-  int eps[7], pw[7];
-  Costs C;
-  int32_t best;
-  if (g.mode == M_QUALITY) c = clampc(g.code, b.cf, b.cc);
-  else if (g.mode == M_RATE) c = clampc(g.code, b.cf, b.cc);
-  const uint32_t emask = g.mode == M_RATE ? (g.mask & 0x7Fu) : g.mask;
-  b.quantize(c, g.mode == M_LOSSLESS, a);
-  b.sizes(g, emask, a, v, eps, pw, C);
-  st = B_::argmin(C, emask, best);
-  if (g.mode == M_RATE) {
-    const bool need = b.act && best > 32 * g.budget;
-    if (__ballot(need)) {
-      // some block of this wave does not fit at its start code: search, then
-      // re-evaluate every block of the wave at its final code
-      c = b.rate_search(g, c, st, need);
-      b.quantize(c, false, a);
-      b.sizes(g, emask, a, v, eps, pw, C);
-      best = B_::size_sel(C, st);
-    }
-  }
-  const int nw = !b.blk_ok ? 0 : (g.mode == M_RATE ? g.budget : ((best + 31) >> 5));
-
-  // ---- emit into this segment's LDS buffer
-  const int seg = b.L.seg, gi = b.L.gi;
-  const int stride = g.ldsw;
-  uint32_t* buf = lds + (wave * BPW + seg) * stride;
-  for (int w = 4 * gi; w < stride; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
-  __syncthreads();
-
-  const bool verb = st == 7;
-  int32_t vv[4];
-  B_::select_stream(st, v, vv);
-  int e = B_::pick_int(st, eps);
-  int p = B_::pick_int(st, pw);
-  if (verb) { e = 0; p = 0; }
-
-  const int em1 = (int)shr1((uint32_t)e);
-  const int d = e - em1;
-  const bool pos = b.act && gi >= 1 && !verb;
-  const uint64_t m1 = __ballot(pos && (uint32_t)(d + 1) <= 2u);
-  const uint64_t m2 = __ballot(pos && (uint32_t)(d + 2) <= 4u);
-  const uint64_t vp = __ballot(pos);
-  const uint64_t Tm = jee_token_starts(m1);
-  const uint64_t starts = Tm | (~m1 & vp);
-  const uint64_t ab = ~m2 & vp;
-  const int dnext = (int)shl1((uint32_t)d);
-  const int ntot = seg_popc<LPB>(starts, seg) + seg_popc<LPB>(ab, seg);
-  const int pay0 = H + 4 * ntot;
-  const int pex = (int)seg_scan_add<LPB>((uint32_t)(4 * p)) - 4 * p;
-  if (b.act) {
-    if ((starts >> lane) & 1) {
-      int nib_off = below_in_seg<LPB>(starts, seg) + below_in_seg<LPB>(ab, seg);
-      bool pair = ((Tm >> lane) & 1) && lane < 63 && ((m1 >> (lane + 1)) & 1);
-      bool isabs = (ab >> lane) & 1;
-      uint32_t tok;
-      int len = 4;
-      if (pair) tok = (uint32_t)(3 * (d + 1) + (dnext + 1));
-      else if (isabs) { tok = (uint32_t)(14 + (e >> 4)) | ((uint32_t)(e & 15) << 4); len = 8; }
-      else tok = (uint32_t)(11 + d);
-      or_bits(buf, H + 4 * nib_off, tok, len);
-    }
-    if (!verb) {
-      // the group's 4 fields are contiguous: pack them into 128 bits, then
-      // OR the (up to 5) words they touch
-      if (p > 0) {
-        uint64_t m = p >= 32 ? 0xFFFFFFFFull : ((1ull << p) - 1ull);
-        uint64_t lo = ((uint64_t)(uint32_t)vv[0] & m) | (((uint64_t)(uint32_t)vv[1] & m) << p);
-        uint64_t hi = ((uint64_t)(uint32_t)vv[2] & m) | (((uint64_t)(uint32_t)vv[3] & m) << p);
-        int s2 = 2 * p;  // 2..64
-        uint64_t f0 = s2 >= 64 ? lo : (lo | (hi << s2));
-        uint64_t f1 = s2 >= 64 ? hi : (hi >> (64 - s2));
-        int o = pay0 + pex;
-        int w0 = o >> 5, sh = o & 31;
-        uint32_t wd[5];
-        wd[0] = (uint32_t)(f0 << sh);
-        wd[1] = (uint32_t)((f0 << sh) >> 32);
-        wd[2] = (uint32_t)((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0));
-        wd[3] = (uint32_t)(((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0)) >> 32);
-        wd[4] = sh ? (uint32_t)(f1 >> (64 - sh)) : 0u;
-        const int nwd = (sh + 4 * p + 31) >> 5;
-#pragma unroll
-        for (int i = 0; i < 5; i++)
-          if (i < nwd && wd[i]) atomicOr(&buf[w0 + i], wd[i]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; k++) or_bits(buf, H + (4 * gi + k) * W, low_bits(a[k], W), W);
-    }
-    if (gi == 0) {
-      uint32_t cm = H == 32 ? 0x3FFu : 0xFFFFu;
-      uint32_t hdr = (uint32_t)st | ((uint32_t)e << 3) | (((uint32_t)c & cm) << 8);
-      or_bits(buf, 0, hdr, 32);
-    }
-  }
-  if (gi == 0) s_nw[wave * BPW + seg] = (uint32_t)nw;
-  __syncthreads();
-
-  // ---- placement
-  if (threadIdx.x == 0) {
-    uint64_t agg = 0;
-    for (int i = 0; i < WPG * BPW; i++) {
-      s_off[i] = agg;
-      agg += s_nw[i];
-    }
-    uint64_t base = 0;
-    if (variable) {
-      const uint64_t FLAG_A = 1ull << 62, FLAG_P = 2ull << 62, VAL = (1ull << 62) - 1;
-      if (tile == 0) {
-        __hip_atomic_store(&A.tile_state[0], FLAG_P | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&A.tile_state[tile], FLAG_A | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t pidx = tile - 1;
-        uint32_t spins = 0;
-        for (;;) {
-          uint64_t s = __hip_atomic_load(&A.tile_state[pidx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          uint64_t flag = s >> 62;
-          if (flag == 0) {
-            if (++spins > (1u << 26)) {  // safety valve: never hang the GPU
-              atomicOr(A.status, ST_INTERNAL);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          base += s & VAL;
-          if (flag == 2) break;
-          --pidx;
-        }
-        __hip_atomic_store(&A.tile_state[tile], FLAG_P | (base + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (tile == A.ntiles - 1) {
-        uint64_t total = base + agg;
-        *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
-        *A.d_nbytes = A.area + 4 * total;
-      }
-    } else {
-      base = (uint64_t)tile * (WPG * BPW) * (uint64_t)g.budget;
-    }
-    if (tile == 0) {
-      uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
-      for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
-      for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
-      for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
-      if (!variable) {
-        h[14] = A.hdr[14];
-        h[15] = A.hdr[15];
-        *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
-      }
-    }
-    for (int i = 0; i < WPG * BPW; i++) s_off[i] += base;
-  }
-  __syncthreads();
-
-  if (b.blk_ok) {
-    const uint64_t off = s_off[wave * BPW + seg];
-    uint32_t* dst = A.out_words + off;
-    for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
-    if (variable && gi == 0) {
-      A.lens[b.j] = (uint16_t)nw;
-      if ((b.j & 63) == 0) A.sbo[b.j >> 6] = off;
-    }
-  }
+  encode_tile<T, LPB, NDIM, WP>(A, sm.tile, sm, lds);
 }
 
 // ------------------------------------------------------------ launcher
@@ -234,7 +28,7 @@ template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   constexpr int BPW = 64 / LPB;
   size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
-  hipLaunchKernelGGL((k_encode<T, LPB, NDIM>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
+  hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
 }
 
@@ -252,11 +46,15 @@ static hipError_t launch_nd(const EncArgs& A, int ndim, hipStream_t s) {
   return launch_lpb<T, 3>(A, s);
 }
 
-int64_t encode_tiles(const Geo& g) {
-  int lpb = g.G <= 16 ? 16 : (g.G <= 32 ? 32 : 64);
-  int64_t per = (int64_t)WPG * (64 / lpb);
+int lpb_of(const Geo& g) { return g.G <= 16 ? 16 : (g.G <= 32 ? 32 : 64); }
+
+
+int64_t encode_tiles_wp(const Geo& g, int wp) {
+  int64_t per = (int64_t)wp * (64 / lpb_of(g));
   return (g.nblocks + per - 1) / per;
 }
+
+int64_t encode_tiles(const Geo& g) { return encode_tiles_wp(g, WPG); }
 
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s) {
   A.ntiles = encode_tiles(A.g);

@@ -98,7 +98,35 @@ struct CtlArgs {
   double target;
 };
 
+// ---- batches: many arrays, one persistent launch per (LPB, NDIM) class
+struct BatchEnc {
+  int32_t dtype, ndim;
+  int64_t tile_start;  // first global tile of this item
+  EncArgs a;           // per-item arguments (a.ntiles, a.tile_state for the batch tile size)
+};
+struct BatchDec {
+  int32_t dtype, ndim;
+  int64_t tile_start;
+  DecArgs a;
+};
+struct BatchArgs {
+  const void* items;       // BatchEnc* / BatchDec* (device)
+  const int64_t* starts;   // tile_start of items 0..n-1 (device)
+  uint32_t* ticket;        // work-queue counter (zeroed by the reset kernel)
+  uint64_t* tile_state;    // look-back states of every tile of the class
+  int64_t total_tiles;
+  uint32_t n;
+  uint32_t tiles_per_ticket;
+};
+
+int lpb_of(const Geo& g);
 int64_t encode_tiles(const Geo& g);
+int64_t encode_tiles_wp(const Geo& g, int wp);
+hipError_t launch_encode_batch(int lpb, int ndim, int wp, const BatchArgs& B, int grid,
+                               size_t lds, hipStream_t s);
+hipError_t launch_decode_batch(int lpb, int ndim, int wp, const BatchArgs& B, int grid,
+                               size_t lds, hipStream_t s);
+hipError_t launch_batch_reset(uint32_t* ticket, uint64_t* tile_state, int64_t n, hipStream_t s);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
