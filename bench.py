@@ -66,11 +66,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--copies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("c1", "batch", "serve"), default="c1",
+                    help="c1: the headline single-array path; batch: many arrays per persistent "
+                         "launch vs separate launches; serve: Poisson request stream")
+    ap.add_argument("--items", type=int, default=4096, help="batch: number of arrays")
+    ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
+    ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load / plain throughput")
+    ap.add_argument("--pool", type=int, default=1 << 26, help="batch/serve: samples per pool")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU design is described, not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -180,6 +191,213 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, params)
+    print(json.dumps(out), flush=True)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def item_params(spec, code):
+    if spec["mode"] == "lossless":
+        return {"mode": "lossless", "brick": (256,)}
+    return {"mode": "fixed_rate", "brick": (256,), "rate": spec["rate"], "code": code}
+
+
+def profiled_items(specs, pools, dev, A):
+    """Cut each item from the device pools; fixed-rate items get the
+    profiler's operating point and stream mask (untimed set-up)."""
+    import torch
+    out = []
+    for k, spec in enumerate(specs):
+        x = pools.item_device(spec, dev)
+        p = item_params(spec, 0)
+        if p["mode"] == "fixed_rate":
+            prof = A.apax_profile(x, p)
+            p = dict(p, code=prof["code"], stream_mask=prof["stream_mask"] & 0x7F)
+        out.append((x, p))
+        if k % 512 == 511:
+            log(f"set-up {k + 1}/{len(specs)} items")
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_batch(args):
+    """Many arrays (log-uniform 4 KB..64 MB, int16/int32/fp32/fp64, lossless
+    or fixed rate 3:1..10:1, 1-D, 256-sample blocks) encoded and decoded by
+    one persistent launch per block-shape class replayed from a hipGraph,
+    against the same arrays encoded one apax_encode call at a time."""
+    import torch
+
+    import synth
+    from paper_1303_4994_amd import apax as A
+    from paper_1303_4994_amd import tune as T
+
+    dev = torch.device("cuda:0")
+    log(f"pools of {args.pool} samples")
+    pools = synth.Pools(n=args.pool)
+    specs = [synth.item_spec(i) for i in range(args.items)]
+    arrays = profiled_items(specs, pools, dev, A)
+    nbytes_in = sum(x.numel() * x.element_size() for x, _ in arrays)
+    log(f"{len(arrays)} items, {nbytes_in / 1e9:.2f} GB; tuning")
+    tune = T.tune(A.OP_ENCODE, arrays[:256], reps=2, verbose=True)
+    b = A.Batch.encode(arrays, tune=tune)
+    b.capture()
+    for _ in range(args.warmup):
+        b.launch()
+    torch.cuda.synchronize()
+    assert b.status() == 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.launch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    log(f"batched encode {t_batch * 1e3:.2f} ms")
+    # plain: one apax_encode call per array, same outputs, one stream
+    # one workspace, sized for the largest call, shared by the sequential calls
+    ws = torch.empty(max(A.apax_workspace_size(x.dtype, tuple(x.shape), p) for x, p in arrays),
+                     dtype=torch.uint8, device=dev)
+
+    def plain():
+        for i, (x, p) in enumerate(arrays):
+            A.apax_encode(x, p, out=b.outs[i], nbytes=b.nbytes[i:i + 1], clear_status=False, ws=ws)
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    log(f"plain encode {t_plain * 1e3:.2f} ms")
+    # batched decode of the batch's streams
+    nb = b.nbytes.cpu().numpy()
+    hdrs = [bytes(o[:64].cpu().numpy().tobytes()) for o in b.outs]
+    d = A.Batch.decode([(b.outs[i], int(nb[i]), hdrs[i]) for i in range(len(arrays))], tune=tune)
+    d.capture()
+    d.launch()
+    torch.cuda.synchronize()
+    assert d.status() == 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d.launch()
+    torch.cuda.synchronize()
+    t_dec = (time.perf_counter() - t0) / args.steps
+    ok = all(torch.equal(d.outs[i], arrays[i][0]) for i in range(len(arrays))
+             if arrays[i][1]["mode"] == "lossless")
+    stream_bytes = int(nb.sum())
+    out = {
+        "metric": "batched encode/decode GB/s (uncompressed bytes), 1 GPU",
+        "value": round(nbytes_in / t_batch / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "mixed",
+        "data": "synthetic",
+        "config": {"workload": f"C3: {len(arrays)} arrays, log-uniform 4 KB..64 MB, int16/int32/fp32/fp64, "
+                               "lossless or fixed rate 3:1..10:1 (profiler operating point), "
+                               "1-D 256-sample blocks, one hipGraph replay per step",
+                   "input_bytes": nbytes_in, "stream_bytes": stream_bytes, "pool_samples": args.pool,
+                   "tune": tune},
+        "encode_GBps_batched": round(nbytes_in / t_batch / 1e9, 2),
+        "encode_GBps_plain": round(nbytes_in / t_plain / 1e9, 2),
+        "batched_over_plain": round(t_plain / t_batch, 3),
+        "decode_GBps_batched": round(nbytes_in / t_dec / 1e9, 2),
+        "encode_pct_hbm": round(100 * nbytes_in / t_batch / 1e9 / HBM_PEAK_GBPS, 2),
+        "lossless_roundtrip_exact": bool(ok),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson stream of encode/decode requests (payload log-uniform
+    64 KB..256 MB, the batch generators and dtypes, 1:1 encode:decode) served
+    by continuous batching under a 64 GB HBM budget.  The arrival rate is
+    rho times the plain single-call throughput measured first on the same
+    requests."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1303_4994_amd import apax as A
+    from paper_1303_4994_amd import serve as S
+
+    dev = torch.device("cuda:0")
+    log(f"pools of {args.pool} samples")
+    pools = synth.Pools(n=args.pool)
+    specs = synth.requests(args.requests)
+    arrays = profiled_items(specs, pools, dev, A)
+    # decode requests read streams encoded in set-up
+    reqs = []
+    for spec, (x, p) in zip(specs, arrays):
+        r = {"kind": spec["kind"], "x": x, "params": p, "gap_u": spec["gap_u"],
+             "bytes": x.numel() * x.element_size()}
+        if r["kind"] == "decode":
+            buf, nb = A.apax_encode(x, p)
+            r["stream"], r["nbytes"] = buf, int(nb.item())
+            r["hdr"] = bytes(buf[:64].cpu().numpy().tobytes())
+        reqs.append(r)
+    torch.cuda.synchronize()
+    total = sum(r["bytes"] for r in reqs)
+    mean = total / len(reqs)
+    log(f"{len(reqs)} requests, {total / 1e9:.2f} GB")
+    # plain throughput: each request as one call, back to back
+    outs = []
+    for r in reqs:
+        if r["kind"] == "encode":
+            bound = A.apax_encode_bound(r["x"].dtype, tuple(r["x"].shape), r["params"])
+            outs.append((torch.empty(max(bound, 64), dtype=torch.uint8, device=dev),
+                         torch.empty(1, dtype=torch.int64, device=dev)))
+        else:
+            outs.append(torch.empty_like(r["x"]))
+    ws = torch.empty(max(A.apax_workspace_size(r["x"].dtype, tuple(r["x"].shape), r["params"])
+                         for r in reqs), dtype=torch.uint8, device=dev)
+
+    def plain():
+        for r, o in zip(reqs, outs):
+            if r["kind"] == "encode":
+                A.apax_encode(r["x"], r["params"], out=o[0], nbytes=o[1], ws=ws, clear_status=False)
+            else:
+                A.apax_decode(r["stream"], r["nbytes"], hdr=r["hdr"], y=o, ws=ws, clear_status=False)
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    T_plain = total / t_plain
+    lam = args.rho * T_plain / mean
+    gaps = [-np.log(1.0 - r["gap_u"]) / lam for r in reqs]
+    arrivals = list(np.cumsum(gaps))
+    log(f"plain {T_plain / 1e9:.1f} GB/s; arrival rate {lam:.1f}/s over {arrivals[-1]:.1f} s")
+    srv = S.Server(budget_bytes=64 << 30, slots=4, max_group=64, ws_bytes=64 << 20)
+    done = [0]
+
+    def job(k):
+        r, o = reqs[k], outs[k]
+        if r["kind"] == "encode":
+            return srv.submit_encode(r["x"], r["params"], o[0], o[1], tag=k), r["bytes"]
+        return srv.submit_decode(r["stream"], r["nbytes"], r["hdr"], o, tag=k), r["bytes"]
+
+    def on_done(k, c):
+        done[0] += 1
+        if done[0] % 100 == 0:
+            log(f"served {done[0]}/{len(reqs)}")
+    st = S.drive(srv, [lambda k=k: job(k) for k in range(len(reqs))], arrivals, on_done=on_done,
+                 deadline_s=arrivals[-1] + 300.0)
+    srv.close()
+    out = {
+        "metric": "served encode/decode GB/s (uncompressed bytes) with p50/p99 latency, 1 GPU",
+        "value": round(st["GBps"], 2), "unit": "GB/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(st["seconds"] * 1e3, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "mixed", "data": "synthetic",
+        "config": {"workload": f"C4 (scaled: {len(reqs)} of 200k requests): Poisson arrivals at "
+                               f"rho={args.rho} of plain throughput, payload log-uniform 64 KB..256 MB, "
+                               "encode:decode 1:1, 64 GB HBM admission budget, 4 slots x 64 requests",
+                   "requests": len(reqs), "bytes": total, "pool_samples": args.pool},
+        "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+        "max_ms": round(st["max_ms"], 3), "groups": st["groups"],
+        "plain_GBps": round(T_plain / 1e9, 2),
+        "offered_GBps": round(args.rho * T_plain / 1e9, 2),
+        "extrapolation_200k_s": round(200000 * mean / max(1.0, st["GBps"] * 1e9), 1),
+    }
     print(json.dumps(out), flush=True)
 
 

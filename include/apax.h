@@ -185,7 +185,10 @@ typedef struct apax_batch apax_batch; /* opaque host-side plan */
  * valid while the plan is used.  Errors name the first bad item's code. */
 int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const apax_tune* tune,
                       apax_batch** out, uint64_t* ws_bytes);
-/* Copy the plan's descriptor tables into the workspace (synchronous). */
+/* Copy the plan's descriptor tables into the workspace (asynchronous, from a
+ * pinned staging buffer the plan owns) and clear the workspace status.  Each
+ * item records its device-side errors in its own status word; apax_batch_run
+ * ORs them into the workspace status read by apax_status. */
 int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 /* Enqueue the whole batch (work-queue reset + persistent kernels). */
 int apax_batch_run(apax_batch* b, hipStream_t stream);
@@ -194,6 +197,53 @@ int apax_batch_capture(apax_batch* b);
 /* Replay the captured graph on stream (apax_batch_run if none was captured). */
 int apax_batch_launch(apax_batch* b, hipStream_t stream);
 void apax_batch_destroy(apax_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.  Requests (encode or
+ * decode of one array, any size/dtype/mode) are submitted as they arrive and
+ * wait in a FIFO.  apax_server_poll (non-blocking) retires the groups whose
+ * GPU work has finished, then admits requests from the head of the FIFO onto
+ * every free slot while the in-flight footprint (input bytes + output
+ * capacity of each admitted request) stays within the HBM budget, and
+ * launches each admitted group as one persistent batch on the slot's own
+ * stream.  Groups on different slots overlap on the device; a request that
+ * arrives while others run is admitted as soon as a slot and budget free up.
+ * Codec state stays on the device: each slot owns resident workspaces
+ * (status words, work-queue tickets, look-back states, descriptor tables).
+ * Every result is byte-identical to a separate apax_encode / apax_decode
+ * call.  Buffers named by a request are owned by the caller and must stay
+ * valid until its completion is returned.  One host thread drives a server. */
+typedef struct apax_server apax_server;
+
+typedef struct apax_request {
+  int32_t op;            /* APAX_OP_ENCODE / APAX_OP_DECODE */
+  uint32_t reserved;
+  apax_batch_item item;  /* as for a batch; a decode header is copied at submit */
+  uint64_t tag;          /* caller's cookie, returned in the completion */
+} apax_request;
+
+typedef struct apax_completion {
+  uint64_t id, tag;
+  int32_t status;        /* APAX_OK or the request's device-side error */
+  uint32_t slot;
+  double latency_s;      /* submit -> completion observed by apax_server_poll */
+} apax_completion;
+
+/* budget_bytes: HBM admission budget; n_slots (1..16) concurrent groups;
+ * max_group requests per group; ws_bytes: resident workspace per slot and
+ * direction (two per slot, counted against the budget).  Allocates device
+ * and pinned host memory. */
+int apax_server_create(uint64_t budget_bytes, uint32_t n_slots, uint32_t max_group, uint64_t ws_bytes,
+                       const apax_tune* tune, apax_server** out);
+/* Validate and enqueue; *id receives the request id.  APAX_E_CAPACITY when the
+ * request alone exceeds the budget (nothing is enqueued then). */
+int apax_server_submit(apax_server* s, const apax_request* req, uint64_t* id);
+/* Retire, admit, launch; copy up to max_done completions to done[]. */
+int apax_server_poll(apax_server* s, apax_completion* done, uint32_t max_done, uint32_t* n_done);
+/* Queued requests, in-flight footprint bytes, groups launched so far. */
+int apax_server_stats(const apax_server* s, uint64_t* queued, uint64_t* in_flight_bytes, uint64_t* groups);
+/* Waits for in-flight work, then frees the server. */
+void apax_server_destroy(apax_server* s);
 
 #ifdef __cplusplus
 }

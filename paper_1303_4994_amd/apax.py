@@ -73,6 +73,15 @@ class BatchItem(C.Structure):
                 ("h_hdr", C.c_void_p)]
 
 
+class Request(C.Structure):
+    _fields_ = [("op", C.c_int32), ("reserved", C.c_uint32), ("item", BatchItem), ("tag", C.c_uint64)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int32), ("slot", C.c_uint32),
+                ("latency_s", C.c_double)]
+
+
 class Tune(C.Structure):
     _fields_ = [("waves_per_wg", C.c_uint32), ("wgs_per_cu", C.c_uint32),
                 ("tiles_per_ticket", C.c_uint32), ("reserved", C.c_uint32)]
@@ -100,6 +109,12 @@ def _load():
     L.apax_batch_capture.argtypes = [vp]
     L.apax_batch_launch.argtypes = [vp, vp]
     L.apax_batch_destroy.argtypes = [vp]
+    L.apax_server_create.argtypes = [u64, C.c_uint32, C.c_uint32, u64, P(Tune), P(vp)]
+    L.apax_server_submit.argtypes = [vp, P(Request), P(u64)]
+    L.apax_server_poll.argtypes = [vp, P(Completion), C.c_uint32, P(C.c_uint32)]
+    L.apax_server_stats.argtypes = [vp, P(u64), P(u64), P(u64)]
+    L.apax_server_destroy.argtypes = [vp]
+    L.apax_server_destroy.restype = None
     L.apax_batch_destroy.restype = None
     L.apax_strerror.argtypes = [C.c_int]
     L.apax_strerror.restype = C.c_char_p
@@ -308,24 +323,36 @@ class Batch:
     run() enqueues the batch, capture() records it as a hipGraph, launch()
     replays it.  tune: dict of Tune fields (launch geometry only)."""
 
-    def __init__(self, op, items, keep, outs, nbytes, tune=None, device="cuda"):
+    def __init__(self, op, items, keep, outs, nbytes, tune=None, device="cuda", ws=None,
+                 stream=None):
         self.op = op
         self._keep = keep
         self.outs = outs
         self.nbytes = nbytes
+        self.stream = stream
         self.handle, wsb = apax_batch_create(op, items, tune)
-        self.ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=device)
-        apax_batch_upload(self.handle, self.ws)
+        if ws is None or ws.numel() < wsb:
+            ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=device)
+        self.ws = ws
+        apax_batch_upload(self.handle, self.ws, stream)
+
+    @staticmethod
+    def workspace_bytes(op, items, tune=None) -> int:
+        h, n = apax_batch_create(op, items, tune)
+        apax_batch_destroy(h)
+        return n
 
     @classmethod
-    def encode(cls, arrays, tune=None, device="cuda"):
-        items, keep, outs = [], [], []
+    def encode(cls, arrays, tune=None, device="cuda", ws=None, stream=None, outs=None):
+        items, keep = [], []
+        given = outs is not None
+        outs = list(outs) if given else []
         nbytes = torch.empty(max(1, len(arrays)), dtype=torch.int64, device=device)
         for i, (x, params) in enumerate(arrays):
             assert x.is_cuda and x.is_contiguous()
             p = make_params(x.dtype, tuple(x.shape), params)
             bound = apax_encode_bound(x.dtype, tuple(x.shape), params)
-            out = torch.empty(max(bound, 64), dtype=torch.uint8, device=device)
+            out = outs[i] if given else torch.empty(max(bound, 64), dtype=torch.uint8, device=device)
             it = BatchItem()
             it.p = p
             it.d_in = x.data_ptr() if x.numel() else None
@@ -334,15 +361,18 @@ class Batch:
             it.d_nbytes = nbytes.data_ptr() + 8 * i
             items.append(it)
             keep.append(x)
-            outs.append(out)
-        return cls(OP_ENCODE, items, keep, outs, nbytes, tune, device)
+            if not given:
+                outs.append(out)
+        return cls(OP_ENCODE, items, keep, outs, nbytes, tune, device, ws, stream)
 
     @classmethod
-    def decode(cls, streams, tune=None, device="cuda"):
-        items, keep, outs = [], [], []
-        for buf, n, hdr in streams:
+    def decode(cls, streams, tune=None, device="cuda", ws=None, stream=None, outs=None):
+        items, keep = [], []
+        given = outs is not None
+        outs = list(outs) if given else []
+        for k, (buf, n, hdr) in enumerate(streams):
             info = apax_stream_info(hdr)
-            y = torch.empty(info["shape"], dtype=info["dtype"], device=device)
+            y = outs[k] if given else torch.empty(info["shape"], dtype=info["dtype"], device=device)
             hb = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
             it = BatchItem()
             it.d_in = buf.data_ptr()
@@ -352,17 +382,18 @@ class Batch:
             it.h_hdr = C.cast(hb, C.c_void_p)
             items.append(it)
             keep += [buf, hb]
-            outs.append(y)
-        return cls(OP_DECODE, items, keep, outs, None, tune, device)
+            if not given:
+                outs.append(y)
+        return cls(OP_DECODE, items, keep, outs, None, tune, device, ws, stream)
 
     def run(self, stream=None):
-        apax_batch_run(self.handle, stream)
+        apax_batch_run(self.handle, stream if stream is not None else self.stream)
 
     def capture(self):
         apax_batch_capture(self.handle)
 
     def launch(self, stream=None):
-        apax_batch_launch(self.handle, stream)
+        apax_batch_launch(self.handle, stream if stream is not None else self.stream)
 
     def status(self, stream=None) -> int:
         return apax_status(self.ws, stream)

@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <deque>
 #include <vector>
 
 #include "apax.h"
@@ -179,6 +181,17 @@ __global__ void k_clear(uint32_t* p, int nwords) {
   if (i < nwords) p[i] = 0u;
 }
 
+void clear_words(uint32_t* p, int nwords, hipStream_t s) {
+  if (nwords > 0) hipLaunchKernelGGL(k_clear, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s, p, nwords);
+}
+
+// OR the per-item status words of a batch into the workspace status word
+__global__ void k_fold_status(const uint32_t* item_status, uint32_t n, uint32_t* status) {
+  uint32_t acc = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) acc |= item_status[i];
+  if (acc) atomicOr(status, acc);
+}
+
 __global__ void k_header_only(uint32_t* out, uint64_t* d_nbytes, uint64_t nbytes, uint32_t h0,
                               uint32_t h1, uint32_t h2, uint32_t h3, uint32_t h4, uint32_t h5,
                               uint32_t h6, uint32_t h7, uint32_t h8, uint32_t h9, uint32_t h10,
@@ -230,8 +243,11 @@ struct apax_batch {
   std::vector<HG> geo;
   std::vector<BatchClass> classes;
   uint64_t ws_bytes = 0;
+  uint64_t istat_off = 0;       // per-item status words in the workspace
   void* d_ws = nullptr;
   std::vector<uint8_t> tables;  // host image of [descriptors | starts] of every class
+  void* pinned = nullptr;       // pinned staging copy of `tables` (async upload)
+  hipEvent_t upload_done = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -635,6 +651,8 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
   b->tables.assign(tab, 0);
   uint64_t tables_off = off;
   off += tab;
+  b->istat_off = off;
+  off += al256(4 * (uint64_t)std::max<uint32_t>(n, 1));
   for (auto& c : b->classes) {
     c.ticket_off = off;
     off += 256;
@@ -651,7 +669,14 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
   return APAX_OK;
 }
 
-int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Fill the plan's descriptor tables for workspace d_ws, copy them from the
+// pinned buffer `staging` (>= tables bytes; the caller keeps it untouched
+// until the copy has run) and clear the status words.
+int batch_upload_from(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream, void* staging) {
   if (!b || !d_ws || ((uintptr_t)d_ws & 255)) return APAX_E_INVALID;
   if (ws_bytes < b->ws_bytes) return APAX_E_CAPACITY;
   b->d_ws = d_ws;
@@ -681,7 +706,7 @@ int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t 
         A.lens = (uint16_t*)((uint8_t*)it.d_out + 64);
         A.sbo = (uint64_t*)((uint8_t*)it.d_out + 64 + lens_bytes(h));
         A.d_nbytes = it.d_nbytes;
-        A.status = &((PState*)d_ws)->status;
+        A.status = (uint32_t*)(ws + b->istat_off) + i;
         A.ticket = nullptr;
         A.tile_state = (uint64_t*)(ws + c.tstate_off) + start;
         A.ntiles = nt;
@@ -707,7 +732,7 @@ int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t 
         A.lens = (const uint16_t*)((const uint8_t*)it.d_in + 64);
         A.sbo = (const uint64_t*)((const uint8_t*)it.d_in + 64 + lens_bytes(h));
         A.y = it.d_out;
-        A.status = &((PState*)d_ws)->status;
+        A.status = (uint32_t*)(ws + b->istat_off) + i;
         memcpy(&A.payload_words, (const uint8_t*)it.h_hdr + 56, 8);
         A.ntiles = nt;
         memcpy(A.hdr, it.h_hdr, 64);
@@ -717,11 +742,39 @@ int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t 
       start += nt;
     }
   }
-  if (!b->tables.empty() &&
-      hipMemcpyAsync(ws + tables_off, b->tables.data(), b->tables.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return APAX_E_HIP;
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_ws, 1);
-  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  if (!b->tables.empty()) {
+    memcpy(staging, b->tables.data(), b->tables.size());
+    if (hipMemcpyAsync(ws + tables_off, staging, b->tables.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+      return APAX_E_HIP;
+  }
+  clear_words((uint32_t*)d_ws, 1, stream);
+  clear_words((uint32_t*)(ws + b->istat_off), (int)b->items.size(), stream);
+  return hip_err(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+int apax_batch_upload(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!b || !d_ws || ((uintptr_t)d_ws & 255)) return APAX_E_INVALID;
+  if (ws_bytes < b->ws_bytes) return APAX_E_CAPACITY;
+  if (!b->tables.empty()) {
+    // stage in pinned memory owned by the plan, so the copy can stay
+    // asynchronous (the plan outlives it)
+    if (!b->pinned && hipHostMalloc(&b->pinned, b->tables.size(), hipHostMallocDefault) != hipSuccess) {
+      b->pinned = nullptr;
+      return APAX_E_HIP;
+    }
+    if (!b->upload_done && hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming) != hipSuccess) {
+      b->upload_done = nullptr;
+      return APAX_E_HIP;
+    }
+    if (hipEventSynchronize(b->upload_done) != hipSuccess) return APAX_E_HIP;  // staging reused
+  }
+  int e = batch_upload_from(b, d_ws, ws_bytes, stream, b->pinned);
+  if (e) return e;
+  if (b->upload_done && hipEventRecord(b->upload_done, stream) != hipSuccess) return APAX_E_HIP;
   return APAX_OK;
 }
 
@@ -745,6 +798,11 @@ int apax_batch_run(apax_batch* b, hipStream_t stream) {
     if (b->op == APAX_OP_ENCODE) e = hip_err(launch_encode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     else e = hip_err(launch_decode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     if (e) return e;
+  }
+  if (!b->items.empty()) {
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(256), 0, stream, (const uint32_t*)(ws + b->istat_off),
+                       (uint32_t)b->items.size(), &((PState*)ws)->status);
+    return hip_err(hipGetLastError());
   }
   return APAX_OK;
 }
@@ -777,7 +835,266 @@ void apax_batch_destroy(apax_batch* b) {
   if (!b) return;
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  if (b->upload_done) {
+    hipEventSynchronize(b->upload_done);  // an upload may still read the staging buffer
+    hipEventDestroy(b->upload_done);
+  }
+  if (b->pinned) hipHostFree(b->pinned);
   delete b;
+}
+
+// ---------------------------------------------------------------- serving
+// Continuous batching: submitted requests wait in a FIFO; poll() retires the
+// groups whose completion event has fired, then admits FIFO-head requests
+// onto every free slot while their footprint fits the budget, and launches
+// each admitted group as one persistent batch on the slot's stream.  Slots
+// run concurrently, so a group admitted while others run overlaps them.
+
+}  // extern "C"
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SrvReq {
+  uint64_t id = 0;
+  apax_request r{};
+  uint8_t hdr[64];
+  uint64_t footprint = 0;
+  double t_submit = 0.0;
+};
+
+struct SrvSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  void* ws[2] = {nullptr, nullptr};     // resident codec state: encode, decode
+  uint8_t* staging = nullptr;           // pinned: descriptor tables, then item status
+  uint32_t* h_status[2] = {nullptr, nullptr};  // pinned copies of per-item status
+  apax_batch* plan[2] = {nullptr, nullptr};
+  std::vector<SrvReq> reqs;
+  std::vector<uint32_t> which[2];       // request index in reqs for each plan item
+  bool busy = false;
+};
+
+uint64_t req_footprint(const apax_request& q, const HG& h) {
+  const uint64_t in = q.op == APAX_OP_ENCODE ? h.nsamples * (uint64_t)h.esz : q.item.in_bytes;
+  return in + q.item.cap;
+}
+
+}  // namespace
+
+struct apax_server {
+  int dev = 0;
+  uint64_t budget = 0, used = 0, ws_bytes = 0, staging_bytes = 0;
+  uint32_t max_group = 0;
+  apax_tune tune{};
+  uint64_t next_id = 1;
+  std::deque<SrvReq> queue;
+  std::vector<SrvSlot> slots;
+  std::deque<apax_completion> ready;
+  uint64_t groups = 0;
+};
+
+namespace {
+
+void server_free(apax_server* s) {
+  for (auto& sl : s->slots) {
+    if (sl.stream) hipStreamSynchronize(sl.stream);
+    for (int k = 0; k < 2; k++) {
+      if (sl.plan[k]) apax_batch_destroy(sl.plan[k]);
+      if (sl.ws[k]) hipFree(sl.ws[k]);
+    }
+    if (sl.staging) hipHostFree(sl.staging);
+    if (sl.done) hipEventDestroy(sl.done);
+    if (sl.stream) hipStreamDestroy(sl.stream);
+  }
+  delete s;
+}
+
+// launch one admitted group on a free slot
+int server_launch(apax_server* s, SrvSlot& sl) {
+  std::vector<apax_batch_item> items[2];
+  for (int k = 0; k < 2; k++) sl.which[k].clear();
+  for (uint32_t i = 0; i < sl.reqs.size(); i++) {
+    const int k = sl.reqs[i].r.op == APAX_OP_ENCODE ? 0 : 1;
+    items[k].push_back(sl.reqs[i].r.item);
+    if (k == 1) items[k].back().h_hdr = sl.reqs[i].hdr;
+    sl.which[k].push_back(i);
+  }
+  uint64_t soff = 0;
+  for (int k = 0; k < 2; k++) {
+    if (items[k].empty()) continue;
+    uint64_t wsb = 0;
+    int e = apax_batch_create(k == 0 ? APAX_OP_ENCODE : APAX_OP_DECODE, items[k].data(),
+                              (uint32_t)items[k].size(), &s->tune, &sl.plan[k], &wsb);
+    if (e) return e;
+    if (wsb > s->ws_bytes || soff + sl.plan[k]->tables.size() > s->staging_bytes) return APAX_E_CAPACITY;
+    e = batch_upload_from(sl.plan[k], sl.ws[k], s->ws_bytes, sl.stream, sl.staging + soff);
+    soff += (sl.plan[k]->tables.size() + 255) / 256 * 256;
+    if (e) return e;
+    if ((e = apax_batch_run(sl.plan[k], sl.stream))) return e;
+    const uint64_t nst = 4 * items[k].size();
+    if (soff + nst > s->staging_bytes) return APAX_E_CAPACITY;
+    sl.h_status[k] = (uint32_t*)(sl.staging + soff);
+    soff += (nst + 255) / 256 * 256;
+    if (hipMemcpyAsync(sl.h_status[k], (uint8_t*)sl.ws[k] + sl.plan[k]->istat_off, nst,
+                       hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
+      return APAX_E_HIP;
+  }
+  if (hipEventRecord(sl.done, sl.stream) != hipSuccess) return APAX_E_HIP;
+  sl.busy = true;
+  s->groups++;
+  return APAX_OK;
+}
+
+int status_code(uint32_t bits) {
+  if (bits & ST_NONFINITE) return APAX_E_NONFINITE;
+  if (bits & ST_CORRUPT) return APAX_E_CORRUPT;
+  if (bits & ST_INTERNAL) return APAX_E_INTERNAL;
+  return APAX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int apax_server_create(uint64_t budget_bytes, uint32_t n_slots, uint32_t max_group, uint64_t ws_bytes,
+                       const apax_tune* tune, apax_server** out) {
+  if (!out || n_slots == 0 || n_slots > 16 || max_group == 0 || max_group > 65536 || ws_bytes < 4096)
+    return APAX_E_INVALID;
+  *out = nullptr;
+  apax_server* s = new apax_server();
+  ws_bytes = (ws_bytes + 255) / 256 * 256;
+  // workspace and staging are reserved for the server's lifetime and count
+  // against the budget
+  const uint64_t reserved = (uint64_t)n_slots * 2 * ws_bytes;
+  if (budget_bytes <= reserved) { delete s; return APAX_E_CAPACITY; }
+  s->budget = budget_bytes - reserved;
+  s->ws_bytes = ws_bytes;
+  s->max_group = max_group;
+  if (tune) s->tune = *tune;
+  // descriptor tables (<= 1 KiB per item) + two status arrays + alignment
+  s->staging_bytes = (uint64_t)max_group * (sizeof(BatchEnc) > sizeof(BatchDec) ? sizeof(BatchEnc) : sizeof(BatchDec))
+                     + (uint64_t)max_group * 16 + 16 * 4096;
+  if (hipGetDevice(&s->dev) != hipSuccess) { delete s; return APAX_E_HIP; }
+  s->slots.resize(n_slots);
+  for (auto& sl : s->slots) {
+    bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(&sl.ws[0], ws_bytes) == hipSuccess && hipMalloc(&sl.ws[1], ws_bytes) == hipSuccess &&
+              hipHostMalloc((void**)&sl.staging, s->staging_bytes, hipHostMallocDefault) == hipSuccess;
+    if (!ok) { server_free(s); return APAX_E_HIP; }
+  }
+  *out = s;
+  return APAX_OK;
+}
+
+int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
+  if (!s || !q || !id || (q->op != APAX_OP_ENCODE && q->op != APAX_OP_DECODE)) return APAX_E_INVALID;
+  SrvReq r;
+  r.r = *q;
+  HG h;
+  int e;
+  if (q->op == APAX_OP_ENCODE) {
+    if ((e = setup(&q->item.p, h))) return e;
+    if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
+    memset(r.hdr, 0, 64);
+  } else {
+    apax_params p;
+    if (!q->item.h_hdr || apax_stream_info(q->item.h_hdr, 64, &p)) return APAX_E_CORRUPT;
+    uint16_t budget;
+    memcpy(&budget, (const uint8_t*)q->item.h_hdr + 10, 2);
+    if ((e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1))) return e;
+    memcpy(r.hdr, q->item.h_hdr, 64);
+    r.r.item.h_hdr = nullptr;
+  }
+  r.footprint = req_footprint(*q, h);
+  if (r.footprint > s->budget) return APAX_E_CAPACITY;
+  r.id = s->next_id++;
+  r.t_submit = now_s();
+  *id = r.id;
+  s->queue.push_back(r);
+  return APAX_OK;
+}
+
+int apax_server_poll(apax_server* s, apax_completion* done, uint32_t max_done, uint32_t* n_done) {
+  if (!s || !n_done || (max_done && !done)) return APAX_E_INVALID;
+  *n_done = 0;
+  int dev0 = -1;
+  hipGetDevice(&dev0);
+  if (dev0 != s->dev) hipSetDevice(s->dev);
+  int err = APAX_OK;
+  // retire finished groups
+  for (uint32_t k = 0; k < s->slots.size(); k++) {
+    SrvSlot& sl = s->slots[k];
+    if (!sl.busy) continue;
+    hipError_t q = hipEventQuery(sl.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) { err = APAX_E_HIP; break; }
+    const double t = now_s();
+    for (int p = 0; p < 2; p++) {
+      for (uint32_t i = 0; i < sl.which[p].size(); i++) {
+        const SrvReq& r = sl.reqs[sl.which[p][i]];
+        apax_completion c;
+        c.id = r.id;
+        c.tag = r.r.tag;
+        c.status = status_code(sl.h_status[p][i]);
+        c.slot = k;
+        c.latency_s = t - r.t_submit;
+        s->ready.push_back(c);
+        s->used -= r.footprint;
+      }
+      if (sl.plan[p]) { apax_batch_destroy(sl.plan[p]); sl.plan[p] = nullptr; }
+      sl.which[p].clear();
+    }
+    sl.reqs.clear();
+    sl.busy = false;
+  }
+  // admit FIFO-head requests onto free slots
+  for (auto& sl : s->slots) {
+    if (err || s->queue.empty()) break;
+    if (sl.busy) continue;
+    while (!s->queue.empty() && sl.reqs.size() < s->max_group &&
+           s->used + s->queue.front().footprint <= s->budget) {
+      s->used += s->queue.front().footprint;
+      sl.reqs.push_back(s->queue.front());
+      s->queue.pop_front();
+    }
+    if (sl.reqs.empty()) break;  // the head waits for memory
+    int e = server_launch(s, sl);
+    if (e) {
+      // the group could not be launched: complete its requests with the error
+      hipStreamSynchronize(sl.stream);
+      for (auto& r : sl.reqs) {
+        s->ready.push_back(apax_completion{r.id, r.r.tag, e, 0, now_s() - r.t_submit});
+        s->used -= r.footprint;
+      }
+      for (int p = 0; p < 2; p++)
+        if (sl.plan[p]) { apax_batch_destroy(sl.plan[p]); sl.plan[p] = nullptr; }
+      sl.reqs.clear();
+      sl.busy = false;
+    }
+  }
+  while (*n_done < max_done && !s->ready.empty()) {
+    done[(*n_done)++] = s->ready.front();
+    s->ready.pop_front();
+  }
+  if (dev0 >= 0 && dev0 != s->dev) hipSetDevice(dev0);
+  return err;
+}
+
+int apax_server_stats(const apax_server* s, uint64_t* queued, uint64_t* in_flight_bytes, uint64_t* groups) {
+  if (!s) return APAX_E_INVALID;
+  if (queued) *queued = s->queue.size();
+  if (in_flight_bytes) *in_flight_bytes = s->used;
+  if (groups) *groups = s->groups;
+  return APAX_OK;
+}
+
+void apax_server_destroy(apax_server* s) {
+  if (s) server_free(s);
 }
 
 }  // extern "C"

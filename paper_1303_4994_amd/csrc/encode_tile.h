@@ -7,8 +7,7 @@
 // into a zeroed LDS buffer with ds_or (header | JEE tokens | BFPE payload),
 // then copied out with coalesced word stores.  Fixed rate places block j at
 // j * budget words; variable-size modes place blocks with a single-pass
-// decoupled look-back over per-tile word counts (tiles started in increasing
-// order, so every tile waited on is already running).
+// decoupled look-back over per-tile word counts, 64 predecessors per probe.
 #pragma once
 #include "block.h"
 #include "kernels.h"
@@ -28,6 +27,57 @@ __device__ __forceinline__ void or_bits(uint32_t* buf, int bitpos, uint32_t val,
 
 __device__ __forceinline__ uint32_t low_bits(int32_t v, int n) {
   return n >= 32 ? (uint32_t)v : ((uint32_t)v & ((1u << n) - 1u));
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o, 64);
+  return v;
+}
+
+// Decoupled look-back over per-tile word counts, run by one full wave.  Each
+// tile publishes its aggregate (flag A), then the wave reads the states of
+// the 64 nearest unconsumed predecessors in one round trip: aggregates are
+// summed up to and including the nearest inclusive prefix (flag P); a
+// predecessor that has not published yet is waited for.  The value travels
+// in the same 64-bit word as its flag, so relaxed device-scope atomics
+// suffice (no cache invalidation per probe).  Tiles are started in
+// increasing order, so every tile waited on is already running; the wait is
+// still bounded in time and reports ST_INTERNAL if the bound is ever hit.
+// Returns the exclusive prefix (words before this tile).
+__device__ __forceinline__ uint64_t lookback(uint64_t* ts, int64_t tile, uint64_t agg, uint32_t* status) {
+  const uint64_t FLAG_A = 1ull << 62, FLAG_P = 2ull << 62, VAL = FLAG_A - 1;
+  const int lane = lane_id();
+  if (tile == 0) {
+    if (lane == 0) __hip_atomic_store(&ts[0], FLAG_P | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (lane == 0) __hip_atomic_store(&ts[tile], FLAG_A | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint64_t base = 0;
+  int64_t end = tile - 1;
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const int64_t idx = end - lane;
+    const uint64_t s = idx >= 0 ? __hip_atomic_load(&ts[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : FLAG_P;
+    const uint32_t flag = (uint32_t)(s >> 62);
+    const uint64_t mz = __ballot(flag == 0), mp = __ballot(flag == 2);
+    const int fz = mz ? __builtin_ctzll(mz) : 64;
+    const int fp = mp ? __builtin_ctzll(mp) : 64;
+    const int take = fp < fz ? fp + 1 : fz;  // lanes [0, take) are consumed
+    base += wave_sum64(lane < take ? (s & VAL) : 0);
+    if (fp < fz) break;
+    end -= take;
+    if (take == 0) {
+      if (wall_clock64() - t0 > 400000000ull) {  // 4 s of the 100 MHz clock
+        if (lane == 0) atomicOr(status, ST_INTERNAL);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (lane == 0) __hip_atomic_store(&ts[tile], FLAG_P | (base + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return base;
 }
 
 template <int WP>
@@ -159,39 +209,13 @@ __device__ __forceinline__ void encode_tile(const EncArgs& A, const int64_t tile
   __syncthreads();
 
   // ---- placement
-  if (threadIdx.x == 0) {
+  if (wave == 0) {
     uint64_t agg = 0;
-    for (int i = 0; i < WP * BPW; i++) {
-      s_off[i] = agg;
-      agg += s_nw[i];
-    }
-    uint64_t base = 0;
+    for (int i = 0; i < WP * BPW; i++) agg += s_nw[i];
+    uint64_t base;
     if (variable) {
-      const uint64_t FLAG_A = 1ull << 62, FLAG_P = 2ull << 62, VAL = (1ull << 62) - 1;
-      if (tile == 0) {
-        __hip_atomic_store(&A.tile_state[0], FLAG_P | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        __hip_atomic_store(&A.tile_state[tile], FLAG_A | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t pidx = tile - 1;
-        uint32_t spins = 0;
-        for (;;) {
-          uint64_t s = __hip_atomic_load(&A.tile_state[pidx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          uint64_t flag = s >> 62;
-          if (flag == 0) {
-            if (++spins > (1u << 26)) {  // safety valve: never hang the GPU
-              atomicOr(A.status, ST_INTERNAL);
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          base += s & VAL;
-          if (flag == 2) break;
-          --pidx;
-        }
-        __hip_atomic_store(&A.tile_state[tile], FLAG_P | (base + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (tile == A.ntiles - 1) {
+      base = lookback(A.tile_state, tile, agg, A.status);
+      if (tile == A.ntiles - 1 && lane == 0) {
         uint64_t total = base + agg;
         *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
         *A.d_nbytes = A.area + 4 * total;
@@ -199,18 +223,24 @@ __device__ __forceinline__ void encode_tile(const EncArgs& A, const int64_t tile
     } else {
       base = (uint64_t)tile * (WP * BPW) * (uint64_t)g.budget;
     }
-    if (tile == 0) {
-      uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
-      for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
-      for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
-      for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
-      if (!variable) {
-        h[14] = A.hdr[14];
-        h[15] = A.hdr[15];
-        *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
+    if (lane == 0) {
+      if (tile == 0) {
+        uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
+        for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
+        for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
+        for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
+        if (!variable) {
+          h[14] = A.hdr[14];
+          h[15] = A.hdr[15];
+          *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
+        }
+      }
+      uint64_t acc = base;
+      for (int i = 0; i < WP * BPW; i++) {
+        s_off[i] = acc;
+        acc += s_nw[i];
       }
     }
-    for (int i = 0; i < WP * BPW; i++) s_off[i] += base;
   }
   __syncthreads();
 

@@ -13,13 +13,14 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 
 import torch
 
 from . import apax as A
 
 CANDIDATES = [{"waves_per_wg": w, "wgs_per_cu": c, "tiles_per_ticket": t}
-              for w in (2, 4, 8) for c in (2, 4, 8, 16) for t in (1, 2, 4)]
+              for w in (2, 4, 8) for c in (4, 8, 16) for t in (1, 4)]
 DEFAULT = {"waves_per_wg": 4, "wgs_per_cu": 8, "tiles_per_ticket": 1}
 
 
@@ -96,7 +97,7 @@ def tune(op: int, arrays, candidates=None, reps: int = 3, use_cache: bool = True
         b.close()
         log.append((cand, ms))
         if verbose:
-            print(f"tune {cand} {ms:.3f} ms", flush=True)
+            print(f"tune {cand} {ms:.3f} ms", file=sys.stderr, flush=True)
         if ms < best_ms:
             best, best_ms = cand, ms
     cache[key] = {"tune": best, "ms": best_ms}

@@ -149,6 +149,31 @@ class Pools:
             return np.rint(w * scale).astype(dt)
         return w.astype(dt)
 
+    def item_device(self, spec: dict, device):
+        """The same window as item(), cut and cast on the device from a
+        device-resident copy of the pool (identical values: the product and
+        the half-to-even rounding are the same binary64 operations)."""
+        import torch
+        if not hasattr(self, "_dev"):
+            self._dev = {}
+        key = (str(device), spec["gen"])
+        if key not in self._dev:
+            self._dev[key] = torch.from_numpy(self.pool[spec["gen"]]).to(device)
+        p = self._dev[key]
+        n = spec["n"]
+        start = spec["offset"] % max(1, self.n - n) if n < self.n else 0
+        w = p[start:start + n]
+        if w.numel() < n:
+            w = w.repeat((n + w.numel() - 1) // w.numel())[:n]
+        dt = spec["dtype"]
+        tdt = {np.dtype(np.int16): torch.int16, np.dtype(np.int32): torch.int32,
+               np.dtype(np.float32): torch.float32, np.dtype(np.float64): torch.float64,
+               np.dtype(np.int8): torch.int8}[np.dtype(dt)]
+        if dt.kind == "i":
+            scale = 0.366 * np.iinfo(dt).max / self.peak[spec["gen"]]
+            return torch.round(w * scale).to(tdt)
+        return w.to(tdt).contiguous()
+
 
 # --------------------------------------------------------------------------
 # served request stream
