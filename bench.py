@@ -73,6 +73,8 @@ def main():
     ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
     ap.add_argument("--rho", type=float, default=0.8, help="serve: offered load / plain throughput")
     ap.add_argument("--pool", type=int, default=1 << 26, help="batch/serve: samples per pool")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="c1: also run a plain 64 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -189,6 +191,11 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes},
     }
+    if args.copy_probe:
+        # a plain copy of the field: reads and writes exactly input_bytes
+        for _ in range(3):
+            ys[0].copy_(xs[1])
+        torch.cuda.synchronize()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, params)
     print(json.dumps(out), flush=True)

@@ -26,9 +26,9 @@ __device__ __forceinline__ LaneMap<LPB> lane_map(const Geo& g) {
   L.seg = L.lane / LPB;
   L.gi = L.lane % LPB;
   int gi = L.gi < g.G ? L.gi : 0;
-  L.z = gi / g.plane;
+  L.z = (int)fdiv((uint32_t)gi, g.plane_m, g.plane_s);
   int r = gi - L.z * g.plane;
-  L.y = r / g.rowq;
+  L.y = (int)fdiv((uint32_t)r, g.rowq_m, g.rowq_s);
   L.xq = r - L.y * g.rowq;
   L.hx = L.xq > 0;
   L.hy = L.y > 0;
@@ -47,9 +47,9 @@ __device__ __forceinline__ int64_t group_index(const Geo& g, const LaneMap<LPB>&
   } else {
     uint32_t jj = (uint32_t)j;
     uint32_t nbx = (uint32_t)g.nbx, nby = (uint32_t)g.nby;
-    uint32_t t = jj / nbx;
+    uint32_t t = fdiv(jj, g.nbx_m, g.nbx_s);
     uint32_t bxI = jj - t * nbx;
-    uint32_t bzI = t / nby;
+    uint32_t bzI = fdiv(t, g.nby_m, g.nby_s);
     uint32_t byI = t - bzI * nby;
     X = (int64_t)bxI * g.b[2] + 4 * L.xq;
     Y = (int64_t)byI * g.b[1] + L.y;
@@ -136,6 +136,9 @@ struct Blk {
     xch = xch_;
   }
 
+  // BRACKET = false skips the block max and code bracket (callers that get
+  // the block's code from elsewhere)
+  template <bool BRACKET = true>
   __device__ __forceinline__ int64_t load(const T* __restrict__ x, const Geo& g) {
     T v[4];
     int64_t idx = -1;
@@ -149,6 +152,11 @@ struct Blk {
       if constexpr (!ISINT) nf |= !__builtin_isfinite(xd[k]);
     }
     nonfinite = nf;
+    if constexpr (!BRACKET) {
+      M = 0.0;
+      cf = cc = 0;
+      return idx;
+    }
     // block max |x|: reduce the magnitude bit patterns (monotone in value)
     if constexpr (sizeof(T) <= 4) {
       uint32_t key = 0;

@@ -41,6 +41,16 @@ int host_largest(double M, double lim, int cmin, int cmax) {
   return lo;
 }
 
+// Multiplier and shift for n / d with n < 2^31, 1 <= d < 2^31:
+// m = ceil(2^(31+l) / d), l = ceil(log2 d); then n / d = (n * m) >> (31 + l).
+void magic(int64_t d, uint32_t& m, int32_t& sh) {
+  int l = 0;
+  while ((1ll << l) < d) l++;
+  const unsigned __int128 num = (unsigned __int128)1 << (31 + l);
+  m = (uint32_t)((num + (unsigned __int128)(d - 1)) / (unsigned __int128)d);
+  sh = 31 + l;
+}
+
 // Validation of apax_params (the rules of include/apax.h).  forced_budget >= 0
 // takes the fixed-rate budget from a stream header instead of the rate.
 int setup(const apax_params* p, HG& h, int forced_budget = -1) {
@@ -118,6 +128,10 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
   }
   if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not in this build
+  magic(g.nbx, g.nbx_m, g.nbx_s);
+  magic(g.nby, g.nby_m, g.nby_s);
+  magic(g.rowq, g.rowq_m, g.rowq_s);
+  magic(g.plane, g.plane_m, g.plane_s);
   return APAX_OK;
 }
 
@@ -160,18 +174,21 @@ void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
 uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 uint64_t tiles_enc(const HG& h) { return (uint64_t)encode_tiles(h.g); }
 
-uint64_t partial_floats(const HG& h) {
-  uint64_t w = (uint64_t)prof_wgs(prof_tiles(h.g, h.g.nblocks), 1);
-  return (uint64_t)MAXCODES * std::max<uint64_t>(w, 1) * NSUM * 2;
+// partial records of one profile launch: at most about 2048 workgroups over
+// all codes (prof_wgs), or the max pass's PMAX_WGS
+uint64_t partial_bytes(const HG& h) {
+  (void)h;
+  uint64_t recs = 2048 + 2 * (uint64_t)MAXCODES;
+  return std::max<uint64_t>(recs * PPART_BYTES, (uint64_t)PMAX_WGS * 16);
 }
 
 uint64_t ws_tile_off() { return al256(sizeof(PState)); }
 uint64_t ws_cj_off(const HG& h) { return ws_tile_off() + al256(8 * tiles_enc(h)); }
 uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
-uint64_t ws_need(const HG& h) { return ws_part_off(h) + 4 * partial_floats(h); }
+uint64_t ws_need(const HG& h) { return ws_part_off(h) + partial_bytes(h); }
 
 uint64_t* tile_state_ptr(void* ws) { return (uint64_t*)((uint8_t*)ws + ws_tile_off()); }
-float* partials_ptr(void* ws, const HG& h) { return (float*)((uint8_t*)ws + ws_part_off(h)); }
+void* partials_ptr(void* ws, const HG& h) { return (uint8_t*)ws + ws_part_off(h); }
 int32_t* cj_ptr(void* ws, const HG& h) { return (int32_t*)((uint8_t*)ws + ws_cj_off(h)); }
 
 int hip_err(hipError_t e) { return e == hipSuccess ? APAX_OK : APAX_E_HIP; }
@@ -449,7 +466,9 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   // next `depth` steps; fixed quality re-reads the whole array per code, so
   // it evaluates one code per launch once the array outgrows the last-level cache
   const int depth = fr ? 3 : (in_bytes <= (96ull << 20) ? 3 : 1);
-  const int nbatch = (16 + depth - 1) / depth;
+  // c_cap - c_floor <= 512 (the gain grid spans 2^32 in 512 codes), so the
+  // bisection takes at most 9 steps after the first probe at c_cap
+  const int nbatch = (9 + depth - 1) / depth;
   const int tree_n = (1 << depth) - 1 + 1;
 
   CtlArgs C;
@@ -465,7 +484,8 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   C.nsamples = h.nsamples;
   C.target = p->target_corr;
   auto ctl = [&](int step) { C.step = step; return hip_err(launch_ctl(C, stream)); };
-  auto args = [&](int op, int rl, int mask_sel, bool sub, int maxcodes) {
+  // one pass over blocks; its last workgroup reduces and runs control step `next`
+  auto run = [&](int op, int rl, int mask_sel, bool sub, int maxcodes, int next, int flags) -> int {
     ProfArgs A;
     memset(&A, 0, sizeof(A));
     A.x = d_x;
@@ -477,43 +497,38 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     A.jstride = sub ? sub_stride : 1;
     A.nbe = sub ? sub_n : g.nblocks;
     A.maxcodes = maxcodes;
-    A.partials = partials_ptr(d_ws, h);
+    A.parts = partials_ptr(d_ws, h);
     A.cj = cj_ptr(d_ws, h);
-    return A;
+    A.hist = (flags & 1) != 0;
+    A.final_code = (flags & 2) != 0;
+    A.curve = (flags & 4) != 0;
+    A.store_cj = (flags & 8) != 0;
+    A.C = C;
+    A.C.step = next;
+    return hip_err(launch_profile(h.dtype, h.ndim, A, stream));
   };
-  auto run = [&](ProfArgs A, bool fin) -> int {
-    int e2 = hip_err(launch_profile(h.dtype, h.ndim, A, stream));
-    if (e2) return e2;
-    if (fin) e2 = hip_err(launch_finalize(A.partials, A.nwg, A.maxcodes, st, stream));
-    return e2;
-  };
+  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8 };
 
-  // whole profile, asynchronously: clear, max |x|, bisection batches,
-  // histogram -> mask, curve, metrics, centred metrics; then one read-back
+  // whole profile, asynchronously: clear, max |x| (-> bracket), bisection
+  // batches, histogram at the chosen code (-> mask, curve codes), curve
+  // (-> metrics set-up), metrics (-> means), centred metrics; one read-back
   hipLaunchKernelGGL(k_clear, dim3((unsigned)((sizeof(PState) / 4 + 255) / 256)), dim3(256), 0,
                      stream, (uint32_t*)st, (int)(sizeof(PState) / 4));
   if ((e = hip_err(hipGetLastError()))) return e;
-  if ((e = hip_err(launch_pmax(h.dtype, d_x, h.nsamples, st, stream)))) return e;
-  if ((e = ctl(C_INIT))) return e;
   if (g.nblocks) {
+    C.step = C_INIT;
+    if ((e = hip_err(launch_pmax(h.dtype, d_x, h.nsamples, partials_ptr(d_ws, h), C, stream)))) return e;
     for (int b = 0; b < nbatch && (fr || h.mode == APAX_FIXED_QUALITY); b++) {
-      if (fr) { if ((e = run(args(P_FITS, R_RATE, 0, true, tree_n), false))) return e; }
-      else { if ((e = run(args(P_STATS, R_QUALITY, 0, false, tree_n), true))) return e; }
-      if ((e = ctl(C_DECIDE))) return e;
+      if (fr) e = run(P_FITS, R_RATE, 0, true, tree_n, C_DECIDE, 0);
+      else e = run(P_STATS, R_QUALITY, 0, false, tree_n, C_DECIDE, 0);
+      if (e) return e;
     }
-    if ((e = ctl(C_MASK))) return e;
-    ProfArgs H = args(P_FITS, rule, 0, true, 1);
-    H.hist = 1;
-    if ((e = run(H, false))) return e;
-    if ((e = ctl(C_CURVE))) return e;
-    if ((e = run(args(P_STATS, R_QUALITY, 1, true, NCURVE), true))) return e;
-    if ((e = ctl(C_METRICS))) return e;
-    ProfArgs Mx = args(P_STATS, rule, 2, false, 1);
-    Mx.store_cj = 1;
-    if ((e = run(Mx, true))) return e;
-    if ((e = ctl(C_MEANS))) return e;
-    if ((e = run(args(P_CENTER, rule, 2, false, 1), true))) return e;
+    if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL))) return e;
+    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_METRICS, F_CURVE))) return e;
+    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE))) return e;
+    if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL))) return e;
   } else {
+    if ((e = ctl(C_INIT))) return e;
     if ((e = ctl(C_MASK))) return e;
     if ((e = ctl(C_CURVE))) return e;
   }

@@ -40,7 +40,16 @@ struct Geo {
   int32_t cmin, cmax;
   int32_t maxw;     // words of the largest variable-size block (verbatim)
   int32_t ldsw;     // LDS words of one block buffer: worst BFPE encoding + 2
+  // n / d = (n * m) >> sh for n < 2^31 (divisors nbx, nby, rowq, plane)
+  uint32_t nbx_m, nby_m, rowq_m, plane_m;
+  int32_t nbx_s, nby_s, rowq_s, plane_s;
 };
+
+// Division of a numerator below 2^31 by a divisor known on the host
+// (Granlund-Montgomery: m = ceil(2^(31+l) / d), l = ceil(log2 d)).
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint32_t m, int sh) {
+  return (uint32_t)(((uint64_t)n * m) >> sh);
+}
 
 // ------------------------------------------------------------ gain grid
 // Attenuator values (Sec. 6): g(c) = (16 + f) 2^(k-4), c = 16k + f.  An

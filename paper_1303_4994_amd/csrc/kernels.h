@@ -72,24 +72,36 @@ struct PState {
   uint64_t mwords;
 };
 
-struct ProfArgs {
-  const void* x;
-  PState* st;
-  float* partials;            // [MAXCODES][nwg][NSUM][2]
-  int32_t* cj;                // per-block codes (fixed rate): written by P_STATS, read by P_CENTER
-  int64_t jstride;            // 1 (full array) or 16 (subsample)
-  int64_t nbe;                // blocks visited
-  int64_t ntiles;             // tiles of blocks to visit
-  int64_t nwg;                // persistent workgroups per code
-  int op, rule;
-  int maxcodes;               // grid rows launched (rows >= st->ncodes exit)
-  int store_cj, hist;         // P_STATS: store per-block codes; P_FITS: histogram streams
-  int mask_sel;               // 0 st->mask_probe, 1 st->mask_out (+0x81), 2 metrics mask
-  Geo g;
+// Per-(code, workgroup) partial results of a profile pass, one array per
+// field (record r = code * nwg + workgroup, R records), reduced in a fixed
+// order by the one-workgroup reduce kernel that follows the pass.
+struct PParts {
+  float2* s;          // [NSUM][R] float-float sums
+  uint64_t* words;    // [R] encoded words
+  uint64_t* dmax;     // [R] max |d| (binary64 bits)
+  uint32_t* nfit;     // [R] blocks that fit the budget
+  uint32_t* hist;     // [8][R] blocks per chosen stream
+  int64_t R;
 };
+__host__ __device__ inline PParts pparts(void* base, int64_t R) {
+  PParts P;
+  uint8_t* b = (uint8_t*)base;
+  P.s = (float2*)b;
+  b += 8 * NSUM * R;
+  P.words = (uint64_t*)b;
+  b += 8 * R;
+  P.dmax = (uint64_t*)b;
+  b += 8 * R;
+  P.nfit = (uint32_t*)b;
+  b += 4 * R;
+  P.hist = (uint32_t*)b;
+  P.R = R;
+  return P;
+}
+constexpr int PPART_BYTES = 8 * NSUM + 8 + 8 + 4 + 4 * 8;  // per record
 
-// control steps of the profile
-enum { C_INIT = 0, C_DECIDE = 1, C_MASK = 2, C_CURVE = 3, C_METRICS = 4, C_MEANS = 5 };
+// control steps of the profile (run by the last workgroup of a launch)
+enum { C_NONE = -1, C_INIT = 0, C_DECIDE = 1, C_MASK = 2, C_CURVE = 3, C_METRICS = 4, C_MEANS = 5 };
 struct CtlArgs {
   PState* st;
   int step, mode, isint, depth, cmin, cmax;
@@ -97,6 +109,26 @@ struct CtlArgs {
   uint64_t nsub, nsamples;
   double target;
 };
+
+struct ProfArgs {
+  const void* x;
+  PState* st;
+  void* parts;                // PParts of maxcodes * nwg records
+  int32_t* cj;                // per-block codes (fixed rate): written by P_STATS, read by P_CENTER
+  int64_t jstride;            // 1 (full array) or 16 (subsample)
+  int64_t nbe;                // blocks visited
+  int64_t ntiles;             // tiles of blocks to visit
+  int64_t nwg;                // persistent workgroups per code
+  int op, rule;
+  int maxcodes;               // grid rows launched (rows >= st->ncodes idle)
+  int store_cj, hist;         // P_STATS: store per-block codes; P_FITS: histogram streams
+  int mask_sel;               // 0 st->mask_probe, 1 st->mask_out (+0x81), 2 metrics mask
+  int final_code;             // evaluate st->code (one code) instead of st->codes[]
+  int curve;                  // P_STATS: only the four sums of r and the word count
+  CtlArgs C;                  // control step run by the reduce kernel (C.step, C_NONE: none)
+  Geo g;
+};
+constexpr int PMAX_WGS = 1024;
 
 // ---- batches: many arrays, one persistent launch per (LPB, NDIM) class
 struct BatchEnc {
@@ -132,9 +164,8 @@ hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
 int64_t prof_wgs(int64_t ntiles, int ncodes);
 hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s);
-hipError_t launch_finalize(const float* partials, int64_t nwg, int maxcodes, PState* st,
-                           hipStream_t s);
-hipError_t launch_pmax(int dtype, const void* x, uint64_t n, PState* st, hipStream_t s);
+hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,
+                       hipStream_t s);
 hipError_t launch_ctl(const CtlArgs& C, hipStream_t s);
 
 }  // namespace apax

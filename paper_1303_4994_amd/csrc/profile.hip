@@ -7,8 +7,10 @@
 // (TwoSum, Knuth; renormalised with Fast2Sum), every binary64 term split
 // exactly into hi + lo first and scaled by a power of two chosen from max|x|
 // so FP32 never overflows.  Lanes reduce once per workgroup (wave
-// butterflies, then LDS), workgroups in a fixed-order final pass, so results
-// are deterministic.  grid.y indexes the gain codes evaluated in one launch.
+// butterflies, then LDS) into a partial record; a one-workgroup kernel then
+// reduces the records in a fixed order, so results are deterministic, and
+// runs the next control step of the profile.  No global atomics in the
+// passes.  grid.y indexes the gain codes evaluated in one launch.
 #include "block.h"
 #include "kernels.h"
 
@@ -42,53 +44,268 @@ __device__ __forceinline__ FF ff_shfl_xor(FF a, int o) {
   return {__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
 }
 
+__device__ void ctl_step(const CtlArgs& C);
+
+// The profiler state is staged in LDS for the reduce kernels, so the
+// one-thread control step runs on LDS instead of dependent global loads.
+__device__ __forceinline__ void st_copy(uint32_t* dst, const uint32_t* src) {
+  constexpr int NW = (int)(sizeof(PState) / 4);
+  for (int i = threadIdx.x; i < NW; i += blockDim.x) dst[i] = src[i];
+}
+
+
 // ---------------------------------------------------------------- max |x|
 // Streaming pass: max |x| as magnitude bit patterns (monotone in value) and
-// the non-finite flag, 16-byte loads, one atomic per wave.
+// the non-finite flag, 16-byte loads; one partial per workgroup, reduced by
+// the last workgroup, which then brackets the codes (control step C_INIT).
+struct PMaxPart {
+  uint64_t key;
+  uint32_t nf, pad;
+};
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_pmax(const T* __restrict__ x, uint64_t n, PState* st) {
+__device__ __forceinline__ void pmax_take(T v, uint64_t& key, uint32_t& nf) {
+  uint64_t k;
+  if constexpr (Traits<T>::isint) {
+    const int64_t iv = (int64_t)v;
+    k = __builtin_bit_cast(uint64_t, (double)(iv < 0 ? -iv : iv));
+  } else if constexpr (sizeof(T) == 4) {
+    const uint32_t m = __builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu;
+    const uint32_t bad = m >= 0x7F800000u;
+    nf |= bad;
+    k = bad ? 0 : __builtin_bit_cast(uint64_t, (double)__builtin_bit_cast(float, m));
+  } else {
+    const uint64_t m = __builtin_bit_cast(uint64_t, v) & 0x7FFFFFFFFFFFFFFFull;
+    const uint32_t bad = m >= 0x7FF0000000000000ull;
+    nf |= bad;
+    k = bad ? 0 : m;
+  }
+  key = k > key ? k : key;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pmax(const T* __restrict__ x, uint64_t n, PMaxPart* parts) {
   constexpr int PER = 16 / sizeof(T);
+  constexpr int U = 4;  // independent 16-byte loads in flight per thread
+  __shared__ uint64_t s_key[4];
+  __shared__ uint32_t s_nf[4];
   const uint64_t nvec = (((uintptr_t)x) & 15) == 0 ? n / PER : 0;
   uint64_t key = 0;
-  bool nf = false;
-  auto take = [&](T v) {
-    uint64_t k;
-    if constexpr (Traits<T>::isint) {
-      int64_t iv = (int64_t)v;
-      k = (uint64_t)(iv < 0 ? -iv : iv);
-    } else if constexpr (sizeof(T) == 4) {
-      k = __builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu;
-      nf |= k >= 0x7F800000u;
-      k = (uint64_t)__builtin_bit_cast(uint64_t, (double)__builtin_bit_cast(float, (uint32_t)k));
-    } else {
-      k = __builtin_bit_cast(uint64_t, v) & 0x7FFFFFFFFFFFFFFFull;
-      nf |= k >= 0x7FF0000000000000ull;
-    }
-    if constexpr (Traits<T>::isint) k = __builtin_bit_cast(uint64_t, (double)k);
-    bool bad = false;
-    if constexpr (!Traits<T>::isint) bad = nf;
-    key = (!bad && k > key) ? k : key;
-  };
+  uint32_t nf = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
-    uint4 u = reinterpret_cast<const uint4*>(x)[i];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u* xv = reinterpret_cast<const v4u*>(x);
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < nvec; i += U * stride) {
+    v4u u[U];
+#pragma unroll
+    for (int r = 0; r < U; r++) u[r] = __builtin_nontemporal_load(xv + i + r * stride);
+#pragma unroll
+    for (int r = 0; r < U; r++) {
+      T v[PER];
+      __builtin_memcpy(v, &u[r], 16);
+#pragma unroll
+      for (int k = 0; k < PER; k++) pmax_take<T>(v[k], key, nf);
+    }
+  }
+  for (; i < nvec; i += stride) {
+    v4u u = xv[i];
     T v[PER];
     __builtin_memcpy(v, &u, 16);
 #pragma unroll
-    for (int k = 0; k < PER; k++) take(v[k]);
+    for (int k = 0; k < PER; k++) pmax_take<T>(v[k], key, nf);
   }
-  for (uint64_t i = nvec * PER + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    take(x[i]);
+  for (uint64_t t = nvec * PER + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+    pmax_take<T>(x[t], key, nf);
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     uint64_t t = (uint64_t)__shfl_xor((unsigned long long)key, o, 64);
     key = t > key ? t : key;
   }
-  if (__ballot(nf) && lane_id() == 0) atomicOr(&st->status, ST_NONFINITE);
-  if (lane_id() == 0 && key) atomicMax((unsigned long long*)&st->maxbits[0], (unsigned long long)key);
+  const int wave = threadIdx.x >> 6;
+  const bool wnf = __ballot(nf != 0) != 0;
+  if (lane_id() == 0) {
+    s_key[wave] = key;
+    s_nf[wave] = wnf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t k = s_key[0];
+    uint32_t f = s_nf[0];
+    for (int w = 1; w < 4; w++) {
+      k = s_key[w] > k ? s_key[w] : k;
+      f |= s_nf[w];
+    }
+    parts[blockIdx.x].key = k;
+    parts[blockIdx.x].nf = f;
+  }
+}
+
+// One workgroup: max over the partials of the max pass, then C_INIT.
+__global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int nparts, CtlArgs C) {
+  __shared__ uint64_t s_key[4];
+  __shared__ uint32_t s_nf[4];
+  uint64_t k = 0;
+  uint32_t f = 0;
+  for (int w = threadIdx.x; w < nparts; w += blockDim.x) {
+    const uint64_t kw = parts[w].key;
+    k = kw > k ? kw : k;
+    f |= parts[w].nf;
+  }
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t t = (uint64_t)__shfl_xor((unsigned long long)k, o, 64);
+    k = t > k ? t : k;
+  }
+  const bool anyf = __ballot(f != 0) != 0;
+  const int wave = threadIdx.x >> 6;
+  if (lane_id() == 0) {
+    s_key[wave] = k;
+    s_nf[wave] = anyf;
+  }
+  __syncthreads();
+  __shared__ PState s_st;
+  st_copy((uint32_t*)&s_st, (const uint32_t*)C.st);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool nfa = anyf;
+    for (int w = 1; w < 4; w++) {
+      k = s_key[w] > k ? s_key[w] : k;
+      nfa |= s_nf[w] != 0;
+    }
+    s_st.maxbits[0] = k;
+    if (nfa) s_st.status |= ST_NONFINITE;
+    CtlArgs D = C;
+    D.st = &s_st;
+    ctl_step(D);
+  }
+  __syncthreads();
+  st_copy((uint32_t*)C.st, (const uint32_t*)&s_st);
 }
 
 // ---------------------------------------------------------------- block passes
+// Fixed-order reduction of the partial records of one pass (one workgroup,
+// 256 threads): each code's records are split over Lc lanes, lane k taking
+// records k, k + Lc, ... in order (loads of U records issued together), then
+// a butterfly inside the wave and an ordered merge of the waves.  Writes the
+// pass's results into the profiler state.
+__device__ void reduce_parts(const ProfArgs& A, int ncodes, int i0, int i1) {
+  constexpr int U = 4;  // records loaded together per lane
+  __shared__ float s_ff[4][NSUM][2];
+  __shared__ uint64_t s_c64[4][2];
+  __shared__ uint32_t s_c32[4][9];
+  PState* st = A.st;
+  if (ncodes <= 0) return;
+  const int64_t nwg = A.nwg;
+  const PParts P = pparts(A.parts, (int64_t)A.maxcodes * nwg);
+  // Lc lanes per code (power of two), every lane accumulating all fields of
+  // the records k, k + Lc, ... of its code in that order
+  int Lc = 256;
+  while (Lc > 1 && Lc * ncodes > 256) Lc >>= 1;
+  const int per_round = 256 / Lc;
+  const bool hist = A.hist != 0;
+  for (int c0 = 0; c0 < ncodes; c0 += per_round) {
+    const int ci = c0 + (int)threadIdx.x / Lc;
+    const int k = (int)threadIdx.x % Lc;
+    const bool on = ci < ncodes;
+    const int64_t r0 = (int64_t)(on ? ci : 0) * nwg;
+    FF acc[NSUM];
+#pragma unroll
+    for (int i = 0; i < NSUM; i++) acc[i] = {0.f, 0.f};
+    uint64_t w = 0, dm = 0;
+    uint32_t fit = 0, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t q0 = on ? k : nwg; q0 < nwg; q0 += (int64_t)U * Lc) {
+      float2 v[NSUM][U];
+      uint64_t wv[U], dv[U];
+      uint32_t fv[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int64_t q = q0 + (int64_t)u * Lc;
+        const bool in = q < nwg;
+#pragma unroll
+        for (int i = 0; i < NSUM; i++)
+          v[i][u] = (in && i >= i0 && i < i1) ? P.s[(int64_t)i * P.R + r0 + q] : float2{0.f, 0.f};
+        wv[u] = in ? P.words[r0 + q] : 0;
+        dv[u] = in ? P.dmax[r0 + q] : 0;
+        fv[u] = in ? P.nfit[r0 + q] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+#pragma unroll
+        for (int i = 0; i < NSUM; i++)
+          if (i >= i0 && i < i1) acc[i] = ff_add(acc[i], FF{v[i][u].x, v[i][u].y});
+        w += wv[u];
+        dm = dv[u] > dm ? dv[u] : dm;
+        fit += fv[u];
+      }
+      if (hist) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const int64_t q = q0 + (int64_t)u * Lc;
+          uint32_t hv[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) hv[t] = q < nwg ? P.hist[(int64_t)t * P.R + r0 + q] : 0;
+#pragma unroll
+          for (int t = 0; t < 8; t++) h[t] += hv[t];
+        }
+      }
+    }
+    // butterfly inside the code's lanes of one wave
+    const int Lw = Lc < 64 ? Lc : 64;
+    for (int o = 1; o < Lw; o <<= 1) {
+#pragma unroll
+      for (int i = 0; i < NSUM; i++)
+        if (i >= i0 && i < i1) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
+      w += (uint64_t)__shfl_xor((unsigned long long)w, o, 64);
+      const uint64_t d2 = (uint64_t)__shfl_xor((unsigned long long)dm, o, 64);
+      dm = d2 > dm ? d2 : dm;
+      fit += __shfl_xor(fit, o, 64);
+#pragma unroll
+      for (int t = 0; t < 8; t++) h[t] += __shfl_xor(h[t], o, 64);
+    }
+    // codes spanning several waves (Lc > 64): merge the waves in order
+    if (Lc > 64) {
+      const int wave = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < NSUM; i++) { s_ff[wave][i][0] = acc[i].hi; s_ff[wave][i][1] = acc[i].lo; }
+        s_c64[wave][0] = w;
+        s_c64[wave][1] = dm;
+        s_c32[wave][0] = fit;
+#pragma unroll
+        for (int t = 0; t < 8; t++) s_c32[wave][1 + t] = h[t];
+      }
+      __syncthreads();
+      if (k == 0) {
+        const int w0 = (int)threadIdx.x >> 6, nw = Lc / 64;
+        for (int j = 1; j < nw; j++) {
+#pragma unroll
+          for (int i = 0; i < NSUM; i++) acc[i] = ff_add(acc[i], FF{s_ff[w0 + j][i][0], s_ff[w0 + j][i][1]});
+          w += s_c64[w0 + j][0];
+          dm = s_c64[w0 + j][1] > dm ? s_c64[w0 + j][1] : dm;
+          fit += s_c32[w0 + j][0];
+#pragma unroll
+          for (int t = 0; t < 8; t++) h[t] += s_c32[w0 + j][1 + t];
+        }
+      }
+      __syncthreads();
+    }
+    if (on && k == 0) {
+#pragma unroll
+      for (int i = 0; i < NSUM; i++)
+        if (i >= i0 && i < i1) st->sums[ci][i] = (double)acc[i].hi + (double)acc[i].lo;
+      if (A.op == P_FITS) {
+        st->fits[ci] = fit;
+        if (hist && ci == 0)
+          for (int t = 0; t < 8; t++) st->hist[t] = h[t];
+      } else if (A.op == P_STATS) {
+        st->words[ci] = w;
+        if (!A.curve) st->maxbits[1] = dm;
+      }
+    }
+  }
+}
+
 template <typename T, int LPB, int NDIM>
 __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   constexpr int BPW = 64 / LPB;
@@ -96,13 +313,17 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   const Geo& g = A.g;
   PState* st = A.st;
   __shared__ float s_red[WPG][NSUM][2];
+  __shared__ uint64_t s_w[WPG], s_dm[WPG];
+  __shared__ uint32_t s_fit[WPG], s_hist[WPG][8];
   __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
 
   const int ci = blockIdx.y;
-  if (ci >= st->ncodes) return;  // uniform per workgroup
+  const int nset = A.final_code ? 1 : st->ncodes;
+  const int ncodes = nset < (int)gridDim.y ? nset : (int)gridDim.y;
+  if (ci >= ncodes) return;  // uniform per workgroup
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
-  const int code = st->codes[ci];
+  const int code = A.final_code ? st->code : st->codes[ci];
   const int escale = st->escale;
   uint32_t mask;
   if (A.mask_sel == 0) mask = st->mask_probe;
@@ -116,13 +337,15 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   for (int i = 0; i < NSUM; i++) acc[i] = {0.f, 0.f};
   double dmax = 0.0;
   uint32_t nfit = 0;
+  uint32_t hcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // wave-uniform
   unsigned long long wsum = 0;
 
   for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += A.nwg) {
     const int64_t jj = (tile * WPG + wave) * BPW + lane / LPB;
     B_ b;
     b.init(g, jj < A.nbe ? jj * A.jstride : g.nblocks, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
-    b.load((const T*)A.x, g);
+    if (A.op == P_CENTER && A.rule != R_QUALITY) b.template load<false>((const T*)A.x, g);
+    else b.load((const T*)A.x, g);
     int32_t a[4], v[7][4];
     int eps[7], pw[7];
     Costs C;
@@ -133,9 +356,11 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       b.quantize(c, A.rule == R_LOSSLESS, a);
       b.sizes(g, mask, a, v, eps, pw, C);
       int s_ = B_::argmin(C, mask, best);
-      if (b.blk_ok && b.L.gi == 0) {
-        if (best <= 32 * g.budget) nfit++;
-        if (A.hist) atomicAdd(&st->hist[s_], 1u);
+      if (b.blk_ok && b.L.gi == 0 && best <= 32 * g.budget) nfit++;
+      if (A.hist) {
+        const bool lead = b.blk_ok && b.L.gi == 0;
+#pragma unroll
+        for (int t = 0; t < 8; t++) hcnt[t] += (uint32_t)__popcll(__ballot(lead && s_ == t));
       }
       continue;
     }
@@ -183,15 +408,17 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       else y = (double)to_out<T>(dequant(a[k], c));
       double d = x - y;
       if (A.op == P_STATS) {
-        t[S_X] += x;
-        t[S_Y] += y;
-        t[S_D] += d;
+        if (!A.curve) {
+          t[S_X] += x;
+          t[S_Y] += y;
+          t[S_D] += d;
+          double ad = __builtin_fabs(d);
+          dmax = ad > dmax ? ad : dmax;
+        }
         t[S_XX] += x * x;
         t[S_YY] += y * y;
         t[S_DD] += d * d;
         t[S_DS] += d * (x + y);
-        double ad = __builtin_fabs(d);
-        dmax = ad > dmax ? ad : dmax;
       } else {
         double ex = x - mx, ey = y - my, ed = d - md;
         t[S_CXX] += ex * ex;
@@ -200,8 +427,10 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       }
     }
     if (A.op == P_STATS) {
+      if (!A.curve) {
 #pragma unroll
-      for (int i = S_X; i <= S_D; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s1));
+        for (int i = S_X; i <= S_D; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s1));
+      }
 #pragma unroll
       for (int i = S_XX; i <= S_DS; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s2));
     } else {
@@ -210,14 +439,8 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     }
   }
 
-  if (A.op == P_FITS) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) nfit += __shfl_xor(nfit, o, 64);
-    if (lane == 0 && nfit) atomicAdd(&st->fits[ci], nfit);
-    return;
-  }
-  // wave reduction of the sums this op produced
-  const int i0 = A.op == P_STATS ? 0 : S_CXX;
+  // ---- workgroup partial record
+  const int i0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : (A.op == P_CENTER ? S_CXX : NSUM);
   const int i1 = A.op == P_STATS ? S_CXX : NSUM;
 #pragma unroll
   for (int i = 0; i < NSUM; i++) {
@@ -225,17 +448,12 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
   }
-  if (A.op == P_STATS) {
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      double tt = __shfl_xor(dmax, o, 64);
-      dmax = tt > dmax ? tt : dmax;
-      wsum += __shfl_xor(wsum, o, 64);
-    }
-    if (lane == 0) {
-      atomicMax((unsigned long long*)&st->maxbits[1], (unsigned long long)__builtin_bit_cast(uint64_t, dmax));
-      if (wsum) atomicAdd((unsigned long long*)&st->words[ci], wsum);
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    double tt = __shfl_xor(dmax, o, 64);
+    dmax = tt > dmax ? tt : dmax;
+    wsum += __shfl_xor(wsum, o, 64);
+    nfit += __shfl_xor(nfit, o, 64);
   }
   if (lane == 0) {
 #pragma unroll
@@ -243,42 +461,60 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       s_red[wave][i][0] = acc[i].hi;
       s_red[wave][i][1] = acc[i].lo;
     }
+    s_w[wave] = wsum;
+    s_dm[wave] = __builtin_bit_cast(uint64_t, dmax);
+    s_fit[wave] = nfit;
+#pragma unroll
+    for (int t = 0; t < 8; t++) s_hist[wave][t] = hcnt[t];
   }
   __syncthreads();
+  const PParts P = pparts(A.parts, (int64_t)gridDim.y * A.nwg);
+  const int64_t r = (int64_t)ci * A.nwg + blockIdx.x;
   if (threadIdx.x < NSUM) {
-    int i = threadIdx.x;
+    const int i = threadIdx.x;
     FF tt = {s_red[0][i][0], s_red[0][i][1]};
     for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
-    float* p = A.partials + (((int64_t)ci * A.nwg + blockIdx.x) * NSUM + i) * 2;
-    p[0] = tt.hi;
-    p[1] = tt.lo;
+    P.s[(int64_t)i * P.R + r] = float2{tt.hi, tt.lo};
+  } else if (threadIdx.x == 64) {
+    uint64_t ww = 0, dm = 0;
+    uint32_t nf = 0;
+    for (int w = 0; w < WPG; w++) {
+      ww += s_w[w];
+      dm = s_dm[w] > dm ? s_dm[w] : dm;
+      nf += s_fit[w];
+    }
+    P.words[r] = ww;
+    P.dmax[r] = dm;
+    P.nfit[r] = nf;
+  } else if (threadIdx.x >= 128 && threadIdx.x < 136) {
+    const int t = threadIdx.x - 128;
+    uint32_t h = 0;
+    for (int w = 0; w < WPG; w++) h += s_hist[w][t];
+    P.hist[(int64_t)t * P.R + r] = h;
   }
 }
 
-// Fixed-order reduction of the per-workgroup partials of every code.
-__global__ __launch_bounds__(256) void k_finalize(const float* partials, int64_t nwg, PState* st) {
-  __shared__ float s[256][2];
-  const int ci = blockIdx.x / NSUM, i = blockIdx.x % NSUM;
-  if (ci >= st->ncodes) return;
-  FF acc = {0.f, 0.f};
-  for (int64_t t = threadIdx.x; t < nwg; t += 256) {
-    const float* p = partials + ((ci * nwg + t) * NSUM + i) * 2;
-    acc = ff_add(acc, FF{p[0], p[1]});
-  }
-  s[threadIdx.x][0] = acc.hi;
-  s[threadIdx.x][1] = acc.lo;
+// One workgroup: fixed-order reduction of the records of the preceding
+// pass, then its control step.
+__global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
+  __shared__ PState s_st;
+  st_copy((uint32_t*)&s_st, (const uint32_t*)A.st);
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      FF a = {s[threadIdx.x][0], s[threadIdx.x][1]};
-      FF b = {s[threadIdx.x + w][0], s[threadIdx.x + w][1]};
-      FF r = ff_add(a, b);
-      s[threadIdx.x][0] = r.hi;
-      s[threadIdx.x][1] = r.lo;
-    }
-    __syncthreads();
+  ProfArgs B = A;
+  B.st = &s_st;
+  const int nset = A.final_code ? 1 : s_st.ncodes;
+  const int ncodes = nset < A.maxcodes ? nset : A.maxcodes;
+  const int i0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : (A.op == P_CENTER ? S_CXX : NSUM);
+  const int i1 = A.op == P_STATS ? S_CXX : NSUM;
+  reduce_parts(B, ncodes, i0, i1);
+  __syncthreads();
+  if (threadIdx.x == 0 && A.C.step != C_NONE) {
+    CtlArgs C = A.C;
+    C.st = &s_st;
+    ctl_step(C);
   }
-  if (threadIdx.x == 0) st->sums[ci][i] = (double)s[0][0] + (double)s[0][1];
+  __syncthreads();
+  st_copy((uint32_t*)A.st, (const uint32_t*)&s_st);
 }
 
 // ---------------------------------------------------------------- control
@@ -325,8 +561,7 @@ __device__ void ctl_zero(PState* st) {
   for (int i = 0; i < MAXCODES; i++) { st->fits[i] = 0; st->words[i] = 0; }
 }
 
-__global__ void k_ctl(CtlArgs C) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void ctl_step(const CtlArgs& C) {
   PState* st = C.st;
   const bool fr = C.mode == M_RATE;
   switch (C.step) {
@@ -449,6 +684,10 @@ __global__ void k_ctl(CtlArgs C) {
   }
 }
 
+__global__ void k_ctl(CtlArgs C) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl_step(C);
+}
+
 int64_t prof_tiles(const Geo& g, int64_t nbe) {
   int lpb = g.G <= 16 ? 16 : (g.G <= 32 ? 32 : 64);
   int64_t per = (int64_t)WPG * (64 / lpb);
@@ -486,33 +725,34 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
   A.ntiles = prof_tiles(A.g, A.nbe);
   A.nwg = prof_wgs(A.ntiles, A.maxcodes);
   if (A.ntiles == 0) return hipSuccess;
+  hipError_t e;
   switch (dtype) {
-    case DT_I8: return launch_nd<int8_t>(A, ndim, s);
-    case DT_I16: return launch_nd<int16_t>(A, ndim, s);
-    case DT_I32: return launch_nd<int32_t>(A, ndim, s);
-    case DT_F32: return launch_nd<float>(A, ndim, s);
-    default: return launch_nd<double>(A, ndim, s);
+    case DT_I8: e = launch_nd<int8_t>(A, ndim, s); break;
+    case DT_I16: e = launch_nd<int16_t>(A, ndim, s); break;
+    case DT_I32: e = launch_nd<int32_t>(A, ndim, s); break;
+    case DT_F32: e = launch_nd<float>(A, ndim, s); break;
+    default: e = launch_nd<double>(A, ndim, s); break;
   }
-}
-
-hipError_t launch_finalize(const float* partials, int64_t nwg, int maxcodes, PState* st,
-                           hipStream_t s) {
-  if (nwg == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)(maxcodes * NSUM)), dim3(256), 0, s, partials,
-                     nwg, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
-hipError_t launch_pmax(int dtype, const void* x, uint64_t n, PState* st, hipStream_t s) {
+hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,
+                       hipStream_t s) {
   if (n == 0) return hipSuccess;
-  unsigned grid = 2048;
+  const unsigned grid = PMAX_WGS;
+  PMaxPart* P = reinterpret_cast<PMaxPart*>(parts);
   switch (dtype) {
-    case DT_I8: hipLaunchKernelGGL(k_pmax<int8_t>, dim3(grid), dim3(256), 0, s, (const int8_t*)x, n, st); break;
-    case DT_I16: hipLaunchKernelGGL(k_pmax<int16_t>, dim3(grid), dim3(256), 0, s, (const int16_t*)x, n, st); break;
-    case DT_I32: hipLaunchKernelGGL(k_pmax<int32_t>, dim3(grid), dim3(256), 0, s, (const int32_t*)x, n, st); break;
-    case DT_F32: hipLaunchKernelGGL(k_pmax<float>, dim3(grid), dim3(256), 0, s, (const float*)x, n, st); break;
-    default: hipLaunchKernelGGL(k_pmax<double>, dim3(grid), dim3(256), 0, s, (const double*)x, n, st); break;
+    case DT_I8: hipLaunchKernelGGL(k_pmax<int8_t>, dim3(grid), dim3(256), 0, s, (const int8_t*)x, n, P); break;
+    case DT_I16: hipLaunchKernelGGL(k_pmax<int16_t>, dim3(grid), dim3(256), 0, s, (const int16_t*)x, n, P); break;
+    case DT_I32: hipLaunchKernelGGL(k_pmax<int32_t>, dim3(grid), dim3(256), 0, s, (const int32_t*)x, n, P); break;
+    case DT_F32: hipLaunchKernelGGL(k_pmax<float>, dim3(grid), dim3(256), 0, s, (const float*)x, n, P); break;
+    default: hipLaunchKernelGGL(k_pmax<double>, dim3(grid), dim3(256), 0, s, (const double*)x, n, P); break;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pmax_reduce, dim3(1), dim3(256), 0, s, (const PMaxPart*)P, (int)grid, C);
   return hipGetLastError();
 }
 
