@@ -27,7 +27,6 @@ METRIC = "encode/decode GB/s (uncompressed bytes) and % HBM peak at fixed ratio,
 def read_traffic(kernel: str):
     """HBM bytes per launch from the rocprofv3 PMC summary, if it was taken on
     the current kernel sources (a source digest is recorded with it)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_c1.txt")
     if not os.path.exists(path):
         return None
@@ -36,14 +35,62 @@ def read_traffic(kernel: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest():
+        return None
+    v = kv.get(f"{kernel}_hbm_bytes_per_launch")
+    return float(v) if v else None
+
+
+def source_digest() -> str:
+    import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1303_4994_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         h.update(open(os.path.join(csrc, f), "rb").read())
-    if kv.get("source_sha256") != h.hexdigest()[:16]:
-        return None
-    v = kv.get(f"{kernel}_hbm_bytes_per_launch")
-    return float(v) if v else None
+    return h.hexdigest()[:16]
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str):
+    """HBM bytes per launch of the codec kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the plain 64 MiB copy of --copy-probe."""
+    import csv
+    import collections
+
+    def per_kernel(path, counter):
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals[r["Kernel_Name"].split("(")[0]].append(float(r["Counter_Value"]))
+        return vals
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    copy_bytes = 64 * 1024 * 1024
+
+    def copy_factor(vals):
+        big = [v for k, vs in vals.items() if "copyBuffer" in k or "copy" in k.lower() for v in vs]
+        big = [v for v in big if v * 1024 > copy_bytes / 2]
+        return copy_bytes / (sum(big) / len(big) * 1024) if big else None
+    ff, fw = copy_factor(f), copy_factor(w)
+    lines = ["# HBM traffic of the codec kernels, C1 workload (4096x4096 fp32, 16x16 bricks, 4:1)",
+             f"# command (fetch): {command} FETCH_SIZE", f"# command (write): {command} WRITE_SIZE",
+             "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
+             "# the counter's reading for a plain 64 MiB device copy onto 64 MiB",
+             f"source_sha256: {source_digest()}",
+             f"copy_factor_fetch: {ff}", f"copy_factor_write: {fw}"]
+    for k in sorted(set(f) | set(w)):
+        if not k.startswith("void apax::") and "apax::" not in k:
+            continue
+        fv = sum(f.get(k, [0])) / max(1, len(f.get(k, [0])))
+        wv = sum(w.get(k, [0])) / max(1, len(w.get(k, [0])))
+        name = k.split("apax::")[1].split("<")[0]
+        fb = fv * 1024 * (ff or 1.0)
+        wb = wv * 1024 * (fw or 1.0)
+        lines.append(f"{name}<{k.split('<', 1)[1] if '<' in k else ''}: fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
+        if name in ("k_encode", "k_decode") and "float, 64, 2" in k:
+            lines.append(f"{name}_hbm_bytes_per_launch: {fb + wb:.0f}")
+    open(out_path, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def cpu_baseline(x, params):
@@ -75,7 +122,15 @@ def main():
     ap.add_argument("--pool", type=int, default=1 << 26, help="batch/serve: samples per pool")
     ap.add_argument("--copy-probe", action="store_true",
                     help="c1: also run a plain 64 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_c1.txt from two rocprofv3 --pmc counter CSVs")
     args = ap.parse_args()
+    if args.traffic_from:
+        cmd = ("rocprofv3 --pmc <counter> --output-format csv -- python3 bench.py --steps 2 "
+               "--warmup 1 --no-cpu-baseline --copy-probe")
+        traffic_summary(args.traffic_from[0], args.traffic_from[1],
+                        os.path.join(ROOT, "profiles", "traffic_c1.txt"), cmd)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU design is described, not built", file=sys.stderr)
@@ -138,10 +193,27 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     assert A.apax_status(ws) == 0
-    enc_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    dec_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
     ms_step = (t1 - t0) * 1e3 / args.steps
-    prof_ms = ms_step - enc_ms - dec_ms
+    enc_in_step = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    dec_in_step = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    prof_ms = ms_step - enc_in_step - dec_in_step
+
+    # per-launch kernel time: back-to-back launches over the rotating copies,
+    # HIP events on the launch stream around the whole run
+    p_last = dict(params, code=prof["code"], stream_mask=prof["stream_mask"] & 0x7F)
+    reps = max(8, args.steps)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    for k in range(reps):
+        A.apax_encode(xs[k % R], p_last, out=bufs[k % R], nbytes=nbt, ws=ws, clear_status=False)
+    e1.record(stream)
+    for k in range(reps):
+        A.apax_decode(bufs[k % R], bound, hdr=step.hdr, y=ys[k % R], ws=ws, clear_status=False)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    enc_ms = e0.elapsed_time(e1) / reps
+    dec_ms = e1.elapsed_time(e2) / reps
 
     # the decoded field reproduces the profiler's correlation (checked outside timing)
     yd = ys[(args.steps - 1) % R].double()
@@ -182,6 +254,7 @@ def main():
         "decode_pct_hbm": round(100 * dec_gbps / HBM_PEAK_GBPS, 2),
         "encode_ms": round(enc_ms, 4),
         "decode_ms": round(dec_ms, 4),
+        "kernel_timing": f"mean of {reps} back-to-back launches between HIP events on the launch stream",
         "profile_ms": round(prof_ms, 4),
         "ratio": round(ratio, 4),
         "r": prof["metrics"]["r"],
