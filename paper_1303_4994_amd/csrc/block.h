@@ -42,6 +42,10 @@ template <int NDIM, int LPB>
 __device__ __forceinline__ int64_t group_index(const Geo& g, const LaneMap<LPB>& L, int64_t j,
                                                int& nvalid) {
   int64_t X, Y = 0, Z = 0;
+  if constexpr (LPB == 64) {  // one block per wave: block coordinates on the scalar unit
+    j = ((int64_t)__builtin_amdgcn_readfirstlane((int)(j >> 32)) << 32) |
+        (uint32_t)__builtin_amdgcn_readfirstlane((int)j);
+  }
   if constexpr (NDIM == 1) {
     X = j * (int64_t)g.b[2] + 4 * L.xq;
   } else {
@@ -124,6 +128,7 @@ struct Blk {
   double M;      // block max |x| (segment-uniform)
   int cf, cc;    // code bracket (segment-uniform)
   bool nonfinite;
+  bool full;     // wave-uniform: every lane holds 4 valid samples of a real block
   uint64_t vpos; // ballot: lanes with a JEE position (1 <= gi < G)
   uint4* xch;    // per-wave LDS exchange (64 entries), used for NDIM >= 2
 
@@ -144,6 +149,7 @@ struct Blk {
     int64_t idx = -1;
     nvalid = 0;
     if (act) idx = group_index<NDIM, LPB>(g, L, j, nvalid);
+    full = __ballot(nvalid != 4) == 0;
     load4<T>(x, idx, nvalid, v);
     bool nf = false;
 #pragma unroll
@@ -197,6 +203,11 @@ struct Blk {
   // quantized samples at code c (lossless: the integers themselves)
   __device__ __forceinline__ void quantize(int c, bool lossless, int32_t a[4]) const {
     double gv = gain_of(c);
+    if (full) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) a[k] = lossless ? (int32_t)xd[k] : quant(xd[k], gv);
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       int32_t q = lossless ? (int32_t)xd[k] : quant(xd[k], gv);
@@ -204,8 +215,10 @@ struct Blk {
     }
   }
 
-  // candidate streams 0..6 (only those of NDIM are formed), mod 2^W, 0 past the edge
-  __device__ __forceinline__ void streams(const Geo& g, const int32_t a[4], int32_t v[7][4]) const {
+  // candidate streams 0..6 (only those of NDIM in `need` are formed; `need`
+  // is wave-uniform), mod 2^W, 0 past the edge
+  __device__ __forceinline__ void streams(const Geo& g, const int32_t a[4], int32_t v[7][4],
+                                          uint32_t need = 0x7Fu) const {
     uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
     uint32_t p3 = shr1(A[3]), p2 = shr1(A[2]);
     if (!L.hx) { p3 = 0; p2 = 0; }
@@ -220,7 +233,7 @@ struct Blk {
     s[2][3] = d[3] - d[2];
 #pragma unroll
     for (int k = 0; k < 4; k++) { s[3][k] = 0; s[4][k] = 0; s[5][k] = 0; s[6][k] = 0; }
-    if constexpr (NDIM >= 2) {
+    if (NDIM >= 2 && (need & 0x78u)) {
       const int lane = L.lane;
       xch[lane] = make_uint4(A[0], A[1], A[2], A[3]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -263,9 +276,20 @@ struct Blk {
       __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
-    for (int t = 0; t < 7; t++)
+    for (int t = 0; t < 7; t++) {
+      if (!((NDMASK & need) >> t & 1)) {
 #pragma unroll
-      for (int k = 0; k < 4; k++) v[t][k] = valid(k) ? wrapw<W>(s[t][k]) : 0;
+        for (int k = 0; k < 4; k++) v[t][k] = 0;
+        continue;
+      }
+      if (full) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[t][k] = wrapw<W>(s[t][k]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[t][k] = valid(k) ? wrapw<W>(s[t][k]) : 0;
+      }
+    }
   }
 
   // JEE token nibbles of one stream for each segment's block (value of this lane's segment)
@@ -285,14 +309,14 @@ struct Blk {
   // and payload widths (zero for lanes without a group)
   __device__ __forceinline__ void sizes(const Geo& g, uint32_t mask, const int32_t a[4],
                                         int32_t v[7][4], int eps[7], int pw[7], Costs& C) const {
-    streams(g, a, v);
+    streams(g, a, v, mask);
 #pragma unroll
     for (int t = 0; t < 7; t++) {
       eps[t] = 0;
       pw[t] = 0;
-      if ((NDMASK >> t) & 1) {
+      if ((NDMASK & mask) >> t & 1) {  // mask is wave-uniform
         group_eps<W>(v[t], eps[t], pw[t]);
-        if (!act) { eps[t] = 0; pw[t] = 0; }
+        if (!full && !act) { eps[t] = 0; pw[t] = 0; }
       }
     }
     // payload: two streams per 32-bit scan (each segment total <= 64 * 32)
@@ -321,12 +345,25 @@ struct Blk {
     select_stream(st, v, vv);
     int e, p;
     group_eps<W>(vv, e, p);
-    if (!act) { e = 0; p = 0; }
+    if (!full && !act) { e = 0; p = 0; }
     uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)p), L.seg);
     return H + 4 * token_nibbles(e) + 4 * (int)tot;
   }
 
   __device__ __forceinline__ static void select_stream(int st, const int32_t v[7][4], int32_t vv[4]) {
+    if constexpr (LPB == 64) {  // st is wave-uniform: a scalar branch
+      const int su = __builtin_amdgcn_readfirstlane(st);
+#pragma unroll
+      for (int t = 0; t < 7; t++)
+        if (((NDMASK >> t) & 1) && su == t) {
+#pragma unroll
+          for (int k = 0; k < 4; k++) vv[k] = v[t][k];
+          return;
+        }
+#pragma unroll
+      for (int k = 0; k < 4; k++) vv[k] = 0;
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       uint32_t r = 0;
@@ -338,6 +375,13 @@ struct Blk {
   }
 
   __device__ __forceinline__ static int pick_int(int st, const int x[7]) {
+    if constexpr (LPB == 64) {
+      const int su = __builtin_amdgcn_readfirstlane(st);
+#pragma unroll
+      for (int t = 0; t < 7; t++)
+        if (((NDMASK >> t) & 1) && su == t) return x[t];
+      return 0;
+    }
     uint32_t r = 0;
 #pragma unroll
     for (int t = 0; t < 7; t++)
@@ -362,6 +406,13 @@ struct Blk {
     return (int32_t)r;
   }
 
+  // streams a probe of stream st needs: st alone when one block fills the
+  // wave (st is then wave-uniform), else every allowed stream
+  __device__ __forceinline__ static uint32_t need_mask(int st, uint32_t mask) {
+    if constexpr (LPB == 64) return 1u << __builtin_amdgcn_readfirstlane(st);
+    else return mask | 1u;
+  }
+
   // Fixed-rate per-block gain search (cap and descend; reading of the
   // adaptive loop, Sec. 6), from an evaluation at the start code c0 that
   // chose stream st.  Returns the final code (c0 when the block fits there).
@@ -376,7 +427,7 @@ struct Blk {
       if (++guard > 4096) break;  // unreachable: c_floor always fits a valid budget
       int ct = done ? c : (c - 16 < cf ? cf : c - 16);
       quantize(ct, false, a);
-      streams(g, a, v);
+      streams(g, a, v, need_mask(st, g.mask));
       int s_of = size_of(st, v);
       if (!done) {
         if (s_of <= budget_bits) { done = true; lo = ct; }
@@ -390,7 +441,7 @@ struct Blk {
       bool on = hi - lo > 1;
       int mid = lo + ((hi - lo) >> 1);
       quantize(on ? mid : lo, false, a);
-      streams(g, a, v);
+      streams(g, a, v, need_mask(st, g.mask));
       int s_of = size_of(st, v);
       if (on) {
         if (s_of <= budget_bits) lo = mid;

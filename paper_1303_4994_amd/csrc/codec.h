@@ -59,20 +59,16 @@ __device__ __forceinline__ double gain_of(int c) {
 }
 
 // Largest code in [cmin, cmax] with fl64(M * g(c)) <= lim (M * g(cmin) <=
-// lim holds for every finite M).  An estimate from the exponent of lim / M is
-// corrected by exact tests of the predicate (monotone in c).
-__device__ __forceinline__ int largest_code(double M, double lim, int cmin, int cmax) {
+// lim holds for every finite M).  The predicate is monotone in c, so an
+// estimate corrected by exact tests gives the answer whatever the estimate.
+// Estimate for lim near 2^L: with M = m 2^e (m in [0.5, 1)) and r = 1/(2m),
+// g(c) = (16 + f) 2^(k-4) fits for k = L - e and f <= 32 r - 16.
+__device__ __forceinline__ int largest_code(double M, double lim, int L, int cmin, int cmax) {
   if (M == 0.0) return cmax;
-  double q = lim / M;
-  int c;
-  if (!(q < 1.0e300)) {
-    c = cmax;
-  } else {
-    int e;
-    double m = frexp(q, &e);           // q = m 2^e, m in [0.5, 1)
-    int f = (int)((2.0 * m - 1.0) * 16.0);
-    c = 16 * (e - 1) + f;
-  }
+  const int e = __builtin_amdgcn_frexp_exp(M);
+  const double m = __builtin_amdgcn_frexp_mant(M);
+  const double r = __builtin_amdgcn_rcp(2.0 * m);
+  int c = 16 * (L - e) + (int)(32.0 * r - 16.0);
   c = c > cmax ? cmax : (c < cmin ? cmin : c);
   while (c < cmax && M * gain_of(c + 1) <= lim) c++;
   while (c > cmin && !(M * gain_of(c) <= lim)) c--;
@@ -85,13 +81,13 @@ __device__ __forceinline__ int largest_code(double M, double lim, int cmin, int 
 // one code less.
 template <typename T>
 __device__ __forceinline__ void bracket(double M, int cmin, int cmax, int& cf, int& cc) {
-  cf = largest_code(M, 0.5, cmin, cmax);
+  cf = largest_code(M, 0.5, -1, cmin, cmax);
   if constexpr (Traits<T>::isint) {
     cc = 0;
   } else {
     if (cf + 512 >= cmax) {
       cc = (cf + 511 >= cmax || M * gain_of(cmax) <= 2147483647.0) ? cmax : cmax - 1;
-      if (!(M * gain_of(cc) <= 2147483647.0)) cc = largest_code(M, 2147483647.0, cmin, cmax);
+      if (!(M * gain_of(cc) <= 2147483647.0)) cc = largest_code(M, 2147483647.0, 31, cmin, cmax);
     } else {
       cc = M * gain_of(cf + 512) <= 2147483647.0 ? cf + 512 : cf + 511;
     }
