@@ -174,7 +174,7 @@ typedef struct apax_batch_item {
 typedef struct apax_tune {
   uint32_t waves_per_wg;     /* 2, 4 or 8 (0 = 4) */
   uint32_t wgs_per_cu;       /* persistent workgroups per compute unit (0 = 8) */
-  uint32_t tiles_per_ticket; /* tiles taken per atomic ticket (0 = 1) */
+  uint32_t tiles_per_ticket; /* tiles taken per atomic ticket (0 = 4; encode uses at most 4) */
   uint32_t reserved;
 } apax_tune;
 

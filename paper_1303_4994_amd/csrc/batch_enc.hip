@@ -1,63 +1,77 @@
 // batch_enc.hip -- persistent batch encoder: thousands of arrays of mixed
 // dtypes and sizes in one launch per (LPB, NDIM) class.  Workgroups take
-// runs of tiles from an atomic ticket; every tile belongs to one item and is
-// encoded exactly as the single-array kernel would (same tile body), so the
-// output is byte-identical to separate calls.  Tickets are handed out in
-// increasing order, so each item's tiles start in order and its look-back
-// only waits on tiles already taken by running workgroups.
+// runs of up to RUN consecutive global tiles from an atomic ticket (a run may
+// span items); every tile is encoded exactly as the single-array kernel
+// would (same analyse / place / store phases), so the output is
+// byte-identical to separate calls.
+#include "batch.h"
 #include "encode_tile.h"
 
 namespace apax {
 
-// Item owning global tile u: the largest i with starts[i] <= u, found by a
-// 64-ary search (one ballot per round) on wave 0.
-__device__ __forceinline__ uint32_t find_item(const int64_t* starts, uint32_t n, int64_t u) {
-  uint32_t lo = 0, hi = n;
-  const int lane = lane_id();
-  while (hi - lo > 1) {
-    uint32_t step = (hi - lo + 63) / 64;
-    uint32_t idx = lo + (uint32_t)lane * step;
-    bool ok = idx < hi && starts[idx] <= u;
-    uint64_t m = __ballot(ok);
-    int k = 63 - __clzll((long long)m);
-    lo = lo + (uint32_t)k * step;
-    uint32_t h2 = lo + step;
-    hi = h2 < hi ? h2 : hi;
-  }
-  return lo;
-}
-
 template <int LPB, int NDIM, int WP>
 __global__ __launch_bounds__(WP * 64) void k_encode_batch(BatchArgs B) {
+  constexpr int BPW = 64 / LPB;
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared<WP> sm;
   __shared__ uint32_t s_u, s_item;
   const BatchEnc* items = (const BatchEnc*)B.items;
+  const int per = (int)(B.tiles_per_ticket < (uint32_t)RUN ? B.tiles_per_ticket : (uint32_t)RUN);
+  uint32_t it = 0;
+  int64_t it_lo = 0, it_hi = 0;  // tiles [it_lo, it_hi) belong to item it (uniform)
   for (;;) {
-    if (threadIdx.x == 0) s_u = atomicAdd(B.ticket, B.tiles_per_ticket);
+    if (threadIdx.x == 0) s_u = atomicAdd(B.ticket, (uint32_t)per);
     __syncthreads();
     const int64_t u0 = (int64_t)s_u;
     __syncthreads();
     if (u0 >= B.total_tiles) break;
-    const int64_t u1 = u0 + B.tiles_per_ticket < B.total_tiles ? u0 + B.tiles_per_ticket : B.total_tiles;
-    for (int64_t u = u0; u < u1; u++) {
-      if (threadIdx.x < 64) {
-        uint32_t it = find_item(B.starts, B.n, u);
-        if (threadIdx.x == 0) s_item = it;
+    const int n = B.total_tiles - u0 < per ? (int)(B.total_tiles - u0) : per;
+    // phase 1: analyse and assemble every tile of the run, publish its count
+#pragma unroll 1
+    for (int r = 0; r < n; r++) {
+      const int64_t u = u0 + r;
+      if (u < it_lo || u >= it_hi) {
+        if (threadIdx.x < 64) {
+          const uint32_t f = find_item(B.starts, B.n, u);
+          if (threadIdx.x == 0) s_item = f;
+        }
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item);
+        it_lo = B.starts[it];
+        it_hi = it + 1 < B.n ? B.starts[it + 1] : B.total_tiles;
+        __syncthreads();
       }
-      __syncthreads();
-      const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+      if (threadIdx.x == 0) sm.item[r] = it;
       const BatchEnc& E = items[it];
       const int64_t t = u - E.tile_start;
       switch (E.dtype) {
-        case DT_I8: encode_tile<int8_t, LPB, NDIM, WP>(E.a, t, sm, lds); break;
-        case DT_I16: encode_tile<int16_t, LPB, NDIM, WP>(E.a, t, sm, lds); break;
-        case DT_I32: encode_tile<int32_t, LPB, NDIM, WP>(E.a, t, sm, lds); break;
-        case DT_F32: encode_tile<float, LPB, NDIM, WP>(E.a, t, sm, lds); break;
-        default: encode_tile<double, LPB, NDIM, WP>(E.a, t, sm, lds); break;
+        case DT_I8: encode_analyze<int8_t, LPB, NDIM, WP>(E.a, t, r, B.ldsw, sm, lds); break;
+        case DT_I16: encode_analyze<int16_t, LPB, NDIM, WP>(E.a, t, r, B.ldsw, sm, lds); break;
+        case DT_I32: encode_analyze<int32_t, LPB, NDIM, WP>(E.a, t, r, B.ldsw, sm, lds); break;
+        case DT_F32: encode_analyze<float, LPB, NDIM, WP>(E.a, t, r, B.ldsw, sm, lds); break;
+        default: encode_analyze<double, LPB, NDIM, WP>(E.a, t, r, B.ldsw, sm, lds); break;
       }
-      __syncthreads();
     }
+    // phase 2 (wave 0, run order): offsets; consecutive tiles of one item chain
+    if ((threadIdx.x >> 6) == 0) {
+      uint64_t base = 0;
+#pragma unroll 1
+      for (int r = 0; r < n; r++) {
+        const uint32_t ir = sm.item[r];
+        const BatchEnc& E = items[ir];
+        const bool chain = r > 0 && sm.item[r - 1] == ir;
+        if (chain) base += sm.agg[r - 1];
+        encode_place<WP, BPW>(E.a, u0 + r - E.tile_start, r, sm, chain, base);
+      }
+    }
+    __syncthreads();
+    // phase 3: stores
+#pragma unroll 1
+    for (int r = 0; r < n; r++) {
+      const BatchEnc& E = items[sm.item[r]];
+      encode_store<LPB, WP>(E.a, u0 + r - E.tile_start, r, B.ldsw, sm, lds);
+    }
+    __syncthreads();
   }
 }
 

@@ -128,7 +128,6 @@ struct Blk {
   double M;      // block max |x| (segment-uniform)
   int cf, cc;    // code bracket (segment-uniform)
   bool nonfinite;
-  bool full;     // wave-uniform: every lane holds 4 valid samples of a real block
   uint64_t vpos; // ballot: lanes with a JEE position (1 <= gi < G)
   uint4* xch;    // per-wave LDS exchange (64 entries), used for NDIM >= 2
 
@@ -149,7 +148,6 @@ struct Blk {
     int64_t idx = -1;
     nvalid = 0;
     if (act) idx = group_index<NDIM, LPB>(g, L, j, nvalid);
-    full = __ballot(nvalid != 4) == 0;
     load4<T>(x, idx, nvalid, v);
     bool nf = false;
 #pragma unroll
@@ -203,11 +201,6 @@ struct Blk {
   // quantized samples at code c (lossless: the integers themselves)
   __device__ __forceinline__ void quantize(int c, bool lossless, int32_t a[4]) const {
     double gv = gain_of(c);
-    if (full) {
-#pragma unroll
-      for (int k = 0; k < 4; k++) a[k] = lossless ? (int32_t)xd[k] : quant(xd[k], gv);
-      return;
-    }
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       int32_t q = lossless ? (int32_t)xd[k] : quant(xd[k], gv);
@@ -282,13 +275,8 @@ struct Blk {
         for (int k = 0; k < 4; k++) v[t][k] = 0;
         continue;
       }
-      if (full) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) v[t][k] = wrapw<W>(s[t][k]);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; k++) v[t][k] = valid(k) ? wrapw<W>(s[t][k]) : 0;
-      }
+      for (int k = 0; k < 4; k++) v[t][k] = valid(k) ? wrapw<W>(s[t][k]) : 0;
     }
   }
 
@@ -316,7 +304,7 @@ struct Blk {
       pw[t] = 0;
       if ((NDMASK & mask) >> t & 1) {  // mask is wave-uniform
         group_eps<W>(v[t], eps[t], pw[t]);
-        if (!full && !act) { eps[t] = 0; pw[t] = 0; }
+        if (!act) { eps[t] = 0; pw[t] = 0; }
       }
     }
     // payload: two streams per 32-bit scan (each segment total <= 64 * 32)
@@ -339,29 +327,40 @@ struct Blk {
     C.sz[7] = ((mask >> 7) & 1) ? H + g.B * W : BIG;
   }
 
-  // size of one stream st (segment-uniform) at the given values
-  __device__ __forceinline__ int size_of(int st, const int32_t v[7][4]) const {
+  // size of one stream st (segment-uniform) at the given values; `only`:
+  // streams() formed stream st alone (the others are zero)
+  __device__ __forceinline__ int size_of(int st, const int32_t v[7][4], bool only = false) const {
     int32_t vv[4];
-    select_stream(st, v, vv);
+    if (only) {
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        uint32_t r = 0;
+#pragma unroll
+        for (int t = 0; t < 7; t++)
+          if ((NDMASK >> t) & 1) r |= (uint32_t)v[t][k];
+        vv[k] = (int32_t)r;
+      }
+    } else {
+      select_stream(st, v, vv);
+    }
     int e, p;
     group_eps<W>(vv, e, p);
-    if (!full && !act) { e = 0; p = 0; }
+    if (!act) { e = 0; p = 0; }
     uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)p), L.seg);
     return H + 4 * token_nibbles(e) + 4 * (int)tot;
   }
 
   __device__ __forceinline__ static void select_stream(int st, const int32_t v[7][4], int32_t vv[4]) {
-    if constexpr (LPB == 64) {  // st is wave-uniform: a scalar branch
+    if constexpr (LPB == 64) {  // st is wave-uniform: conditional moves on a scalar condition
       const int su = __builtin_amdgcn_readfirstlane(st);
 #pragma unroll
-      for (int t = 0; t < 7; t++)
-        if (((NDMASK >> t) & 1) && su == t) {
+      for (int k = 0; k < 4; k++) {
+        int32_t r = 0;
 #pragma unroll
-          for (int k = 0; k < 4; k++) vv[k] = v[t][k];
-          return;
-        }
-#pragma unroll
-      for (int k = 0; k < 4; k++) vv[k] = 0;
+        for (int t = 0; t < 7; t++)
+          if ((NDMASK >> t) & 1) r = su == t ? v[t][k] : r;
+        vv[k] = r;
+      }
       return;
     }
 #pragma unroll
@@ -377,10 +376,11 @@ struct Blk {
   __device__ __forceinline__ static int pick_int(int st, const int x[7]) {
     if constexpr (LPB == 64) {
       const int su = __builtin_amdgcn_readfirstlane(st);
+      int r = 0;
 #pragma unroll
       for (int t = 0; t < 7; t++)
-        if (((NDMASK >> t) & 1) && su == t) return x[t];
-      return 0;
+        if ((NDMASK >> t) & 1) r = su == t ? x[t] : r;
+      return r;
     }
     uint32_t r = 0;
 #pragma unroll
@@ -428,7 +428,7 @@ struct Blk {
       int ct = done ? c : (c - 16 < cf ? cf : c - 16);
       quantize(ct, false, a);
       streams(g, a, v, need_mask(st, g.mask));
-      int s_of = size_of(st, v);
+      int s_of = size_of(st, v, LPB == 64);
       if (!done) {
         if (s_of <= budget_bits) { done = true; lo = ct; }
         else { hi = ct; }
@@ -442,7 +442,7 @@ struct Blk {
       int mid = lo + ((hi - lo) >> 1);
       quantize(on ? mid : lo, false, a);
       streams(g, a, v, need_mask(st, g.mask));
-      int s_of = size_of(st, v);
+      int s_of = size_of(st, v, LPB == 64);
       if (on) {
         if (s_of <= budget_bits) lo = mid;
         else hi = mid;

@@ -603,7 +603,7 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
   apax_tune t = tune ? *tune : apax_tune{};
   if (t.waves_per_wg == 0) t.waves_per_wg = 4;
   if (t.wgs_per_cu == 0) t.wgs_per_cu = 8;
-  if (t.tiles_per_ticket == 0) t.tiles_per_ticket = 1;
+  if (t.tiles_per_ticket == 0) t.tiles_per_ticket = RUN;
   if ((t.waves_per_wg != 2 && t.waves_per_wg != 4 && t.waves_per_wg != 8) || t.wgs_per_cu > 64 ||
       t.tiles_per_ticket > 64)
     return APAX_E_INVALID;
@@ -807,9 +807,11 @@ int apax_batch_run(apax_batch* b, hipStream_t stream) {
     B.total_tiles = c.total_tiles;
     B.n = (uint32_t)c.items.size();
     B.tiles_per_ticket = b->tune.tiles_per_ticket;
+    B.ldsw = c.maxldsw;
     int e = hip_err(launch_batch_reset(B.ticket, B.tile_state, b->op == APAX_OP_ENCODE ? c.total_tiles : 0, stream));
     if (e) return e;
-    size_t lds = (size_t)wp * (64 / c.lpb) * (size_t)c.maxldsw * 4;
+    const int run = b->op == APAX_OP_ENCODE ? RUN : 1;  // encode keeps a run of tiles in LDS
+    size_t lds = (size_t)run * wp * (64 / c.lpb) * (size_t)c.maxldsw * 4;
     if (b->op == APAX_OP_ENCODE) e = hip_err(launch_encode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     else e = hip_err(launch_decode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     if (e) return e;

@@ -1,6 +1,7 @@
-// encode.hip -- single-array APAX encoder kernel for gfx950: one workgroup
-// per tile; variable-size modes take tiles from an atomic ticket so tiles
-// start in order (the look-back in encode_tile.h relies on it).
+// encode.hip -- single-array APAX encoder kernel for gfx950: fixed rate, one
+// workgroup per tile; variable-size modes, one workgroup per run of RUN tiles
+// taken from an atomic ticket, so runs start in order (the look-back in
+// encode_tile.h relies on it).
 #include "encode_tile.h"
 
 namespace apax {
@@ -13,22 +14,43 @@ __global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64
   (void)status_unused;
 }
 
-template <typename T, int LPB, int NDIM, int WP>
+// VAR: variable-size modes (runs of RUN tiles from the ticket, look-back);
+// else fixed rate (one tile per workgroup, offsets known up front).
+template <typename T, int LPB, int NDIM, int WP, bool VAR>
 __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
+  constexpr int BPW = 64 / LPB;
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared<WP> sm;
-  if (threadIdx.x == 0)
-    sm.tile = A.g.mode != M_RATE ? (int64_t)atomicAdd(A.ticket, 1u) : (int64_t)blockIdx.x;
-  __syncthreads();
-  encode_tile<T, LPB, NDIM, WP>(A, sm.tile, sm, lds);
+  if constexpr (VAR) {
+    if (threadIdx.x == 0) sm.tile = (int64_t)atomicAdd(A.ticket, (uint32_t)RUN);
+    __syncthreads();
+    const int64_t t0 = sm.tile;
+    const int64_t left = A.ntiles - t0;
+    encode_run<T, LPB, NDIM, WP>(A, t0, left < RUN ? (int)left : RUN, sm, lds);
+  } else {
+    const int64_t t = blockIdx.x;
+    encode_analyze<T, LPB, NDIM, WP>(A, t, 0, A.g.ldsw, sm, lds);
+    if ((threadIdx.x >> 6) == 0) {
+      uint64_t base = 0;
+      encode_place<WP, BPW, M_RATE>(A, t, 0, sm, false, base);
+    }
+    __syncthreads();
+    encode_store<LPB, WP>(A, t, 0, A.g.ldsw, sm, lds);
+  }
 }
 
 // ------------------------------------------------------------ launcher
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   constexpr int BPW = 64 / LPB;
-  size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
-  hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG>), dim3((unsigned)A.ntiles), dim3(WPG * 64), lds, s, A);
+  const bool variable = A.g.mode != M_RATE;
+  const int run = variable ? RUN : 1;
+  size_t lds = (size_t)run * WPG * BPW * A.g.ldsw * 4;
+  const int64_t grid = (A.ntiles + run - 1) / run;
+  if (variable)
+    hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG, true>), dim3((unsigned)grid), dim3(WPG * 64), lds, s, A);
+  else
+    hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG, false>), dim3((unsigned)grid), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
 }
 

@@ -6,8 +6,13 @@
 // search), every candidate stream costed in registers, the cheapest emitted
 // into a zeroed LDS buffer with ds_or (header | JEE tokens | BFPE payload),
 // then copied out with coalesced word stores.  Fixed rate places block j at
-// j * budget words; variable-size modes place blocks with a single-pass
-// decoupled look-back over per-tile word counts, 64 predecessors per probe.
+// j * budget words.  Variable-size modes take runs of RUN consecutive tiles
+// per work-queue ticket: every tile of the run is analysed and assembled in
+// LDS and publishes its word count first, then the run's first tile finds
+// its offset with a single-pass decoupled look-back (64 predecessors per
+// probe) and the others follow by addition, then all are stored.  Publishing
+// every count before any wait keeps the runs of different workgroups
+// independent, and one ticket per run cuts the atomics on the shared ticket.
 #pragma once
 #include "block.h"
 #include "kernels.h"
@@ -45,14 +50,21 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
 // increasing order, so every tile waited on is already running; the wait is
 // still bounded in time and reports ST_INTERNAL if the bound is ever hit.
 // Returns the exclusive prefix (words before this tile).
-__device__ __forceinline__ uint64_t lookback(uint64_t* ts, int64_t tile, uint64_t agg, uint32_t* status) {
-  const uint64_t FLAG_A = 1ull << 62, FLAG_P = 2ull << 62, VAL = FLAG_A - 1;
+constexpr uint64_t LB_FLAG_A = 1ull << 62, LB_FLAG_P = 2ull << 62, LB_VAL = LB_FLAG_A - 1;
+
+// publish a tile's own word count (tile 0: its inclusive prefix)
+__device__ __forceinline__ void lb_publish(uint64_t* ts, int64_t tile, uint64_t agg) {
+  __hip_atomic_store(&ts[tile], (tile == 0 ? LB_FLAG_P : LB_FLAG_A) | agg, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_prefix(uint64_t* ts, int64_t tile, uint64_t incl) {
+  __hip_atomic_store(&ts[tile], LB_FLAG_P | incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lookback(uint64_t* ts, int64_t tile, uint32_t* status) {
+  const uint64_t FLAG_P = LB_FLAG_P, VAL = LB_VAL;
   const int lane = lane_id();
-  if (tile == 0) {
-    if (lane == 0) __hip_atomic_store(&ts[0], FLAG_P | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  if (lane == 0) __hip_atomic_store(&ts[tile], FLAG_A | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tile == 0) return 0;
   uint64_t base = 0;
   int64_t end = tile - 1;
   const uint64_t t0 = wall_clock64();
@@ -76,30 +88,32 @@ __device__ __forceinline__ uint64_t lookback(uint64_t* ts, int64_t tile, uint64_
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  if (lane == 0) __hip_atomic_store(&ts[tile], FLAG_P | (base + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return base;
 }
 
 template <int WP>
 struct EncShared {
   int64_t tile;
-  uint32_t nw[WP * 4];
-  uint64_t off[WP * 4];
+  uint64_t agg[RUN];          // words of each tile of the run
+  uint32_t item[RUN];         // batch: item of each tile of the run
+  uint32_t nw[RUN][WP * 4];   // words of each block
+  uint64_t off[RUN][WP * 4];  // word offset of each block
   uint4 xch[WP * 64];
 };
 
-// One tile (WP waves x 64/LPB blocks) of one array.  Tiles of variable-size
-// modes must be processed in increasing order of `tile` start (look-back).
+// Phase 1 for one tile (WP waves x 64/LPB blocks) of one array: analyse
+// every block, assemble it in LDS region r of the run (block slots of
+// `slot` >= g.ldsw words, the same for every tile of a run), record the
+// block word counts and publish the tile's count (variable-size modes).
 template <typename T, int LPB, int NDIM, int WP>
-__device__ __forceinline__ void encode_tile(const EncArgs& A, const int64_t tile, EncShared<WP>& sm,
-                                            uint32_t* lds) {
+__device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t tile, const int r,
+                                               const int slot, EncShared<WP>& sm, uint32_t* lds) {
   constexpr int BPW = 64 / LPB;
   constexpr int H = Traits<T>::H;
   constexpr int W = Traits<T>::W;
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
-  uint32_t* s_nw = sm.nw;
-  uint64_t* s_off = sm.off;
+  uint32_t* s_nw = sm.nw[r];
   const int wave = threadIdx.x >> 6;
   const bool variable = g.mode != M_RATE;
   B_ b;
@@ -136,7 +150,7 @@ __device__ __forceinline__ void encode_tile(const EncArgs& A, const int64_t tile
   // ---- emit into this segment's LDS buffer
   const int seg = b.L.seg, gi = b.L.gi;
   const int stride = g.ldsw;
-  uint32_t* buf = lds + (wave * BPW + seg) * stride;
+  uint32_t* buf = lds + ((r * WP + wave) * BPW + seg) * slot;
   for (int w = 4 * gi; w < stride; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
@@ -207,52 +221,97 @@ __device__ __forceinline__ void encode_tile(const EncArgs& A, const int64_t tile
   }
   if (gi == 0) s_nw[wave * BPW + seg] = (uint32_t)nw;
   __syncthreads();
-
-  // ---- placement
-  if (wave == 0) {
+  if (threadIdx.x == 0) {
     uint64_t agg = 0;
     for (int i = 0; i < WP * BPW; i++) agg += s_nw[i];
-    uint64_t base;
-    if (variable) {
-      base = lookback(A.tile_state, tile, agg, A.status);
-      if (tile == A.ntiles - 1 && lane == 0) {
-        uint64_t total = base + agg;
-        *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
-        *A.d_nbytes = A.area + 4 * total;
-      }
-    } else {
-      base = (uint64_t)tile * (WP * BPW) * (uint64_t)g.budget;
+    sm.agg[r] = agg;
+    if (variable) lb_publish(A.tile_state, tile, agg);
+  }
+}
+
+// Phase 2 for one tile, run by wave 0 in run order: the tile's offset (`base`
+// in: offset of the previous tile of the run when `chain`, else unknown),
+// the stream header and length fields it owns, the block offsets.
+template <int WP, int BPW, int MODE = -1>  // MODE: M_RATE when known fixed rate, else runtime
+__device__ __forceinline__ void encode_place(const EncArgs& A, const int64_t tile, const int r,
+                                             EncShared<WP>& sm, bool chain, uint64_t& base) {
+  const Geo& g = A.g;
+  const int lane = lane_id();
+  const bool variable = MODE == M_RATE ? false : g.mode != M_RATE;
+  const uint64_t agg = sm.agg[r];
+  if (variable) {
+    if (!chain) base = lookback(A.tile_state, tile, A.status);
+    if (tile > 0 && lane == 0) lb_prefix(A.tile_state, tile, base + agg);
+    if (tile == A.ntiles - 1 && lane == 0) {
+      const uint64_t total = base + agg;
+      *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
+      *A.d_nbytes = A.area + 4 * total;
     }
-    if (lane == 0) {
-      if (tile == 0) {
-        uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
-        for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
-        for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
-        for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
-        if (!variable) {
-          h[14] = A.hdr[14];
-          h[15] = A.hdr[15];
-          *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
-        }
+  } else {
+    base = (uint64_t)tile * (WP * BPW) * (uint64_t)g.budget;
+  }
+  if (lane == 0) {
+    if (tile == 0) {
+      uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
+      for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
+      for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
+      for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
+      if (!variable) {
+        h[14] = A.hdr[14];
+        h[15] = A.hdr[15];
+        *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
       }
-      uint64_t acc = base;
-      for (int i = 0; i < WP * BPW; i++) {
-        s_off[i] = acc;
-        acc += s_nw[i];
-      }
+    }
+    uint64_t acc = base;
+    for (int i = 0; i < WP * BPW; i++) {
+      sm.off[r][i] = acc;
+      acc += sm.nw[r][i];
+    }
+  }
+}
+
+// Phase 3 for one tile: coalesced word stores of its LDS blocks and, in
+// variable-size modes, their length and superblock-offset fields.
+template <int LPB, int WP>
+__device__ __forceinline__ void encode_store(const EncArgs& A, const int64_t tile, const int r,
+                                             const int slot, EncShared<WP>& sm, const uint32_t* lds) {
+  constexpr int BPW = 64 / LPB;
+  const Geo& g = A.g;
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int seg = lane / LPB, gi = lane % LPB;
+  const int64_t j = (tile * WP + wave) * BPW + seg;
+  if (j >= g.nblocks) return;
+  const int stride = g.ldsw;
+  const uint32_t* buf = lds + ((r * WP + wave) * BPW + seg) * slot;
+  const int nw = (int)sm.nw[r][wave * BPW + seg];
+  const uint64_t off = sm.off[r][wave * BPW + seg];
+  uint32_t* dst = A.out_words + off;
+  for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
+  if (g.mode != M_RATE && gi == 0) {
+    A.lens[j] = (uint16_t)nw;
+    if ((j & 63) == 0) A.sbo[j >> 6] = off;
+  }
+}
+
+// A whole run of tiles [t0, t0 + n) of one array (n <= RUN; fixed rate: 1).
+template <typename T, int LPB, int NDIM, int WP>
+__device__ __forceinline__ void encode_run(const EncArgs& A, const int64_t t0, const int n,
+                                           EncShared<WP>& sm, uint32_t* lds) {
+  constexpr int BPW = 64 / LPB;
+#pragma unroll 1
+  for (int r = 0; r < n; r++) encode_analyze<T, LPB, NDIM, WP>(A, t0 + r, r, A.g.ldsw, sm, lds);
+  if ((threadIdx.x >> 6) == 0) {
+    uint64_t base = 0;
+#pragma unroll 1
+    for (int r = 0; r < n; r++) {
+      if (r > 0) base += sm.agg[r - 1];
+      encode_place<WP, BPW>(A, t0 + r, r, sm, r > 0, base);
     }
   }
   __syncthreads();
-
-  if (b.blk_ok) {
-    const uint64_t off = s_off[wave * BPW + seg];
-    uint32_t* dst = A.out_words + off;
-    for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
-    if (variable && gi == 0) {
-      A.lens[b.j] = (uint16_t)nw;
-      if ((b.j & 63) == 0) A.sbo[b.j >> 6] = off;
-    }
-  }
+#pragma unroll 1
+  for (int r = 0; r < n; r++) encode_store<LPB, WP>(A, t0 + r, r, A.g.ldsw, sm, lds);
 }
 
 }  // namespace apax

@@ -8,6 +8,7 @@
 namespace apax {
 
 constexpr int WPG = 4;  // wavefronts per workgroup (one tile per workgroup)
+constexpr int RUN = 4;  // encode: tiles per work-queue ticket in variable-size modes
 
 struct EncArgs {
   const void* x;
@@ -149,6 +150,8 @@ struct BatchArgs {
   int64_t total_tiles;
   uint32_t n;
   uint32_t tiles_per_ticket;
+  int32_t ldsw;            // LDS words per block slot: the class's largest block buffer
+  int32_t pad;
 };
 
 int lpb_of(const Geo& g);

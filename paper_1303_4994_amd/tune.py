@@ -21,7 +21,7 @@ from . import apax as A
 
 CANDIDATES = [{"waves_per_wg": w, "wgs_per_cu": c, "tiles_per_ticket": t}
               for w in (2, 4, 8) for c in (4, 8, 16) for t in (1, 4)]
-DEFAULT = {"waves_per_wg": 4, "wgs_per_cu": 8, "tiles_per_ticket": 1}
+DEFAULT = {"waves_per_wg": 4, "wgs_per_cu": 8, "tiles_per_ticket": 4}
 
 
 def cache_path() -> str:
