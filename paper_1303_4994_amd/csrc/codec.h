@@ -101,10 +101,20 @@ __device__ __forceinline__ int32_t quant(double x, double g) {
   return (int32_t)__builtin_rint(x * g);
 }
 
-// Dequantizer: y = ldexp(fl64(a * R[f]), -k), R[f] = 16 / (16 + f).
+// Dequantizer: y = ldexp(fl64(a * R[f]), -k), R[f] = fl64(16 / (16 + f)).
+// The 16 correctly rounded quotients are folded at compile time.
+__device__ __forceinline__ double inv_mantissa(int c) {
+  constexpr double R[16] = {16.0 / 16, 16.0 / 17, 16.0 / 18, 16.0 / 19, 16.0 / 20, 16.0 / 21,
+                            16.0 / 22, 16.0 / 23, 16.0 / 24, 16.0 / 25, 16.0 / 26, 16.0 / 27,
+                            16.0 / 28, 16.0 / 29, 16.0 / 30, 16.0 / 31};
+  return R[c & 15];
+}
 __device__ __forceinline__ double dequant(int32_t a, int c) {
-  double R = 16.0 / (double)(16 + (c & 15));
-  return ldexp((double)a * R, -(c >> 4));
+  return ldexp((double)a * inv_mantissa(c), -(c >> 4));
+}
+// the same with the code's factors hoisted (R = inv_mantissa(c), e = -(c >> 4))
+__device__ __forceinline__ double dequant_rk(int32_t a, double R, int e) {
+  return ldexp((double)a * R, e);
 }
 
 template <typename T>

@@ -358,11 +358,13 @@ __device__ __forceinline__ void decode_tile(const DecArgs& A, const int64_t tile
     int nvalid = 0;
     int64_t idx = group_index<NDIM, LPB>(g, L, j, nvalid);
     T out[4];
+    const double R = inv_mantissa(c);
+    const int e = -(c >> 4);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       int32_t av = wrapw<W>(r[k]);
       if (g.mode == M_LOSSLESS) out[k] = (T)av;
-      else out[k] = to_out<T>(dequant(av, c));
+      else out[k] = to_out<T>(dequant_rk(av, R, e));
     }
     store4<T>((T*)A.y, idx, nvalid, out);
   }

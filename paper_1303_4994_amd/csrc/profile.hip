@@ -312,7 +312,8 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
   PState* st = A.st;
-  __shared__ float s_red[WPG][NSUM][2];
+  constexpr int NL = S_CXX;  // accumulator slots; the centred pass uses slots S_XX..S_DD
+  __shared__ float s_red[WPG][NL][2];
   __shared__ uint64_t s_w[WPG], s_dm[WPG];
   __shared__ uint32_t s_fit[WPG], s_hist[WPG][8];
   __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
@@ -332,9 +333,27 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   const double s1 = ldexp(1.0, -escale);
   const double s2 = ldexp(1.0, -2 * escale);
   const double mx = st->mean[0], my = st->mean[1], md = st->mean[2];
-  FF acc[NSUM];
+  // active accumulator slots of this pass
+  const int l0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : S_XX;
+  const int l1 = A.op == P_STATS ? NL : (A.op == P_CENTER ? S_DS : 0);
+  FF acc[NL];
 #pragma unroll
-  for (int i = 0; i < NSUM; i++) acc[i] = {0.f, 0.f};
+  for (int i = 0; i < NL; i++) acc[i] = {0.f, 0.f};
+  // each lane sums its groups' binary64 terms over up to 64 tiles, then
+  // moves the partial (scaled by a power of two) into the FP32 float-float
+  // accumulators that every further reduction level uses
+  double lacc[NL];
+#pragma unroll
+  for (int i = 0; i < NL; i++) lacc[i] = 0.0;
+  int lcount = 0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int i = 0; i < NL; i++)
+      if (i >= l0 && i < l1) acc[i] = ff_add(acc[i], ff_of(lacc[i] * (i < S_XX ? s1 : s2)));
+#pragma unroll
+    for (int i = 0; i < NL; i++) lacc[i] = 0.0;
+    lcount = 0;
+  };
   double dmax = 0.0;
   uint32_t nfit = 0;
   uint32_t hcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // wave-uniform
@@ -366,6 +385,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     }
     // P_STATS / P_CENTER: operating point of the block, decoded values
     int c = 0;
+    bool have_a = false;  // a[] already holds the block quantized at c
     if (A.rule == R_QUALITY) {
       c = clampc(code, b.cf, b.cc);
     } else if (A.rule == R_RATE) {
@@ -379,10 +399,11 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
         int s_ = B_::argmin(C, m7, best);
         bool need = b.act && best > 32 * g.budget;
         if (__ballot(need)) c = b.rate_search(g, c, s_, need);
+        else have_a = true;
         if (A.store_cj && b.blk_ok && b.L.gi == 0) A.cj[b.j] = c;
       }
     }
-    b.quantize(c, A.rule == R_LOSSLESS, a);
+    if (!have_a) b.quantize(c, A.rule == R_LOSSLESS, a);
     if (A.op == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
@@ -396,16 +417,18 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     }
     // the group's terms are summed in binary64 first (4 terms, relative error
     // ~1e-16), then added to the FP32 float-float accumulators
-    double t[NSUM];
+    double t[NL];
 #pragma unroll
-    for (int i = 0; i < NSUM; i++) t[i] = 0.0;
+    for (int i = 0; i < NL; i++) t[i] = 0.0;
+    const double Rq = inv_mantissa(c);
+    const int eq = -(c >> 4);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (!(b.act && b.valid(k))) continue;
       double x = b.xd[k];
       double y;
       if (A.rule == R_LOSSLESS) y = (double)a[k];
-      else y = (double)to_out<T>(dequant(a[k], c));
+      else y = (double)to_out<T>(dequant_rk(a[k], Rq, eq));
       double d = x - y;
       if (A.op == P_STATS) {
         if (!A.curve) {
@@ -421,30 +444,21 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
         t[S_DS] += d * (x + y);
       } else {
         double ex = x - mx, ey = y - my, ed = d - md;
-        t[S_CXX] += ex * ex;
-        t[S_CYY] += ey * ey;
-        t[S_CDD] += ed * ed;
+        t[S_XX] += ex * ex;  // slots of the centred sums S_CXX, S_CYY, S_CDD
+        t[S_YY] += ey * ey;
+        t[S_DD] += ed * ed;
       }
     }
-    if (A.op == P_STATS) {
-      if (!A.curve) {
 #pragma unroll
-        for (int i = S_X; i <= S_D; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s1));
-      }
-#pragma unroll
-      for (int i = S_XX; i <= S_DS; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s2));
-    } else {
-#pragma unroll
-      for (int i = S_CXX; i < NSUM; i++) acc[i] = ff_add(acc[i], ff_of(t[i] * s2));
-    }
+    for (int i = 0; i < NL; i++) lacc[i] += t[i];
+    if (++lcount == 64) flush();
   }
+  flush();
 
   // ---- workgroup partial record
-  const int i0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : (A.op == P_CENTER ? S_CXX : NSUM);
-  const int i1 = A.op == P_STATS ? S_CXX : NSUM;
 #pragma unroll
-  for (int i = 0; i < NSUM; i++) {
-    if (i < i0 || i >= i1) continue;
+  for (int i = 0; i < NL; i++) {
+    if (i < l0 || i >= l1) continue;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
   }
@@ -457,7 +471,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   }
   if (lane == 0) {
 #pragma unroll
-    for (int i = 0; i < NSUM; i++) {
+    for (int i = 0; i < NL; i++) {
       s_red[wave][i][0] = acc[i].hi;
       s_red[wave][i][1] = acc[i].lo;
     }
@@ -470,11 +484,14 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   __syncthreads();
   const PParts P = pparts(A.parts, (int64_t)gridDim.y * A.nwg);
   const int64_t r = (int64_t)ci * A.nwg + blockIdx.x;
-  if (threadIdx.x < NSUM) {
+  if (threadIdx.x < NL) {
     const int i = threadIdx.x;
-    FF tt = {s_red[0][i][0], s_red[0][i][1]};
-    for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
-    P.s[(int64_t)i * P.R + r] = float2{tt.hi, tt.lo};
+    if (i >= l0 && i < l1) {
+      FF tt = {s_red[0][i][0], s_red[0][i][1]};
+      for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
+      const int si = A.op == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
+      P.s[(int64_t)si * P.R + r] = float2{tt.hi, tt.lo};
+    }
   } else if (threadIdx.x == 64) {
     uint64_t ww = 0, dm = 0;
     uint32_t nf = 0;
