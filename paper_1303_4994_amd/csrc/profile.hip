@@ -306,7 +306,7 @@ __device__ void reduce_parts(const ProfArgs& A, int ncodes, int i0, int i1) {
   }
 }
 
-template <typename T, int LPB, int NDIM>
+template <typename T, int LPB, int NDIM, int OP>  // OP: the pass (P_FITS, P_STATS, P_CENTER)
 __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   constexpr int BPW = 64 / LPB;
   using B_ = Blk<T, LPB, NDIM>;
@@ -334,8 +334,8 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   const double s2 = ldexp(1.0, -2 * escale);
   const double mx = st->mean[0], my = st->mean[1], md = st->mean[2];
   // active accumulator slots of this pass
-  const int l0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : S_XX;
-  const int l1 = A.op == P_STATS ? NL : (A.op == P_CENTER ? S_DS : 0);
+  const int l0 = OP == P_STATS ? (A.curve ? S_XX : 0) : S_XX;
+  const int l1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
   FF acc[NL];
 #pragma unroll
   for (int i = 0; i < NL; i++) acc[i] = {0.f, 0.f};
@@ -363,13 +363,13 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     const int64_t jj = (tile * WPG + wave) * BPW + lane / LPB;
     B_ b;
     b.init(g, jj < A.nbe ? jj * A.jstride : g.nblocks, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
-    if (A.op == P_CENTER && A.rule != R_QUALITY) b.template load<false>((const T*)A.x, g);
+    if (OP == P_CENTER && A.rule != R_QUALITY) b.template load<false>((const T*)A.x, g);
     else b.load((const T*)A.x, g);
     int32_t a[4], v[7][4];
     int eps[7], pw[7];
     Costs C;
     int32_t best;
-    if (A.op == P_FITS) {
+    if (OP == P_FITS) {
       // argmin over the mask at the clamped code: fit test + stream histogram
       int c = A.rule == R_LOSSLESS ? 0 : clampc(code, b.cf, b.cc);
       b.quantize(c, A.rule == R_LOSSLESS, a);
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     if (A.rule == R_QUALITY) {
       c = clampc(code, b.cf, b.cc);
     } else if (A.rule == R_RATE) {
-      if (A.op == P_CENTER) {
+      if (OP == P_CENTER) {
         c = b.blk_ok ? A.cj[b.j] : 0;
       } else {
         c = clampc(code, b.cf, b.cc);
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       }
     }
     if (!have_a) b.quantize(c, A.rule == R_LOSSLESS, a);
-    if (A.op == P_STATS) {
+    if (OP == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
         b.sizes(g, mask, a, v, eps, pw, C);
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       if (A.rule == R_LOSSLESS) y = (double)a[k];
       else y = (double)to_out<T>(dequant_rk(a[k], Rq, eq));
       double d = x - y;
-      if (A.op == P_STATS) {
+      if (OP == P_STATS) {
         if (!A.curve) {
           t[S_X] += x;
           t[S_Y] += y;
@@ -489,7 +489,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     if (i >= l0 && i < l1) {
       FF tt = {s_red[0][i][0], s_red[0][i][1]};
       for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
-      const int si = A.op == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
+      const int si = OP == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
       P.s[(int64_t)si * P.R + r] = float2{tt.hi, tt.lo};
     }
   } else if (threadIdx.x == 64) {
@@ -719,8 +719,10 @@ int64_t prof_wgs(int64_t ntiles, int ncodes) {
 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
-  hipLaunchKernelGGL((k_profile<T, LPB, NDIM>), dim3((unsigned)A.nwg, A.maxcodes), dim3(WPG * 64),
-                     0, s, A);
+  const dim3 grid((unsigned)A.nwg, A.maxcodes), block(WPG * 64);
+  if (A.op == P_FITS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_FITS>), grid, block, 0, s, A);
+  else if (A.op == P_STATS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_STATS>), grid, block, 0, s, A);
+  else hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CENTER>), grid, block, 0, s, A);
   return hipGetLastError();
 }
 
