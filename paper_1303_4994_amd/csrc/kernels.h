@@ -40,7 +40,7 @@ struct DecArgs {
   Geo g;
 };
 
-enum { P_STATS = 1, P_FITS = 2, P_CENTER = 3 };
+enum { P_STATS = 1, P_FITS = 2, P_CENTER = 3, P_CURVE = 4 /* P_STATS on the curve's sums only */ };
 enum { R_LOSSLESS = 0, R_RATE = 1, R_QUALITY = 2 };
 enum { S_X = 0, S_Y, S_D, S_XX, S_YY, S_DD, S_DS, S_CXX, S_CYY, S_CDD, NSUM };
 constexpr int MAXCODES = 17;

@@ -306,8 +306,11 @@ __device__ void reduce_parts(const ProfArgs& A, int ncodes, int i0, int i1) {
   }
 }
 
-template <typename T, int LPB, int NDIM, int OP>  // OP: the pass (P_FITS, P_STATS, P_CENTER)
+template <typename T, int LPB, int NDIM, int OPK>  // OPK: the pass (P_FITS, P_STATS, P_CENTER, P_CURVE)
 __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
+  constexpr int OP = OPK == P_CURVE ? P_STATS : OPK;
+  A.curve = OPK == P_CURVE;
+  if (OPK == P_CURVE) A.rule = R_QUALITY;  // curve codes are fixed per block
   constexpr int BPW = 64 / LPB;
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
@@ -721,6 +724,7 @@ template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
   const dim3 grid((unsigned)A.nwg, A.maxcodes), block(WPG * 64);
   if (A.op == P_FITS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_FITS>), grid, block, 0, s, A);
+  else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CURVE>), grid, block, 0, s, A);
   else if (A.op == P_STATS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_STATS>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CENTER>), grid, block, 0, s, A);
   return hipGetLastError();
