@@ -133,7 +133,29 @@ def _check(rc, what):
         raise ApaxError(rc, what)
 
 
+_PCACHE: dict = {}
+
+
 def make_params(dtype: torch.dtype, shape, params: dict) -> Params:
+    """apax_params for (dtype, shape, params); marshalled structs are cached
+    (callers never modify them)."""
+    try:
+        key = (dtype, tuple(shape), tuple(sorted((k, tuple(v) if isinstance(v, (list, tuple)) else v)
+                                                  for k, v in params.items())))
+        hit = _PCACHE.get(key)
+    except TypeError:
+        key, hit = None, None
+    if hit is not None:
+        return hit
+    p = _make_params(dtype, shape, params)
+    if key is not None:
+        if len(_PCACHE) > 4096:
+            _PCACHE.clear()
+        _PCACHE[key] = p
+    return p
+
+
+def _make_params(dtype: torch.dtype, shape, params: dict) -> Params:
     p = Params()
     p.size = C.sizeof(Params)
     p.dtype = _DT[dtype]

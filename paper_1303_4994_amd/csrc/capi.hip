@@ -231,16 +231,6 @@ void r_of(double sxx, double syy, double sdd, double sds, double& r, double& omr
   r = 1.0 - omr;
 }
 
-// valid samples in block j
-uint64_t block_valid(const HG& h, int64_t j) {
-  const Geo& g = h.g;
-  int64_t bx = j % g.nbx, t = j / g.nbx, by = t % g.nby, bz = t / g.nby;
-  int64_t ex = std::min<int64_t>(g.b[2], g.n[2] - bx * g.b[2]);
-  int64_t ey = std::min<int64_t>(g.b[1], g.n[1] - by * g.b[1]);
-  int64_t ez = std::min<int64_t>(g.b[0], g.n[0] - bz * g.b[0]);
-  return (uint64_t)(ex * ey * ez);
-}
-
 // ---- batch plans
 struct BatchClass {
   int lpb, ndim;
@@ -546,9 +536,7 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   out->stream_mask = hs.mask_out;
   const int es = hs.escale;
   auto unscale = [&](double v, int i) { return ldexp(v, i >= S_XX ? 2 * es : es); };
-  double in_bits = 0.0;
-  for (int64_t jj = 0; jj < sub_n; jj++) in_bits += (double)block_valid(h, jj * sub_stride);
-  in_bits *= 8.0 * h.esz;
+  const double in_bits = (double)hs.sub_samples * 8.0 * h.esz;  // counted by the histogram pass
   for (int t = 0; t < APAX_NCURVE; t++) {
     out->curve[t].code = hs.curve_codes[t];
     double r = 1.0, omr = 0.0, ob = 0.0;

@@ -71,6 +71,7 @@ struct PState {
   int32_t pad2;
   double msums[NSUM];                 // metrics at the operating point
   uint64_t mwords;
+  uint64_t sub_samples;               // samples in the subsample blocks (histogram pass)
 };
 
 // Per-(code, workgroup) partial results of a profile pass, one array per

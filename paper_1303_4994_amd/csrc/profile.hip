@@ -298,6 +298,7 @@ __device__ void reduce_parts(const ProfArgs& A, int ncodes, int i0, int i1) {
         st->fits[ci] = fit;
         if (hist && ci == 0)
           for (int t = 0; t < 8; t++) st->hist[t] = h[t];
+        if (hist && ci == 0) st->sub_samples = w;
       } else if (A.op == P_STATS) {
         st->words[ci] = w;
         if (!A.curve) st->maxbits[1] = dm;
@@ -380,6 +381,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
       int s_ = B_::argmin(C, mask, best);
       if (b.blk_ok && b.L.gi == 0 && best <= 32 * g.budget) nfit++;
       if (A.hist) {
+        if (b.act) wsum += (unsigned long long)b.nvalid;  // samples of the subsample
         const bool lead = b.blk_ok && b.L.gi == 0;
 #pragma unroll
         for (int t = 0; t < 8; t++) hcnt[t] += (uint32_t)__popcll(__ballot(lead && s_ == t));
