@@ -61,6 +61,13 @@ enum {
 };
 #define APAX_NEAR_TIE 1u /* profile: a bisection probe was within 1e-11 of the target */
 #define APAX_NCURVE 17
+/* apax_params.code for apax_encode: take the code and stream mask
+ * (intersected with p->stream_mask; lossless mode: the mask) from the
+ * profile the workspace holds, on the device.  The stream header records the
+ * adopted values.  A workspace without a profile result (or one for another
+ * code range) makes the encode fall back to code 0 and the caller's mask and
+ * report APAX_E_INVALID through apax_status.  Not accepted by batches. */
+#define APAX_CODE_PROFILED ((int32_t)0x80000000)
 
 typedef struct apax_params {
   uint32_t size;        /* = sizeof(apax_params) */
@@ -123,6 +130,20 @@ int apax_workspace_size(const apax_params* p, uint64_t* bytes);
  * fills *h_out on return.  p->code is ignored. */
 int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* h_out,
                  void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* The same profile, enqueued on `stream` without waiting: the result stays
+ * in d_ws (device memory).  A later apax_encode of the same array with
+ * p->code = APAX_CODE_PROFILED, the same workspace and stream adopts the
+ * profile's code and stream mask on the device, so profile -> encode needs no
+ * host round trip.  apax_profile_read reads the result when wanted. */
+int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                       hipStream_t stream);
+
+/* Waits for `stream`, then fills *h_out from the profile that d_ws holds
+ * (p: the parameters that profile was called with).  Same errors as
+ * apax_profile. */
+int apax_profile_read(const apax_params* p, apax_profile_result* h_out, const void* d_ws,
+                        hipStream_t stream);
 
 /* Sec. 6 encoder.  Writes the whole stream (header, index, blocks) to
  * d_stream (cap bytes, >= apax_encode_bound) and its byte length to

@@ -28,6 +28,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE, E_HIP, E_INTER
     0, -1, -2, -3, -4, -5, -6, -7
 NEAR_TIE = 1
 NCURVE = 17
+CODE_PROFILED = -(1 << 31)  # apax_encode: adopt the code and mask of the profile in ws
 
 _DT = {torch.int8: I8, torch.int16: I16, torch.int32: I32, torch.float32: F32,
        torch.float64: F64}
@@ -98,6 +99,8 @@ def _load():
     L.apax_encode_bound.argtypes = [P(Params), P(u64)]
     L.apax_workspace_size.argtypes = [P(Params), P(u64)]
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
+    L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
+    L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
     L.apax_decode.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp]
     L.apax_stream_info.argtypes = [vp, u64, P(Params)]
@@ -220,6 +223,26 @@ def apax_profile(x: torch.Tensor, params: dict, ws: torch.Tensor | None = None, 
     r = ProfileResult()
     _check(lib.apax_profile(_dev_ptr(x), C.byref(p), C.byref(r), _dev_ptr(ws), ws.numel(),
                             _stream_ptr(stream)), "apax_profile")
+    return profile_dict(r)
+
+
+def apax_profile_async(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None):
+    """Enqueue the profile of x on the stream; the result stays in ws.  An
+    apax_encode of x with code=CODE_PROFILED on the same ws and stream adopts
+    its code and stream mask on the device."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    _check(lib.apax_profile_async(_dev_ptr(x), C.byref(p), _dev_ptr(ws), ws.numel(),
+                                  _stream_ptr(stream)), "apax_profile_async")
+
+
+def apax_profile_read(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None) -> dict:
+    """Wait for the stream and read the profile that ws holds (x: the array
+    that was profiled, for its dtype and shape)."""
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    r = ProfileResult()
+    _check(lib.apax_profile_read(C.byref(p), C.byref(r), _dev_ptr(ws), _stream_ptr(stream)),
+           "apax_profile_read")
     return profile_dict(r)
 
 

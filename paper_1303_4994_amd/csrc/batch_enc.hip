@@ -61,7 +61,7 @@ __global__ __launch_bounds__(WP * 64) void k_encode_batch(BatchArgs B) {
         const BatchEnc& E = items[ir];
         const bool chain = r > 0 && sm.item[r - 1] == ir;
         if (chain) base += sm.agg[r - 1];
-        encode_place<WP, BPW>(E.a, u0 + r - E.tile_start, r, sm, chain, base);
+        encode_place<WP, BPW>(E.a, E.a.hdr, u0 + r - E.tile_start, r, sm, chain, base);
       }
     }
     __syncthreads();

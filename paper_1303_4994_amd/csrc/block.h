@@ -417,7 +417,7 @@ struct Blk {
   // adaptive loop, Sec. 6), from an evaluation at the start code c0 that
   // chose stream st.  Returns the final code (c0 when the block fits there).
   // Probes need only the chosen stream's size.
-  __device__ int rate_search(const Geo& g, int c0, int st, bool need) const {
+  __device__ int rate_search(const Geo& g, uint32_t mask, int c0, int st, bool need) const {
     int32_t a[4], v[7][4];
     const int32_t budget_bits = 32 * g.budget;
     int c = c0, hi = c0, lo = c0;
@@ -427,7 +427,7 @@ struct Blk {
       if (++guard > 4096) break;  // unreachable: c_floor always fits a valid budget
       int ct = done ? c : (c - 16 < cf ? cf : c - 16);
       quantize(ct, false, a);
-      streams(g, a, v, need_mask(st, g.mask));
+      streams(g, a, v, need_mask(st, mask));
       int s_of = size_of(st, v, LPB == 64);
       if (!done) {
         if (s_of <= budget_bits) { done = true; lo = ct; }
@@ -441,7 +441,7 @@ struct Blk {
       bool on = hi - lo > 1;
       int mid = lo + ((hi - lo) >> 1);
       quantize(on ? mid : lo, false, a);
-      streams(g, a, v, need_mask(st, g.mask));
+      streams(g, a, v, need_mask(st, mask));
       int s_of = size_of(st, v, LPB == 64);
       if (on) {
         if (s_of <= budget_bits) lo = mid;

@@ -209,15 +209,20 @@ __global__ void k_fold_status(const uint32_t* item_status, uint32_t n, uint32_t*
   if (acc) atomicOr(status, acc);
 }
 
-__global__ void k_header_only(uint32_t* out, uint64_t* d_nbytes, uint64_t nbytes, uint32_t h0,
-                              uint32_t h1, uint32_t h2, uint32_t h3, uint32_t h4, uint32_t h5,
-                              uint32_t h6, uint32_t h7, uint32_t h8, uint32_t h9, uint32_t h10,
-                              uint32_t h11, uint32_t h12, uint32_t h13, uint32_t h14,
-                              uint32_t h15) {
+__global__ void k_header_only(HdrArgs A) {
   if (threadIdx.x == 0) {
-    uint32_t h[16] = {h0, h1, h2, h3, h4, h5, h6, h7, h8, h9, h10, h11, h12, h13, h14, h15};
-    for (int i = 0; i < 16; i++) out[i] = h[i];
-    *d_nbytes = nbytes;
+    uint32_t h[16];
+    for (int i = 0; i < 16; i++) h[i] = A.hdr[i];
+    if (A.sel) {
+      int32_t code;
+      uint32_t mask;
+      if (!operating_point(A.sel, A.status, A.cmin, A.cmax, A.ucode, A.umask, code, mask))
+        atomicOr(A.status, ST_NOPROFILE);
+      h[2] = (h[2] & ~0xFF00u) | ((mask & 0xFFu) << 8);
+      h[3] = (uint32_t)code;
+    }
+    for (int i = 0; i < 16; i++) A.out[i] = h[i];
+    *A.d_nbytes = A.nbytes;
   }
 }
 
@@ -278,8 +283,11 @@ const char* apax_strerror(int code) {
 }
 
 int apax_encode_bound(const apax_params* p, uint64_t* bytes) {
+  if (!p || !bytes) return APAX_E_INVALID;
+  apax_params q = *p;
+  if (q.code == APAX_CODE_PROFILED) q.code = 0;  // the bound does not depend on the code
   HG h;
-  int e = setup(p, h);
+  int e = setup(&q, h);
   if (e) return e;
   *bytes = bound_of(h);
   return APAX_OK;
@@ -356,13 +364,22 @@ int apax_status(const void* d_ws, hipStream_t stream) {
   if (st & ST_NONFINITE) return APAX_E_NONFINITE;
   if (st & ST_CORRUPT) return APAX_E_CORRUPT;
   if (st & ST_INTERNAL) return APAX_E_INTERNAL;
+  if (st & ST_NOPROFILE) return APAX_E_INVALID;
   return APAX_OK;
 }
 
 int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
                 uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
   HG h;
-  int e = setup(p, h);
+  const bool profiled = p && p->code == APAX_CODE_PROFILED;
+  int e;
+  if (profiled) {
+    apax_params q = *p;
+    q.code = 0;  // placeholder; the kernels read the profiled code on the device
+    e = setup(&q, h);
+  } else {
+    e = setup(p, h);
+  }
   if (e) return e;
   if (!d_stream || !d_nbytes || !d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
@@ -388,11 +405,21 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
     A.zpad[2] = (uint64_t)(64 + lens_bytes(h) + 8 * sbo_count(h));
     A.zpad[3] = A.area;
   }
+  if (profiled) A.sel = ((PState*)d_ws)->sel;
   if (h.g.nblocks == 0) {
-    const uint32_t* q = A.hdr;
-    hipLaunchKernelGGL(k_header_only, dim3(1), dim3(64), 0, stream, (uint32_t*)d_stream, d_nbytes,
-                       A.area, q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7], q[8], q[9], q[10],
-                       q[11], q[12], q[13], q[14], q[15]);
+    HdrArgs Hd;
+    memset(&Hd, 0, sizeof(Hd));
+    Hd.out = (uint32_t*)d_stream;
+    Hd.d_nbytes = d_nbytes;
+    Hd.nbytes = A.area;
+    memcpy(Hd.hdr, A.hdr, 64);
+    Hd.sel = A.sel;
+    Hd.status = A.status;
+    Hd.cmin = h.g.cmin;
+    Hd.cmax = h.g.cmax;
+    Hd.ucode = h.g.code;
+    Hd.umask = h.g.mask;
+    hipLaunchKernelGGL(k_header_only, dim3(1), dim3(64), 0, stream, Hd);
     return hip_err(hipGetLastError());
   }
   return hip_err(launch_encode(h.dtype, h.ndim, A, stream));
@@ -431,24 +458,34 @@ int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* 
   return hip_err(launch_decode(h.dtype, h.ndim, A, stream));
 }
 
-int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out, void* d_ws,
-                 uint64_t ws_bytes, hipStream_t stream) {
-  if (!p || !out) return APAX_E_INVALID;
+// Subsample of the profiler's statistics passes: every 16th block once the
+// array has 1024 blocks, else every block.
+static int64_t sub_count(const Geo& g, int64_t* stride = nullptr) {
+  const int64_t sub_stride = g.nblocks >= 1024 ? 16 : 1;
+  if (stride) *stride = sub_stride;
+  return (g.nblocks + sub_stride - 1) / sub_stride;
+}
+
+static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws, uint64_t ws_bytes, HG& h) {
+  if (!p) return APAX_E_INVALID;
   apax_params q = *p;
   q.code = 0;
-  HG h;
   int e = setup(&q, h);
   if (e) return e;
   if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
   if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
-  memset(out, 0, sizeof(*out));
-  out->size = sizeof(*out);
+  return APAX_OK;
+}
+
+// The whole profile as one asynchronous launch sequence on `stream`; its
+// result stays in the workspace's PState.
+static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream) {
+  int e;
   const Geo& g = h.g;
   PState* st = (PState*)d_ws;
-  const int64_t sub_stride = g.nblocks >= 1024 ? 16 : 1;
-  const int64_t sub_n = (g.nblocks + sub_stride - 1) / sub_stride;
-  out->n_sub = (uint32_t)sub_n;
+  int64_t sub_stride;
+  const int64_t sub_n = sub_count(g, &sub_stride);
   const int rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
   const bool fr = h.mode == APAX_FIXED_RATE;
   const uint64_t in_bytes = h.nsamples * (uint64_t)h.esz;
@@ -522,9 +559,16 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     if ((e = ctl(C_MASK))) return e;
     if ((e = ctl(C_CURVE))) return e;
   }
-  PState hs;
-  if (hipMemcpyAsync(&hs, st, sizeof(PState), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  return APAX_OK;
+}
+
+// Result record of a finished profile from the host copy of its PState.
+static int profile_finish(const HG& h, const PState& hs, apax_profile_result* out) {
+  memset(out, 0, sizeof(*out));
+  out->size = sizeof(*out);
+  const Geo& g = h.g;
+  const bool fr = h.mode == APAX_FIXED_RATE;
+  out->n_sub = (uint32_t)sub_count(g);
   if (hs.status & ST_NONFINITE) return APAX_E_NONFINITE;
   if (hs.status & ST_INTERNAL) return APAX_E_INTERNAL;
 
@@ -579,6 +623,38 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
     m.std_d = sqrt(unscale(hs.sums[0][S_CDD], S_CDD) / nn);
   }
   return APAX_OK;
+}
+
+int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out, void* d_ws,
+                 uint64_t ws_bytes, hipStream_t stream) {
+  if (!out) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  if ((e = profile_enqueue(d_x, p, h, d_ws, stream))) return e;
+  return apax_profile_read(p, out, d_ws, stream);
+}
+
+int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                       hipStream_t stream) {
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  return profile_enqueue(d_x, p, h, d_ws, stream);
+}
+
+int apax_profile_read(const apax_params* p, apax_profile_result* out, const void* d_ws,
+                        hipStream_t stream) {
+  if (!p || !out || !d_ws) return APAX_E_INVALID;
+  apax_params q = *p;
+  q.code = 0;
+  HG h;
+  int e = setup(&q, h);
+  if (e) return e;
+  PState hs;
+  if (hipMemcpyAsync(&hs, d_ws, sizeof(PState), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  return profile_finish(h, hs, out);
 }
 
 static int batch_error(int e, uint32_t i) { (void)i; return e; }
@@ -958,6 +1034,7 @@ int status_code(uint32_t bits) {
   if (bits & ST_NONFINITE) return APAX_E_NONFINITE;
   if (bits & ST_CORRUPT) return APAX_E_CORRUPT;
   if (bits & ST_INTERNAL) return APAX_E_INTERNAL;
+  if (bits & ST_NOPROFILE) return APAX_E_INVALID;
   return APAX_OK;
 }
 

@@ -15,7 +15,7 @@ namespace apax {
 
 enum { DT_I8 = 1, DT_I16 = 2, DT_I32 = 3, DT_F32 = 4, DT_F64 = 5 };
 enum { M_LOSSLESS = 0, M_RATE = 1, M_QUALITY = 2 };
-enum : uint32_t { ST_NONFINITE = 1u, ST_CORRUPT = 2u, ST_INTERNAL = 4u };
+enum : uint32_t { ST_NONFINITE = 1u, ST_CORRUPT = 2u, ST_INTERNAL = 4u, ST_NOPROFILE = 8u };
 
 template <typename T> struct Traits;
 template <> struct Traits<int8_t> { static constexpr int W = 8, H = 32; static constexpr bool isint = true; };

@@ -19,6 +19,9 @@ __global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64
 template <typename T, int LPB, int NDIM, int WP, bool VAR>
 __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
   constexpr int BPW = 64 / LPB;
+  // the header words as the argument block holds them in memory
+  const uint32_t* hsrc =
+      (const uint32_t*)((const uint8_t*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(EncArgs, hdr));
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared<WP> sm;
   if constexpr (VAR) {
@@ -26,13 +29,13 @@ __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
     __syncthreads();
     const int64_t t0 = sm.tile;
     const int64_t left = A.ntiles - t0;
-    encode_run<T, LPB, NDIM, WP>(A, t0, left < RUN ? (int)left : RUN, sm, lds);
+    encode_run<T, LPB, NDIM, WP>(A, hsrc, t0, left < RUN ? (int)left : RUN, sm, lds);
   } else {
     const int64_t t = blockIdx.x;
     encode_analyze<T, LPB, NDIM, WP>(A, t, 0, A.g.ldsw, sm, lds);
     if ((threadIdx.x >> 6) == 0) {
       uint64_t base = 0;
-      encode_place<WP, BPW, M_RATE>(A, t, 0, sm, false, base);
+      encode_place<WP, BPW, M_RATE>(A, hsrc, t, 0, sm, false, base);
     }
     __syncthreads();
     encode_store<LPB, WP>(A, t, 0, A.g.ldsw, sm, lds);

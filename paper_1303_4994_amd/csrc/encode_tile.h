@@ -101,6 +101,11 @@ struct EncShared {
   uint4 xch[WP * 64];
 };
 
+__device__ __forceinline__ bool profiled_point(const EncArgs& A, const Geo& g, int32_t& code,
+                                               uint32_t& mask) {
+  return operating_point(A.sel, A.status, g.cmin, g.cmax, g.code, g.mask, code, mask);
+}
+
 // Phase 1 for one tile (WP waves x 64/LPB blocks) of one array: analyse
 // every block, assemble it in LDS region r of the run (block slots of
 // `slot` >= g.ldsw words, the same for every tile of a run), record the
@@ -116,6 +121,9 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   uint32_t* s_nw = sm.nw[r];
   const int wave = threadIdx.x >> 6;
   const bool variable = g.mode != M_RATE;
+  int32_t code0;  // operating point, read before the block so the loads overlap
+  uint32_t mask0;
+  profiled_point(A, g, code0, mask0);
   B_ b;
   const int lane = lane_id();
   b.init(g, (tile * WP + wave) * BPW + lane / LPB, NDIM >= 2 ? sm.xch + wave * 64 : nullptr);
@@ -128,9 +136,9 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   int eps[7], pw[7];
   Costs C;
   int32_t best;
-  if (g.mode == M_QUALITY) c = clampc(g.code, b.cf, b.cc);
-  else if (g.mode == M_RATE) c = clampc(g.code, b.cf, b.cc);
-  const uint32_t emask = g.mode == M_RATE ? (g.mask & 0x7Fu) : g.mask;
+  if (g.mode == M_QUALITY) c = clampc(code0, b.cf, b.cc);
+  else if (g.mode == M_RATE) c = clampc(code0, b.cf, b.cc);
+  const uint32_t emask = g.mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
   b.quantize(c, g.mode == M_LOSSLESS, a);
   b.sizes(g, emask, a, v, eps, pw, C);
   st = B_::argmin(C, emask, best);
@@ -139,7 +147,7 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     if (__ballot(need)) {
       // some block of this wave does not fit at its start code: search, then
       // re-evaluate every block of the wave at its final code
-      c = b.rate_search(g, c, st, need);
+      c = b.rate_search(g, emask, c, st, need);
       b.quantize(c, false, a);
       b.sizes(g, emask, a, v, eps, pw, C);
       best = B_::size_sel(C, st);
@@ -233,8 +241,8 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
 // in: offset of the previous tile of the run when `chain`, else unknown),
 // the stream header and length fields it owns, the block offsets.
 template <int WP, int BPW, int MODE = -1>  // MODE: M_RATE when known fixed rate, else runtime
-__device__ __forceinline__ void encode_place(const EncArgs& A, const int64_t tile, const int r,
-                                             EncShared<WP>& sm, bool chain, uint64_t& base) {
+__device__ __forceinline__ void encode_place(const EncArgs& A, const uint32_t* hsrc, const int64_t tile,
+                                             const int r, EncShared<WP>& sm, bool chain, uint64_t& base) {
   const Geo& g = A.g;
   const int lane = lane_id();
   const bool variable = MODE == M_RATE ? false : g.mode != M_RATE;
@@ -250,18 +258,28 @@ __device__ __forceinline__ void encode_place(const EncArgs& A, const int64_t til
   } else {
     base = (uint64_t)tile * (WP * BPW) * (uint64_t)g.budget;
   }
-  if (lane == 0) {
-    if (tile == 0) {
-      uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
-      for (int i = 0; i < 14; i++) h[i] = A.hdr[i];
+  if (tile == 0 && lane < 16) {
+    // the stream header, one word per lane, read from `hsrc` (the argument
+    // block in memory: no scalar registers held for it across the kernel);
+    // in variable-size modes words 14-15 (the payload size) come with the
+    // last tile
+    uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
+    uint32_t w = hsrc[lane];
+    if (A.sel && (lane == 2 || lane == 3)) {  // operating point adopted on the device
+      int32_t code0;
+      uint32_t mask0;
+      const bool ok = profiled_point(A, g, code0, mask0);
+      if (!ok && lane == 2) atomicOr(A.status, ST_NOPROFILE);
+      w = lane == 2 ? ((w & ~0xFF00u) | ((mask0 & 0xFFu) << 8)) : (uint32_t)code0;
+    }
+    if (lane < 14 || !variable) h[lane] = w;
+    if (lane == 0) {
       for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
       for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
-      if (!variable) {
-        h[14] = A.hdr[14];
-        h[15] = A.hdr[15];
-        *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
-      }
+      if (!variable) *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
     }
+  }
+  if (lane == 0) {
     uint64_t acc = base;
     for (int i = 0; i < WP * BPW; i++) {
       sm.off[r][i] = acc;
@@ -296,8 +314,8 @@ __device__ __forceinline__ void encode_store(const EncArgs& A, const int64_t til
 
 // A whole run of tiles [t0, t0 + n) of one array (n <= RUN; fixed rate: 1).
 template <typename T, int LPB, int NDIM, int WP>
-__device__ __forceinline__ void encode_run(const EncArgs& A, const int64_t t0, const int n,
-                                           EncShared<WP>& sm, uint32_t* lds) {
+__device__ __forceinline__ void encode_run(const EncArgs& A, const uint32_t* hsrc, const int64_t t0,
+                                           const int n, EncShared<WP>& sm, uint32_t* lds) {
   constexpr int BPW = 64 / LPB;
 #pragma unroll 1
   for (int r = 0; r < n; r++) encode_analyze<T, LPB, NDIM, WP>(A, t0 + r, r, A.g.ldsw, sm, lds);
@@ -306,7 +324,7 @@ __device__ __forceinline__ void encode_run(const EncArgs& A, const int64_t t0, c
 #pragma unroll 1
     for (int r = 0; r < n; r++) {
       if (r > 0) base += sm.agg[r - 1];
-      encode_place<WP, BPW>(A, t0 + r, r, sm, r > 0, base);
+      encode_place<WP, BPW>(A, hsrc, t0 + r, r, sm, r > 0, base);
     }
   }
   __syncthreads();

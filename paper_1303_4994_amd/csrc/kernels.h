@@ -24,7 +24,39 @@ struct EncArgs {
   int64_t ntiles;
   uint32_t hdr[16];      // stream header (payload words written on device)
   uint64_t zpad[4];      // byte ranges [0,1) and [2,3) of index padding to zero
+  const int32_t* sel;    // {code, stream mask} a profile left in the workspace, or null
   Geo g;
+};
+
+// Operating point of an encode: the caller's code and stream mask, or, when
+// `sel` is set, those a preceding profile of the same workspace chose on the
+// device (its mask intersected with the caller's).  Returns false, keeping
+// the caller's, when `sel` holds no profile result for this code range.
+// `any`: 8 readable bytes, read instead of `sel` when it is null, so the
+// loads carry no branch and their latency can overlap the block's.
+__device__ __forceinline__ bool operating_point(const int32_t* sel, const void* any, int32_t cmin,
+                                                int32_t cmax, int32_t ucode, uint32_t umask,
+                                                int32_t& code, uint32_t& mask) {
+  const int32_t* sp = sel ? sel : reinterpret_cast<const int32_t*>(any);
+  const int32_t c = sp[0];
+  const uint32_t m = (uint32_t)sp[1];
+  const bool ok = !sel || (m != 0 && c >= cmin && c <= cmax);
+  const bool use = sel && ok;
+  code = use ? c : ucode;
+  mask = use ? (m & umask) : umask;
+  return ok;
+}
+
+// Stream of an array without blocks: the header alone.
+struct HdrArgs {
+  uint32_t* out;
+  uint64_t* d_nbytes;
+  uint64_t nbytes;
+  uint32_t hdr[16];
+  const int32_t* sel;  // as EncArgs::sel
+  uint32_t* status;
+  int32_t cmin, cmax, ucode;
+  uint32_t umask;
 };
 
 struct DecArgs {
@@ -58,6 +90,7 @@ struct PState {
   int32_t lo, hi, done, n_probes;    // bisection state
   int32_t flags, ncodes, first, pad0;
   uint32_t mask_probe, mask_out, need, pad1;
+  int32_t sel[2];           // operating point for the encoder: code, encoder stream mask
   int32_t codes[MAXCODES];  // codes evaluated by the next probe launch
   int32_t probe[MAXCODES];  // codes of the last probe launch (tree order)
   uint32_t fits[MAXCODES];

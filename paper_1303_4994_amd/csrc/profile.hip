@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
         b.sizes(g, m7, a, v, eps, pw, C);
         int s_ = B_::argmin(C, m7, best);
         bool need = b.act && best > 32 * g.budget;
-        if (__ballot(need)) c = b.rate_search(g, c, s_, need);
+        if (__ballot(need)) c = b.rate_search(g, g.mask, c, s_, need);
         else have_a = true;
         if (A.store_cj && b.blk_ok && b.L.gi == 0) A.cj[b.j] = c;
       }
@@ -670,6 +670,9 @@ __device__ void ctl_step(const CtlArgs& C) {
       for (int t = 0; t < 8; t++)
         if (st->hist[t] >= thresh) mask |= 1u << t;
       st->mask_out = mask & (C.mask_user | 0x81u);
+      // the operating point an encode of this workspace may adopt on the device
+      st->sel[0] = st->code;
+      st->sel[1] = (int32_t)(fr ? ((st->mask_out & 0x7Fu) | 1u) : (st->mask_out | 0x81u));
       for (int t = 0; t < NCURVE; t++) {
         int ct = st->code + 4 * (t - NCURVE / 2);
         ct = ct < C.cmin ? C.cmin : (ct > C.cmax ? C.cmax : ct);

@@ -250,6 +250,55 @@ def test_corrupt_status(A):
         assert decode_status(bad) == A.E_CORRUPT
 
 
+@pytest.mark.parametrize("name,dt,shape,params,kind", CASES, ids=[c[0] for c in CASES])
+def test_profiled_handoff(A, name, dt, shape, params, kind):
+    """apax_profile_async -> apax_encode(code=CODE_PROFILED): the encoder adopts
+    the profile's operating point on the device and writes the oracle's stream
+    at the oracle profile's point; the read-back result equals apax_profile's."""
+    print(f"case {name}", flush=True)
+    x = tiny(dt, shape, 8, kind)
+    pp = {k: v for k, v in params.items() if k != "code"}
+    pp["target_corr"] = 0.9999
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, tuple(x.shape), pp, DEV)
+    A.apax_profile_async(xg, pp, ws)
+    buf, nb = A.apax_encode(xg, dict(pp, code=A.CODE_PROFILED), ws=ws, clear_status=False)
+    assert A.apax_status(ws) == 0
+    got = buf[: int(nb.item())].cpu().numpy()
+    pg = A.apax_profile_read(xg, pp, ws)
+    assert pg == A.apax_profile(xg, pp)
+    po = O.profile_dict(O.profile(x, pp))
+    if pg["code"] != po["code"] and (pg["flags"] | po["flags"]) & 1:
+        return  # a near-tie decision; test_small_profile covers it
+    p_at, _ = decoded_at(x, pp, po)
+    assert np.array_equal(got, O.encode(x, p_at))
+
+
+def test_profiled_handoff_without_profile(A):
+    """An encode asking for the profiled point on a workspace without a profile
+    reports E_INVALID and falls back to the caller's code and mask."""
+    x = tiny(np.float32, (64, 64), 5)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, x.shape, params, DEV)
+    ws.zero_()
+    buf, nb = A.apax_encode(xg, dict(params, code=A.CODE_PROFILED), ws=ws, clear_status=False)
+    assert A.apax_status(ws) == A.E_INVALID
+    got = buf[: int(nb.item())].cpu().numpy()
+    assert np.array_equal(got, O.encode(x, dict(params, code=0)))
+    for x0, p0 in [(np.zeros((0, 16), np.float32), params),
+                   (np.zeros(0, np.float64), {"mode": "fixed_quality", "brick": (64,)})]:
+        x0g = torch.from_numpy(x0).to(DEV)
+        ws0 = A.workspace(x0g.dtype, x0.shape, p0, DEV)
+        A.apax_profile_async(x0g, p0, ws0)
+        b0, n0 = A.apax_encode(x0g, dict(p0, code=A.CODE_PROFILED), ws=ws0, clear_status=False)
+        assert A.apax_status(ws0) == 0
+        pr = A.apax_profile_read(x0g, p0, ws0)
+        exp = O.encode(x0, dict(p0, code=pr["code"], stream_mask=pr["stream_mask"] &
+                                (0x7F if p0["mode"] == "fixed_rate" else 0xFF)))
+        assert np.array_equal(b0[: int(n0.item())].cpu().numpy(), exp)
+
+
 # ------------------------------------------------------------------ full size
 
 def test_c0_full(A):
