@@ -145,9 +145,18 @@ __global__ __launch_bounds__(256) void k_pmax(const T* __restrict__ x, uint64_t 
 __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int nparts, CtlArgs C) {
   __shared__ uint64_t s_key[4];
   __shared__ uint32_t s_nf[4];
+  __shared__ PState s_st;
   uint64_t k = 0;
   uint32_t f = 0;
-  for (int w = threadIdx.x; w < nparts; w += blockDim.x) {
+  // the first record of every thread is loaded before the state is copied
+  // into LDS, so the two loads are in flight together
+  const int w0 = threadIdx.x;
+  const uint64_t k0 = w0 < nparts ? parts[w0].key : 0;
+  const uint32_t f0 = w0 < nparts ? parts[w0].nf : 0;
+  st_copy((uint32_t*)&s_st, (const uint32_t*)C.st);
+  k = k0;
+  f = f0;
+  for (int w = w0 + blockDim.x; w < nparts; w += blockDim.x) {
     const uint64_t kw = parts[w].key;
     k = kw > k ? kw : k;
     f |= parts[w].nf;
@@ -163,9 +172,6 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
     s_key[wave] = k;
     s_nf[wave] = anyf;
   }
-  __syncthreads();
-  __shared__ PState s_st;
-  st_copy((uint32_t*)&s_st, (const uint32_t*)C.st);
   __syncthreads();
   if (threadIdx.x == 0) {
     bool nfa = anyf;
@@ -186,124 +192,128 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
 // ---------------------------------------------------------------- block passes
 // Fixed-order reduction of the partial records of one pass (one workgroup,
 // 256 threads): each code's records are split over Lc lanes, lane k taking
-// records k, k + Lc, ... in order (loads of U records issued together), then
-// a butterfly inside the wave and an ordered merge of the waves.  Writes the
-// pass's results into the profiler state.
-__device__ void reduce_parts(const ProfArgs& A, int ncodes, int i0, int i1) {
-  constexpr int U = 4;  // records loaded together per lane
-  __shared__ float s_ff[4][NSUM][2];
+// records k, k + Lc, ... in order (U records loaded together), then a
+// butterfly inside the wave and an ordered merge of the waves.  OPK / HIST
+// name the pass, so only its fields are loaded.  The first batch is loaded
+// before the profiler state is copied into LDS (S), so both are in flight
+// together; the results are written into S.
+template <int OPK, bool HIST>
+__device__ void reduce_recs(const ProfArgs& A, PState* S) {
+  constexpr int I0 = OPK == P_STATS ? 0 : (OPK == P_CURVE ? S_XX : (OPK == P_CENTER ? S_CXX : NSUM));
+  constexpr int I1 = (OPK == P_STATS || OPK == P_CURVE) ? S_CXX : NSUM;
+  constexpr int NS = I1 - I0;  // sums of the pass
+  constexpr int NSA = NS > 0 ? NS : 1;
+  constexpr bool WORDS = OPK == P_STATS || OPK == P_CURVE || HIST;
+  constexpr bool DMAX = OPK == P_STATS;
+  constexpr bool FITS = OPK == P_FITS;
+  constexpr int U = OPK == P_CURVE ? 16 : 8;
+  __shared__ float s_ff[4][NSA][2];
   __shared__ uint64_t s_c64[4][2];
   __shared__ uint32_t s_c32[4][9];
-  PState* st = A.st;
-  if (ncodes <= 0) return;
+  const int mc = A.maxcodes;  // <= MAXCODES, so every code gets Lc >= 8 lanes
   const int64_t nwg = A.nwg;
-  const PParts P = pparts(A.parts, (int64_t)A.maxcodes * nwg);
-  // Lc lanes per code (power of two), every lane accumulating all fields of
-  // the records k, k + Lc, ... of its code in that order
+  const PParts P = pparts(A.parts, (int64_t)mc * nwg);
   int Lc = 256;
-  while (Lc > 1 && Lc * ncodes > 256) Lc >>= 1;
-  const int per_round = 256 / Lc;
-  const bool hist = A.hist != 0;
-  for (int c0 = 0; c0 < ncodes; c0 += per_round) {
-    const int ci = c0 + (int)threadIdx.x / Lc;
-    const int k = (int)threadIdx.x % Lc;
-    const bool on = ci < ncodes;
-    const int64_t r0 = (int64_t)(on ? ci : 0) * nwg;
-    FF acc[NSUM];
+  while (Lc > 1 && Lc * mc > 256) Lc >>= 1;
+  const int ci = (int)threadIdx.x / Lc;
+  const int k = (int)threadIdx.x % Lc;
+  const bool in_code = ci < mc;
+  const int64_t r0 = (int64_t)(in_code ? ci : 0) * nwg;
+  FF acc[NSA];
 #pragma unroll
-    for (int i = 0; i < NSUM; i++) acc[i] = {0.f, 0.f};
-    uint64_t w = 0, dm = 0;
-    uint32_t fit = 0, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t q0 = on ? k : nwg; q0 < nwg; q0 += (int64_t)U * Lc) {
-      float2 v[NSUM][U];
-      uint64_t wv[U], dv[U];
-      uint32_t fv[U];
+  for (int i = 0; i < NSA; i++) acc[i] = {0.f, 0.f};
+  uint64_t w = 0, dm = 0;
+  uint32_t fit = 0, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto batch = [&](const int64_t q0, const bool copy_state) {
+    float2 v[NSA][U];
+    uint64_t wv[U], dv[U];
+    uint32_t fv[U], hv[8][U];
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int64_t q = q0 + (int64_t)u * Lc;
-        const bool in = q < nwg;
+    for (int u = 0; u < U; u++) {
+      const int64_t q = q0 + (int64_t)u * Lc;
+      const bool in = in_code && q < nwg;
 #pragma unroll
-        for (int i = 0; i < NSUM; i++)
-          v[i][u] = (in && i >= i0 && i < i1) ? P.s[(int64_t)i * P.R + r0 + q] : float2{0.f, 0.f};
-        wv[u] = in ? P.words[r0 + q] : 0;
-        dv[u] = in ? P.dmax[r0 + q] : 0;
-        fv[u] = in ? P.nfit[r0 + q] : 0;
-      }
+      for (int i = 0; i < NS; i++) v[i][u] = in ? P.s[(int64_t)(I0 + i) * P.R + r0 + q] : float2{0.f, 0.f};
+      if (WORDS) wv[u] = in ? P.words[r0 + q] : 0;
+      if (DMAX) dv[u] = in ? P.dmax[r0 + q] : 0;
+      if (FITS) fv[u] = in ? P.nfit[r0 + q] : 0;
+      if (HIST) {
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-#pragma unroll
-        for (int i = 0; i < NSUM; i++)
-          if (i >= i0 && i < i1) acc[i] = ff_add(acc[i], FF{v[i][u].x, v[i][u].y});
-        w += wv[u];
-        dm = dv[u] > dm ? dv[u] : dm;
-        fit += fv[u];
-      }
-      if (hist) {
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const int64_t q = q0 + (int64_t)u * Lc;
-          uint32_t hv[8];
-#pragma unroll
-          for (int t = 0; t < 8; t++) hv[t] = q < nwg ? P.hist[(int64_t)t * P.R + r0 + q] : 0;
-#pragma unroll
-          for (int t = 0; t < 8; t++) h[t] += hv[t];
-        }
+        for (int t = 0; t < 8; t++) hv[t][u] = in ? P.hist[(int64_t)t * P.R + r0 + q] : 0;
       }
     }
-    // butterfly inside the code's lanes of one wave
-    const int Lw = Lc < 64 ? Lc : 64;
-    for (int o = 1; o < Lw; o <<= 1) {
+    if (copy_state) st_copy((uint32_t*)S, (const uint32_t*)A.st);
 #pragma unroll
-      for (int i = 0; i < NSUM; i++)
-        if (i >= i0 && i < i1) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
-      w += (uint64_t)__shfl_xor((unsigned long long)w, o, 64);
+    for (int u = 0; u < U; u++) {
+#pragma unroll
+      for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], FF{v[i][u].x, v[i][u].y});
+      if (WORDS) w += wv[u];
+      if (DMAX) dm = dv[u] > dm ? dv[u] : dm;
+      if (FITS) fit += fv[u];
+      if (HIST) {
+#pragma unroll
+        for (int t = 0; t < 8; t++) h[t] += hv[t][u];
+      }
+    }
+  };
+  batch(k, true);
+  for (int64_t q0 = k + (int64_t)U * Lc; q0 < nwg; q0 += (int64_t)U * Lc) batch(q0, false);
+  __syncthreads();  // the state copy is complete
+  const int nset = A.final_code ? 1 : S->ncodes;
+  const int ncodes = nset < mc ? nset : mc;
+
+  // butterfly inside the code's lanes of one wave
+  const int Lw = Lc < 64 ? Lc : 64;
+  for (int o = 1; o < Lw; o <<= 1) {
+#pragma unroll
+    for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
+    if (WORDS) w += (uint64_t)__shfl_xor((unsigned long long)w, o, 64);
+    if (DMAX) {
       const uint64_t d2 = (uint64_t)__shfl_xor((unsigned long long)dm, o, 64);
       dm = d2 > dm ? d2 : dm;
-      fit += __shfl_xor(fit, o, 64);
+    }
+    if (FITS) fit += __shfl_xor(fit, o, 64);
+    if (HIST) {
 #pragma unroll
       for (int t = 0; t < 8; t++) h[t] += __shfl_xor(h[t], o, 64);
     }
-    // codes spanning several waves (Lc > 64): merge the waves in order
-    if (Lc > 64) {
-      const int wave = threadIdx.x >> 6;
-      if ((threadIdx.x & 63) == 0) {
+  }
+  // codes spanning several waves (Lc > 64): merge the waves in order
+  if (Lc > 64) {
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int i = 0; i < NSUM; i++) { s_ff[wave][i][0] = acc[i].hi; s_ff[wave][i][1] = acc[i].lo; }
-        s_c64[wave][0] = w;
-        s_c64[wave][1] = dm;
-        s_c32[wave][0] = fit;
+      for (int i = 0; i < NS; i++) { s_ff[wave][i][0] = acc[i].hi; s_ff[wave][i][1] = acc[i].lo; }
+      s_c64[wave][0] = w;
+      s_c64[wave][1] = dm;
+      s_c32[wave][0] = fit;
 #pragma unroll
-        for (int t = 0; t < 8; t++) s_c32[wave][1 + t] = h[t];
-      }
-      __syncthreads();
-      if (k == 0) {
-        const int w0 = (int)threadIdx.x >> 6, nw = Lc / 64;
-        for (int j = 1; j < nw; j++) {
-#pragma unroll
-          for (int i = 0; i < NSUM; i++) acc[i] = ff_add(acc[i], FF{s_ff[w0 + j][i][0], s_ff[w0 + j][i][1]});
-          w += s_c64[w0 + j][0];
-          dm = s_c64[w0 + j][1] > dm ? s_c64[w0 + j][1] : dm;
-          fit += s_c32[w0 + j][0];
-#pragma unroll
-          for (int t = 0; t < 8; t++) h[t] += s_c32[w0 + j][1 + t];
-        }
-      }
-      __syncthreads();
+      for (int t = 0; t < 8; t++) s_c32[wave][1 + t] = h[t];
     }
-    if (on && k == 0) {
+    __syncthreads();
+    if (k == 0) {
+      const int wb = (int)threadIdx.x >> 6, nw = Lc / 64;
+      for (int j = 1; j < nw; j++) {
 #pragma unroll
-      for (int i = 0; i < NSUM; i++)
-        if (i >= i0 && i < i1) st->sums[ci][i] = (double)acc[i].hi + (double)acc[i].lo;
-      if (A.op == P_FITS) {
-        st->fits[ci] = fit;
-        if (hist && ci == 0)
-          for (int t = 0; t < 8; t++) st->hist[t] = h[t];
-        if (hist && ci == 0) st->sub_samples = w;
-      } else if (A.op == P_STATS) {
-        st->words[ci] = w;
-        if (!A.curve) st->maxbits[1] = dm;
+        for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], FF{s_ff[wb + j][i][0], s_ff[wb + j][i][1]});
+        w += s_c64[wb + j][0];
+        dm = s_c64[wb + j][1] > dm ? s_c64[wb + j][1] : dm;
+        fit += s_c32[wb + j][0];
+#pragma unroll
+        for (int t = 0; t < 8; t++) h[t] += s_c32[wb + j][1 + t];
       }
     }
+  }
+  if (ci < ncodes && k == 0) {
+#pragma unroll
+    for (int i = 0; i < NS; i++) S->sums[ci][I0 + i] = (double)acc[i].hi + (double)acc[i].lo;
+    if (FITS) S->fits[ci] = fit;
+    if (HIST && ci == 0) {
+      for (int t = 0; t < 8; t++) S->hist[t] = h[t];
+      S->sub_samples = w;
+    }
+    if (OPK == P_STATS || OPK == P_CURVE) S->words[ci] = w;
+    if (DMAX) S->maxbits[1] = dm;
   }
 }
 
@@ -518,17 +528,10 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
 
 // One workgroup: fixed-order reduction of the records of the preceding
 // pass, then its control step.
+template <int OPK, bool HIST>
 __global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
   __shared__ PState s_st;
-  st_copy((uint32_t*)&s_st, (const uint32_t*)A.st);
-  __syncthreads();
-  ProfArgs B = A;
-  B.st = &s_st;
-  const int nset = A.final_code ? 1 : s_st.ncodes;
-  const int ncodes = nset < A.maxcodes ? nset : A.maxcodes;
-  const int i0 = A.op == P_STATS ? (A.curve ? S_XX : 0) : (A.op == P_CENTER ? S_CXX : NSUM);
-  const int i1 = A.op == P_STATS ? S_CXX : NSUM;
-  reduce_parts(B, ncodes, i0, i1);
+  reduce_recs<OPK, HIST>(A, &s_st);
   __syncthreads();
   if (threadIdx.x == 0 && A.C.step != C_NONE) {
     CtlArgs C = A.C;
@@ -762,7 +765,11 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
     default: e = launch_nd<double>(A, ndim, s); break;
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, A);
+  if (A.op == P_FITS && A.hist) hipLaunchKernelGGL((k_reduce<P_FITS, true>), dim3(1), dim3(256), 0, s, A);
+  else if (A.op == P_FITS) hipLaunchKernelGGL((k_reduce<P_FITS, false>), dim3(1), dim3(256), 0, s, A);
+  else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_reduce<P_CURVE, false>), dim3(1), dim3(256), 0, s, A);
+  else if (A.op == P_STATS) hipLaunchKernelGGL((k_reduce<P_STATS, false>), dim3(1), dim3(256), 0, s, A);
+  else hipLaunchKernelGGL((k_reduce<P_CENTER, false>), dim3(1), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
