@@ -44,6 +44,45 @@ __device__ __forceinline__ FF ff_shfl_xor(FF a, int o) {
   return {__shfl_xor(a.hi, o, 64), __shfl_xor(a.lo, o, 64)};
 }
 
+// Totals over the 64 lanes of a wave of the N float-float values v[] (N <= 8,
+// padded to P = 2^k): recursive halving -- at level k a lane keeps half of
+// its values, adds its partner's (lane ^ 2^k) copies of that half, and
+// hands over the other half -- so the first levels take P/2, P/4, ...
+// additions instead of N each; a butterfly over the remaining levels
+// follows.  Lane l then holds the total of value bitrev(l mod P) (returned).
+template <int N>
+__device__ __forceinline__ FF wave_totals(const FF (&v)[N], int lane) {
+  constexpr int P = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
+  FF w[P];
+#pragma unroll
+  for (int i = 0; i < P; i++) w[i] = i < N ? v[i] : FF{0.f, 0.f};
+  int lvl = 0;
+#pragma unroll
+  for (int m = P; m > 1; m >>= 1, lvl++) {
+    const int h = m >> 1;
+    const bool up = (lane >> lvl) & 1;
+#pragma unroll
+    for (int j = 0; j < h; j++) {
+      const FF keep = up ? w[j + h] : w[j];
+      const FF give = up ? w[j] : w[j + h];
+      w[j] = ff_add(keep, ff_shfl_xor(give, 1 << lvl));
+    }
+  }
+#pragma unroll
+  for (int o = P; o < 64; o <<= 1) w[0] = ff_add(w[0], ff_shfl_xor(w[0], o));
+  return w[0];
+}
+
+// index of the value whose total lane l holds after wave_totals<N>
+template <int N>
+__device__ __forceinline__ int wave_totals_index(int lane) {
+  constexpr int P = N <= 1 ? 1 : (N <= 2 ? 2 : (N <= 4 ? 4 : 8));
+  int idx = 0;
+#pragma unroll
+  for (int k = 0, h = P >> 1; h >= 1; k++, h >>= 1) idx += ((lane >> k) & 1) * h;
+  return idx;
+}
+
 __device__ void ctl_step(const CtlArgs& C);
 
 // The profiler state is staged in LDS for the reduce kernels, so the
@@ -471,11 +510,18 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   flush();
 
   // ---- workgroup partial record
+  constexpr int L0 = OP == P_STATS ? (OPK == P_CURVE ? S_XX : 0) : S_XX;  // = l0, l1
+  constexpr int L1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
+  if constexpr (L1 > L0) {
+    FF part[L1 - L0];
 #pragma unroll
-  for (int i = 0; i < NL; i++) {
-    if (i < l0 || i >= l1) continue;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
+    for (int i = 0; i < L1 - L0; i++) part[i] = acc[L0 + i];
+    const FF tot = wave_totals<L1 - L0>(part, lane);
+    const int idx = wave_totals_index<L1 - L0>(lane);
+    if (lane < 8 && idx < L1 - L0) {
+      s_red[wave][L0 + idx][0] = tot.hi;
+      s_red[wave][L0 + idx][1] = tot.lo;
+    }
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -485,11 +531,6 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
     nfit += __shfl_xor(nfit, o, 64);
   }
   if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < NL; i++) {
-      s_red[wave][i][0] = acc[i].hi;
-      s_red[wave][i][1] = acc[i].lo;
-    }
     s_w[wave] = wsum;
     s_dm[wave] = __builtin_bit_cast(uint64_t, dmax);
     s_fit[wave] = nfit;
