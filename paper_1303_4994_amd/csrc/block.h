@@ -143,12 +143,24 @@ struct Blk {
   // BRACKET = false skips the block max and code bracket (callers that get
   // the block's code from elsewhere)
   template <bool BRACKET = true>
-  __device__ __forceinline__ int64_t load(const T* __restrict__ x, const Geo& g) {
+  __device__ __forceinline__ void load(const T* __restrict__ x, const Geo& g) {
     T v[4];
+    fetch(x, g, v);
+    take<BRACKET>(g, v);
+  }
+
+  // load() in two halves: fetch() issues the loads of this lane's samples
+  // into v[] (other work can run while they are in flight), take() finishes
+  // with the values
+  __device__ __forceinline__ void fetch(const T* __restrict__ x, const Geo& g, T v[4]) {
     int64_t idx = -1;
     nvalid = 0;
     if (act) idx = group_index<NDIM, LPB>(g, L, j, nvalid);
     load4<T>(x, idx, nvalid, v);
+  }
+
+  template <bool BRACKET = true>
+  __device__ __forceinline__ void take(const Geo& g, const T v[4]) {
     bool nf = false;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
@@ -159,7 +171,7 @@ struct Blk {
     if constexpr (!BRACKET) {
       M = 0.0;
       cf = cc = 0;
-      return idx;
+      return;
     }
     // block max |x|: reduce the magnitude bit patterns (monotone in value)
     if constexpr (sizeof(T) <= 4) {
@@ -193,7 +205,6 @@ struct Blk {
       M = __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
     }
     bracket<T>(M, g.cmin, g.cmax, cf, cc);
-    return idx;
   }
 
   __device__ __forceinline__ bool valid(int k) const { return k < nvalid; }

@@ -412,12 +412,29 @@ __global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
   uint32_t hcnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // wave-uniform
   unsigned long long wsum = 0;
 
+  // block of this lane in tile t (past the end: an empty block)
+  auto block_of = [&](int64_t t) -> int64_t {
+    const int64_t jj = (t * WPG + wave) * BPW + lane / LPB;
+    return jj < A.nbe ? jj * A.jstride : g.nblocks;
+  };
+  uint4* xw = NDIM >= 2 ? s_xch + wave * 64 : nullptr;
+  // the samples of the next tile are fetched while the current one is
+  // evaluated (a tile past the end fetches nothing)
+  B_ nb;
+  T nv[4];
+  nb.init(g, block_of(blockIdx.x), xw);
+  nb.fetch((const T*)A.x, g, nv);
   for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += A.nwg) {
-    const int64_t jj = (tile * WPG + wave) * BPW + lane / LPB;
-    B_ b;
-    b.init(g, jj < A.nbe ? jj * A.jstride : g.nblocks, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
-    if (OP == P_CENTER && A.rule != R_QUALITY) b.template load<false>((const T*)A.x, g);
-    else b.load((const T*)A.x, g);
+    B_ b = nb;
+    T cv[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) cv[k] = nv[k];
+    if (tile + A.nwg < A.ntiles) {
+      nb.init(g, block_of(tile + A.nwg), xw);
+      nb.fetch((const T*)A.x, g, nv);
+    }
+    if (OP == P_CENTER && A.rule != R_QUALITY) b.template take<false>(g, cv);
+    else b.take(g, cv);
     int32_t a[4], v[7][4];
     int eps[7], pw[7];
     Costs C;
