@@ -226,8 +226,10 @@ void apax_batch_destroy(apax_batch* b);
  * GPU work has finished, then admits requests from the head of the FIFO onto
  * every free slot while the in-flight footprint (input bytes + output
  * capacity of each admitted request) stays within the HBM budget, and
- * launches each admitted group as one persistent batch on the slot's own
- * stream.  Groups on different slots overlap on the device; a request that
+ * launches each admitted group on the slot's own stream: requests of 16 MB
+ * and more as single apax_encode / apax_decode calls (each with its own
+ * status word), the rest as one persistent batch.  Groups on different slots
+ * overlap on the device; a request that
  * arrives while others run is admitted as soon as a slot and budget free up.
  * Codec state stays on the device: each slot owns resident workspaces
  * (status words, work-queue tickets, look-back states, descriptor tables).

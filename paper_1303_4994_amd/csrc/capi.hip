@@ -956,8 +956,16 @@ struct SrvSlot {
   apax_batch* plan[2] = {nullptr, nullptr};
   std::vector<SrvReq> reqs;
   std::vector<uint32_t> which[2];       // request index in reqs for each plan item
+  std::vector<uint32_t> solo;           // requests run as single calls (request index)
+  uint32_t* d_solo = nullptr;           // their status words (device), then
+  uint32_t* h_solo = nullptr;           // pinned copies
   bool busy = false;
 };
+
+// Requests of at least this many payload bytes run as single apax_encode /
+// apax_decode calls on the slot's stream (the single-array kernels are faster
+// than the batch kernels on large arrays); smaller ones share batch launches.
+constexpr uint64_t SOLO_BYTES = 16ull << 20;
 
 uint64_t req_footprint(const apax_request& q, const HG& h) {
   const uint64_t in = q.op == APAX_OP_ENCODE ? h.nsamples * (uint64_t)h.esz : q.item.in_bytes;
@@ -980,9 +988,14 @@ struct apax_server {
 
 namespace {
 
+__global__ void k_copy_word(uint32_t* dst, const uint32_t* src) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 void server_free(apax_server* s) {
   for (auto& sl : s->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
+    if (sl.d_solo) hipFree(sl.d_solo);
     for (int k = 0; k < 2; k++) {
       if (sl.plan[k]) apax_batch_destroy(sl.plan[k]);
       if (sl.ws[k]) hipFree(sl.ws[k]);
@@ -995,16 +1008,53 @@ void server_free(apax_server* s) {
 }
 
 // launch one admitted group on a free slot
+// workspace bytes of a single call for request q (0 if it cannot be found)
+uint64_t solo_ws(const SrvReq& q) {
+  apax_params p = q.r.item.p;
+  if (q.r.op == APAX_OP_DECODE && apax_stream_info(q.hdr, 64, &p) != APAX_OK) return 0;
+  uint64_t need = 0;
+  return apax_workspace_size(&p, &need) == APAX_OK ? need : 0;
+}
+
 int server_launch(apax_server* s, SrvSlot& sl) {
   std::vector<apax_batch_item> items[2];
   for (int k = 0; k < 2; k++) sl.which[k].clear();
+  sl.solo.clear();
   for (uint32_t i = 0; i < sl.reqs.size(); i++) {
-    const int k = sl.reqs[i].r.op == APAX_OP_ENCODE ? 0 : 1;
-    items[k].push_back(sl.reqs[i].r.item);
-    if (k == 1) items[k].back().h_hdr = sl.reqs[i].hdr;
+    const SrvReq& q = sl.reqs[i];
+    const int k = q.r.op == APAX_OP_ENCODE ? 0 : 1;
+    const uint64_t w = q.footprint - q.r.item.cap >= SOLO_BYTES ? solo_ws(q) : 0;
+    if (w && w <= s->ws_bytes) {
+      sl.solo.push_back(i);
+      continue;
+    }
+    items[k].push_back(q.r.item);
+    if (k == 1) items[k].back().h_hdr = q.hdr;
     sl.which[k].push_back(i);
   }
   uint64_t soff = 0;
+  // large requests: single calls, each status word kept on the device, then
+  // one copy of them all
+  if (!sl.solo.empty()) {
+    for (uint32_t n = 0; n < sl.solo.size(); n++) {
+      const SrvReq& q = sl.reqs[sl.solo[n]];
+      const apax_batch_item& it = q.r.item;
+      const int k = q.r.op == APAX_OP_ENCODE ? 0 : 1;
+      int e = apax_status_clear(sl.ws[k], sl.stream);
+      if (!e)
+        e = k == 0 ? apax_encode(it.d_in, &it.p, it.d_out, it.cap, it.d_nbytes, sl.ws[k], s->ws_bytes, sl.stream)
+                   : apax_decode(q.hdr, it.d_in, it.in_bytes, it.d_out, it.cap, sl.ws[k], s->ws_bytes, sl.stream);
+      if (e) return e;
+      hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(64), 0, sl.stream, sl.d_solo + n,
+                         (const uint32_t*)sl.ws[k]);
+      if (hipGetLastError() != hipSuccess) return APAX_E_HIP;
+    }
+    const uint64_t nst = 4 * sl.solo.size();
+    sl.h_solo = (uint32_t*)(sl.staging + soff);
+    soff += (nst + 255) / 256 * 256;
+    if (hipMemcpyAsync(sl.h_solo, sl.d_solo, nst, hipMemcpyDeviceToHost, sl.stream) != hipSuccess)
+      return APAX_E_HIP;
+  }
   for (int k = 0; k < 2; k++) {
     if (items[k].empty()) continue;
     uint64_t wsb = 0;
@@ -1057,7 +1107,7 @@ int apax_server_create(uint64_t budget_bytes, uint32_t n_slots, uint32_t max_gro
   s->ws_bytes = ws_bytes;
   s->max_group = max_group;
   if (tune) s->tune = *tune;
-  // descriptor tables (<= 1 KiB per item) + two status arrays + alignment
+  // descriptor tables (<= 1 KiB per item) + three status arrays + alignment
   s->staging_bytes = (uint64_t)max_group * (sizeof(BatchEnc) > sizeof(BatchDec) ? sizeof(BatchEnc) : sizeof(BatchDec))
                      + (uint64_t)max_group * 16 + 16 * 4096;
   if (hipGetDevice(&s->dev) != hipSuccess) { delete s; return APAX_E_HIP; }
@@ -1066,6 +1116,7 @@ int apax_server_create(uint64_t budget_bytes, uint32_t n_slots, uint32_t max_gro
     bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&sl.ws[0], ws_bytes) == hipSuccess && hipMalloc(&sl.ws[1], ws_bytes) == hipSuccess &&
+              hipMalloc((void**)&sl.d_solo, 4 * (uint64_t)max_group) == hipSuccess &&
               hipHostMalloc((void**)&sl.staging, s->staging_bytes, hipHostMallocDefault) == hipSuccess;
     if (!ok) { server_free(s); return APAX_E_HIP; }
   }
@@ -1116,6 +1167,12 @@ int apax_server_poll(apax_server* s, apax_completion* done, uint32_t max_done, u
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) { err = APAX_E_HIP; break; }
     const double t = now_s();
+    for (uint32_t n = 0; n < sl.solo.size(); n++) {
+      const SrvReq& r = sl.reqs[sl.solo[n]];
+      s->ready.push_back(apax_completion{r.id, r.r.tag, status_code(sl.h_solo[n]), k, t - r.t_submit});
+      s->used -= r.footprint;
+    }
+    sl.solo.clear();
     for (int p = 0; p < 2; p++) {
       for (uint32_t i = 0; i < sl.which[p].size(); i++) {
         const SrvReq& r = sl.reqs[sl.which[p][i]];

@@ -129,3 +129,50 @@ def test_per_request_status_and_budget_refusal(A, S):
         srv.submit_encode(big, p, out, torch.zeros(1, dtype=torch.int64, device=DEV))
     assert ei.value.code == A.E_CAPACITY
     srv.close()
+
+
+def test_large_requests_run_alone_with_their_status(A, S):
+    """Requests of 16 MB and more run as single calls inside their group: the
+    results equal the standalone ones, and a non-finite large request fails
+    alone (the small and large requests around it succeed)."""
+    seed = 515
+    pools = synth.Pools(n=1 << 24, seed=seed)
+    srv = S.Server(budget_bytes=8 << 30, slots=2, max_group=6, ws_bytes=64 << 20)
+    jobs, refs, outs = [], [], []
+    planted = False
+    for i in range(12):
+        lo, hi = ((16 << 20), (40 << 20)) if i % 3 != 2 else ((4 << 10), (1 << 20))
+        spec = synth.item_spec(i, seed=seed, lo_bytes=lo, hi_bytes=hi)
+        x = pools.item_device(spec, DEV)
+        if x.dtype in (torch.float32, torch.float64):
+            params = {"mode": "fixed_rate", "brick": (256,), "rate": spec.get("rate", 4.0), "code": 150}
+        else:
+            params = {"mode": "lossless", "brick": (256,)}
+        if not planted and i % 3 != 2 and x.dtype in (torch.float32, torch.float64):
+            x = x.clone()  # one large request fails alone
+            x[x.numel() // 2] = float("inf")
+            planted = True
+        buf, nb = A.apax_encode(x, params, ws=A.workspace(x.dtype, tuple(x.shape), params, DEV))
+        n_ = int(nb.item())
+        refs.append(buf[:n_].clone())
+        out = torch.empty_like(buf)
+        nbo = torch.zeros(1, dtype=torch.int64, device=DEV)
+        outs.append((out, nbo))
+        jobs.append((x, params, out, nbo))
+    torch.cuda.synchronize()
+    ids = {srv.submit_encode(x, p, o, nb, tag=k): k for k, (x, p, o, nb) in enumerate(jobs)}
+    status = {}
+    for _ in range(2000000):
+        for c in srv.poll():
+            status[ids[c["id"]]] = c["status"]
+        if len(status) == len(jobs):
+            break
+    assert len(status) == len(jobs) and planted
+    torch.cuda.synchronize()
+    for k, (x, p, o, nb) in enumerate(jobs):
+        nonfinite = not bool(torch.isfinite(x).all()) if x.is_floating_point() else False
+        assert status[k] == (A.E_NONFINITE if nonfinite else 0), (k, status[k])
+        if not nonfinite:
+            n_ = int(nb.item())
+            assert n_ == refs[k].numel() and torch.equal(o[:n_], refs[k]), k
+    srv.close()
