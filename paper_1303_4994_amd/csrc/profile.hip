@@ -356,8 +356,11 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
   }
 }
 
-template <typename T, int LPB, int NDIM, int OPK>  // OPK: the pass (P_FITS, P_STATS, P_CENTER, P_CURVE)
-__global__ __launch_bounds__(256) void k_profile(ProfArgs A) {
+// OPK: the pass (P_FITS, P_STATS, P_CENTER, P_CURVE).  The statistics passes
+// over 1-4 byte samples are held to five waves per SIMD (a few spilled
+// values cost less than the latency the fifth wave hides).
+template <typename T, int LPB, int NDIM, int OPK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_STATS || OPK == P_CURVE) && sizeof(T) <= 4 ? 5 : 1))) void k_profile(ProfArgs A) {
   constexpr int OP = OPK == P_CURVE ? P_STATS : OPK;
   A.curve = OPK == P_CURVE;
   if (OPK == P_CURVE) A.rule = R_QUALITY;  // curve codes are fixed per block
