@@ -53,6 +53,17 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+TRAFFIC_KEYS = {  # kernel (trace name) -> key of its bytes per launch
+    "apax::k_encode<float, 64, 2, 4, false>": "k_encode",
+    "apax::k_decode<float, 64, 2, 4>": "k_decode",
+    "apax::k_profile<float, 64, 2, 1>": "k_profile_metrics",
+    "apax::k_profile<float, 64, 2, 4>": "k_profile_curve",
+    "apax::k_profile<float, 64, 2, 3>": "k_profile_centred",
+    "apax::k_profile<float, 64, 2, 2>": "k_profile_fits",
+    "apax::k_pmax<float>": "k_pmax",
+}
+
+
 def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str):
     """HBM bytes per launch of the codec kernels from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
@@ -90,8 +101,9 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
         fb = fv * 1024 * (ff or 1.0)
         wb = wv * 1024 * (fw or 1.0)
         lines.append(f"{name}<{k.split('<', 1)[1] if '<' in k else ''}: fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
-        if name in ("k_encode", "k_decode") and "float, 64, 2" in k:
-            lines.append(f"{name}_hbm_bytes_per_launch: {fb + wb:.0f}")
+        key = TRAFFIC_KEYS.get(k.replace("void ", "").split("(")[0].strip())
+        if key:
+            lines.append(f"{key}_hbm_bytes_per_launch: {fb + wb:.0f}")
     open(out_path, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -228,6 +240,14 @@ def main():
     assert A.apax_status(ws) == 0
     enc_ms = e0.elapsed_time(e1) / reps
     dec_ms = e1.elapsed_time(e2) / reps
+    # kernel of each profile pass: HIP events around it on the launch stream
+    # (apax_profile_timed), mean over `reps` profiles of the rotating copies
+    pass_runs = {}
+    for k in range(reps):
+        _, pm = A.apax_profile_timed(xs[k % R], params, ws)
+        for name, v in pm.items():
+            pass_runs.setdefault(name, []).append(v)
+    pass_ms = {name: sum(v) / len(v) for name, v in pass_runs.items()}
 
     # the decoded field reproduces the profiler's correlation (checked outside timing)
     yd = ys[(args.steps - 1) % R].double()
@@ -240,9 +260,23 @@ def main():
     dec_bytes = bound + nbytes_in          # read the stream, write the field
     enc_gbps = nbytes_in / (enc_ms * 1e-3) / 1e9
     dec_gbps = nbytes_in / (dec_ms * 1e-3) / 1e9
-    dominant = "k_encode" if enc_ms >= dec_ms else "k_decode"
-    dom_ms = max(enc_ms, dec_ms)
-    dom_bytes = enc_bytes if dominant == "k_encode" else dec_bytes
+    # algorithmic bytes per launch: every kernel reads its samples once; the
+    # subsample passes read every 16th block; the metrics pass writes, and the
+    # centred pass reads, one 4-byte code per block
+    nblocks = (4096 // 16) * (4096 // 16)
+    sub_bytes = ((nblocks + 15) // 16) * 256 * 4
+    probes = [v for name, v in pass_ms.items() if name.startswith("probe")]
+    kernels = {  # name: (trace name, ms per launch, algorithmic bytes per launch)
+        "k_encode": ("k_encode<float, 64, 2, 4, false>", enc_ms, enc_bytes),
+        "k_decode": ("k_decode<float, 64, 2, 4>", dec_ms, dec_bytes),
+        "k_profile_metrics": ("k_profile<float, 64, 2, 1>", pass_ms["metrics"], nbytes_in + 4 * nblocks),
+        "k_profile_curve": ("k_profile<float, 64, 2, 4>", pass_ms["curve"], sub_bytes),
+        "k_profile_centred": ("k_profile<float, 64, 2, 3>", pass_ms["centred"], nbytes_in + 4 * nblocks),
+        "k_profile_fits": ("k_profile<float, 64, 2, 2>", sum(probes) / len(probes), sub_bytes),
+        "k_pmax": ("k_pmax<float>", pass_ms["max"], nbytes_in),
+    }
+    dominant = max(kernels, key=lambda k: kernels[k][1])  # longest launch
+    dom_name, dom_ms, dom_bytes = kernels[dominant]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic = read_traffic(dominant)
     out = {
@@ -273,10 +307,14 @@ def main():
         "ratio": round(ratio, 4),
         "r": prof["metrics"]["r"],
         "code": prof["code"],
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 2),
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_launch": dom_bytes},
+        "kernels_us": {n: {"kernel": t, "us": round(1e3 * ms, 2),
+                           "GBps": round(b / (ms * 1e-3) / 1e9, 1)}
+                       for n, (t, ms, b) in kernels.items()},
+        "profile_pass_us": {n: round(1e3 * v, 2) for n, v in pass_ms.items()},
     }
     if args.copy_probe:
         # a plain copy of the field: reads and writes exactly input_bytes

@@ -139,6 +139,23 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* h_o
 int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                        hipStream_t stream);
 
+/* Instrumentation for benchmarks: apax_profile with HIP events recorded on
+ * `stream` just before and after the main kernel of each pass; pass_ms[i]
+ * (APAX_NPASS entries) receives that kernel's duration for pass i, or -1 if
+ * the pass did not run (the one-workgroup reduction after each pass lies
+ * outside the pair).  Synchronous, like apax_profile. */
+enum {
+  APAX_PASS_MAX = 0,      /* max |x| pass (P1) */
+  APAX_PASS_PROBE0 = 1,   /* bisection probe launches 1..9 (P2) */
+  APAX_PASS_HIST = 10,    /* stream histogram at the chosen code (P3) */
+  APAX_PASS_CURVE = 11,   /* the 17-code curve (P3) */
+  APAX_PASS_METRICS = 12, /* metrics at the operating point (P4) */
+  APAX_PASS_CENTRED = 13, /* centred sums for the standard deviations (P4) */
+  APAX_NPASS = 14
+};
+int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* h_out,
+                       float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* Waits for `stream`, then fills *h_out from the profile that d_ws holds
  * (p: the parameters that profile was called with).  Same errors as
  * apax_profile. */

@@ -100,6 +100,7 @@ def _load():
     L.apax_workspace_size.argtypes = [P(Params), P(u64)]
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
+    L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
     L.apax_decode.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp]
@@ -234,6 +235,22 @@ def apax_profile_async(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=N
     p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
     _check(lib.apax_profile_async(_dev_ptr(x), C.byref(p), _dev_ptr(ws), ws.numel(),
                                   _stream_ptr(stream)), "apax_profile_async")
+
+
+PASS_NAMES = ["max", "probe1", "probe2", "probe3", "probe4", "probe5", "probe6", "probe7", "probe8",
+              "probe9", "hist", "curve", "metrics", "centred"]
+
+
+def apax_profile_timed(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None):
+    """apax_profile plus the duration (ms, HIP events on the stream) of the
+    kernel of each pass that ran: returns (result dict, {pass name: ms})."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    r = ProfileResult()
+    ms = (C.c_float * len(PASS_NAMES))()
+    _check(lib.apax_profile_timed(_dev_ptr(x), C.byref(p), C.byref(r), ms, _dev_ptr(ws), ws.numel(),
+                                  _stream_ptr(stream)), "apax_profile_timed")
+    return profile_dict(r), {n: ms[i] for i, n in enumerate(PASS_NAMES) if ms[i] >= 0}
 
 
 def apax_profile_read(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None) -> dict:

@@ -480,8 +480,17 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
 
 // The whole profile as one asynchronous launch sequence on `stream`; its
 // result stays in the workspace's PState.
-static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream) {
+// ev (optional): 2 * APAX_NPASS events, a pair around the kernel of each
+// pass that runs (bit of *ran set)
+static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
+                           hipEvent_t* ev = nullptr, uint32_t* ran = nullptr) {
   int e;
+  if (ran) *ran = 0;
+  auto pair = [&](int pass) -> hipEvent_t* {
+    if (!ev) return nullptr;
+    *ran |= 1u << pass;
+    return ev + 2 * pass;
+  };
   const Geo& g = h.g;
   PState* st = (PState*)d_ws;
   int64_t sub_stride;
@@ -512,7 +521,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
   C.target = p->target_corr;
   auto ctl = [&](int step) { C.step = step; return hip_err(launch_ctl(C, stream)); };
   // one pass over blocks; its last workgroup reduces and runs control step `next`
-  auto run = [&](int op, int rl, int mask_sel, bool sub, int maxcodes, int next, int flags) -> int {
+  auto run = [&](int op, int rl, int mask_sel, bool sub, int maxcodes, int next, int flags, int pass) -> int {
     ProfArgs A;
     memset(&A, 0, sizeof(A));
     A.x = d_x;
@@ -532,7 +541,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     A.store_cj = (flags & 8) != 0;
     A.C = C;
     A.C.step = next;
-    return hip_err(launch_profile(h.dtype, h.ndim, A, stream));
+    return hip_err(launch_profile(h.dtype, h.ndim, A, stream, pair(pass)));
   };
   enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8 };
 
@@ -544,16 +553,18 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
   if ((e = hip_err(hipGetLastError()))) return e;
   if (g.nblocks) {
     C.step = C_INIT;
-    if ((e = hip_err(launch_pmax(h.dtype, d_x, h.nsamples, partials_ptr(d_ws, h), C, stream)))) return e;
+    if ((e = hip_err(launch_pmax(h.dtype, d_x, h.nsamples, partials_ptr(d_ws, h), C, stream,
+                                 pair(APAX_PASS_MAX)))))
+      return e;
     for (int b = 0; b < nbatch && (fr || h.mode == APAX_FIXED_QUALITY); b++) {
-      if (fr) e = run(P_FITS, R_RATE, 0, true, tree_n, C_DECIDE, 0);
-      else e = run(P_STATS, R_QUALITY, 0, false, tree_n, C_DECIDE, 0);
+      if (fr) e = run(P_FITS, R_RATE, 0, true, tree_n, C_DECIDE, 0, APAX_PASS_PROBE0 + b);
+      else e = run(P_STATS, R_QUALITY, 0, false, tree_n, C_DECIDE, 0, APAX_PASS_PROBE0 + b);
       if (e) return e;
     }
-    if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL))) return e;
-    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_METRICS, F_CURVE))) return e;
-    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE))) return e;
-    if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL))) return e;
+    if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL, APAX_PASS_HIST))) return e;
+    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_METRICS, F_CURVE, APAX_PASS_CURVE))) return e;
+    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE, APAX_PASS_METRICS))) return e;
+    if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL, APAX_PASS_CENTRED))) return e;
   } else {
     if ((e = ctl(C_INIT))) return e;
     if ((e = ctl(C_MASK))) return e;
@@ -633,6 +644,29 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   if (e) return e;
   if ((e = profile_enqueue(d_x, p, h, d_ws, stream))) return e;
   return apax_profile_read(p, out, d_ws, stream);
+}
+
+int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* out,
+                       float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!out || !pass_ms) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  hipEvent_t ev[2 * APAX_NPASS];
+  int made = 0;
+  for (; made < 2 * APAX_NPASS; made++)
+    if (hipEventCreate(&ev[made]) != hipSuccess) break;
+  uint32_t ran = 0;
+  if (made < 2 * APAX_NPASS) e = APAX_E_HIP;
+  if (!e) e = profile_enqueue(d_x, p, h, d_ws, stream, ev, &ran);
+  if (!e) e = apax_profile_read(p, out, d_ws, stream);  // waits for the stream
+  for (int i = 0; i < APAX_NPASS; i++) {
+    pass_ms[i] = -1.0f;
+    if (!e && ((ran >> i) & 1) && hipEventElapsedTime(&pass_ms[i], ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+      e = APAX_E_HIP;
+  }
+  for (int i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
+  return e;
 }
 
 int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,

@@ -200,9 +200,11 @@ hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
 int64_t prof_wgs(int64_t ntiles, int ncodes);
-hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s);
+// ev (optional): events recorded just before and just after the pass kernel
+// (its one-workgroup reduce follows outside the pair)
+hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,
-                       hipStream_t s);
+                       hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_ctl(const CtlArgs& C, hipStream_t s);
 
 }  // namespace apax

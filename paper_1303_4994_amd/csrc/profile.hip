@@ -390,22 +390,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   const double s2 = ldexp(1.0, -2 * escale);
   const double mx = st->mean[0], my = st->mean[1], md = st->mean[2];
   // active accumulator slots of this pass
-  const int l0 = OP == P_STATS ? (A.curve ? S_XX : 0) : S_XX;
-  const int l1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
-  FF acc[NL];
-#pragma unroll
-  for (int i = 0; i < NL; i++) acc[i] = {0.f, 0.f};
+  constexpr int L0 = OP == P_STATS ? (OPK == P_CURVE ? S_XX : 0) : S_XX;
+  constexpr int L1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
+  constexpr int NA = L1 > L0 ? L1 - L0 : 1;
   // each lane sums its groups' binary64 terms over up to 64 tiles, then
   // moves the partial (scaled by a power of two) into the FP32 float-float
-  // accumulators that every further reduction level uses
+  // accumulators that every further reduction level uses; those are only
+  // touched by these moves, so they live in LDS (one slot per thread)
+  __shared__ float2 s_acc[NA][WPG * 64];
+#pragma unroll
+  for (int i = 0; i < NA; i++) s_acc[i][threadIdx.x] = float2{0.f, 0.f};
   double lacc[NL];
 #pragma unroll
   for (int i = 0; i < NL; i++) lacc[i] = 0.0;
   int lcount = 0;
   auto flush = [&]() {
 #pragma unroll
-    for (int i = 0; i < NL; i++)
-      if (i >= l0 && i < l1) acc[i] = ff_add(acc[i], ff_of(lacc[i] * (i < S_XX ? s1 : s2)));
+    for (int i = L0; i < L1; i++) {
+      const float2 v = s_acc[i - L0][threadIdx.x];
+      const FF a = ff_add(FF{v.x, v.y}, ff_of(lacc[i] * (i < S_XX ? s1 : s2)));
+      s_acc[i - L0][threadIdx.x] = float2{a.hi, a.lo};
+    }
 #pragma unroll
     for (int i = 0; i < NL; i++) lacc[i] = 0.0;
     lcount = 0;
@@ -530,12 +535,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   flush();
 
   // ---- workgroup partial record
-  constexpr int L0 = OP == P_STATS ? (OPK == P_CURVE ? S_XX : 0) : S_XX;  // = l0, l1
-  constexpr int L1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
   if constexpr (L1 > L0) {
     FF part[L1 - L0];
 #pragma unroll
-    for (int i = 0; i < L1 - L0; i++) part[i] = acc[L0 + i];
+    for (int i = 0; i < L1 - L0; i++) part[i] = FF{s_acc[i][threadIdx.x].x, s_acc[i][threadIdx.x].y};
     const FF tot = wave_totals<L1 - L0>(part, lane);
     const int idx = wave_totals_index<L1 - L0>(lane);
     if (lane < 8 && idx < L1 - L0) {
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   const int64_t r = (int64_t)ci * A.nwg + blockIdx.x;
   if (threadIdx.x < NL) {
     const int i = threadIdx.x;
-    if (i >= l0 && i < l1) {
+    if (i >= L0 && i < L1) {
       FF tt = {s_red[0][i][0], s_red[0][i][1]};
       for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
       const int si = OP == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
@@ -813,11 +816,12 @@ static hipError_t launch_nd(const ProfArgs& A, int ndim, hipStream_t s) {
   return launch_lpb<T, 3>(A, s);
 }
 
-hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
+hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev) {
   A.ntiles = prof_tiles(A.g, A.nbe);
   A.nwg = prof_wgs(A.ntiles, A.maxcodes);
   if (A.ntiles == 0) return hipSuccess;
   hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
   switch (dtype) {
     case DT_I8: e = launch_nd<int8_t>(A, ndim, s); break;
     case DT_I16: e = launch_nd<int16_t>(A, ndim, s); break;
@@ -826,6 +830,7 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
     default: e = launch_nd<double>(A, ndim, s); break;
   }
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   if (A.op == P_FITS && A.hist) hipLaunchKernelGGL((k_reduce<P_FITS, true>), dim3(1), dim3(256), 0, s, A);
   else if (A.op == P_FITS) hipLaunchKernelGGL((k_reduce<P_FITS, false>), dim3(1), dim3(256), 0, s, A);
   else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_reduce<P_CURVE, false>), dim3(1), dim3(256), 0, s, A);
@@ -835,10 +840,11 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s) {
 }
 
 hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t* ev) {
   if (n == 0) return hipSuccess;
   const unsigned grid = PMAX_WGS;
   PMaxPart* P = reinterpret_cast<PMaxPart*>(parts);
+  if (ev && hipEventRecord(ev[0], s) != hipSuccess) return hipErrorUnknown;
   switch (dtype) {
     case DT_I8: hipLaunchKernelGGL(k_pmax<int8_t>, dim3(grid), dim3(256), 0, s, (const int8_t*)x, n, P); break;
     case DT_I16: hipLaunchKernelGGL(k_pmax<int16_t>, dim3(grid), dim3(256), 0, s, (const int16_t*)x, n, P); break;
@@ -848,6 +854,7 @@ hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_pmax_reduce, dim3(1), dim3(256), 0, s, (const PMaxPart*)P, (int)grid, C);
   return hipGetLastError();
 }
