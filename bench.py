@@ -121,6 +121,28 @@ def cpu_baseline(x, params):
                       "single-threaded C oracle", "seconds": round(dt, 3)}
 
 
+def cpu_baseline_items(arrays, op, budget_bytes=192 << 20):
+    """Oracle timed on the first items of a batch or request mix (about
+    budget_bytes of input): encode (op "encode") or encode + decode of each."""
+    from oracle import oracle as O
+    sample, nb = [], 0
+    for x, p in arrays:
+        if nb >= budget_bytes:
+            break
+        sample.append((x.cpu().numpy(), p))
+        nb += sample[-1][0].nbytes
+    t0 = time.perf_counter()
+    for xh, p in sample:
+        st = O.encode(xh, p)
+        if op != "encode":
+            O.decode(st)
+    dt = time.perf_counter() - t0
+    what = "encode" if op == "encode" else "encode + decode"
+    return {"value": round(nb / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {len(sample)} items ({nb / 1e6:.0f} MB), {what} of each, "
+                      "single-threaded C oracle", "seconds": round(dt, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,7 +456,17 @@ def bench_batch(args):
         "decode_GBps_batched": round(nbytes_in / t_dec / 1e9, 2),
         "encode_pct_hbm": round(100 * nbytes_in / t_batch / 1e9 / HBM_PEAK_GBPS, 2),
         "lossless_roundtrip_exact": bool(ok),
+        # one graph replay launches one persistent kernel per block-shape class
+        # (1-D 256-sample blocks: k_encode_batch<64, 1, WP>); it reads every
+        # array and writes every stream once
+        "roofline": {"bound": "hbm", "kernel": "k_encode_batch (one hipGraph replay)",
+                     "achieved": round((nbytes_in + stream_bytes) / t_batch / 1e9, 2),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round((nbytes_in + stream_bytes) / t_batch / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": nbytes_in + stream_bytes},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_items(arrays, "encode")
     print(json.dumps(out), flush=True)
 
 
@@ -548,6 +580,8 @@ def bench_serve(args):
         "offered_GBps": round(args.rho * T_plain / 1e9, 2),
         "checked_items": len(ref),
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_items([(r["x"], r["params"]) for r in items], "both")
     print(json.dumps(out), flush=True)
 
 
