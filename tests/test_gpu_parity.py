@@ -371,3 +371,22 @@ def test_c2_full_sampled(A):
         assert np.array_equal(yn[sl], brute.dequant_np(a, code_j)), j
     m = O.stats(x.ravel(), yn.ravel())
     assert abs(m["one_minus_r"] - pg["metrics"]["one_minus_r"]) <= 1e-9 * m["one_minus_r"]
+
+
+def test_profile_timed_equals_profile(A):
+    """apax_profile_timed returns apax_profile's result and a positive duration
+    for the kernel of every pass that ran (and only those)."""
+    x = tiny(np.float32, (300, 200), 21)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, x.shape, params, DEV)
+    res, ms = A.apax_profile_timed(xg, params, ws)
+    assert res == A.apax_profile(xg, params)
+    assert {"max", "hist", "curve", "metrics", "centred", "probe1"} <= set(ms)
+    assert all(v > 0 for v in ms.values())
+    xl = torch.from_numpy(tiny(np.int16, (5000,), 22)).to(DEV)
+    pl = {"mode": "lossless", "brick": (256,)}
+    wl = A.workspace(xl.dtype, (5000,), pl, DEV)
+    res, ms = A.apax_profile_timed(xl, pl, wl)
+    assert res == A.apax_profile(xl, pl)
+    assert not any(k.startswith("probe") for k in ms)  # lossless: no bisection
