@@ -7,6 +7,7 @@ Everything here works on host numpy arrays.  Parameters are plain dicts:
 The array's dtype and shape give the dtype and dims.
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -239,3 +240,43 @@ def corr_at(x: np.ndarray, params, code: int) -> float:
     r = C.c_double()
     _check(lib().orc_corr_at(_ptr(x), C.byref(p), int(code), C.byref(r)), "corr_at")
     return r.value
+
+
+# ---------------------------------------------------------------- Sec. 4, Window 4
+# The 2-sigma signal-to-residual margin: the per-sample ratio |x| / |d| of the
+# input to the residual d = x - y of the decoded array y, taken at the level
+# that 95.5 % of the samples reach or exceed (the 4.5th percentile, nearest
+# rank: the ceil(0.045 n)-th smallest ratio), in dB.  A sample with d = 0 has
+# an infinite ratio; one with x = 0 and d != 0 has ratio 0 (-inf dB).
+S2R_P = 0.045
+
+
+def s2r_ratios(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Per-sample |x| / |x - y| in binary64 (x, y as binary64)."""
+    xd = np.ascontiguousarray(x, np.float64).ravel()
+    yd = np.ascontiguousarray(y, np.float64).ravel()
+    d = xd - yd
+    out = np.full(xd.shape, np.inf)
+    nz = d != 0
+    out[nz] = np.abs(xd[nz]) / np.abs(d[nz])
+    return out
+
+
+def s2r_margin_xy(x: np.ndarray, y: np.ndarray, p: float = S2R_P):
+    """(ratio, dB) at the nearest-rank p-quantile of s2r_ratios(x, y)."""
+    r = s2r_ratios(x, y)
+    if r.size == 0:
+        return float("nan"), float("nan")
+    k = int(math.ceil(p * r.size))
+    k = min(max(k, 1), r.size)
+    v = float(np.partition(r, k - 1)[k - 1])
+    if v == 0.0:
+        return v, float("-inf")
+    return v, (float("inf") if math.isinf(v) else 20.0 * math.log10(v))
+
+
+def s2r_margin(x: np.ndarray, params):
+    """2-sigma S2R margin of encoding x at the operating point in params
+    (code, stream mask), against the decoded array."""
+    y = decode(encode(x, params))
+    return s2r_margin_xy(x, y)

@@ -643,3 +643,39 @@ def test_empty_array():
     st = brute.Stream(s)
     assert st.nblocks == 0 and len(s) == st.area
     assert O.decode(s).size == 0
+
+
+# ------------------------------------------------ Sec. 4 Window 4: 2-sigma S2R margin
+def test_s2r_margin_constructed_ranks():
+    # ratios 1..n by construction (x = i, y = i - 1): the nearest-rank 4.5th
+    # percentile is the ceil(0.045 n)-th smallest
+    for n, k in ((1000, 45), (100, 5), (200, 9), (1, 1), (23, 2)):
+        x = np.arange(1, n + 1, dtype=np.float64)
+        perm = np.random.default_rng(n).permutation(n)
+        ratio, db = O.s2r_margin_xy(x[perm], x[perm] - 1)
+        assert ratio == float(k)
+        assert db == 20.0 * math.log10(k)
+
+
+def test_s2r_margin_infinities():
+    x = np.linspace(1, 2, 100)
+    assert O.s2r_margin_xy(x, x) == (float("inf"), float("inf"))  # exact: d = 0
+    x0 = np.concatenate([np.zeros(5), np.linspace(1, 2, 95)])
+    y0 = x0 - 0.25                                                  # d != 0 everywhere
+    assert O.s2r_margin_xy(x0, y0) == (0.0, float("-inf"))          # 5 of 100 zeros reach rank 5
+    x1 = np.concatenate([np.zeros(4), np.linspace(1, 2, 96)])
+    ratio, _ = O.s2r_margin_xy(x1, x1 - 0.25)
+    assert ratio == 4.0                                             # rank 5: the smallest nonzero, 1 / 0.25
+
+
+def test_s2r_margin_respects_the_attenuation_error_bound():
+    # fixed quality at code c: |d| <= 1/(2 g(c)) plus the output rounding, so
+    # every ratio is at least 2 g(c) |x| (to 1 %), hence so is the percentile
+    rng = np.random.default_rng(5)
+    x = (np.cumsum(rng.standard_normal(4096)) * 10 + 50).astype(np.float64)
+    for c in (40, 200, 300):
+        params = {"mode": "fixed_quality", "brick": (256,), "code": c}
+        ratio, _ = O.s2r_margin(x, params)
+        ax = np.sort(np.abs(x))
+        bound = 2 * O.gain(c) * ax[math.ceil(0.045 * x.size) - 1]
+        assert ratio >= 0.99 * bound, (c, ratio, bound)
