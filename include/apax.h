@@ -156,6 +156,17 @@ enum {
 int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* h_out,
                        float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* Sec. 4 Window 4: the 2-sigma signal-to-residual margin of the operating
+ * point of the profile that d_ws holds (run apax_profile / _async on d_x with
+ * the same p first; fixed rate uses the per-block codes of its metrics pass).
+ * With d = x - y, y the decoded array: the ceil(0.045 n)-th smallest of the
+ * per-sample ratios |x| / |d| (binary64; d = 0 gives +inf) in *h_ratio, and
+ * 20 log10 of it in *h_db (-inf for a zero ratio).  Exact (a digit-by-digit
+ * selection on the ratio's bit pattern, five passes over d_x).  Synchronous;
+ * NaN for an empty array. */
+int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,
+                    uint64_t ws_bytes, hipStream_t stream);
+
 /* Waits for `stream`, then fills *h_out from the profile that d_ws holds
  * (p: the parameters that profile was called with).  Same errors as
  * apax_profile. */

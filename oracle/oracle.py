@@ -267,7 +267,8 @@ def s2r_margin_xy(x: np.ndarray, y: np.ndarray, p: float = S2R_P):
     r = s2r_ratios(x, y)
     if r.size == 0:
         return float("nan"), float("nan")
-    k = int(math.ceil(p * r.size))
+    # nearest rank ceil(p n), computed exactly for p = 45/1000
+    k = (45 * r.size + 999) // 1000 if p == S2R_P else int(math.ceil(p * r.size))
     k = min(max(k, 1), r.size)
     v = float(np.partition(r, k - 1)[k - 1])
     if v == 0.0:

@@ -100,6 +100,7 @@ def _load():
     L.apax_workspace_size.argtypes = [P(Params), P(u64)]
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
+    L.apax_s2r_margin.argtypes = [vp, P(Params), P(C.c_double), P(C.c_double), vp, u64, vp]
     L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
@@ -251,6 +252,17 @@ def apax_profile_timed(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=N
     _check(lib.apax_profile_timed(_dev_ptr(x), C.byref(p), C.byref(r), ms, _dev_ptr(ws), ws.numel(),
                                   _stream_ptr(stream)), "apax_profile_timed")
     return profile_dict(r), {n: ms[i] for i, n in enumerate(PASS_NAMES) if ms[i] >= 0}
+
+
+def apax_s2r_margin(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None):
+    """2-sigma S2R margin (ratio, dB) at the operating point of the profile
+    of x that ws holds (apax_profile / apax_profile_async with params)."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    ratio, db = C.c_double(), C.c_double()
+    _check(lib.apax_s2r_margin(_dev_ptr(x), C.byref(p), C.byref(ratio), C.byref(db), _dev_ptr(ws),
+                               ws.numel(), _stream_ptr(stream)), "apax_s2r_margin")
+    return ratio.value, db.value
 
 
 def apax_profile_read(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None) -> dict:

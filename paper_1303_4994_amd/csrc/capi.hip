@@ -669,6 +669,37 @@ int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_resul
   return e;
 }
 
+int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,
+                    uint64_t ws_bytes, hipStream_t stream) {
+  if (!h_ratio || !h_db) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  *h_ratio = NAN;
+  *h_db = NAN;
+  if (h.nsamples == 0) return APAX_OK;
+  S2RArgs A;
+  memset(&A, 0, sizeof(A));
+  A.x = d_x;
+  A.st = (PState*)d_ws;
+  A.cj = cj_ptr(d_ws, h);
+  A.hist = (uint32_t*)partials_ptr(d_ws, h);  // the profile's partial records are spent
+  A.rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
+  A.g = h.g;
+  const uint64_t rank = (45 * h.nsamples + 999) / 1000;  // ceil(0.045 n), n >= 1
+  if ((e = hip_err(launch_s2r(h.dtype, h.ndim, A, rank, stream)))) return e;
+  PState hs;
+  if (hipMemcpyAsync(&hs, d_ws, sizeof(PState), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  if (hs.status & ST_NONFINITE) return APAX_E_NONFINITE;
+  if (hs.status & ST_INTERNAL) return APAX_E_INTERNAL;
+  double r;
+  memcpy(&r, &hs.s2r_prefix, 8);
+  *h_ratio = r;
+  *h_db = r == 0.0 ? -INFINITY : (isinf(r) ? INFINITY : 20.0 * log10(r));
+  return APAX_OK;
+}
+
 int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                        hipStream_t stream) {
   HG h;

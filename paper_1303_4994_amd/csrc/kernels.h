@@ -105,6 +105,8 @@ struct PState {
   double msums[NSUM];                 // metrics at the operating point
   uint64_t mwords;
   uint64_t sub_samples;               // samples in the subsample blocks (histogram pass)
+  uint64_t s2r_prefix, s2r_rank;      // S2R margin selection: digits chosen, rank left
+  int32_t s2r_level, pad3;
 };
 
 // Per-(code, workgroup) partial results of a profile pass, one array per
@@ -164,6 +166,18 @@ struct ProfArgs {
   Geo g;
 };
 constexpr int PMAX_WGS = 1024;
+
+// 2-sigma S2R margin passes (after a profile of the same array)
+struct S2RArgs {
+  const void* x;
+  PState* st;
+  const int32_t* cj;  // fixed rate: per-block codes of the profile's metrics pass
+  uint32_t* hist;     // 8192 bins
+  int64_t ntiles, nwg;
+  int rule, pad;
+  Geo g;
+};
+hipError_t launch_s2r(int dtype, int ndim, S2RArgs& A, uint64_t rank, hipStream_t s);
 
 // ---- batches: many arrays, one persistent launch per (LPB, NDIM) class
 struct BatchEnc {

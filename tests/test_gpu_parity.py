@@ -390,3 +390,57 @@ def test_profile_timed_equals_profile(A):
     res, ms = A.apax_profile_timed(xl, pl, wl)
     assert res == A.apax_profile(xl, pl)
     assert not any(k.startswith("probe") for k in ms)  # lossless: no bisection
+
+
+S2R_CASES = [c for c in CASES if c[0] in ("f32-2d-16x16-fr", "f64-3d-2x4x8-fq", "f32-1d-B128-fr",
+                                         "i16-1d-B64-fr", "i32-2d-fq", "i16-1d-B256-lossless",
+                                         "f64-2d-8x8-fr", "f32-1d-noise-fr-top")]
+
+
+@pytest.mark.parametrize("name,dt,shape,params,kind", S2R_CASES, ids=[c[0] for c in S2R_CASES])
+def test_s2r_margin_small(A, name, dt, shape, params, kind):
+    """2-sigma S2R margin at the profiled operating point: the GPU's digit
+    selection finds exactly the oracle's nearest-rank ratio."""
+    print(f"case {name}", flush=True)
+    x = tiny(dt, shape, 8, kind)
+    pp = {k: v for k, v in params.items() if k != "code"}
+    pp["target_corr"] = 0.9999
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, tuple(x.shape), pp, DEV)
+    pg = A.apax_profile(xg, pp, ws=ws)
+    ratio, db = A.apax_s2r_margin(xg, pp, ws)
+    p_at = dict(pp, code=pg["code"],
+                stream_mask=pg["stream_mask"] & (0x7F if pp["mode"] == "fixed_rate" else 0xFF))
+    r_o, db_o = O.s2r_margin(x, p_at)
+    assert ratio == r_o and db == db_o, (ratio, r_o, db, db_o)
+    assert A.apax_profile_read(xg, pp, ws) == pg  # the profile result is left intact
+
+
+def test_s2r_margin_c1_full(A):
+    """C1 field at its profiled 4:1 operating point."""
+    x = synth.grf2d(4096, 4096)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, x.shape, params, DEV)
+    pg = A.apax_profile(xg, params, ws=ws)
+    ratio, db = A.apax_s2r_margin(xg, params, ws)
+    p_at = dict(params, code=pg["code"], stream_mask=pg["stream_mask"] & 0x7F)
+    buf, nb = A.apax_encode(xg, p_at)
+    y = A.apax_decode(buf, int(nb.item())).cpu().numpy()
+    r_o, db_o = O.s2r_margin_xy(x, y)   # against the GPU's own decode, which equals the oracle's
+    assert ratio == r_o and db == db_o, (ratio, r_o)
+    assert np.isfinite(db) and db > 0
+
+
+def test_s2r_margin_empty_and_exact(A):
+    x = torch.zeros((0, 16), dtype=torch.float32, device=DEV)
+    p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    ws = A.workspace(x.dtype, (0, 16), p, DEV)
+    A.apax_profile(x, p, ws=ws)
+    r, db = A.apax_s2r_margin(x, p, ws)
+    assert math.isnan(r) and math.isnan(db)
+    xi = torch.from_numpy(tiny(np.int16, (3000,), 3)).to(DEV)   # lossless: exact, +inf
+    pl = {"mode": "lossless", "brick": (64,)}
+    wl = A.workspace(xi.dtype, (3000,), pl, DEV)
+    A.apax_profile(xi, pl, ws=wl)
+    assert A.apax_s2r_margin(xi, pl, wl) == (math.inf, math.inf)
