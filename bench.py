@@ -271,6 +271,14 @@ def main():
             pass_runs.setdefault(name, []).append(v)
     pass_ms = {name: sum(v) / len(v) for name, v in pass_runs.items()}
 
+    # the 2-sigma S2R margin at the operating point (Sec. 4 Window 4; not part
+    # of the step): the workspace holds the last timed profile of this field
+    xl = xs[(reps - 1) % R]
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    s2r_ratio, s2r_db = A.apax_s2r_margin(xl, params, ws)
+    s2r_ms = (time.perf_counter() - ts0) * 1e3
+
     # the decoded field reproduces the profiler's correlation (checked outside timing)
     yd = ys[(args.steps - 1) % R].double()
     xd = xs[(args.steps - 1) % R].double()
@@ -337,6 +345,9 @@ def main():
                            "GBps": round(b / (ms * 1e-3) / 1e9, 1)}
                        for n, (t, ms, b) in kernels.items()},
         "profile_pass_us": {n: round(1e3 * v, 2) for n, v in pass_ms.items()},
+        "s2r_margin": {"db": round(s2r_db, 4), "ratio": s2r_ratio, "ms_per_call": round(s2r_ms, 3),
+                       "note": "2-sigma S2R margin at the operating point, five selection passes; "
+                               "outside the step"},
     }
     if args.copy_probe:
         # a plain copy of the field: reads and writes exactly input_bytes
