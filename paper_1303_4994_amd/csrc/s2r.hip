@@ -47,14 +47,27 @@ __global__ __launch_bounds__(256) void k_s2r(S2RArgs A) {
     const int eq = -(c >> 4);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      if (!(b.act && b.valid(k))) continue;
-      const double x = b.xd[k];
-      const double y = A.rule == R_LOSSLESS ? (double)a[k] : (double)to_out<T>(dequant_rk(a[k], Rq, eq));
-      const double d = x - y;
-      const uint64_t key = d == 0.0 ? 0x7FF0000000000000ull
-                                    : __builtin_bit_cast(uint64_t, __builtin_fabs(x) / __builtin_fabs(d));
-      const bool match = level == 0 || (key >> (shift + width)) == prefix;
-      if (match) atomicAdd(&s_hist[(uint32_t)(key >> shift) & ((1u << width) - 1u)], 1u);
+      bool match = false;
+      uint32_t digit = 0;
+      if (b.act && b.valid(k)) {
+        const double x = b.xd[k];
+        const double y = A.rule == R_LOSSLESS ? (double)a[k] : (double)to_out<T>(dequant_rk(a[k], Rq, eq));
+        const double d = x - y;
+        const uint64_t key = d == 0.0 ? 0x7FF0000000000000ull
+                                      : __builtin_bit_cast(uint64_t, __builtin_fabs(x) / __builtin_fabs(d));
+        match = level == 0 || (key >> (shift + width)) == prefix;
+        digit = (uint32_t)(key >> shift) & ((1u << width) - 1u);
+      }
+      // one LDS add per distinct digit of the wave (neighbouring samples
+      // mostly share a digit): the lowest pending lane's digit, counted by ballot
+      uint64_t pending = __ballot(match);
+      while (pending) {
+        const int lead = __builtin_ctzll(pending);
+        const uint32_t dl = (uint32_t)__shfl((int)digit, lead, 64);
+        const uint64_t same = __ballot(match && digit == dl) & pending;
+        if (lane == lead) atomicAdd(&s_hist[dl], (uint32_t)__popcll(same));
+        pending &= ~same;
+      }
     }
   }
   __syncthreads();
