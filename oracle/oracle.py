@@ -281,3 +281,55 @@ def s2r_margin(x: np.ndarray, params):
     (code, stream mask), against the decoded array."""
     y = decode(encode(x, params))
     return s2r_margin_xy(x, y)
+
+
+# ---------------------------------------------------------------- Sec. 4, Windows 3-4 (spectra)
+# Spectral reading (the paper names the metrics but not the estimator): a
+# Welch power spectrum of the array in memory order -- segments of L = 1024
+# samples, hop L/2, periodic Hann window w_i = sin^2(pi i / L), one-sided
+# bins f = 1..L/2 (DC excluded), P[f] = mean over segments of |DFT(w s)[f]|^2.
+# Of x, y and d = x - y: peak = max P (dB), floor = the L/4-th smallest bin
+# (nearest-rank median of the L/2 bins, dB); residual mean = mean of P_d (dB);
+# DR = peak_x - floor_x, SRR = peak_x - residual mean, FFT S2R margin =
+# floor_x - residual mean.  Fewer than L samples: no segment (NaN).
+PSD_L = 1024
+
+
+def _db(p):
+    return 10.0 * math.log10(p) if p > 0 else float("-inf")
+
+
+def welch_psd(s: np.ndarray) -> np.ndarray:
+    """P[f], f = 1..L/2, of the binary64 sequence s (segments L, hop L/2)."""
+    s = np.ascontiguousarray(s, np.float64).ravel()
+    L = PSD_L
+    K = 1 + (s.size - L) // (L // 2)
+    w = np.sin(np.pi * np.arange(L) / L) ** 2
+    acc = np.zeros(L // 2 + 1)
+    for k in range(K):
+        seg = s[k * (L // 2): k * (L // 2) + L] * w
+        acc += np.abs(np.fft.rfft(seg)) ** 2
+    return acc[1:] / K
+
+
+def spectral_metrics(x: np.ndarray, y: np.ndarray) -> dict:
+    xd = np.ascontiguousarray(x, np.float64).ravel()
+    yd = np.ascontiguousarray(y, np.float64).ravel()
+    keys = ("peak_x", "floor_x", "peak_y", "floor_y", "peak_d", "floor_d", "resid_mean",
+            "dr", "srr", "fft_s2r_margin")
+    if xd.size < PSD_L:
+        out = {k: float("nan") for k in keys}
+        out["segments"] = 0
+        return out
+    out = {"segments": 1 + (xd.size - PSD_L) // (PSD_L // 2)}
+    rank = PSD_L // 4  # nearest-rank median of the L/2 bins
+    for name, s in (("x", xd), ("y", yd), ("d", xd - yd)):
+        P = welch_psd(s)
+        out[f"peak_{name}"] = _db(float(P.max()))
+        out[f"floor_{name}"] = _db(float(np.partition(P, rank - 1)[rank - 1]))
+        if name == "d":
+            out["resid_mean"] = _db(float(P.mean()))
+    out["dr"] = out["peak_x"] - out["floor_x"]
+    out["srr"] = out["peak_x"] - out["resid_mean"]
+    out["fft_s2r_margin"] = out["floor_x"] - out["resid_mean"]
+    return out

@@ -679,3 +679,43 @@ def test_s2r_margin_respects_the_attenuation_error_bound():
         ax = np.sort(np.abs(x))
         bound = 2 * O.gain(c) * ax[math.ceil(0.045 * x.size) - 1]
         assert ratio >= 0.99 * bound, (c, ratio, bound)
+
+
+# ------------------------------------------------ Sec. 4 Windows 3-4: Welch spectra
+def test_psd_tone_peak_closed_form():
+    # a cosine of amplitude A at bin f0 (integer cycles per segment): the
+    # Hann-windowed DFT has |X_f0| = A * sum(w) / 2 = A L / 4, at every segment
+    L = O.PSD_L
+    for f0, A in ((37, 3.0), (200, 0.5), (511, 10.0)):
+        i = np.arange(4 * L)
+        x = A * np.cos(2 * np.pi * f0 * i / L)
+        P = O.welch_psd(x)
+        assert int(np.argmax(P)) + 1 == f0
+        assert abs(P.max() / (A * L / 4) ** 2 - 1) < 1e-12
+        m = O.spectral_metrics(x, x)
+        assert abs(m["peak_x"] - 20 * math.log10(A * L / 4)) < 1e-9
+        assert m["resid_mean"] == float("-inf") and m["srr"] == float("inf")  # d = 0
+
+
+def test_psd_white_noise_level():
+    # white noise of variance s2: E P[f] = s2 * sum(w^2) = s2 * 3L/8 for the Hann window
+    L = O.PSD_L
+    rng = np.random.default_rng(11)
+    s = 2.0
+    x = rng.standard_normal(1 << 17) * s
+    P = O.welch_psd(x)
+    assert abs(P.mean() / (s * s * 3 * L / 8) - 1) < 0.03
+
+
+def test_psd_segments_and_scaling():
+    L = O.PSD_L
+    for n, K in ((L, 1), (L + L // 2 - 1, 1), (L + L // 2, 2), (3 * L, 5)):
+        assert O.spectral_metrics(np.ones(n), np.zeros(n))["segments"] == K
+    assert math.isnan(O.spectral_metrics(np.ones(L - 1), np.zeros(L - 1))["peak_x"])
+    rng = np.random.default_rng(3)
+    x = np.cumsum(rng.standard_normal(8 * L))
+    m = O.spectral_metrics(x, x / 2)            # d = x / 2: every P_d = P_x / 4
+    assert abs(m["peak_d"] - (m["peak_x"] - 20 * math.log10(2))) < 1e-9
+    assert abs(m["floor_d"] - (m["floor_x"] - 20 * math.log10(2))) < 1e-9
+    assert abs(m["srr"] - (m["peak_x"] - m["resid_mean"])) < 1e-12
+    assert abs(m["dr"] - (m["peak_x"] - m["floor_x"])) < 1e-12
