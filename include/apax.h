@@ -167,6 +167,25 @@ int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_resul
 int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,
                     uint64_t ws_bytes, hipStream_t stream);
 
+/* Sec. 4 Windows 3-4, spectral metrics of an array x and its decoded array y
+ * (same dtype and n; device).  The paper names them without an estimator;
+ * this library reads them as a Welch power spectrum of the samples in memory
+ * order: segments of 1024 samples, hop 512, periodic Hann window
+ * sin^2(pi i / 1024), one-sided bins 1..512 (no DC), P = mean over segments
+ * of |DFT|^2 (binary64).  For x, y and d = x - y: peak = max P, floor = the
+ * 256th smallest bin (nearest-rank median); resid_mean = mean of P_d; all in
+ * dB (10 log10 P; -inf for 0); dr = peak_x - floor_x, srr = peak_x -
+ * resid_mean, fft_s2r_margin = floor_x - resid_mean.  n < 1024: NaN fields,
+ * 0 segments.  d_ws: at least apax_spectral_workspace_bytes().  Synchronous. */
+typedef struct apax_spectral {
+  double peak_x, floor_x, peak_y, floor_y, peak_d, floor_d;
+  double resid_mean, dr, srr, fft_s2r_margin;
+  uint64_t segments;
+} apax_spectral;
+uint64_t apax_spectral_workspace_bytes(void);
+int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint64_t n, apax_spectral* h_out,
+                          void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* Waits for `stream`, then fills *h_out from the profile that d_ws holds
  * (p: the parameters that profile was called with).  Same errors as
  * apax_profile. */

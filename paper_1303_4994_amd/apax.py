@@ -91,6 +91,12 @@ class Tune(C.Structure):
 OP_ENCODE, OP_DECODE = 0, 1
 
 
+class Spectral(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("peak_x", "floor_x", "peak_y", "floor_y", "peak_d", "floor_d",
+                                           "resid_mean", "dr", "srr", "fft_s2r_margin")] + \
+               [("segments", C.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -101,6 +107,9 @@ def _load():
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
     L.apax_s2r_margin.argtypes = [vp, P(Params), P(C.c_double), P(C.c_double), vp, u64, vp]
+    L.apax_spectral_workspace_bytes.argtypes = []
+    L.apax_spectral_workspace_bytes.restype = u64
+    L.apax_spectral_metrics.argtypes = [vp, vp, C.c_uint32, u64, P(Spectral), vp, u64, vp]
     L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
@@ -263,6 +272,19 @@ def apax_s2r_margin(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None
     _check(lib.apax_s2r_margin(_dev_ptr(x), C.byref(p), C.byref(ratio), C.byref(db), _dev_ptr(ws),
                                ws.numel(), _stream_ptr(stream)), "apax_s2r_margin")
     return ratio.value, db.value
+
+
+def apax_spectral_metrics(x: torch.Tensor, y: torch.Tensor, ws: torch.Tensor | None = None,
+                          stream=None) -> dict:
+    """Welch-spectrum metrics of x and its decoded array y (Sec. 4 Windows 3-4)."""
+    assert x.is_cuda and y.is_cuda and x.dtype == y.dtype and x.numel() == y.numel()
+    assert x.is_contiguous() and y.is_contiguous()
+    if ws is None:
+        ws = torch.empty(int(lib.apax_spectral_workspace_bytes()), dtype=torch.uint8, device=x.device)
+    r = Spectral()
+    _check(lib.apax_spectral_metrics(_dev_ptr(x), _dev_ptr(y), _DT[x.dtype], x.numel(), C.byref(r),
+                                     _dev_ptr(ws), ws.numel(), _stream_ptr(stream)), "apax_spectral_metrics")
+    return {f: getattr(r, f) for f, _ in Spectral._fields_}
 
 
 def apax_profile_read(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None) -> dict:

@@ -700,6 +700,77 @@ int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, doub
   return APAX_OK;
 }
 
+uint64_t apax_spectral_workspace_bytes(void) {
+  return 8 * 1024 + 16 * 1024 + (uint64_t)PSD_MAX_WGS * 3 * 512 * 8 + 3 * 512 * 8;
+}
+
+int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint64_t n, apax_spectral* out,
+                          void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!out || dtype < APAX_I8 || dtype > APAX_F64) return APAX_E_INVALID;
+  memset(out, 0, sizeof(*out));
+  const double nan = NAN;
+  double* fields[10] = {&out->peak_x, &out->floor_x, &out->peak_y, &out->floor_y, &out->peak_d,
+                        &out->floor_d, &out->resid_mean, &out->dr, &out->srr, &out->fft_s2r_margin};
+  for (double* f : fields) *f = nan;
+  if (n < 1024) return APAX_OK;
+  if (!d_x || !d_y || !d_ws) return APAX_E_INVALID;
+  if (((uintptr_t)d_ws & 15) || ws_bytes < apax_spectral_workspace_bytes()) return APAX_E_CAPACITY;
+  const uint64_t K = 1 + (n - 1024) / 512;
+  // window and twiddles (host binary64 sin/cos), then the partial spectra
+  double table[1024 + 2 * 1024];
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < 1024; i++) {
+    const double sn = sin(pi * i / 1024.0);
+    table[i] = sn * sn;
+    table[1024 + 2 * i] = cos(2.0 * pi * i / 1024.0);
+    table[1024 + 2 * i + 1] = -sin(2.0 * pi * i / 1024.0);
+  }
+  uint8_t* w = (uint8_t*)d_ws;
+  if (hipMemcpyAsync(w, table, sizeof(table), hipMemcpyHostToDevice, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;  // the table is on this stack
+  PsdArgs A;
+  A.x = d_x;
+  A.y = d_y;
+  A.window = (const double*)w;
+  A.twiddle = w + 8 * 1024;
+  A.partial = (double*)(w + 24 * 1024);
+  A.out = (double*)(w + 24 * 1024 + (uint64_t)PSD_MAX_WGS * 3 * 512 * 8);
+  A.segments = (int64_t)K;
+  int e = hip_err(launch_psd((int)dtype, A, stream));
+  if (e) return e;
+  double P[3 * 512];
+  if (hipMemcpyAsync(P, A.out, sizeof(P), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  auto db = [](double v) { return v > 0.0 ? 10.0 * log10(v) : -INFINITY; };
+  double peak[3], floor_[3], mean_d = 0.0;
+  for (int s = 0; s < 3; s++) {
+    double v[512];
+    for (int f = 0; f < 512; f++) v[f] = P[s * 512 + f] / (double)K;
+    double mx = v[0];
+    for (int f = 1; f < 512; f++) mx = v[f] > mx ? v[f] : mx;
+    if (s == 2) {
+      double sum = 0.0;
+      for (int f = 0; f < 512; f++) sum += v[f];
+      mean_d = sum / 512.0;
+    }
+    std::nth_element(v, v + 255, v + 512);  // nearest-rank median: the 256th smallest
+    peak[s] = db(mx);
+    floor_[s] = db(v[255]);
+  }
+  out->segments = K;
+  out->peak_x = peak[0];
+  out->floor_x = floor_[0];
+  out->peak_y = peak[1];
+  out->floor_y = floor_[1];
+  out->peak_d = peak[2];
+  out->floor_d = floor_[2];
+  out->resid_mean = db(mean_d);
+  out->dr = out->peak_x - out->floor_x;
+  out->srr = out->peak_x - out->resid_mean;
+  out->fft_s2r_margin = out->floor_x - out->resid_mean;
+  return APAX_OK;
+}
+
 int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                        hipStream_t stream) {
   HG h;

@@ -444,3 +444,47 @@ def test_s2r_margin_empty_and_exact(A):
     wl = A.workspace(xi.dtype, (3000,), pl, DEV)
     A.apax_profile(xi, pl, ws=wl)
     assert A.apax_s2r_margin(xi, pl, wl) == (math.inf, math.inf)
+
+
+def _spectral_close(g, o):
+    assert g["segments"] == o["segments"]
+    for k, v in o.items():
+        if k == "segments":
+            continue
+        gv = g[k]
+        if math.isnan(v) or math.isinf(v):
+            assert (math.isnan(gv) and math.isnan(v)) or gv == v, (k, gv, v)
+        else:
+            assert abs(gv - v) < 1e-9, (k, gv, v)
+
+
+@pytest.mark.parametrize("dt,shape,params,kind", [
+    (np.float32, (256, 384), {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0, "code": 100}, "smooth"),
+    (np.float64, (6000,), {"mode": "fixed_quality", "brick": (128,), "code": 260}, "smooth"),
+    (np.float32, (5000,), {"mode": "fixed_rate", "brick": (64,), "rate": 6.0, "code": 150}, "noise"),
+    (np.int16, (4096 + 37,), {"mode": "fixed_rate", "brick": (256,), "rate": 3.0, "code": 0}, "smooth"),
+    (np.int32, (1024,), {"mode": "lossless", "brick": (64,)}, "smooth"),
+    (np.float32, (1535,), {"mode": "fixed_quality", "brick": (64,), "code": 40}, "smooth"),
+    (np.float32, (1000,), {"mode": "fixed_quality", "brick": (64,), "code": 40}, "smooth"),
+])
+def test_spectral_metrics(A, dt, shape, params, kind):
+    """Welch-spectrum metrics (Sec. 4 Windows 3-4 reading) of x and its decoded
+    array against the oracle (numpy FFT), to 1e-9 dB."""
+    x = tiny(dt, shape, 12, kind)
+    y = O.decode(O.encode(x, params))
+    g = A.apax_spectral_metrics(torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV))
+    _spectral_close(g, O.spectral_metrics(x, y))
+
+
+def test_spectral_metrics_c1(A):
+    """The C1 field at its profiled 4:1 point (16 MSamples, 32767 segments)."""
+    x = synth.grf2d(4096, 4096)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    xg = torch.from_numpy(x).to(DEV)
+    pg = A.apax_profile(xg, params)
+    p_at = dict(params, code=pg["code"], stream_mask=pg["stream_mask"] & 0x7F)
+    buf, nb = A.apax_encode(xg, p_at)
+    yg = A.apax_decode(buf, int(nb.item()))
+    g = A.apax_spectral_metrics(xg, yg)
+    _spectral_close(g, O.spectral_metrics(x, yg.cpu().numpy()))
+    assert g["srr"] > 0 and g["dr"] > 0
