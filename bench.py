@@ -280,6 +280,16 @@ def main():
     s2r_ratio, s2r_db = A.apax_s2r_margin(xl, params, ws)
     s2r_ms = (time.perf_counter() - ts0) * 1e3
 
+    # spectral metrics of the field and its decoded copy (Sec. 4 Windows 3-4;
+    # not part of the step), warm call timed
+    yl = ys[(reps - 1) % R]
+    sws = torch.empty(A.lib.apax_spectral_workspace_bytes(), dtype=torch.uint8, device=dev)
+    A.apax_spectral_metrics(xl, yl, ws=sws)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    spec = A.apax_spectral_metrics(xl, yl, ws=sws)
+    spec_ms = (time.perf_counter() - ts0) * 1e3
+
     # the decoded field reproduces the profiler's correlation (checked outside timing)
     yd = ys[(args.steps - 1) % R].double()
     xd = xs[(args.steps - 1) % R].double()
@@ -349,6 +359,11 @@ def main():
         "s2r_margin": {"db": round(s2r_db, 4), "ratio": s2r_ratio, "ms_per_call": round(s2r_ms, 3),
                        "note": "2-sigma S2R margin at the operating point, five selection passes; "
                                "outside the step"},
+        "spectral": {"dr_db": round(spec["dr"], 3), "srr_db": round(spec["srr"], 3),
+                     "fft_s2r_margin_db": round(spec["fft_s2r_margin"], 3),
+                     "segments": spec["segments"], "ms_per_call": round(spec_ms, 3),
+                     "note": "Welch spectra of x, y, x - y (1024-sample Hann segments, hop 512); "
+                             "outside the step"},
     }
     if args.copy_probe:
         # a plain copy of the field: reads and writes exactly input_bytes
