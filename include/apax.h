@@ -167,6 +167,22 @@ int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_resul
 int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,
                     uint64_t ws_bytes, hipStream_t stream);
 
+/* Decode-on-read consumer (the "time to results" use of Sec. 1, Fig. 1): the
+ * dot product sum_i y_i w_i of the array y a stream decodes with the array
+ * d_w (same dtype and shape), computed while decoding -- y is never written.
+ * Arguments as apax_decode; the result (binary64, deterministic order: per
+ * tile, then tiles in order) goes to the device double *d_out.  Enqueued on
+ * `stream`; corrupt streams are reported through apax_status. */
+int apax_decode_dot(const void* h_hdr, const void* d_stream, uint64_t nbytes, const void* d_w, double* d_out,
+                    void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* The same consumer on an uncompressed array (the baseline of the above):
+ * *d_out = sum_i x_i w_i over n samples of `dtype`, binary64.  d_ws: at
+ * least APAX_DOT_WGS * 8 bytes.  Enqueued on `stream`. */
+#define APAX_DOT_WGS 1024
+int apax_dot(const void* d_x, const void* d_w, uint32_t dtype, uint64_t n, double* d_out, void* d_ws,
+             uint64_t ws_bytes, hipStream_t stream);
+
 /* Sec. 4 Windows 3-4, spectral metrics of an array x and its decoded array y
  * (same dtype and n; device).  The paper names them without an estimator;
  * this library reads them as a Welch power spectrum of the samples in memory

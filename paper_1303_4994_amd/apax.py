@@ -107,6 +107,8 @@ def _load():
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
     L.apax_s2r_margin.argtypes = [vp, P(Params), P(C.c_double), P(C.c_double), vp, u64, vp]
+    L.apax_decode_dot.argtypes = [vp, vp, u64, vp, vp, vp, u64, vp]
+    L.apax_dot.argtypes = [vp, vp, C.c_uint32, u64, vp, vp, u64, vp]
     L.apax_spectral_workspace_bytes.argtypes = []
     L.apax_spectral_workspace_bytes.restype = u64
     L.apax_spectral_metrics.argtypes = [vp, vp, C.c_uint32, u64, P(Spectral), vp, u64, vp]
@@ -272,6 +274,39 @@ def apax_s2r_margin(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None
     _check(lib.apax_s2r_margin(_dev_ptr(x), C.byref(p), C.byref(ratio), C.byref(db), _dev_ptr(ws),
                                ws.numel(), _stream_ptr(stream)), "apax_s2r_margin")
     return ratio.value, db.value
+
+
+DOT_WGS = 1024
+
+
+def apax_decode_dot(stream_buf: torch.Tensor, nbytes: int, hdr: bytes, w: torch.Tensor,
+                    out: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Decode-on-read dot product with w; returns a device float64 tensor (1,)."""
+    assert stream_buf.is_cuda and w.is_cuda and w.is_contiguous()
+    info = apax_stream_info(hdr)
+    if ws is None:
+        params = {"mode": info["mode"], "brick": info["brick"], "rate": info["rate"],
+                  "code": info["code"], "target_corr": 0.5}
+        ws = workspace(info["dtype"], info["shape"], params, w.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=w.device)
+    h = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
+    _check(lib.apax_decode_dot(C.cast(h, C.c_void_p), _dev_ptr(stream_buf), int(nbytes), _dev_ptr(w),
+                               _dev_ptr(out), _dev_ptr(ws), ws.numel(), _stream_ptr(stream)), "apax_decode_dot")
+    return out
+
+
+def apax_dot(x: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None,
+             ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The same consumer on an uncompressed array: sum x * w in binary64."""
+    assert x.is_cuda and w.is_cuda and x.dtype == w.dtype and x.numel() == w.numel()
+    if ws is None:
+        ws = torch.empty(DOT_WGS * 8, dtype=torch.uint8, device=x.device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib.apax_dot(_dev_ptr(x), _dev_ptr(w), _DT[x.dtype], x.numel(), _dev_ptr(out), _dev_ptr(ws),
+                        ws.numel(), _stream_ptr(stream)), "apax_dot")
+    return out
 
 
 def apax_spectral_metrics(x: torch.Tensor, y: torch.Tensor, ws: torch.Tensor | None = None,

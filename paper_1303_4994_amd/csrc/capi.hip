@@ -177,9 +177,10 @@ uint64_t tiles_enc(const HG& h) { return (uint64_t)encode_tiles(h.g); }
 // partial records of one profile launch: at most about 2048 workgroups over
 // all codes (prof_wgs), or the max pass's PMAX_WGS
 uint64_t partial_bytes(const HG& h) {
-  (void)h;
   uint64_t recs = 2048 + 2 * (uint64_t)MAXCODES;
-  return std::max<uint64_t>(recs * PPART_BYTES, (uint64_t)PMAX_WGS * 16);
+  // also: one binary64 partial per tile of a decode-on-read consumer
+  return std::max<uint64_t>(std::max<uint64_t>(recs * PPART_BYTES, (uint64_t)PMAX_WGS * 16),
+                            8 * (uint64_t)encode_tiles(h.g));
 }
 
 uint64_t ws_tile_off() { return al256(sizeof(PState)); }
@@ -425,37 +426,71 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
   return hip_err(launch_encode(h.dtype, h.ndim, A, stream));
 }
 
-int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* d_y, uint64_t cap,
-                void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+// Header checks and kernel arguments of a decode (no output pointer yet).
+static int decode_setup(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* d_ws, uint64_t ws_bytes,
+                        HG& h, DecArgs& A) {
   apax_params p;
   int e = apax_stream_info(h_hdr, 64, &p);
   if (e) return e;
   uint16_t budget;
   memcpy(&budget, (const uint8_t*)h_hdr + 10, 2);
-  HG h;
   e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1);
   if (e) return e == APAX_E_UNSUPPORTED ? e : APAX_E_CORRUPT;
-  if (!d_stream || !d_ws || (!d_y && h.nsamples)) return APAX_E_INVALID;
+  if (!d_stream || !d_ws) return APAX_E_INVALID;
   if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
-  if (cap < h.nsamples * (uint64_t)h.esz) return APAX_E_CAPACITY;
   if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
   uint64_t pw;
   memcpy(&pw, (const uint8_t*)h_hdr + 56, 8);
   uint64_t area = area_offset(h);
   if (h.mode == APAX_FIXED_RATE && pw != (uint64_t)h.g.budget * (uint64_t)h.g.nblocks) return APAX_E_CORRUPT;
   if (nbytes < area || (nbytes - area) / 4 < pw) return APAX_E_CORRUPT;
-  DecArgs A;
   memset(&A, 0, sizeof(A));
   A.g = h.g;
   A.in = (const uint8_t*)d_stream;
   A.words = (const uint32_t*)((const uint8_t*)d_stream + area);
   A.lens = (const uint16_t*)((const uint8_t*)d_stream + 64);
   A.sbo = (const uint64_t*)((const uint8_t*)d_stream + 64 + lens_bytes(h));
-  A.y = d_y;
   A.status = &((PState*)d_ws)->status;
   A.payload_words = pw;
   memcpy(A.hdr, h_hdr, 64);
+  return APAX_OK;
+}
+
+int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* d_y, uint64_t cap,
+                void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  HG h;
+  DecArgs A;
+  int e = decode_setup(h_hdr, d_stream, nbytes, d_ws, ws_bytes, h, A);
+  if (e) return e;
+  if (!d_y && h.nsamples) return APAX_E_INVALID;
+  if (cap < h.nsamples * (uint64_t)h.esz) return APAX_E_CAPACITY;
+  A.y = d_y;
   return hip_err(launch_decode(h.dtype, h.ndim, A, stream));
+}
+
+int apax_decode_dot(const void* h_hdr, const void* d_stream, uint64_t nbytes, const void* d_w, double* d_out,
+                    void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  HG h;
+  DecArgs A;
+  int e = decode_setup(h_hdr, d_stream, nbytes, d_ws, ws_bytes, h, A);
+  if (e) return e;
+  if (!d_out || (!d_w && h.nsamples)) return APAX_E_INVALID;
+  if (h.g.nblocks == 0) {
+    hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_out, 2);
+    return hip_err(hipGetLastError());
+  }
+  return hip_err(launch_decode_dot(h.dtype, h.ndim, A, d_w, (double*)partials_ptr(d_ws, h), d_out, stream));
+}
+
+int apax_dot(const void* d_x, const void* d_w, uint32_t dtype, uint64_t n, double* d_out, void* d_ws,
+             uint64_t ws_bytes, hipStream_t stream) {
+  if (dtype < APAX_I8 || dtype > APAX_F64 || !d_out || !d_ws || (n && (!d_x || !d_w))) return APAX_E_INVALID;
+  if (ws_bytes < APAX_DOT_WGS * 8) return APAX_E_CAPACITY;
+  if (n == 0) {
+    hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_out, 2);
+    return hip_err(hipGetLastError());
+  }
+  return hip_err(launch_dot_plain((int)dtype, d_x, d_w, (int64_t)n, (double*)d_ws, APAX_DOT_WGS, d_out, stream));
 }
 
 // Subsample of the profiler's statistics passes: every 16th block once the

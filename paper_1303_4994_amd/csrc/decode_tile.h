@@ -120,10 +120,13 @@ struct DecShared {
   int32_t end[WP * 4];
 };
 
-// One tile (WP waves x 64/LPB blocks) of one stream.
-template <typename T, int LPB, int NDIM, int WP>
+// One tile (WP waves x 64/LPB blocks) of one stream.  DOT: instead of storing
+// the decoded samples, add their products with w (same layout) into *dot
+// (this lane's binary64 partial) -- decode-on-read for a consumer.
+template <typename T, int LPB, int NDIM, int WP, bool DOT = false>
 __device__ __forceinline__ void decode_tile(const DecArgs& A, const int64_t tile, DecShared<WP>& sm,
-                                            uint32_t* lds) {
+                                            uint32_t* lds, const T* __restrict__ w = nullptr,
+                                            double* dot = nullptr) {
   constexpr int BPW = 64 / LPB;
   constexpr int H = Traits<T>::H;
   constexpr int W = Traits<T>::W;
@@ -366,7 +369,15 @@ __device__ __forceinline__ void decode_tile(const DecArgs& A, const int64_t tile
       if (g.mode == M_LOSSLESS) out[k] = (T)av;
       else out[k] = to_out<T>(dequant_rk(av, R, e));
     }
-    store4<T>((T*)A.y, idx, nvalid, out);
+    if constexpr (DOT) {
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; k++)
+        if (k < nvalid) sum += (double)out[k] * (double)w[idx + k];
+      *dot += sum;
+    } else {
+      store4<T>((T*)A.y, idx, nvalid, out);
+    }
   }
 }
 

@@ -225,6 +225,11 @@ hipError_t launch_decode_batch(int lpb, int ndim, int wp, const BatchArgs& B, in
 hipError_t launch_batch_reset(uint32_t* ticket, uint64_t* tile_state, int64_t n, hipStream_t s);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
+// decode-on-read dot product (partial: one double per tile) and the plain one
+hipError_t launch_decode_dot(int dtype, int ndim, DecArgs& A, const void* w, double* partial, double* out,
+                             hipStream_t s);
+hipError_t launch_dot_plain(int dtype, const void* x, const void* w, int64_t n, double* partial, int nwg,
+                            double* out, hipStream_t s);
 int64_t prof_tiles(const Geo& g, int64_t nbe);
 int64_t prof_wgs(int64_t ntiles, int ncodes);
 // ev (optional): events recorded just before and just after the pass kernel

@@ -488,3 +488,45 @@ def test_spectral_metrics_c1(A):
     g = A.apax_spectral_metrics(xg, yg)
     _spectral_close(g, O.spectral_metrics(x, yg.cpu().numpy()))
     assert g["srr"] > 0 and g["dr"] > 0
+
+
+@pytest.mark.parametrize("name,dt,shape,params,kind", [c for c in CASES if c[0] in (
+    "i16-1d-B256-lossless", "i32-3d-2x4x8-lossless", "f32-2d-4x16-fq", "f64-3d-2x4x8-fq", "f32-1d-B128-fr",
+    "f64-2d-8x8-fr", "i8-1d-fr", "f32-2d-16x16-fr")], ids=lambda v: v if isinstance(v, str) else None)
+def test_decode_dot(A, name, dt, shape, params, kind):
+    """Decode-on-read consumer: sum(decode(stream) * w) equals the binary64 dot
+    of the oracle's decoded array with w (to 1e-12 of sum |y w|), and the
+    plain consumer on the uncompressed array agrees with numpy."""
+    print(f"case {name}", flush=True)
+    x = tiny(dt, shape, 9, kind)
+    w = tiny(dt, shape, 10, "noise")
+    xg, wg = torch.from_numpy(x).to(DEV), torch.from_numpy(w).to(DEV)
+    buf, nb = A.apax_encode(xg, params)
+    n = int(nb.item())
+    hdr = bytes(buf[:64].cpu().numpy().tobytes())
+    ws = A.workspace(xg.dtype, tuple(x.shape), params, DEV)
+    got = float(A.apax_decode_dot(buf, n, hdr, wg, ws=ws).item())
+    assert A.apax_status(ws) == 0
+    y = O.decode(O.encode(x, params)).astype(np.float64).ravel()
+    wd = w.astype(np.float64).ravel()
+    exp = float(np.dot(y, wd))
+    assert abs(got - exp) <= 1e-12 * float(np.abs(y * wd).sum()) + 1e-300, (got, exp)
+    plain = float(A.apax_dot(xg, wg).item())
+    xd = x.astype(np.float64).ravel()
+    assert abs(plain - float(np.dot(xd, wd))) <= 1e-12 * float(np.abs(xd * wd).sum()) + 1e-300
+
+
+def test_decode_dot_c1_and_empty(A):
+    x = synth.grf2d(4096, 4096)
+    w = np.random.default_rng(7).standard_normal(x.shape).astype(np.float32)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0, "code": 23}
+    xg, wg = torch.from_numpy(x).to(DEV), torch.from_numpy(w).to(DEV)
+    buf, nb = A.apax_encode(xg, params)
+    n = int(nb.item())
+    hdr = bytes(buf[:64].cpu().numpy().tobytes())
+    got = float(A.apax_decode_dot(buf, n, hdr, wg).item())
+    y = A.apax_decode(buf, n).double().cpu().numpy().ravel()
+    exp = float(np.dot(y, w.astype(np.float64).ravel()))
+    assert abs(got - exp) <= 1e-12 * float(np.abs(y * w.ravel()).sum())
+    e = torch.zeros(0, dtype=torch.float32, device=DEV)
+    assert float(A.apax_dot(e, e).item()) == 0.0
