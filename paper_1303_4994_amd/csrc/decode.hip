@@ -1,5 +1,6 @@
 // decode.hip -- single-array APAX decoder kernel for gfx950 (one workgroup
 // per tile; the tile body is in decode_tile.h).
+#include "block.h"
 #include "decode_tile.h"
 
 namespace apax {
@@ -40,10 +41,14 @@ __global__ __launch_bounds__(256) void k_dot_plain(const T* __restrict__ x, cons
   __shared__ double s_sum[4];
   double dot = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+#pragma unroll 4
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < n; i += stride) {
+    const int nv = n - i >= 4 ? 4 : (int)(n - i);
+    T xv[4], wv[4];
+    load4<T>(x, i, nv, xv);  // 4 * sizeof(T)-byte vector loads where aligned
+    load4<T>(w, i, nv, wv);
 #pragma unroll
-    for (int k = 0; k < 4; k++)
-      if (i + k < n) dot += (double)x[i + k] * (double)w[i + k];
+    for (int k = 0; k < 4; k++) dot += (double)xv[k] * (double)wv[k];
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) dot += __shfl_down(dot, o, 64);
