@@ -139,6 +139,19 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* h_o
 int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                        hipStream_t stream);
 
+/* apax_profile_async that also records point_ready on `stream` as soon as
+ * the operating point (code, stream mask) is final -- after the stream
+ * histogram, before the curve and metrics passes.  Work that needs only the
+ * operating point (an encode with APAX_CODE_PROFILED) can wait for that event
+ * on another stream and overlap the rest of the profile. */
+int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                             hipStream_t stream, hipEvent_t point_ready);
+
+/* Copies the operating point of the profile in d_ws_from into d_ws_to
+ * (enqueued on `stream`), so an encode with APAX_CODE_PROFILED can run on its
+ * own workspace while d_ws_from goes on with the profile. */
+int apax_adopt_point(const void* d_ws_from, void* d_ws_to, hipStream_t stream);
+
 /* Instrumentation for benchmarks: apax_profile with HIP events recorded on
  * `stream` just before and after the main kernel of each pass; pass_ms[i]
  * (APAX_NPASS entries) receives that kernel's duration for pass i, or -1 if

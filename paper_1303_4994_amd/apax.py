@@ -106,6 +106,8 @@ def _load():
     L.apax_workspace_size.argtypes = [P(Params), P(u64)]
     L.apax_profile.argtypes = [vp, P(Params), P(ProfileResult), vp, u64, vp]
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
+    L.apax_profile_async_point.argtypes = [vp, P(Params), vp, u64, vp, vp]
+    L.apax_adopt_point.argtypes = [vp, vp, vp]
     L.apax_s2r_margin.argtypes = [vp, P(Params), P(C.c_double), P(C.c_double), vp, u64, vp]
     L.apax_decode_dot.argtypes = [vp, vp, u64, vp, vp, vp, u64, vp]
     L.apax_dot.argtypes = [vp, vp, C.c_uint32, u64, vp, vp, u64, vp]
@@ -251,6 +253,27 @@ def apax_profile_async(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=N
 
 PASS_NAMES = ["max", "probe1", "probe2", "probe3", "probe4", "probe5", "probe6", "probe7", "probe8",
               "probe9", "hist", "curve", "metrics", "centred"]
+
+
+def _event_ptr(ev):
+    if ev.cuda_event == 0:  # torch creates the event at its first record
+        ev.record()
+    return C.c_void_p(ev.cuda_event)
+
+
+def apax_profile_async_point(x: torch.Tensor, params: dict, ws: torch.Tensor, point_ready, stream=None):
+    """apax_profile_async that records the torch.cuda.Event point_ready once
+    the operating point is final (after the stream histogram)."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    ev = _event_ptr(point_ready)
+    _check(lib.apax_profile_async_point(_dev_ptr(x), C.byref(p), _dev_ptr(ws), ws.numel(),
+                                        _stream_ptr(stream), ev), "apax_profile_async_point")
+
+
+def apax_adopt_point(ws_from: torch.Tensor, ws_to: torch.Tensor, stream=None):
+    """Copy the profiled operating point of ws_from into ws_to (enqueued)."""
+    _check(lib.apax_adopt_point(_dev_ptr(ws_from), _dev_ptr(ws_to), _stream_ptr(stream)), "apax_adopt_point")
 
 
 def apax_profile_timed(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None):

@@ -210,6 +210,11 @@ __global__ void k_fold_status(const uint32_t* item_status, uint32_t n, uint32_t*
   if (acc) atomicOr(status, acc);
 }
 
+// the operating point of one workspace's profile, into another workspace
+__global__ void k_adopt_point(const PState* from, PState* to) {
+  if (threadIdx.x < 2) to->sel[threadIdx.x] = from->sel[threadIdx.x];
+}
+
 __global__ void k_header_only(HdrArgs A) {
   if (threadIdx.x == 0) {
     uint32_t h[16];
@@ -518,7 +523,8 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
 // ev (optional): 2 * APAX_NPASS events, a pair around the kernel of each
 // pass that runs (bit of *ran set)
 static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
-                           hipEvent_t* ev = nullptr, uint32_t* ran = nullptr) {
+                           hipEvent_t* ev = nullptr, uint32_t* ran = nullptr,
+                           hipEvent_t point_ready = nullptr) {
   int e;
   if (ran) *ran = 0;
   auto pair = [&](int pass) -> hipEvent_t* {
@@ -597,6 +603,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       if (e) return e;
     }
     if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL, APAX_PASS_HIST))) return e;
+    if (point_ready && hipEventRecord(point_ready, stream) != hipSuccess) return APAX_E_HIP;
     if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_METRICS, F_CURVE, APAX_PASS_CURVE))) return e;
     if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE, APAX_PASS_METRICS))) return e;
     if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL, APAX_PASS_CENTRED))) return e;
@@ -604,6 +611,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     if ((e = ctl(C_INIT))) return e;
     if ((e = ctl(C_MASK))) return e;
     if ((e = ctl(C_CURVE))) return e;
+    if (point_ready && hipEventRecord(point_ready, stream) != hipSuccess) return APAX_E_HIP;
   }
   return APAX_OK;
 }
@@ -812,6 +820,21 @@ int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64
   int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
   if (e) return e;
   return profile_enqueue(d_x, p, h, d_ws, stream);
+}
+
+int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                             hipStream_t stream, hipEvent_t point_ready) {
+  if (!point_ready) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  return profile_enqueue(d_x, p, h, d_ws, stream, nullptr, nullptr, point_ready);
+}
+
+int apax_adopt_point(const void* d_ws_from, void* d_ws_to, hipStream_t stream) {
+  if (!d_ws_from || !d_ws_to) return APAX_E_INVALID;
+  hipLaunchKernelGGL(k_adopt_point, dim3(1), dim3(64), 0, stream, (const PState*)d_ws_from, (PState*)d_ws_to);
+  return hip_err(hipGetLastError());
 }
 
 int apax_profile_read(const apax_params* p, apax_profile_result* out, const void* d_ws,

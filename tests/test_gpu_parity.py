@@ -530,3 +530,26 @@ def test_decode_dot_c1_and_empty(A):
     assert abs(got - exp) <= 1e-12 * float(np.abs(y * w.ravel()).sum())
     e = torch.zeros(0, dtype=torch.float32, device=DEV)
     assert float(A.apax_dot(e, e).item()) == 0.0
+
+
+def test_overlapped_handoff(A):
+    """Profile on one stream, encode on another from the point-ready event on
+    with the operating point copied to its own workspace: the stream equals an
+    encode at the host-read operating point."""
+    x = tiny(np.float32, (320, 256), 31)
+    params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, x.shape, params, DEV)
+    ws2 = A.workspace(xg.dtype, x.shape, params, DEV)
+    codec = torch.cuda.Stream()
+    ev = torch.cuda.Event()
+    A.apax_profile_async_point(xg, params, ws, ev)
+    codec.wait_event(ev)
+    A.apax_adopt_point(ws, ws2, stream=codec)
+    buf, nb = A.apax_encode(xg, dict(params, code=A.CODE_PROFILED), ws=ws2, stream=codec, clear_status=False)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws2) == 0
+    pg = A.apax_profile_read(xg, params, ws)
+    ref, nref = A.apax_encode(xg, dict(params, code=pg["code"], stream_mask=pg["stream_mask"] & 0x7F))
+    n = int(nref.item())
+    assert int(nb.item()) == n and torch.equal(buf[:n], ref[:n])
