@@ -65,6 +65,8 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   if (p->dtype < ORC_I8 || p->dtype > ORC_F64) return ORC_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return ORC_E_INVALID;
   if (p->mode > ORC_FIXED_QUALITY) return ORC_E_INVALID;
+  if (p->flags & ~ORC_FLAG_LAGGED) return ORC_E_INVALID;
+  if ((p->flags & ORC_FLAG_LAGGED) && p->mode != ORC_LOSSLESS) return ORC_E_INVALID;
   g->dtype = (int)p->dtype;
   g->mode = (int)p->mode;
   g->ndim = (int)p->ndim;
@@ -537,7 +539,7 @@ static int max_block_words(const geom* g) { return (g->H + g->B * g->W + 31) / 3
 
 /* Operating-point rule for one block: 0 lossless, 1 fixed-rate search from
  * `code`, 2 fixed quality at clamp(code). */
-typedef struct { int rule; int code; uint32_t mask; } oprule;
+typedef struct { int rule; int code; uint32_t mask; int lag_st; } oprule;  /* lag_st: stream to use (lagged), or -1 */
 
 /* Analyse (and, if words != NULL, emit) block j.  Returns the number of
  * words; leaves the quantized block in s->a and its samples in s->x. */
@@ -551,7 +553,28 @@ static int do_block(const geom* g, const void* xin, int64_t j, const oprule* r, 
   bracket(g, M, &cf, &cc);
   int c, st, nn;
   int64_t bits;
-  if (r->rule == ORC_LOSSLESS) {
+  if (r->rule == ORC_LOSSLESS && r->lag_st >= 0) {
+    /* the block's own best stream is reported (for the next block); the
+     * block is coded with the previous block's */
+    c = 0;
+    quantize_block(g, s, c);
+    int own;
+    best_stream(g, s, r->mask, &own, &nn);
+    bits = cost_stream(g, s, r->lag_st, &nn);
+    memcpy(s->best, s->v, sizeof(int64_t) * g->B);
+    memcpy(s->beps, s->eps, sizeof(int) * g->G);
+    memcpy(s->bnib, s->nib, (size_t)nn);
+    int nw = (int)((bits + 31) / 32);
+    if (words) {
+      if (nw > cap_words) return -1;
+      int64_t pos = emit_block(g, s, r->lag_st, c, nn, words, nw);
+      if (pos != bits) return -2;
+    }
+    *st_out = own;
+    *cj_out = c;
+    *bits_out = bits;
+    return nw;
+  } else if (r->rule == ORC_LOSSLESS) {
     c = 0;
     quantize_block(g, s, c);
     bits = best_stream(g, s, r->mask, &st, &nn);
@@ -625,6 +648,7 @@ static oprule rule_of(const geom* g) {
   r.rule = g->mode;
   r.code = g->code;
   r.mask = g->mask;
+  r.lag_st = -1;
   return r;
 }
 
@@ -643,6 +667,8 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
   scratch s;
   if (scratch_alloc(&s, g.B)) { scratch_free(&s); return ORC_E_INVALID; }
   oprule r = rule_of(&g);
+  const int lagged = (p->flags & ORC_FLAG_LAGGED) != 0;
+  if (lagged) r.lag_st = 0;  /* block 0: stream 0 */
   uint64_t wpos = 0;
   int cap_words = g.budget ? g.budget : max_block_words(&g);
   uint8_t* lens = o + 64;
@@ -653,6 +679,7 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
     int64_t bits;
     int nw = do_block(&g, x, j, &r, &s, w, cap_words, &st, &cj, &bits, NULL);
     if (nw < 0) { scratch_free(&s); return ORC_E_INVALID; }
+    if (lagged) r.lag_st = st;
     if (g.mode != ORC_FIXED_RATE) {
       if (j % 64 == 0) put64(sbo + 8 * (j / 64), wpos);
       put16(lens + 2 * j, (uint16_t)nw);

@@ -50,8 +50,14 @@ typedef struct {
   double rate;          /* fixed-rate: input bits per encoded bit */
   double target_corr;   /* fixed-quality: correlation target */
   int32_t code;         /* gain code (fixed-rate start code / fixed-quality code) */
-  uint32_t reserved;
+  uint32_t flags;       /* ORC_FLAG_LAGGED: lossless only */
 } orc_params;
+
+/* Lagged stream choice (Sec. 6, the streaming hardware's form): block j is
+ * coded with the stream that was best for block j-1 (block 0: stream 0);
+ * each block's header still names the stream it uses, so decoding is
+ * unchanged. */
+#define ORC_FLAG_LAGGED 1u
 
 typedef struct {
   double r, one_minus_r, snr_db, rms_pct, rms_db;

@@ -36,7 +36,7 @@ class Params(C.Structure):
     _fields_ = [("size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32),
                 ("mode", C.c_uint32), ("dims", C.c_uint64 * 3), ("brick", C.c_uint32 * 3),
                 ("stream_mask", C.c_uint32), ("rate", C.c_double),
-                ("target_corr", C.c_double), ("code", C.c_int32), ("reserved", C.c_uint32)]
+                ("target_corr", C.c_double), ("code", C.c_int32), ("flags", C.c_uint32)]
 
 
 class Metrics(C.Structure):
@@ -110,6 +110,7 @@ def make_params(x_or_dtype, shape, params) -> Params:
     p.rate = float(params.get("rate", 0.0))
     p.target_corr = float(params.get("target_corr", 0.99999))
     p.code = int(params.get("code", 0))
+    p.flags = 1 if params.get("lagged", False) else 0  # ORC_FLAG_LAGGED
     return p
 
 

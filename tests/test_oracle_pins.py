@@ -719,3 +719,28 @@ def test_psd_segments_and_scaling():
     assert abs(m["floor_d"] - (m["floor_x"] - 20 * math.log10(2))) < 1e-9
     assert abs(m["srr"] - (m["peak_x"] - m["resid_mean"])) < 1e-12
     assert abs(m["dr"] - (m["peak_x"] - m["floor_x"])) < 1e-12
+
+
+# ------------------------------------------------ lagged stream choice (lossless)
+@pytest.mark.parametrize("dt,shape,brick", [(np.int16, (5000,), (64,)), (np.int32, (40, 48), (8, 8)),
+                                            (np.int8, (6, 10, 16), (2, 4, 8))])
+def test_lagged_stream_is_the_previous_blocks_best(dt, shape, brick):
+    rng = np.random.default_rng(4)
+    n = int(np.prod(shape))
+    base = np.cumsum(rng.standard_normal(n)) * (3 if dt == np.int8 else 25)
+    x = np.clip(base, np.iinfo(dt).min, np.iinfo(dt).max).astype(dt).reshape(shape)
+    p = {"mode": "lossless", "brick": brick}
+    std = brute.Stream(O.encode(x, p))
+    lag_buf = O.encode(x, dict(p, lagged=True))
+    lag = brute.Stream(lag_buf)
+    assert np.array_equal(O.decode(lag_buf), x)                     # still exact
+    for j in range(std.nblocks):
+        own_prev = int(std.block(j - 1)[0] & 7) if j > 0 else 0    # best stream of block j-1
+        assert int(lag.block(j)[0] & 7) == own_prev, j
+        assert lag.lens[j] >= std.lens[j]                          # never smaller than the best
+
+
+def test_lagged_needs_lossless():
+    x = np.linspace(0, 1, 1000).astype(np.float32)
+    with pytest.raises(O.OracleError):
+        O.encode(x, {"mode": "fixed_rate", "brick": (64,), "rate": 4.0, "code": 100, "lagged": True})
