@@ -87,8 +87,15 @@ typedef struct apax_params {
                            start code / fixed-quality code (from apax_profile);
                            ignored in lossless mode.  ints: [-512, 0];
                            floats: [-17120, 16383] */
-  uint32_t reserved;    /* 0 */
+  uint32_t flags;       /* 0, or APAX_FLAG_LAGGED (lossless only) */
 } apax_params;
+
+/* apax_params.flags: the streaming hardware's lagged stream choice (Sec. 6):
+ * block j is coded with the stream that was best for block j-1 (block 0:
+ * stream 0), as an encoder that decides after the block has streamed out.
+ * Lossless mode only; the stream format is unchanged (each block header
+ * names its stream).  Not accepted by batches. */
+#define APAX_FLAG_LAGGED 1u
 
 typedef struct apax_metrics {
   double r, one_minus_r;   /* Sec. 4 correlation (uncentered, as printed) */

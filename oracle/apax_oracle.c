@@ -560,14 +560,23 @@ static int do_block(const geom* g, const void* xin, int64_t j, const oprule* r, 
     quantize_block(g, s, c);
     int own;
     best_stream(g, s, r->mask, &own, &nn);
-    bits = cost_stream(g, s, r->lag_st, &nn);
+    /* a lagged stream that would code the block above its verbatim size
+     * gives way to verbatim (stream 7), so no block outgrows the bound */
+    int use = r->lag_st;
+    bits = cost_stream(g, s, use, &nn);
+    if (use != 7 && bits > cost_stream(g, s, 7, &nn)) {
+      use = 7;
+      bits = cost_stream(g, s, use, &nn);
+    } else {
+      bits = cost_stream(g, s, use, &nn);  /* s->v, eps, nib of the stream used */
+    }
     memcpy(s->best, s->v, sizeof(int64_t) * g->B);
     memcpy(s->beps, s->eps, sizeof(int) * g->G);
     memcpy(s->bnib, s->nib, (size_t)nn);
     int nw = (int)((bits + 31) / 32);
     if (words) {
       if (nw > cap_words) return -1;
-      int64_t pos = emit_block(g, s, r->lag_st, c, nn, words, nw);
+      int64_t pos = emit_block(g, s, use, c, nn, words, nw);
       if (pos != bits) return -2;
     }
     *st_out = own;

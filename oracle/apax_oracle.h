@@ -54,9 +54,9 @@ typedef struct {
 } orc_params;
 
 /* Lagged stream choice (Sec. 6, the streaming hardware's form): block j is
- * coded with the stream that was best for block j-1 (block 0: stream 0);
- * each block's header still names the stream it uses, so decoding is
- * unchanged. */
+ * coded with the stream that was best for block j-1 (block 0: stream 0), or
+ * verbatim where that stream would code it above the verbatim size; each
+ * block's header still names the stream it uses, so decoding is unchanged. */
 #define ORC_FLAG_LAGGED 1u
 
 typedef struct {

@@ -28,6 +28,7 @@ OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE, E_HIP, E_INTER
     0, -1, -2, -3, -4, -5, -6, -7
 NEAR_TIE = 1
 NCURVE = 17
+FLAG_LAGGED = 1  # apax_params.flags: lagged stream choice (lossless)
 CODE_PROFILED = -(1 << 31)  # apax_encode: adopt the code and mask of the profile in ws
 
 _DT = {torch.int8: I8, torch.int16: I16, torch.int32: I32, torch.float32: F32,
@@ -46,7 +47,7 @@ class Params(C.Structure):
     _fields_ = [("size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32),
                 ("mode", C.c_uint32), ("dims", C.c_uint64 * 3), ("brick", C.c_uint32 * 3),
                 ("stream_mask", C.c_uint32), ("rate", C.c_double),
-                ("target_corr", C.c_double), ("code", C.c_int32), ("reserved", C.c_uint32)]
+                ("target_corr", C.c_double), ("code", C.c_int32), ("flags", C.c_uint32)]
 
 
 class Metrics(C.Structure):
@@ -190,6 +191,7 @@ def _make_params(dtype: torch.dtype, shape, params: dict) -> Params:
     p.rate = float(params.get("rate", 0.0))
     p.target_corr = float(params.get("target_corr", 0.99999))
     p.code = int(params.get("code", 0))
+    p.flags = FLAG_LAGGED if params.get("lagged", False) else 0
     return p
 
 

@@ -22,6 +22,7 @@ struct HG {
   Geo g;
   int dtype, mode, ndim, esz, W, H;
   bool isint;
+  bool lagged;  // APAX_FLAG_LAGGED
   uint64_t nsamples;
 };
 
@@ -59,6 +60,9 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (p->dtype < APAX_I8 || p->dtype > APAX_F64) return APAX_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return APAX_E_INVALID;
   if (p->mode > APAX_FIXED_QUALITY) return APAX_E_INVALID;
+  if (p->flags & ~APAX_FLAG_LAGGED) return APAX_E_INVALID;
+  if ((p->flags & APAX_FLAG_LAGGED) && p->mode != APAX_LOSSLESS) return APAX_E_INVALID;
+  h.lagged = (p->flags & APAX_FLAG_LAGGED) != 0;
   static const int ESZ[6] = {0, 1, 2, 4, 4, 8};
   static const int WQ[6] = {0, 8, 16, 32, 32, 32};
   h.dtype = (int)p->dtype;
@@ -412,6 +416,11 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
     A.zpad[3] = A.area;
   }
   if (profiled) A.sel = ((PState*)d_ws)->sel;
+  if (h.lagged && h.g.nblocks) {
+    int32_t* best = cj_ptr(d_ws, h);  // each block's own best stream
+    if ((e = hip_err(launch_stream_choice(h.dtype, h.ndim, A, best, stream)))) return e;
+    A.lag = best;
+  }
   if (h.g.nblocks == 0) {
     HdrArgs Hd;
     memset(&Hd, 0, sizeof(Hd));
@@ -876,6 +885,7 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
     int e;
     if (op == APAX_OP_ENCODE) {
       if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
+      if (h.lagged) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
       if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
         delete b;
         return batch_error(APAX_E_INVALID, i);
@@ -1326,6 +1336,7 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   int e;
   if (q->op == APAX_OP_ENCODE) {
     if ((e = setup(&q->item.p, h))) return e;
+    if (h.lagged) return APAX_E_UNSUPPORTED;  // served encodes may share a batch launch
     if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
     memset(r.hdr, 0, 64);
   } else {

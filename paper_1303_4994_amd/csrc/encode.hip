@@ -42,6 +42,56 @@ __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
   }
 }
 
+// Lagged choice, first pass: every block's own best stream (lossless).
+template <typename T, int LPB, int NDIM>
+__global__ __launch_bounds__(WPG * 64) void k_stream_choice(EncArgs A, int32_t* best_st) {
+  constexpr int BPW = 64 / LPB;
+  using B_ = Blk<T, LPB, NDIM>;
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
+  const Geo& g = A.g;
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  B_ b;
+  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
+  b.template load<false>((const T*)A.x, g);
+  int32_t a[4], v[7][4];
+  int eps[7], pw[7];
+  Costs C;
+  int32_t best;
+  b.quantize(0, true, a);
+  b.sizes(g, g.mask, a, v, eps, pw, C);
+  const int st = B_::argmin(C, g.mask, best);
+  if (b.blk_ok && b.L.gi == 0) best_st[b.j] = st;
+}
+
+template <typename T, int LPB, int NDIM>
+static hipError_t launch_choice_t(const EncArgs& A, int32_t* best, hipStream_t s) {
+  hipLaunchKernelGGL((k_stream_choice<T, LPB, NDIM>), dim3((unsigned)encode_tiles(A.g)), dim3(WPG * 64), 0, s,
+                     A, best);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_choice_nd(const EncArgs& A, int ndim, int32_t* best, hipStream_t s) {
+  const int G = A.g.G;
+#define APAX_CHOICE_LPB(ND)                                            \
+  if (G <= 16) return launch_choice_t<T, 16, ND>(A, best, s);         \
+  if (G <= 32) return launch_choice_t<T, 32, ND>(A, best, s);         \
+  return launch_choice_t<T, 64, ND>(A, best, s);
+  if (ndim == 1) { APAX_CHOICE_LPB(1) }
+  if (ndim == 2) { APAX_CHOICE_LPB(2) }
+  APAX_CHOICE_LPB(3)
+#undef APAX_CHOICE_LPB
+}
+
+hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s) {
+  switch (dtype) {  // lossless: integer dtypes only
+    case DT_I8: return launch_choice_nd<int8_t>(A, ndim, best, s);
+    case DT_I16: return launch_choice_nd<int16_t>(A, ndim, best, s);
+    default: return launch_choice_nd<int32_t>(A, ndim, best, s);
+  }
+}
+
 // ------------------------------------------------------------ launcher
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const EncArgs& A, hipStream_t s) {

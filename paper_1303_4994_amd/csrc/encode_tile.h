@@ -142,6 +142,15 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   b.quantize(c, g.mode == M_LOSSLESS, a);
   b.sizes(g, emask, a, v, eps, pw, C);
   st = B_::argmin(C, emask, best);
+  if (A.lag) {  // lagged choice (lossless): the previous block's best stream,
+                // or verbatim where that would code the block above verbatim size
+    st = b.j == 0 ? 0 : (b.blk_ok ? A.lag[b.j - 1] : 0);
+    best = B_::size_sel(C, st);
+    if (best > C.sz[7]) {
+      st = 7;
+      best = C.sz[7];
+    }
+  }
   if (g.mode == M_RATE) {
     const bool need = b.act && best > 32 * g.budget;
     if (__ballot(need)) {

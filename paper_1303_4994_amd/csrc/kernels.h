@@ -25,6 +25,7 @@ struct EncArgs {
   uint32_t hdr[16];      // stream header (payload words written on device)
   uint64_t zpad[4];      // byte ranges [0,1) and [2,3) of index padding to zero
   const int32_t* sel;    // {code, stream mask} a profile left in the workspace, or null
+  const int32_t* lag;    // lagged stream choice: each block's own best stream, or null
   Geo g;
 };
 
@@ -224,6 +225,8 @@ hipError_t launch_decode_batch(int lpb, int ndim, int wp, const BatchArgs& B, in
                                size_t lds, hipStream_t s);
 hipError_t launch_batch_reset(uint32_t* ticket, uint64_t* tile_state, int64_t n, hipStream_t s);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
+// each block's own best stream into best[nblocks] (lossless; the lagged choice)
+hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
 // decode-on-read dot product (partial: one double per tile) and the plain one
 hipError_t launch_decode_dot(int dtype, int ndim, DecArgs& A, const void* w, double* partial, double* out,

@@ -553,3 +553,29 @@ def test_overlapped_handoff(A):
     ref, nref = A.apax_encode(xg, dict(params, code=pg["code"], stream_mask=pg["stream_mask"] & 0x7F))
     n = int(nref.item())
     assert int(nb.item()) == n and torch.equal(buf[:n], ref[:n])
+
+
+LAG_CASES = [c for c in CASES if c[3]["mode"] == "lossless"]
+
+
+@pytest.mark.parametrize("name,dt,shape,params,kind", LAG_CASES, ids=[c[0] for c in LAG_CASES])
+def test_lagged_stream_choice(A, name, dt, shape, params, kind):
+    """Lagged stream choice (lossless flag): the GPU stream equals the
+    oracle's byte for byte and decodes exactly."""
+    print(f"case {name}", flush=True)
+    x = tiny(dt, shape, 8, kind)
+    p = dict(params, lagged=True)
+    exp = O.encode(x, p)
+    got, y = gpu_roundtrip(A, x, p)
+    assert np.array_equal(got, exp)
+    assert np.array_equal(y, x)
+
+
+def test_lagged_rejected_where_unsupported(A):
+    xi = torch.from_numpy(tiny(np.int16, (3000,), 2)).to(DEV)
+    with pytest.raises(A.ApaxError) as e:
+        A.apax_encode(xi, {"mode": "fixed_rate", "brick": (64,), "rate": 3.0, "code": 0, "lagged": True})
+    assert e.value.code == A.E_INVALID
+    with pytest.raises(A.ApaxError) as e:
+        A.Batch.encode([(xi, {"mode": "lossless", "brick": (64,), "lagged": True})])
+    assert e.value.code == A.E_UNSUPPORTED

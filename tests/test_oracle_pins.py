@@ -734,10 +734,29 @@ def test_lagged_stream_is_the_previous_blocks_best(dt, shape, brick):
     lag_buf = O.encode(x, dict(p, lagged=True))
     lag = brute.Stream(lag_buf)
     assert np.array_equal(O.decode(lag_buf), x)                     # still exact
+    verbatim_words = (32 + int(np.prod(brick)) * np.dtype(dt).itemsize * 8 + 31) // 32
+    if dt == np.int32:
+        verbatim_words = (32 + int(np.prod(brick)) * 32 + 31) // 32
     for j in range(std.nblocks):
         own_prev = int(std.block(j - 1)[0] & 7) if j > 0 else 0    # best stream of block j-1
-        assert int(lag.block(j)[0] & 7) == own_prev, j
-        assert lag.lens[j] >= std.lens[j]                          # never smaller than the best
+        st = int(lag.block(j)[0] & 7)
+        # the previous block's best, or verbatim where that would be larger
+        assert st == own_prev or (st == 7 and lag.lens[j] == verbatim_words), j
+        assert std.lens[j] <= lag.lens[j] <= verbatim_words        # never below the best, never above verbatim
+
+
+def test_lagged_noise_falls_back_to_verbatim():
+    # white noise: derivative streams are larger than verbatim, so a lagged
+    # derivative choice must give way to verbatim
+    rng = np.random.default_rng(9)
+    x = rng.integers(-32768, 32767, 4096, endpoint=True).astype(np.int16)
+    x[:512] = np.arange(512, dtype=np.int16)          # smooth start: derivative is best there
+    p = {"mode": "lossless", "brick": (64,)}
+    buf = O.encode(x, dict(p, lagged=True))
+    s = brute.Stream(buf)
+    assert np.array_equal(O.decode(buf), x)
+    assert max(s.lens) <= (32 + 64 * 16 + 31) // 32
+    assert int(s.block(8)[0] & 7) == 7                 # first noise block: lagged choice was a derivative
 
 
 def test_lagged_needs_lossless():
