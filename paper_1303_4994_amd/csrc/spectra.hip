@@ -149,7 +149,15 @@ __global__ __launch_bounds__(256) void k_psd_reduce(const double* partial, int n
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 3 * 512) return;
   double sum = 0.0;
-  for (int w = 0; w < nwg; w++) sum += partial[(int64_t)w * 3 * 512 + t];
+  int w = 0;
+  for (; w + 8 <= nwg; w += 8) {  // eight loads in flight, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = partial[(int64_t)(w + u) * 3 * 512 + t];
+#pragma unroll
+    for (int u = 0; u < 8; u++) sum += v[u];
+  }
+  for (; w < nwg; w++) sum += partial[(int64_t)w * 3 * 512 + t];
   out[t] = sum;
 }
 
