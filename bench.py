@@ -179,7 +179,7 @@ def main():
                         os.path.join(ROOT, "profiles", "traffic_c1.txt"), cmd)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for {args.gpus}); "
               "the multi-GPU design is described, not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":

@@ -52,7 +52,7 @@ enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2 };
 enum {
   APAX_OK = 0,
   APAX_E_INVALID = -1,     /* bad parameters */
-  APAX_E_UNSUPPORTED = -2, /* valid request this build does not implement (lossless floats) */
+  APAX_E_UNSUPPORTED = -2, /* valid request the library does not implement (lossless floats, blocks above 256 samples) */
   APAX_E_CAPACITY = -3,    /* output or workspace buffer too small */
   APAX_E_CORRUPT = -4,     /* stream fails validation */
   APAX_E_NONFINITE = -5,   /* NaN or Inf in the input */

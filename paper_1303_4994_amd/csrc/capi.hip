@@ -131,7 +131,7 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (h.mode == APAX_FIXED_QUALITY && forced_budget < 0) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
   }
-  if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not in this build
+  if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not implemented on the GPU
   magic(g.nbx, g.nbx_m, g.nbx_s);
   magic(g.nby, g.nby_m, g.nby_s);
   magic(g.rowq, g.rowq_m, g.rowq_s);
