@@ -334,3 +334,77 @@ def spectral_metrics(x: np.ndarray, y: np.ndarray) -> dict:
     out["srr"] = out["peak_x"] - out["resid_mean"]
     out["fft_s2r_margin"] = out["floor_x"] - out["resid_mean"]
     return out
+
+
+# ---------------------------------------------------------------- Sec. 6, signal monitor
+# Reading (the paper names the monitor's outputs, center frequency and SNR,
+# and says the center frequency tells which nearby elements are correlated,
+# without formulas): of the array x in memory order, binary64,
+#   R[k] = sum_{n >= k} x[n] x[n - k], k = 0..16, and the normalised
+#   acf[k] = (R[k] / (N - k)) / (R[0] / N), each lag's mean product over that
+#   of lag 0 (all zero when R[0] = 0; lags >= N zero);
+#   peak_bin b = the first largest bin of the Welch spectrum above (1..512),
+#   center_freq = b / 1024 cycles per sample, peak / floor in dB as above,
+#   snr = 10 log10(mean P / floor);
+#   correlated neighbour: the lag phase of bin b at lag k is m = b k mod 1024
+#   (units of 1/1024 turn); a tone there is cancelled by x[n] - x[n - k] when m
+#   is a multiple of 1024 and by x[n] + x[n - k] when m is 512 off one.  The
+#   stride is the smallest k in 1..16 whose m is nearest a multiple of 512;
+#   sign = +1 (difference) when m is nearer 0 mod 1024 (ties at a quarter turn
+#   go to +1), else -1 (sum);
+#   gain = 10 log10(sum_{n >= k} x[n]^2 / sum_{n >= k} (x[n] - sign x[n - k])^2)
+#   at k = stride: what the filter takes out of the samples it applies to
+#   (+inf for a zero residual, NaN when both sums are zero).
+# Fewer than 1024 samples: no spectrum (NaN fields, peak_bin = stride = sign = 0).
+MON_LAGS = 16
+
+
+def autocorr(x: np.ndarray, lags: int = MON_LAGS) -> np.ndarray:
+    """R[k] = sum_{n >= k} x[n] x[n - k], k = 0..lags, binary64."""
+    s = np.ascontiguousarray(x, np.float64).ravel()
+    R = np.zeros(lags + 1)
+    for k in range(min(lags, s.size - 1) + 1):
+        R[k] = float(np.dot(s[k:], s[:s.size - k]))
+    return R
+
+
+def monitor_stride(b: int):
+    """(stride, sign) that the center bin b selects (0, 0 for no bin)."""
+    if b <= 0:
+        return 0, 0
+    best_k, best_dist = 0, PSD_L
+    for k in range(1, MON_LAGS + 1):
+        r = (b * k) % (PSD_L // 2)
+        dist = min(r, PSD_L // 2 - r)
+        if dist < best_dist:
+            best_k, best_dist = k, dist
+    m = (b * best_k) % PSD_L
+    sign = 1 if (m <= PSD_L // 4 or m >= 3 * PSD_L // 4) else -1
+    return best_k, sign
+
+
+def signal_monitor(x: np.ndarray) -> dict:
+    s = np.ascontiguousarray(x, np.float64).ravel()
+    R = autocorr(s)
+    N = s.size
+    acf = np.zeros_like(R)
+    if R[0] > 0:
+        for k in range(min(MON_LAGS, N - 1) + 1):
+            acf[k] = (R[k] / (N - k)) / (R[0] / N)
+    out = {"acf": acf, "segments": 0, "peak_bin": 0, "center_freq": float("nan"),
+           "peak_db": float("nan"), "floor_db": float("nan"), "snr_db": float("nan"),
+           "stride": 0, "sign": 0, "gain_db": float("nan")}
+    if s.size < PSD_L:
+        return out
+    P = welch_psd(s)
+    b = 1 + int(np.argmax(P))                 # first largest bin
+    rank = PSD_L // 4
+    fl = float(np.partition(P, rank - 1)[rank - 1])
+    k, sg = monitor_stride(b)
+    e_in = float(np.dot(s[k:], s[k:]))
+    e_out = float(np.sum((s[k:] - sg * s[:N - k]) ** 2))
+    out.update(segments=1 + (s.size - PSD_L) // (PSD_L // 2), peak_bin=b, center_freq=b / PSD_L,
+               peak_db=_db(float(P[b - 1])), floor_db=_db(fl),
+               snr_db=_db(float(P.mean())) - _db(fl), stride=k, sign=sg,
+               gain_db=_db(e_in) - _db(e_out))
+    return out

@@ -763,3 +763,75 @@ def test_lagged_needs_lossless():
     x = np.linspace(0, 1, 1000).astype(np.float32)
     with pytest.raises(O.OracleError):
         O.encode(x, {"mode": "fixed_rate", "brick": (64,), "rate": 4.0, "code": 100, "lagged": True})
+
+
+# ------------------------------------------------ Sec. 6 signal monitor
+def test_autocorr_brute_force_and_wiener_khinchin():
+    rng = np.random.default_rng(21)
+    x = rng.integers(-50, 50, 40).astype(np.int32)
+    R = O.autocorr(x)
+    for k in range(O.MON_LAGS + 1):              # the definition, term by term
+        want = 0
+        for n in range(k, x.size):
+            want += int(x[n]) * int(x[n - k])
+        assert R[k] == want, k
+    # the inverse transform of the zero-padded power spectrum is the same sum
+    y = rng.standard_normal(3001)
+    F = np.fft.fft(y, 2 * y.size)
+    r = np.fft.ifft(np.abs(F) ** 2).real
+    assert np.allclose(O.autocorr(y), r[:O.MON_LAGS + 1], rtol=0, atol=1e-9 * r[0])
+    short = O.autocorr(np.array([2.0, 3.0, 5.0]))  # lags beyond the array sum nothing
+    assert list(short[:3]) == [38.0, 21.0, 10.0] and not short[3:].any()
+
+
+def test_monitor_stride_matches_tone_cancellation():
+    # for a tone at bin b, x[n] - s x[n - k] keeps 2 (1 - s cos(2 pi b k / L)) of
+    # its power: the chosen (k, s) reaches the least of it over k = 1..16 (s
+    # of the same sign as the cosine), and no smaller lag does as well
+    L = O.PSD_L
+    assert O.monitor_stride(0) == (0, 0)
+    for b in range(1, L // 2 + 1):
+        k, s = O.monitor_stride(b)
+        res = [1 - abs(math.cos(2 * math.pi * b * j / L)) for j in range(1, 17)]
+        assert res[k - 1] <= min(res) + 1e-12, (b, k)
+        assert all(res[j - 1] > res[k - 1] + 1e-12 for j in range(1, k)), (b, k)
+        c = math.cos(2 * math.pi * b * k / L)
+        assert s * c >= -1e-12, (b, k, s)
+    assert O.monitor_stride(1) == (1, 1)         # oversampled low-pass: first difference
+    assert O.monitor_stride(512) == (1, -1)      # Nyquist tone: x[n] + x[n - 1]
+    assert O.monitor_stride(256) == (2, -1)      # quarter rate: x[n] + x[n - 2]
+
+
+def test_monitor_tone_center_and_gain():
+    L = O.PSD_L
+    rng = np.random.default_rng(22)
+    n = 1 << 16
+    i = np.arange(n)
+    for b, A in ((3, 5.0), (102, 1.0), (341, 2.0), (500, 0.25)):
+        x = A * np.cos(2 * np.pi * b * i / L + 0.3) + 0.001 * rng.standard_normal(n)
+        m = O.signal_monitor(x)
+        assert m["peak_bin"] == b and m["center_freq"] == b / L
+        assert abs(m["peak_db"] - 20 * math.log10(A * L / 4)) < 0.01
+        k, s = O.monitor_stride(b)
+        assert (m["stride"], m["sign"]) == (k, s)
+        # tone A plus white noise sg: the filter keeps 2 (1 - s cos) of the
+        # tone's power A^2 / 2 and doubles the noise power sg^2
+        th = 2 * math.pi * b * k / L
+        want = (A * A / 2 + 1e-6) / (A * A * (1 - s * math.cos(th)) + 2e-6)
+        assert abs(m["gain_db"] - 10 * math.log10(want)) < 0.1, (b, m["gain_db"], 10 * math.log10(want))
+        # the autocorrelation of a tone is the cosine of its lag phase
+        for j in range(1, 17):
+            assert abs(m["acf"][j] - math.cos(2 * math.pi * b * j / L)) < 2e-3
+
+
+def test_monitor_white_noise_and_edges():
+    rng = np.random.default_rng(23)
+    m = O.signal_monitor(rng.standard_normal(1 << 17))
+    assert abs(m["snr_db"]) < 0.3              # flat spectrum: mean over median about 1
+    assert np.all(np.abs(m["acf"][1:]) < 0.02) and m["acf"][0] == 1.0
+    assert abs(m["gain_db"] + 10 * math.log10(2)) < 0.05  # a filter of white noise doubles it
+    short = O.signal_monitor(np.arange(1023, dtype=np.float64))
+    assert short["peak_bin"] == 0 and short["stride"] == 0 and math.isnan(short["snr_db"])
+    assert short["segments"] == 0 and short["acf"][0] == 1.0
+    zero = O.signal_monitor(np.zeros(4096))
+    assert not zero["acf"].any() and zero["peak_bin"] == 1 and math.isnan(zero["snr_db"])
