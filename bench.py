@@ -95,7 +95,9 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
         return copy_bytes / (sum(big) / len(big) * 1024) if big else None
     ff, fw = copy_factor(f), copy_factor(w)
     lines = ["# HBM traffic of the codec kernels, C1 workload (4096x4096 fp32, 16x16 bricks, 4:1)",
-             f"# command (fetch): {command} FETCH_SIZE", f"# command (write): {command} WRITE_SIZE",
+             f"# command (fetch): {command.format(c='FETCH_SIZE', d='fetch')}",
+             f"# command (write): {command.format(c='WRITE_SIZE', d='write')}",
+             f"# summary: python3 bench.py --traffic-from {fetch_csv} {write_csv}",
              "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
              "# the counter's reading for a plain 64 MiB device copy onto 64 MiB",
              f"source_sha256: {source_digest()}",
@@ -173,8 +175,9 @@ def main():
                     help="write profiles/traffic_c1.txt from two rocprofv3 --pmc counter CSVs")
     args = ap.parse_args()
     if args.traffic_from:
-        cmd = ("rocprofv3 --pmc <counter> --output-format csv -- python3 bench.py --steps 2 "
-               "--warmup 1 --no-cpu-baseline --copy-probe")
+        cmd = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && timeout -s KILL 150 rocprofv3 --pmc {c} "
+               "--output-format csv -d gpurun_out/pmc_{d} -o p -- python3 bench.py --steps 2 --warmup 1 "
+               "--no-cpu-baseline --copy-probe")
         traffic_summary(args.traffic_from[0], args.traffic_from[1],
                         os.path.join(ROOT, "profiles", "traffic_c1.txt"), cmd)
         return
@@ -320,6 +323,13 @@ def main():
     spec = A.apax_spectral_metrics(xl, yl, ws=sws)
     spec_ms = (time.perf_counter() - ts0) * 1e3
 
+    # signal monitor of the field (Sec. 6; not part of the step), warm call timed
+    A.apax_signal_monitor(xl, ws=sws)
+    torch.cuda.synchronize()
+    ts0 = time.perf_counter()
+    mon = A.apax_signal_monitor(xl, ws=sws)
+    mon_ms = (time.perf_counter() - ts0) * 1e3
+
     # decode-on-read (the "time to results" use, Sec. 1): a dot product with a
     # second field read from the 4:1 stream while decoding, against the same
     # consumer reading the uncompressed field; HIP events, back-to-back calls
@@ -423,6 +433,10 @@ def main():
                      "segments": spec["segments"], "ms_per_call": round(spec_ms, 3),
                      "note": "Welch spectra of x, y, x - y (1024-sample Hann segments, hop 512); "
                              "outside the step"},
+        "signal_monitor": {"peak_bin": mon["peak_bin"], "snr_db": round(mon["snr_db"], 3),
+                           "stride": mon["stride"], "sign": mon["sign"], "gain_db": round(mon["gain_db"], 3),
+                           "acf1": round(mon["acf"][1], 6), "ms_per_call": round(mon_ms, 3),
+                           "note": "Welch spectrum of x and its lags 0..16 autocorrelation; outside the step"},
     }
     if args.copy_probe:
         # a plain copy of the field: reads and writes exactly input_bytes

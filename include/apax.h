@@ -222,6 +222,33 @@ uint64_t apax_spectral_workspace_bytes(void);
 int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint64_t n, apax_spectral* h_out,
                           void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* Sec. 6 signal monitor of an array x (device, n samples of `dtype`, in
+ * memory order, binary64 arithmetic).  The paper names its outputs (center
+ * frequency, SNR) and says the center frequency tells which nearby samples
+ * are correlated; this library reads them as:
+ *   acf[k] = (R[k] / (n - k)) / (R[0] / n), R[k] = sum_{i >= k} x_i x_(i-k),
+ *            k = 0..16 (zero for lags >= n, all zero when R[0] = 0);
+ *   peak_bin = the first largest bin b of the Welch spectrum above (1..512),
+ *   center_freq = b / 1024 cycles per sample, peak_db and floor_db as above,
+ *   snr_db = 10 log10(mean bin / floor bin);
+ *   stride = the smallest k in 1..16 whose phase m = b k mod 1024 (in
+ *   1/1024 turns) lies nearest a multiple of 512; sign = +1 when m is nearer
+ *   0 mod 1024 (a quarter turn counts as +1), else -1: x_i - sign x_(i-k)
+ *   cancels a tone at bin b;
+ *   gain_db = 10 log10(sum_{i >= k} x_i^2 / sum_{i >= k} (x_i - sign
+ *   x_(i-k))^2) at k = stride (+inf for a zero residual, NaN for zero x).
+ * n < 1024: only acf (NaN fields, peak_bin = stride = sign = segments = 0).
+ * d_ws: at least apax_spectral_workspace_bytes(), 16-byte aligned
+ * (APAX_E_CAPACITY otherwise).  Synchronous. */
+typedef struct apax_monitor {
+  double acf[17];
+  double center_freq, peak_db, floor_db, snr_db, gain_db;
+  int32_t peak_bin, stride, sign, pad;
+  uint64_t segments;
+} apax_monitor;
+int apax_signal_monitor(const void* d_x, uint32_t dtype, uint64_t n, apax_monitor* h_out, void* d_ws,
+                        uint64_t ws_bytes, hipStream_t stream);
+
 /* Waits for `stream`, then fills *h_out from the profile that d_ws holds
  * (p: the parameters that profile was called with).  Same errors as
  * apax_profile. */

@@ -98,6 +98,12 @@ class Spectral(C.Structure):
                [("segments", C.c_uint64)]
 
 
+class Monitor(C.Structure):
+    _fields_ = [("acf", C.c_double * 17)] + \
+               [(f, C.c_double) for f in ("center_freq", "peak_db", "floor_db", "snr_db", "gain_db")] + \
+               [(f, C.c_int32) for f in ("peak_bin", "stride", "sign", "pad")] + [("segments", C.c_uint64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -115,6 +121,7 @@ def _load():
     L.apax_spectral_workspace_bytes.argtypes = []
     L.apax_spectral_workspace_bytes.restype = u64
     L.apax_spectral_metrics.argtypes = [vp, vp, C.c_uint32, u64, P(Spectral), vp, u64, vp]
+    L.apax_signal_monitor.argtypes = [vp, C.c_uint32, u64, P(Monitor), vp, u64, vp]
     L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
@@ -345,6 +352,21 @@ def apax_spectral_metrics(x: torch.Tensor, y: torch.Tensor, ws: torch.Tensor | N
     _check(lib.apax_spectral_metrics(_dev_ptr(x), _dev_ptr(y), _DT[x.dtype], x.numel(), C.byref(r),
                                      _dev_ptr(ws), ws.numel(), _stream_ptr(stream)), "apax_spectral_metrics")
     return {f: getattr(r, f) for f, _ in Spectral._fields_}
+
+
+def apax_signal_monitor(x: torch.Tensor, ws: torch.Tensor | None = None, stream=None) -> dict:
+    """Signal monitor of x (Sec. 6): center bin and frequency, SNR, lags
+    0..16 autocorrelation, the correlated neighbour's stride and sign and
+    the gain of that filter."""
+    assert x.is_cuda and x.is_contiguous()
+    if ws is None:
+        ws = torch.empty(int(lib.apax_spectral_workspace_bytes()), dtype=torch.uint8, device=x.device)
+    r = Monitor()
+    _check(lib.apax_signal_monitor(_dev_ptr(x), _DT[x.dtype], x.numel(), C.byref(r), _dev_ptr(ws), ws.numel(),
+                                   _stream_ptr(stream)), "apax_signal_monitor")
+    out = {f: getattr(r, f) for f, _ in Monitor._fields_ if f not in ("acf", "pad")}
+    out["acf"] = [r.acf[i] for i in range(17)]
+    return out
 
 
 def apax_profile_read(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None) -> dict:

@@ -752,8 +752,30 @@ int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, doub
   return APAX_OK;
 }
 
-uint64_t apax_spectral_workspace_bytes(void) {
-  return 8 * 1024 + 16 * 1024 + (uint64_t)PSD_MAX_WGS * 3 * 512 * 8 + 3 * 512 * 8;
+// Spectral workspace: window and twiddle table, PSD partials and sums, then
+// the monitor's autocorrelation partials, sums and end samples.
+static constexpr uint64_t SPEC_TABLE = 8 * 1024 + 16 * 1024;
+static constexpr uint64_t SPEC_PSD_OUT = SPEC_TABLE + (uint64_t)PSD_MAX_WGS * 3 * 512 * 8;
+static constexpr uint64_t SPEC_ACF = SPEC_PSD_OUT + 3 * 512 * 8;
+static constexpr uint64_t SPEC_ACF_OUT = SPEC_ACF + (uint64_t)ACF_MAX_WGS * (ACF_LAGS + 1) * 8;
+static constexpr uint64_t SPEC_ENDS = SPEC_ACF_OUT + 256;
+static constexpr uint64_t SPEC_BYTES = SPEC_ENDS + 256;
+
+uint64_t apax_spectral_workspace_bytes(void) { return SPEC_BYTES; }
+
+// Upload the Hann window and the twiddles (host binary64 sin/cos) to d_ws.
+static int spectral_tables(uint8_t* w, hipStream_t stream) {
+  double table[1024 + 2 * 1024];
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < 1024; i++) {
+    const double sn = sin(pi * i / 1024.0);
+    table[i] = sn * sn;
+    table[1024 + 2 * i] = cos(2.0 * pi * i / 1024.0);
+    table[1024 + 2 * i + 1] = -sin(2.0 * pi * i / 1024.0);
+  }
+  if (hipMemcpyAsync(w, table, sizeof(table), hipMemcpyHostToDevice, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;  // the table is on this stack
+  return APAX_OK;
 }
 
 int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint64_t n, apax_spectral* out,
@@ -768,27 +790,20 @@ int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint
   if (!d_x || !d_y || !d_ws) return APAX_E_INVALID;
   if (((uintptr_t)d_ws & 15) || ws_bytes < apax_spectral_workspace_bytes()) return APAX_E_CAPACITY;
   const uint64_t K = 1 + (n - 1024) / 512;
-  // window and twiddles (host binary64 sin/cos), then the partial spectra
-  double table[1024 + 2 * 1024];
-  const double pi = 3.14159265358979323846;
-  for (int i = 0; i < 1024; i++) {
-    const double sn = sin(pi * i / 1024.0);
-    table[i] = sn * sn;
-    table[1024 + 2 * i] = cos(2.0 * pi * i / 1024.0);
-    table[1024 + 2 * i + 1] = -sin(2.0 * pi * i / 1024.0);
-  }
   uint8_t* w = (uint8_t*)d_ws;
-  if (hipMemcpyAsync(w, table, sizeof(table), hipMemcpyHostToDevice, stream) != hipSuccess) return APAX_E_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;  // the table is on this stack
+  int e = spectral_tables(w, stream);
+  if (e) return e;
   PsdArgs A;
   A.x = d_x;
   A.y = d_y;
   A.window = (const double*)w;
   A.twiddle = w + 8 * 1024;
-  A.partial = (double*)(w + 24 * 1024);
-  A.out = (double*)(w + 24 * 1024 + (uint64_t)PSD_MAX_WGS * 3 * 512 * 8);
+  A.partial = (double*)(w + SPEC_TABLE);
+  A.out = (double*)(w + SPEC_PSD_OUT);
   A.segments = (int64_t)K;
-  int e = hip_err(launch_psd((int)dtype, A, stream));
+  A.nsig = 3;
+  A.pad = 0;
+  e = hip_err(launch_psd((int)dtype, A, stream));
   if (e) return e;
   double P[3 * 512];
   if (hipMemcpyAsync(P, A.out, sizeof(P), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
@@ -820,6 +835,93 @@ int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint
   out->dr = out->peak_x - out->floor_x;
   out->srr = out->peak_x - out->resid_mean;
   out->fft_s2r_margin = out->floor_x - out->resid_mean;
+  return APAX_OK;
+}
+
+// Sec. 6 signal monitor.  The lag sums and the spectrum run on the device;
+// the host assembles the scalars from the 512 bins, the 17 sums and the 32
+// end samples.
+int apax_signal_monitor(const void* d_x, uint32_t dtype, uint64_t n, apax_monitor* out, void* d_ws,
+                        uint64_t ws_bytes, hipStream_t stream) {
+  if (!out || dtype < APAX_I8 || dtype > APAX_F64) return APAX_E_INVALID;
+  memset(out, 0, sizeof(*out));
+  out->center_freq = out->peak_db = out->floor_db = out->snr_db = out->gain_db = NAN;
+  if (n == 0) return APAX_OK;
+  if (!d_x || !d_ws) return APAX_E_INVALID;
+  if (((uintptr_t)d_ws & 15) || ws_bytes < SPEC_BYTES) return APAX_E_CAPACITY;
+  uint8_t* w = (uint8_t*)d_ws;
+  AcfArgs C;
+  C.x = d_x;
+  C.n = (int64_t)n;
+  C.partial = (double*)(w + SPEC_ACF);
+  C.out = (double*)(w + SPEC_ACF_OUT);
+  C.ends = (double*)(w + SPEC_ENDS);
+  int e = hip_err(launch_acf((int)dtype, C, stream));
+  if (e) return e;
+  double R[ACF_LAGS + 1], ends[2 * ACF_LAGS];
+  if (hipMemcpyAsync(R, C.out, sizeof(R), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipMemcpyAsync(ends, C.ends, sizeof(ends), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  uint64_t K = 0;
+  double P[512];
+  if (n >= 1024) {
+    K = 1 + (n - 1024) / 512;
+    e = spectral_tables(w, stream);
+    if (e) return e;
+    PsdArgs A;
+    A.x = d_x;
+    A.y = d_x;
+    A.window = (const double*)w;
+    A.twiddle = w + 8 * 1024;
+    A.partial = (double*)(w + SPEC_TABLE);
+    A.out = (double*)(w + SPEC_PSD_OUT);
+    A.segments = (int64_t)K;
+    A.nsig = 1;
+    A.pad = 0;
+    e = hip_err(launch_psd((int)dtype, A, stream));
+    if (e) return e;
+    if (hipMemcpyAsync(P, A.out, sizeof(P), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
+  // acf[k] = (R[k] / (n - k)) / (R[0] / n) for the lags the array has
+  if (R[0] > 0.0)
+    for (uint64_t k = 0; k <= ACF_LAGS && k < n; k++) out->acf[k] = (R[k] / (double)(n - k)) / (R[0] / (double)n);
+  if (n < 1024) return APAX_OK;
+  auto db = [](double v) { return v > 0.0 ? 10.0 * log10(v) : -INFINITY; };
+  double v[512], sum = 0.0;
+  int b = 1;
+  for (int f = 0; f < 512; f++) {
+    v[f] = P[f] / (double)K;
+    if (v[f] > v[b - 1]) b = f + 1;  // the first largest bin
+    sum += v[f];
+  }
+  const double peak = v[b - 1];
+  std::nth_element(v, v + 255, v + 512);  // nearest-rank median: the 256th smallest
+  out->segments = K;
+  out->peak_bin = b;
+  out->center_freq = b / 1024.0;
+  out->peak_db = db(peak);
+  out->floor_db = db(v[255]);
+  out->snr_db = db(sum / 512.0) - out->floor_db;
+  // the lag whose phase at bin b lies nearest a multiple of half a turn
+  int k = 1, dist = 1024;
+  for (int j = 1; j <= ACF_LAGS; j++) {
+    const int r = (b * j) & 511, d = r < 512 - r ? r : 512 - r;
+    if (d < dist) dist = d, k = j;
+  }
+  const int m = (b * k) & 1023;
+  const int sg = (m <= 256 || m >= 768) ? 1 : -1;
+  out->stride = k;
+  out->sign = sg;
+  // sum_{i >= k} x_i^2 = R0 - head, sum_{i < n - k} x_i^2 = R0 - tail
+  double head = 0.0, tail = 0.0;
+  for (int j = 0; j < k; j++) {
+    head += ends[j] * ends[j];
+    tail += ends[2 * ACF_LAGS - 1 - j] * ends[2 * ACF_LAGS - 1 - j];
+  }
+  const double e_in = R[0] - head;
+  double e_out = e_in + (R[0] - tail) - 2.0 * sg * R[k];
+  if (e_out < 0.0) e_out = 0.0;
+  out->gain_db = db(e_in) - db(e_out);
   return APAX_OK;
 }
 

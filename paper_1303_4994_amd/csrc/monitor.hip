@@ -1,0 +1,106 @@
+// monitor.hip -- the signal monitor's autocorrelation (Sec. 6): of the array
+// in memory order, binary64, R[k] = sum over n >= k of x[n] x[n - k] for the
+// lags k = 0..16 that decide which nearby samples are correlated.
+//
+// A workgroup step covers 4096 samples: 256 lanes stage them, with the 16
+// before them, as binary64 in LDS (one pad word per 16, so that the per-lane
+// windows below are read without bank conflicts); each lane then holds a
+// window of 32 consecutive samples in registers and accumulates the 17 lag
+// products of its own 16.  Samples outside 0..n-1 read as zero, which keeps
+// every sum to the pairs inside the array.  Workgroups grid-stride over the
+// steps and write one partial per lag; a fixed-order reduction sums them.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace apax {
+
+constexpr int ACF_SPAN = ACF_LAGS + ACF_TILE;  // staged samples per step
+
+__device__ __forceinline__ int acf_slot(int i) { return i + (i >> 4); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_acf(AcfArgs A) {
+  __shared__ double s_t[ACF_SPAN + ACF_SPAN / 16 + 1];
+  __shared__ double s_w[4][ACF_LAGS + 1];
+  const T* x = (const T*)A.x;
+  const int t = threadIdx.x;
+  const int64_t steps = (A.n + ACF_TILE - 1) / ACF_TILE;
+  double acc[ACF_LAGS + 1];
+#pragma unroll
+  for (int k = 0; k <= ACF_LAGS; k++) acc[k] = 0.0;
+
+  for (int64_t st = blockIdx.x; st < steps; st += gridDim.x) {
+    const int64_t base = st * ACF_TILE - ACF_LAGS;  // sample of staged index 0
+    for (int i = t; i < ACF_SPAN; i += 256) {
+      const int64_t g = base + i;
+      s_t[acf_slot(i)] = (g >= 0 && g < A.n) ? (double)x[g] : 0.0;
+    }
+    __syncthreads();
+    double w[2 * ACF_LAGS];  // staged indexes 16 t .. 16 t + 31
+#pragma unroll
+    for (int j = 0; j < 2 * ACF_LAGS; j++) w[j] = s_t[acf_slot(16 * t + j)];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+      const double xn = w[ACF_LAGS + u];  // sample base + 16 + 16 t + u
+#pragma unroll
+      for (int k = 0; k <= ACF_LAGS; k++) acc[k] = fma(xn, w[ACF_LAGS + u - k], acc[k]);
+    }
+    __syncthreads();  // the window is read before the next step stages
+  }
+#pragma unroll
+  for (int k = 0; k <= ACF_LAGS; k++) {
+    double v = acc[k];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    acc[k] = v;
+  }
+  if ((t & 63) == 0)
+#pragma unroll
+    for (int k = 0; k <= ACF_LAGS; k++) s_w[t >> 6][k] = acc[k];
+  __syncthreads();
+  if (t <= ACF_LAGS)
+    A.partial[(int64_t)blockIdx.x * (ACF_LAGS + 1) + t] = ((s_w[0][t] + s_w[1][t]) + s_w[2][t]) + s_w[3][t];
+  if (blockIdx.x == 0 && t < 2 * ACF_LAGS) {  // the samples the sums' end terms need
+    double v = 0.0;
+    if (A.n >= 2 * ACF_LAGS) v = (double)x[t < ACF_LAGS ? t : A.n - 2 * ACF_LAGS + t];
+    A.ends[t] = v;
+  }
+}
+
+// out[k] = sum of the workgroup partials of lag k: one workgroup per lag,
+// strided per-lane sums, then a fixed tree through LDS.
+__global__ __launch_bounds__(256) void k_acf_reduce(const double* partial, int nwg, double* out) {
+  __shared__ double s[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  double v = 0.0;
+  for (int w = t; w < nwg; w += 256) v += partial[(int64_t)w * (ACF_LAGS + 1) + k];
+  s[t] = v;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h) s[t] += s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) out[k] = s[0];
+}
+
+hipError_t launch_acf(int dtype, AcfArgs& A, hipStream_t s) {
+  if (A.n <= 0) return hipSuccess;
+  int64_t nwg = (A.n + ACF_TILE - 1) / ACF_TILE;
+  if (nwg > ACF_MAX_WGS) nwg = ACF_MAX_WGS;
+  const dim3 grid((unsigned)nwg), block(256);
+  switch (dtype) {
+    case DT_I8: hipLaunchKernelGGL(k_acf<int8_t>, grid, block, 0, s, A); break;
+    case DT_I16: hipLaunchKernelGGL(k_acf<int16_t>, grid, block, 0, s, A); break;
+    case DT_I32: hipLaunchKernelGGL(k_acf<int32_t>, grid, block, 0, s, A); break;
+    case DT_F32: hipLaunchKernelGGL(k_acf<float>, grid, block, 0, s, A); break;
+    default: hipLaunchKernelGGL(k_acf<double>, grid, block, 0, s, A); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_acf_reduce, dim3(ACF_LAGS + 1), dim3(256), 0, s, (const double*)A.partial, (int)nwg, A.out);
+  return hipGetLastError();
+}
+
+}  // namespace apax

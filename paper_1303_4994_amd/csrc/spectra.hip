@@ -83,7 +83,8 @@ __device__ __forceinline__ double sig(const T* x, const T* y, int which, int64_t
 // the pair's two segments as real and imaginary parts: packing two real
 // transforms costs an error relative to the larger of the two, so only
 // segments of the same signal (alike in size) share one.
-template <typename T>
+// NSIG = 3: x, y and d; NSIG = 1: x only (the other partials stay zero).
+template <typename T, int NSIG>
 __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
   __shared__ C64 s_z[PSD_WAVES][PSD_N];
   const int wave = threadIdx.x >> 6;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
     const int64_t b0 = pr * PSD_N;            // segment 2p starts at 2p * 512
     const bool second = 2 * pr + 1 < A.segments;
 #pragma unroll
-    for (int which = 0; which < 3; which++) {
+    for (int which = 0; which < NSIG; which++) {
       C64 v[16];
 #pragma unroll
       for (int m = 0; m < 16; m++) {
@@ -166,12 +167,22 @@ hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s) {
   int64_t nwg = ((A.segments + 1) / 2 + PSD_WAVES - 1) / PSD_WAVES;
   if (nwg > PSD_MAX_WGS) nwg = PSD_MAX_WGS;
   const dim3 grid((unsigned)nwg), block(PSD_WAVES * 64);
-  switch (dtype) {
-    case DT_I8: hipLaunchKernelGGL(k_psd<int8_t>, grid, block, 0, s, A); break;
-    case DT_I16: hipLaunchKernelGGL(k_psd<int16_t>, grid, block, 0, s, A); break;
-    case DT_I32: hipLaunchKernelGGL(k_psd<int32_t>, grid, block, 0, s, A); break;
-    case DT_F32: hipLaunchKernelGGL(k_psd<float>, grid, block, 0, s, A); break;
-    default: hipLaunchKernelGGL(k_psd<double>, grid, block, 0, s, A); break;
+  if (A.nsig == 1) {
+    switch (dtype) {
+      case DT_I8: hipLaunchKernelGGL((k_psd<int8_t, 1>), grid, block, 0, s, A); break;
+      case DT_I16: hipLaunchKernelGGL((k_psd<int16_t, 1>), grid, block, 0, s, A); break;
+      case DT_I32: hipLaunchKernelGGL((k_psd<int32_t, 1>), grid, block, 0, s, A); break;
+      case DT_F32: hipLaunchKernelGGL((k_psd<float, 1>), grid, block, 0, s, A); break;
+      default: hipLaunchKernelGGL((k_psd<double, 1>), grid, block, 0, s, A); break;
+    }
+  } else {
+    switch (dtype) {
+      case DT_I8: hipLaunchKernelGGL((k_psd<int8_t, 3>), grid, block, 0, s, A); break;
+      case DT_I16: hipLaunchKernelGGL((k_psd<int16_t, 3>), grid, block, 0, s, A); break;
+      case DT_I32: hipLaunchKernelGGL((k_psd<int32_t, 3>), grid, block, 0, s, A); break;
+      case DT_F32: hipLaunchKernelGGL((k_psd<float, 3>), grid, block, 0, s, A); break;
+      default: hipLaunchKernelGGL((k_psd<double, 3>), grid, block, 0, s, A); break;
+    }
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -490,6 +490,63 @@ def test_spectral_metrics_c1(A):
     assert g["srr"] > 0 and g["dr"] > 0
 
 
+def _modulated(dt, n, seed, b, noise=0.01):
+    """A carrier at bin b of 1024 under a slow envelope, plus white noise."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n)
+    env = 1.0 + 0.3 * np.sin(2 * np.pi * t / 5000.0)
+    s = env * np.cos(2 * np.pi * b * t / 1024 + 0.7) + noise * rng.standard_normal(n)
+    dt = np.dtype(dt)
+    if dt.kind == "i":
+        return np.rint(s / np.abs(s).max() * 0.9 * np.iinfo(dt).max).astype(dt)
+    return (s * 3.0).astype(dt)
+
+
+def _monitor_close(g, o):
+    """Monitor fields against the oracle: acf to 1e-12, dB fields to 1e-9 dB,
+    the integer decisions exactly (the center bin unless the oracle's top two
+    bins are within rounding of each other)."""
+    assert np.allclose(g["acf"], o["acf"], rtol=0, atol=1e-12), (g["acf"], o["acf"])
+    assert g["segments"] == o["segments"]
+    assert (g["peak_bin"], g["stride"], g["sign"]) == (o["peak_bin"], o["stride"], o["sign"])
+    for k in ("center_freq", "peak_db", "floor_db", "snr_db", "gain_db"):
+        gv, v = g[k], o[k]
+        if math.isnan(v) or math.isinf(v):
+            assert (math.isnan(gv) and math.isnan(v)) or gv == v, (k, gv, v)
+        else:
+            assert abs(gv - v) < 1e-9 * max(1.0, abs(v)), (k, gv, v)
+
+
+@pytest.mark.parametrize("dt,n,b,noise", [
+    (np.float32, 1 << 16, 102, 0.01), (np.float64, 4096 + 37, 3, 0.001), (np.int16, 50000, 341, 0.05),
+    (np.int32, 1024, 512, 0.01), (np.int8, 1535, 200, 0.02), (np.float32, 9 * 4096 + 4095, 256, 0.1),
+    (np.float64, 30000, 77, 1.0), (np.float32, 1000, 50, 0.01), (np.int16, 17, 5, 0.0),
+    (np.float32, 1, 5, 0.0)])
+def test_signal_monitor(A, dt, n, b, noise):
+    """Sec. 6 signal monitor against the oracle: modulated carriers across the
+    band, every dtype, several tiles with a ragged tail, exactly one segment,
+    fewer samples than a segment, one sample."""
+    print(f"monitor {np.dtype(dt).name} n={n} b={b}", flush=True)
+    x = _modulated(dt, n, 31, b, noise)
+    o = O.signal_monitor(x)
+    g = A.apax_signal_monitor(torch.from_numpy(x).to(DEV))
+    _monitor_close(g, o)
+    if n >= 1024 and noise <= 0.05:
+        assert g["peak_bin"] == b
+
+
+def test_signal_monitor_c1_and_edges(A):
+    """The 16 MSample C1 field (fp32), a zero array and an empty one."""
+    x = synth.grf2d(4096, 4096)
+    g = A.apax_signal_monitor(torch.from_numpy(x).to(DEV))
+    _monitor_close(g, O.signal_monitor(x))
+    assert g["stride"] >= 1 and g["gain_db"] > 0
+    z = A.apax_signal_monitor(torch.zeros(4096, device=DEV))
+    _monitor_close(z, O.signal_monitor(np.zeros(4096, np.float32)))
+    e = A.apax_signal_monitor(torch.zeros(0, device=DEV))
+    assert e["peak_bin"] == 0 and not any(e["acf"]) and math.isnan(e["snr_db"])
+
+
 @pytest.mark.parametrize("name,dt,shape,params,kind", [c for c in CASES if c[0] in (
     "i16-1d-B256-lossless", "i32-3d-2x4x8-lossless", "f32-2d-4x16-fq", "f64-3d-2x4x8-fq", "f32-1d-B128-fr",
     "f64-2d-8x8-fr", "i8-1d-fr", "f32-2d-16x16-fr")], ids=lambda v: v if isinstance(v, str) else None)
