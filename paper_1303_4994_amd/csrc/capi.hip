@@ -10,6 +10,7 @@
 
 #include "apax.h"
 #include "kernels.h"
+#include "monitor.h"
 
 using namespace apax;
 

@@ -195,18 +195,6 @@ struct PsdArgs {
 };
 hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s);
 
-// ---- signal monitor (Sec. 6): R[k] = sum_{n >= k} x[n] x[n - k], k = 0..16
-constexpr int ACF_LAGS = 16;
-constexpr int ACF_TILE = 4096;     // samples per workgroup step
-constexpr int ACF_MAX_WGS = 1024;
-struct AcfArgs {
-  const void* x;
-  int64_t n;
-  double* partial;  // [workgroup][ACF_LAGS + 1]
-  double* out;      // [ACF_LAGS + 1]
-  double* ends;     // [32]: x[0..15] and x[n - 16..n - 1] (n >= 32; zeros otherwise)
-};
-hipError_t launch_acf(int dtype, AcfArgs& A, hipStream_t s);
 
 // ---- batches: many arrays, one persistent launch per (LPB, NDIM) class
 struct BatchEnc {

@@ -6,13 +6,15 @@
 // before them, as binary64 in LDS (one pad word per 16, so that the per-lane
 // windows below are read without bank conflicts); each lane then holds a
 // window of 32 consecutive samples in registers and accumulates the 17 lag
-// products of its own 16.  Samples outside 0..n-1 read as zero, which keeps
-// every sum to the pairs inside the array.  Workgroups grid-stride over the
-// steps and write one partial per lag; a fixed-order reduction sums them.
+// products of its own 16, while the loads of its next step are in flight.
+// Samples outside 0..n-1 read as zero, which keeps every sum to the pairs
+// inside the array.  Workgroups grid-stride over the steps and write one
+// partial per lag; a fixed-order reduction sums them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "kernels.h"
+#include "codec.h"
+#include "monitor.h"
 
 namespace apax {
 
@@ -21,9 +23,24 @@ constexpr int ACF_SPAN = ACF_LAGS + ACF_TILE;  // staged samples per step
 __device__ __forceinline__ int acf_slot(int i) { return i + (i >> 4); }
 
 template <typename T>
+struct AcfStage {
+  T v[ACF_TILE / 256];  // samples st * 4096 + t + 256 m
+  T h;                  // lanes 0..15: sample st * 4096 - 16 + t
+  __device__ __forceinline__ void load(const T* x, int64_t n, int64_t st, int t) {
+    const int64_t base = st * ACF_TILE;
+#pragma unroll
+    for (int m = 0; m < ACF_TILE / 256; m++) {
+      const int64_t g = base + t + 256 * m;
+      v[m] = g < n ? x[g] : T(0);
+    }
+    h = (t < ACF_LAGS && base - ACF_LAGS + t >= 0) ? x[base - ACF_LAGS + t] : T(0);
+  }
+};
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_acf(AcfArgs A) {
   __shared__ double s_t[ACF_SPAN + ACF_SPAN / 16 + 1];
-  __shared__ double s_w[4][ACF_LAGS + 1];
+  __shared__ double s_p[ACF_LAGS + 1][8];
   const T* x = (const T*)A.x;
   const int t = threadIdx.x;
   const int64_t steps = (A.n + ACF_TILE - 1) / ACF_TILE;
@@ -31,37 +48,44 @@ __global__ __launch_bounds__(256) void k_acf(AcfArgs A) {
 #pragma unroll
   for (int k = 0; k <= ACF_LAGS; k++) acc[k] = 0.0;
 
+  // every load of a step is issued before any is used, and the next step's
+  // loads are in flight while this step computes
+  AcfStage<T> nx;
+  if ((int64_t)blockIdx.x < steps) nx.load(x, A.n, blockIdx.x, t);
   for (int64_t st = blockIdx.x; st < steps; st += gridDim.x) {
-    const int64_t base = st * ACF_TILE - ACF_LAGS;  // sample of staged index 0
-    for (int i = t; i < ACF_SPAN; i += 256) {
-      const int64_t g = base + i;
-      s_t[acf_slot(i)] = (g >= 0 && g < A.n) ? (double)x[g] : 0.0;
-    }
+#pragma unroll
+    for (int m = 0; m < ACF_TILE / 256; m++) s_t[acf_slot(ACF_LAGS + t + 256 * m)] = (double)nx.v[m];
+    if (t < ACF_LAGS) s_t[acf_slot(t)] = (double)nx.h;
     __syncthreads();
+    if (st + gridDim.x < steps) nx.load(x, A.n, st + gridDim.x, t);
     double w[2 * ACF_LAGS];  // staged indexes 16 t .. 16 t + 31
 #pragma unroll
     for (int j = 0; j < 2 * ACF_LAGS; j++) w[j] = s_t[acf_slot(16 * t + j)];
 #pragma unroll
     for (int u = 0; u < 16; u++) {
-      const double xn = w[ACF_LAGS + u];  // sample base + 16 + 16 t + u
+      const double xn = w[ACF_LAGS + u];  // sample st * 4096 + 16 t + u
 #pragma unroll
       for (int k = 0; k <= ACF_LAGS; k++) acc[k] = fma(xn, w[ACF_LAGS + u - k], acc[k]);
     }
     __syncthreads();  // the window is read before the next step stages
   }
+  // workgroup sum per lag through LDS: lag k's 256 values in s_t[k * 256 ..],
+  // eight runs of 32 summed by eight lanes, then the eight in order
 #pragma unroll
-  for (int k = 0; k <= ACF_LAGS; k++) {
-    double v = acc[k];
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    acc[k] = v;
-  }
-  if ((t & 63) == 0)
-#pragma unroll
-    for (int k = 0; k <= ACF_LAGS; k++) s_w[t >> 6][k] = acc[k];
+  for (int k = 0; k <= ACF_LAGS; k++) s_t[k * 256 + t] = acc[k];
   __syncthreads();
-  if (t <= ACF_LAGS)
-    A.partial[(int64_t)blockIdx.x * (ACF_LAGS + 1) + t] = ((s_w[0][t] + s_w[1][t]) + s_w[2][t]) + s_w[3][t];
+  if (t < (ACF_LAGS + 1) * 8) {
+    const int k = t >> 3, r = t & 7;
+    double v = 0.0;
+    for (int i = 0; i < 32; i++) v += s_t[k * 256 + r * 32 + i];
+    s_p[k][r] = v;
+  }
+  __syncthreads();
+  if (t <= ACF_LAGS) {
+    double v = s_p[t][0];
+    for (int r = 1; r < 8; r++) v += s_p[t][r];
+    A.partial[(int64_t)blockIdx.x * (ACF_LAGS + 1) + t] = v;
+  }
   if (blockIdx.x == 0 && t < 2 * ACF_LAGS) {  // the samples the sums' end terms need
     double v = 0.0;
     if (A.n >= 2 * ACF_LAGS) v = (double)x[t < ACF_LAGS ? t : A.n - 2 * ACF_LAGS + t];
