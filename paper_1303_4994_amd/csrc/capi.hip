@@ -11,6 +11,7 @@
 #include "apax.h"
 #include "kernels.h"
 #include "monitor.h"
+#include "spectra.h"
 
 using namespace apax;
 

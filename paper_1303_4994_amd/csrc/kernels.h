@@ -180,20 +180,6 @@ struct S2RArgs {
 };
 hipError_t launch_s2r(int dtype, int ndim, S2RArgs& A, uint64_t rank, hipStream_t s);
 
-// Welch spectra of x, y, x - y (1024-sample segments, hop 512)
-constexpr int PSD_MAX_WGS = 256;
-struct PsdArgs {
-  const void* x;
-  const void* y;
-  const double* window;   // 1024 Hann weights
-  const void* twiddle;    // 1024 complex e^(-2 pi i k / 1024)
-  double* partial;        // [workgroup][3][512]
-  double* out;            // [3][512] sums over segments
-  int64_t segments;
-  int32_t nsig;           // 3: x, y and d; 1: x only
-  int32_t pad;
-};
-hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s);
 
 
 // ---- batches: many arrays, one persistent launch per (LPB, NDIM) class

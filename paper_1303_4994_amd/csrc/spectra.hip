@@ -1,9 +1,11 @@
 // spectra.hip -- Welch power spectra of x, y and d = x - y for the spectral
-// metrics of Sec. 4 (Windows 3-4): segments of 1024 samples of the array in
-// memory order, hop 512, periodic Hann window, one-sided bins 1..512.
+// metrics of Sec. 4 (Windows 3-4), or of x alone for the signal monitor of
+// Sec. 6: segments of 1024 samples of the array in memory order, hop 512,
+// periodic Hann window, one-sided bins 1..512.
 //
-// One wave per pair of segments: for each of x, y and d (binary64, d formed
-// per sample), the two windowed segments form one complex sequence,
+// One launch per signal, one wave per pair of segments: for x, y or d
+// (binary64, d formed per sample), the two windowed segments form one complex
+// sequence,
 // transformed by a radix-4 Stockham FFT (five stages, in place in the wave's
 // LDS buffer: every lane reads its 16 inputs before any lane writes); the two
 // real spectra follow from Z_f and Z_(1024-f).  Each lane accumulates the
@@ -12,7 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "kernels.h"
+#include "codec.h"
+#include "spectra.h"
 
 namespace apax {
 
@@ -38,8 +41,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // v: this lane's stage-0 inputs, v[m] = input[lane + 64 m]; the result is
 // left in z in natural order.
 __device__ __forceinline__ void fft1024(C64 (&v)[16], C64* z, const C64* tw, int lane) {
-#pragma unroll 1
-  for (int ns = 1; ns < PSD_N; ns *= 4) {
+#pragma unroll
+  for (int ns = 1; ns < PSD_N; ns *= 4) {  // five stages, unrolled: ns, step are constants
     if (ns > 1) {
 #pragma unroll
       for (int q = 0; q < 4; q++)
@@ -83,8 +86,10 @@ __device__ __forceinline__ double sig(const T* x, const T* y, int which, int64_t
 // the pair's two segments as real and imaginary parts: packing two real
 // transforms costs an error relative to the larger of the two, so only
 // segments of the same signal (alike in size) share one.
-// NSIG = 3: x, y and d; NSIG = 1: x only (the other partials stay zero).
-template <typename T, int NSIG>
+// One launch per signal SIG (0 x, 1 y, 2 d), which writes row SIG of the
+// workgroup partials: three signals in one wave would hold three spectra of
+// sums and halve the waves a SIMD can run.
+template <typename T, int SIG>
 __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
   __shared__ C64 s_z[PSD_WAVES][PSD_N];
   const int wave = threadIdx.x >> 6;
@@ -94,11 +99,9 @@ __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
   const C64* tw = (const C64*)A.twiddle;  // e^(-2 pi i k / 1024)
   const double* win = A.window;           // sin^2(pi i / 1024)
   C64* z = s_z[wave];
-  double acc[3][8];
+  double acc[8];
 #pragma unroll
-  for (int s = 0; s < 3; s++)
-#pragma unroll
-    for (int m = 0; m < 8; m++) acc[s][m] = 0.0;
+  for (int m = 0; m < 8; m++) acc[m] = 0.0;
 
   const int64_t pairs = (A.segments + 1) / 2;
   const int64_t wid = (int64_t)blockIdx.x * PSD_WAVES + wave;
@@ -106,8 +109,8 @@ __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
   for (int64_t pr = wid; pr < pairs; pr += nw) {
     const int64_t b0 = pr * PSD_N;            // segment 2p starts at 2p * 512
     const bool second = 2 * pr + 1 < A.segments;
-#pragma unroll
-    for (int which = 0; which < NSIG; which++) {
+    {
+      constexpr int which = SIG;
       C64 v[16];
 #pragma unroll
       for (int m = 0; m < 16; m++) {
@@ -125,68 +128,76 @@ __global__ __launch_bounds__(PSD_WAVES * 64) void k_psd(PsdArgs A) {
         const double br = 0.5 * (zf.im + zn.im), bi = -0.5 * (zf.re - zn.re);
         double p = ar * ar + ai * ai;
         if (second) p += br * br + bi * bi;
-        acc[which][m] += p;
+        acc[m] += p;
       }
       wave_sync_lds();  // the bins are read before the next transform writes
     }
   }
   // workgroup partial: the waves in order, through LDS
   __syncthreads();
-  double* red = reinterpret_cast<double*>(&s_z[0][0]);  // [wave][3][512]
+  double* red = reinterpret_cast<double*>(&s_z[0][0]);  // [wave][512]
 #pragma unroll
-  for (int s = 0; s < 3; s++)
-#pragma unroll
-    for (int m = 0; m < 8; m++) red[(wave * 3 + s) * 512 + lane + 64 * m] = acc[s][m];
+  for (int m = 0; m < 8; m++) red[wave * 512 + lane + 64 * m] = acc[m];
   __syncthreads();
-  for (int t = threadIdx.x; t < 3 * 512; t += blockDim.x) {
+  for (int t = threadIdx.x; t < 512; t += blockDim.x) {
     double sum = red[t];
-    for (int w = 1; w < PSD_WAVES; w++) sum += red[w * 3 * 512 + t];
-    A.partial[(int64_t)blockIdx.x * 3 * 512 + t] = sum;
+    for (int w = 1; w < PSD_WAVES; w++) sum += red[w * 512 + t];
+    A.partial[(int64_t)blockIdx.x * 3 * 512 + SIG * 512 + t] = sum;
   }
 }
 
-// Sum of the workgroup partials in workgroup order: out[s][f - 1].
+// Sum of the workgroup partials, out[s][f - 1], in a fixed order: a
+// workgroup takes 64 of the 1536 columns; its four waves sum four
+// consecutive runs of rows (eight loads in flight), then the runs in order.
 __global__ __launch_bounds__(256) void k_psd_reduce(const double* partial, int nwg, double* out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 3 * 512) return;
+  __shared__ double s_run[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  const int per = (nwg + 3) / 4;
+  const int lo = g * per, hi = lo + per < nwg ? lo + per : nwg;
   double sum = 0.0;
-  int w = 0;
-  for (; w + 8 <= nwg; w += 8) {  // eight loads in flight, added in order
+  int w = lo;
+  for (; w + 8 <= hi; w += 8) {
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; u++) v[u] = partial[(int64_t)(w + u) * 3 * 512 + t];
+    for (int u = 0; u < 8; u++) v[u] = partial[(int64_t)(w + u) * 3 * 512 + c];
 #pragma unroll
     for (int u = 0; u < 8; u++) sum += v[u];
   }
-  for (; w < nwg; w++) sum += partial[(int64_t)w * 3 * 512 + t];
-  out[t] = sum;
+  for (; w < hi; w++) sum += partial[(int64_t)w * 3 * 512 + c];
+  s_run[g][threadIdx.x & 63] = sum;
+  __syncthreads();
+  if (g == 0) {
+    const int l = threadIdx.x;
+    out[c] = ((s_run[0][l] + s_run[1][l]) + s_run[2][l]) + s_run[3][l];
+  }
 }
 
 hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s) {
   if (A.segments <= 0) return hipSuccess;
+  if (A.nsig < 1 || A.nsig > 3) return hipErrorInvalidValue;
   int64_t nwg = ((A.segments + 1) / 2 + PSD_WAVES - 1) / PSD_WAVES;
   if (nwg > PSD_MAX_WGS) nwg = PSD_MAX_WGS;
   const dim3 grid((unsigned)nwg), block(PSD_WAVES * 64);
-  if (A.nsig == 1) {
-    switch (dtype) {
-      case DT_I8: hipLaunchKernelGGL((k_psd<int8_t, 1>), grid, block, 0, s, A); break;
-      case DT_I16: hipLaunchKernelGGL((k_psd<int16_t, 1>), grid, block, 0, s, A); break;
-      case DT_I32: hipLaunchKernelGGL((k_psd<int32_t, 1>), grid, block, 0, s, A); break;
-      case DT_F32: hipLaunchKernelGGL((k_psd<float, 1>), grid, block, 0, s, A); break;
-      default: hipLaunchKernelGGL((k_psd<double, 1>), grid, block, 0, s, A); break;
+  for (int sg = 0; sg < A.nsig; sg++) {
+    switch (dtype * 4 + sg) {
+#define PSD_CASE(DT, TY)                                                                  \
+  case DT * 4 + 0: hipLaunchKernelGGL((k_psd<TY, 0>), grid, block, 0, s, A); break;      \
+  case DT * 4 + 1: hipLaunchKernelGGL((k_psd<TY, 1>), grid, block, 0, s, A); break;      \
+  case DT * 4 + 2: hipLaunchKernelGGL((k_psd<TY, 2>), grid, block, 0, s, A); break;
+      PSD_CASE(DT_I8, int8_t)
+      PSD_CASE(DT_I16, int16_t)
+      PSD_CASE(DT_I32, int32_t)
+      PSD_CASE(DT_F32, float)
+      PSD_CASE(DT_F64, double)
+#undef PSD_CASE
+      default: return hipErrorInvalidValue;
     }
-  } else {
-    switch (dtype) {
-      case DT_I8: hipLaunchKernelGGL((k_psd<int8_t, 3>), grid, block, 0, s, A); break;
-      case DT_I16: hipLaunchKernelGGL((k_psd<int16_t, 3>), grid, block, 0, s, A); break;
-      case DT_I32: hipLaunchKernelGGL((k_psd<int32_t, 3>), grid, block, 0, s, A); break;
-      case DT_F32: hipLaunchKernelGGL((k_psd<float, 3>), grid, block, 0, s, A); break;
-      default: hipLaunchKernelGGL((k_psd<double, 3>), grid, block, 0, s, A); break;
-    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_psd_reduce, dim3(6), dim3(256), 0, s, (const double*)A.partial, (int)nwg, A.out);
+  // only the rows of the signals computed (row r: columns r * 512 ..)
+  hipLaunchKernelGGL(k_psd_reduce, dim3(A.nsig * 512 / 64), dim3(256), 0, s, (const double*)A.partial, (int)nwg, A.out);
   return hipGetLastError();
 }
 
