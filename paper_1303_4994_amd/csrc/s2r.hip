@@ -58,16 +58,10 @@ __global__ __launch_bounds__(256) void k_s2r(S2RArgs A) {
         match = level == 0 || (key >> (shift + width)) == prefix;
         digit = (uint32_t)(key >> shift) & ((1u << width) - 1u);
       }
-      // one LDS add per distinct digit of the wave (neighbouring samples
-      // mostly share a digit): the lowest pending lane's digit, counted by ballot
-      uint64_t pending = __ballot(match);
-      while (pending) {
-        const int lead = __builtin_ctzll(pending);
-        const uint32_t dl = (uint32_t)__shfl((int)digit, lead, 64);
-        const uint64_t same = __ballot(match && digit == dl) & pending;
-        if (lane == lead) atomicAdd(&s_hist[dl], (uint32_t)__popcll(same));
-        pending &= ~same;
-      }
+      // one LDS add per matching lane: the digits of neighbouring ratios
+      // differ (the residual is noise-like), so grouping lanes by digit
+      // costs more rounds than the adds it saves
+      if (match) atomicAdd(&s_hist[digit], 1u);
     }
   }
   __syncthreads();
