@@ -118,6 +118,99 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
     print("\n".join(lines))
 
 
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && rocprofv3 --kernel-trace --stats "
+             "-d gpurun_out/kt_c1 -o kt -- python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline")
+INSTMIX_CMD = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES "
+               "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM SQ_BUSY_CYCLES --output-format csv "
+               "-d gpurun_out/pmc_sq -o p -- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+
+
+def trace_summary(db_path: str, out_path: str):
+    """Per-kernel durations from a rocprofv3 kernel-trace results database:
+    all launches, and the launches that ran alone (the step overlaps two
+    streams, so launches that shared the GPU run longer), plus one step's
+    launch sequence."""
+    import collections
+    import sqlite3
+    rows = list(sqlite3.connect(db_path).execute("select name, start, end from kernels order by start"))
+    every, alone = collections.defaultdict(list), collections.defaultdict(list)
+    latest = 0
+    for i, (n, a, b) in enumerate(rows):
+        nm = n.split("(")[0].replace("void ", "")
+        every[nm].append((b - a) / 1e3)
+        nxt = rows[i + 1][1] if i + 1 < len(rows) else float("inf")
+        if latest <= a and nxt >= b:
+            alone[nm].append((b - a) / 1e3)
+        latest = max(latest, b)
+    out = ["# rocprofv3 kernel trace, C1 bench (4096x4096 fp32, 16x16 bricks, fixed rate 4:1)",
+           f"# command: {TRACE_CMD}",
+           f"# summary: python3 bench.py --trace-from {db_path}",
+           "# durations in microseconds; per bench step: k_clear; k_pmax + k_pmax_reduce; 3 bisection probes",
+           "# k_profile<.., 2> + k_reduce<2, false>; histogram k_profile<.., 2> + k_reduce<2, true>; curve",
+           "# k_profile<.., 4> + k_reduce<4, false>; metrics k_profile<.., 1> + k_reduce<1, false>; centred",
+           "# k_profile<.., 3> + k_reduce<3, false>; k_encode; k_decode.  The run also times back-to-back",
+           "# encode/decode launches, event-bracketed profiles and the calls outside the step.",
+           "# The encode and decode of a step run on a second stream, overlapping the profile's curve,",
+           "# metrics and centred passes; iso_avg_us is the mean over launches with no other kernel",
+           "# running (the per-launch figure bench.py reports)",
+           f"{'kernel':52s} {'calls':>6s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'total_us':>9s} "
+           f"{'iso_n':>6s} {'iso_avg_us':>10s}"]
+    for k, v in sorted(every.items(), key=lambda kv: -sum(kv[1])):
+        if "apax::" not in k:
+            continue
+        w = alone.get(k, [])
+        ia = f"{sum(w) / len(w):10.2f}" if w else f"{'-':>10s}"
+        out.append(f"{k[:52]:52s} {len(v):6d} {sum(v) / len(v):8.2f} {min(v):8.2f} {max(v):8.2f} "
+                   f"{sum(v):9.1f} {len(w):6d} {ia}")
+    starts = [i for i, r in enumerate(rows) if "k_pmax<" in r[0]]
+    if len(starts) > 3:
+        seq = rows[starts[3]:starts[3] + 18]
+        out += ["", "# one step of the timed loop (start offset and duration, us)"]
+        for n, a, b in seq:
+            nm = n.split("(")[0].replace("void ", "")
+            if "apax::" in nm:
+                out.append(f"{(a - seq[0][1]) / 1e3:9.1f} {(b - a) / 1e3:9.2f}  {nm}")
+    open(out_path, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def instmix_summary(csv_path: str, out_path: str):
+    """Instruction counts per wave and VALU issue time per dispatch from a
+    rocprofv3 --pmc run of the SQ counters."""
+    import collections
+    import csv
+    disp = collections.OrderedDict()
+    for r in csv.DictReader(open(csv_path)):
+        d = disp.setdefault((r["Dispatch_Id"], r["Kernel_Name"]), {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = collections.OrderedDict()
+    for (_, name), d in disp.items():
+        a = agg.setdefault(name.split("(")[0].replace("void ", ""), collections.Counter())
+        a["n"] += 1
+        for k, v in d.items():
+            a[k] += v
+    out = ["# rocprofv3 instruction counters per dispatch, C1 bench (4096x4096 fp32, 16x16 bricks, 4:1)",
+           f"# command: {INSTMIX_CMD}",
+           f"# summary: python3 bench.py --instmix-from {csv_path}",
+           "# values are means over the dispatches of each kernel; per-wave figures divide by SQ_WAVES",
+           "# (k_encode / k_decode: one wave per 256-sample block; the profile passes loop over blocks)",
+           "# VALU_Ginstr: wave-level VALU instructions per dispatch (1e9); at one wave-instruction per CU",
+           "# per clock (256 CUs x 2.4 GHz = 614 G/s) this is the VALU issue time",
+           f"{'kernel':46s} {'n':>4s} {'waves':>8s} {'VALU/wave':>10s} {'SALU/wave':>10s} {'LDS/wave':>9s} "
+           f"{'VMEM/wave':>10s} {'VALU_Ginstr':>12s} {'issue_us':>9s}"]
+    for nm, a in agg.items():
+        if "apax::" not in nm:
+            continue
+        n = a["n"]
+        w = a["SQ_WAVES"] / n
+        valu = a["SQ_INSTS_VALU"] / n
+        out.append(f"{nm[:46]:46s} {n:4d} {w:8.0f} {valu / w:10.1f} {a['SQ_INSTS_SALU'] / n / w:10.1f} "
+                   f"{a['SQ_INSTS_LDS'] / n / w:9.1f} {a['SQ_INSTS_VMEM'] / n / w:10.1f} {valu / 1e9:12.4f} "
+                   f"{valu / 614e9 * 1e6:9.1f}")
+    open(out_path, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def cpu_baseline(x, params):
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -171,9 +264,19 @@ def main():
     ap.add_argument("--pool", type=int, default=1 << 26, help="batch/serve: samples per pool")
     ap.add_argument("--copy-probe", action="store_true",
                     help="c1: also run a plain 64 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--trace-from", metavar="RESULTS_DB",
+                    help="write profiles/kernels_c1_bench.txt from a rocprofv3 kernel-trace results database")
+    ap.add_argument("--instmix-from", metavar="COUNTER_CSV",
+                    help="write profiles/pmc_c1_instmix.txt from a rocprofv3 --pmc SQ counter CSV")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_c1.txt from two rocprofv3 --pmc counter CSVs")
     args = ap.parse_args()
+    if args.trace_from:
+        trace_summary(args.trace_from, os.path.join(ROOT, "profiles", "kernels_c1_bench.txt"))
+        return
+    if args.instmix_from:
+        instmix_summary(args.instmix_from, os.path.join(ROOT, "profiles", "pmc_c1_instmix.txt"))
+        return
     if args.traffic_from:
         cmd = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && timeout -s KILL 150 rocprofv3 --pmc {c} "
                "--output-format csv -d gpurun_out/pmc_{d} -o p -- python3 bench.py --steps 2 --warmup 1 "

@@ -737,7 +737,14 @@ int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, doub
   A.x = d_x;
   A.st = (PState*)d_ws;
   A.cj = cj_ptr(d_ws, h);
-  A.hist = (uint32_t*)partials_ptr(d_ws, h);  // the profile's partial records are spent
+  // the profile's partial records are spent: 8192 bins, the kept-key count,
+  // then as many kept keys as the rest of the region holds
+  uint8_t* part = (uint8_t*)partials_ptr(d_ws, h);
+  A.hist = (uint32_t*)part;
+  A.ncand = (uint64_t*)(part + S2R_HIST_BYTES);
+  A.cand = (uint64_t*)(part + S2R_HIST_BYTES + 256);
+  const uint64_t region = partial_bytes(h);
+  A.cand_cap = region > S2R_HIST_BYTES + 256 ? (region - S2R_HIST_BYTES - 256) / 8 : 0;
   A.rule = h.mode == APAX_LOSSLESS ? R_LOSSLESS : (h.mode == APAX_FIXED_RATE ? R_RATE : R_QUALITY);
   A.g = h.g;
   const uint64_t rank = (45 * h.nsamples + 999) / 1000;  // ceil(0.045 n), n >= 1

@@ -169,11 +169,15 @@ struct ProfArgs {
 constexpr int PMAX_WGS = 1024;
 
 // 2-sigma S2R margin passes (after a profile of the same array)
+constexpr uint64_t S2R_HIST_BYTES = 8192 * 4;  // the selection's 8192 bins
 struct S2RArgs {
   const void* x;
   PState* st;
   const int32_t* cj;  // fixed rate: per-block codes of the profile's metrics pass
   uint32_t* hist;     // 8192 bins
+  uint64_t* ncand;    // keys that matched the level-2 prefix (all of them counted)
+  uint64_t* cand;     // the first cand_cap of those keys
+  uint64_t cand_cap;
   int64_t ntiles, nwg;
   int rule, pad;
   Geo g;

@@ -8,7 +8,9 @@
 // recomputes the keys from x (quantize at the block's code, dequantize),
 // histograms the next digit of the keys that match the digits chosen so far
 // (per-workgroup LDS histogram, then one global add per non-empty bin), and a
-// one-workgroup control kernel picks the bin holding the wanted rank.
+// one-workgroup control kernel picks the bin holding the wanted rank.  The
+// third pass also keeps the keys that match its 26-bit prefix (few, as a
+// rule): when they all fit, the last two passes select from them alone.
 #include "block.h"
 #include "kernels.h"
 
@@ -30,6 +32,24 @@ __global__ __launch_bounds__(256) void k_s2r(S2RArgs A) {
   const uint64_t prefix = st->s2r_prefix;
   const int shift = s2r_shift(level), width = s2r_width(level);
   const int code = st->code;
+  if (level >= 3) {
+    const uint64_t nc = *A.ncand;
+    if (nc <= A.cand_cap) {
+      // the kept keys hold every key the remaining digits can match;
+      // workgroups past the last one return before any barrier
+      if ((uint64_t)blockIdx.x * blockDim.x >= nc) return;
+      __syncthreads();
+      const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+      for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += stride) {
+        const uint64_t key = A.cand[i];
+        if ((key >> (shift + width)) == prefix) atomicAdd(&s_hist[(uint32_t)(key >> shift) & ((1u << width) - 1u)], 1u);
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < S2R_BINS; i += blockDim.x)
+        if (s_hist[i]) atomicAdd(&A.hist[i], s_hist[i]);
+      return;
+    }
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
@@ -49,14 +69,26 @@ __global__ __launch_bounds__(256) void k_s2r(S2RArgs A) {
     for (int k = 0; k < 4; k++) {
       bool match = false;
       uint32_t digit = 0;
+      uint64_t key = 0;
       if (b.act && b.valid(k)) {
         const double x = b.xd[k];
         const double y = A.rule == R_LOSSLESS ? (double)a[k] : (double)to_out<T>(dequant_rk(a[k], Rq, eq));
         const double d = x - y;
-        const uint64_t key = d == 0.0 ? 0x7FF0000000000000ull
-                                      : __builtin_bit_cast(uint64_t, __builtin_fabs(x) / __builtin_fabs(d));
+        key = d == 0.0 ? 0x7FF0000000000000ull
+                       : __builtin_bit_cast(uint64_t, __builtin_fabs(x) / __builtin_fabs(d));
         match = level == 0 || (key >> (shift + width)) == prefix;
         digit = (uint32_t)(key >> shift) & ((1u << width) - 1u);
+      }
+      if (level == 2) {  // keep the matching keys: one counter add per wave
+        const uint64_t bal = __ballot(match);
+        if (bal) {
+          const int lead = __builtin_ctzll(bal);
+          unsigned long long base = 0;
+          if (lane == lead) base = atomicAdd((unsigned long long*)A.ncand, (unsigned long long)__popcll(bal));
+          base = __shfl(base, lead, 64);
+          const uint64_t idx = base + (uint64_t)__popcll(bal & ((1ull << lane) - 1ull));
+          if (match && idx < A.cand_cap) A.cand[idx] = key;
+        }
       }
       // one LDS add per matching lane: the digits of neighbouring ratios
       // differ (the residual is noise-like), so grouping lanes by digit
@@ -108,11 +140,12 @@ __global__ __launch_bounds__(256) void k_s2r_ctl(PState* st, uint32_t* hist) {
   for (int i = 0; i < PER; i++) hist[t * PER + i] = 0;
 }
 
-__global__ void k_s2r_init(PState* st, uint32_t* hist, uint64_t rank) {
+__global__ void k_s2r_init(PState* st, uint32_t* hist, uint64_t* ncand, uint64_t rank) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->s2r_level = 0;
     st->s2r_prefix = 0;
     st->s2r_rank = rank;
+    *ncand = 0;
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < S2R_BINS; i += gridDim.x * blockDim.x) hist[i] = 0;
 }
@@ -142,7 +175,7 @@ hipError_t launch_s2r(int dtype, int ndim, S2RArgs& A, uint64_t rank, hipStream_
   const int64_t per = (int64_t)WPG * (64 / lpb);
   A.ntiles = (A.g.nblocks + per - 1) / per;
   A.nwg = A.ntiles < 2048 ? A.ntiles : 2048;
-  hipLaunchKernelGGL(k_s2r_init, dim3(8), dim3(256), 0, s, A.st, A.hist, rank);
+  hipLaunchKernelGGL(k_s2r_init, dim3(8), dim3(256), 0, s, A.st, A.hist, A.ncand, rank);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || A.ntiles == 0) return e;
   for (int level = 0; level < 5; level++) {

@@ -444,6 +444,12 @@ def test_s2r_margin_empty_and_exact(A):
     wl = A.workspace(xi.dtype, (3000,), pl, DEV)
     A.apax_profile(xi, pl, ws=wl)
     assert A.apax_s2r_margin(xi, pl, wl) == (math.inf, math.inf)
+    # 100 000 equal keys: more than the kept-key capacity of the workspace, so
+    # the last two digit passes read the whole array again
+    xb = torch.from_numpy(tiny(np.int16, (100000,), 4)).to(DEV)
+    wb = A.workspace(xb.dtype, (100000,), pl, DEV)
+    A.apax_profile(xb, pl, ws=wb)
+    assert A.apax_s2r_margin(xb, pl, wb) == (math.inf, math.inf)
 
 
 def _spectral_close(g, o):
