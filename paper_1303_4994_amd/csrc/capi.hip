@@ -772,19 +772,9 @@ static constexpr uint64_t SPEC_BYTES = SPEC_ENDS + 256;
 
 uint64_t apax_spectral_workspace_bytes(void) { return SPEC_BYTES; }
 
-// Upload the Hann window and the twiddles (host binary64 sin/cos) to d_ws.
+// The Hann window and the twiddles, written into d_ws on the stream.
 static int spectral_tables(uint8_t* w, hipStream_t stream) {
-  double table[1024 + 2 * 1024];
-  const double pi = 3.14159265358979323846;
-  for (int i = 0; i < 1024; i++) {
-    const double sn = sin(pi * i / 1024.0);
-    table[i] = sn * sn;
-    table[1024 + 2 * i] = cos(2.0 * pi * i / 1024.0);
-    table[1024 + 2 * i + 1] = -sin(2.0 * pi * i / 1024.0);
-  }
-  if (hipMemcpyAsync(w, table, sizeof(table), hipMemcpyHostToDevice, stream) != hipSuccess) return APAX_E_HIP;
-  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;  // the table is on this stack
-  return APAX_OK;
+  return hip_err(launch_psd_tables((double*)w, stream));
 }
 
 int apax_spectral_metrics(const void* d_x, const void* d_y, uint32_t dtype, uint64_t n, apax_spectral* out,

@@ -20,5 +20,7 @@ struct PsdArgs {
   int32_t pad;
 };
 hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s);
+// window (1024 doubles) then twiddles (1024 complex doubles) into t
+hipError_t launch_psd_tables(double* t, hipStream_t s);
 
 }  // namespace apax

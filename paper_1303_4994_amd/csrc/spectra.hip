@@ -173,6 +173,24 @@ __global__ __launch_bounds__(256) void k_psd_reduce(const double* partial, int n
   }
 }
 
+// The Hann window sin^2(pi i / 1024) and the twiddles e^(-2 pi i k / 1024),
+// binary64, with the argument reduction of sinpi/cospi (exact multiples of pi).
+__global__ __launch_bounds__(256) void k_psd_tables(double* t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= PSD_N) return;
+  const double sn = sinpi(i / (double)PSD_N);
+  t[i] = sn * sn;
+  double s2, c2;
+  sincospi(2.0 * i / (double)PSD_N, &s2, &c2);
+  t[PSD_N + 2 * i] = c2;
+  t[PSD_N + 2 * i + 1] = -s2;
+}
+
+hipError_t launch_psd_tables(double* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_psd_tables, dim3(PSD_N / 256), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+
 hipError_t launch_psd(int dtype, PsdArgs& A, hipStream_t s) {
   if (A.segments <= 0) return hipSuccess;
   if (A.nsig < 1 || A.nsig > 3) return hipErrorInvalidValue;
