@@ -182,8 +182,11 @@ int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_resul
  * With d = x - y, y the decoded array: the ceil(0.045 n)-th smallest of the
  * per-sample ratios |x| / |d| (binary64; d = 0 gives +inf) in *h_ratio, and
  * 20 log10 of it in *h_db (-inf for a zero ratio).  Exact (a digit-by-digit
- * selection on the ratio's bit pattern, five passes over d_x).  Synchronous;
- * NaN for an empty array. */
+ * selection on the ratio's bit pattern: three passes over d_x, then two over
+ * the ratios that share the first 26 bits of the answer, kept in d_ws's
+ * partial-record region, or two more passes over d_x when they do not fit).
+ * Uses the profile's partial records (spent by then; the profile result is
+ * kept).  Synchronous; NaN for an empty array. */
 int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,
                     uint64_t ws_bytes, hipStream_t stream);
 
