@@ -541,6 +541,26 @@ def test_signal_monitor(A, dt, n, b, noise):
         assert g["peak_bin"] == b
 
 
+def test_signal_monitor_every_bin(A):
+    """A tone at each of the 512 bins (one segment): the GPU's centre bin,
+    stride and sign equal the oracle's.  The gain agrees to 1e-4 dB up to
+    100 dB; beyond that the residual is at rounding level (the GPU forms it
+    from the lag sums, to about 2e-16 of the energy), so both report at least
+    100 dB."""
+    t = np.arange(1024)
+    ws = torch.empty(int(A.lib.apax_spectral_workspace_bytes()), dtype=torch.uint8, device=DEV)
+    for b in range(1, 513):
+        x = np.cos(2 * np.pi * b * t / 1024 + 0.3)
+        g = A.apax_signal_monitor(torch.from_numpy(x).to(DEV), ws=ws)
+        o = O.signal_monitor(x)
+        assert (g["peak_bin"], g["stride"], g["sign"]) == (o["peak_bin"], o["stride"], o["sign"]) == \
+            (b,) + O.monitor_stride(b), b
+        if o["gain_db"] <= 100.0:
+            assert abs(g["gain_db"] - o["gain_db"]) < 1e-4, (b, g["gain_db"], o["gain_db"])
+        else:
+            assert g["gain_db"] >= 100.0, (b, g["gain_db"], o["gain_db"])
+
+
 def test_signal_monitor_c1_and_edges(A):
     """The 16 MSample C1 field (fp32), a zero array and an empty one."""
     x = synth.grf2d(4096, 4096)
