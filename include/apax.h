@@ -276,6 +276,13 @@ int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* 
 /* Parse a 64-byte stream header (host memory) into parameters. */
 int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out);
 
+/* Length in bytes of the whole stream whose 64-byte header h_hdr holds (host
+ * memory, n >= 64 readable bytes): the header, the block-length index of the
+ * variable-size modes and the block area.  APAX_E_CORRUPT when the header is
+ * not a valid stream header or its payload size exceeds the largest encoding
+ * of its blocks (fixed rate: differs from nblocks * budget words). */
+int apax_stream_size(const void* h_hdr, uint64_t n, uint64_t* nbytes);
+
 /* Clear the workspace status word (enqueued on stream). */
 int apax_status_clear(void* d_ws, hipStream_t stream);
 
@@ -353,10 +360,17 @@ typedef struct apax_server apax_server;
 
 typedef struct apax_request {
   int32_t op;            /* APAX_OP_ENCODE / APAX_OP_DECODE */
-  uint32_t reserved;
+  uint32_t flags;        /* 0 or APAX_REQ_AFTER */
   apax_batch_item item;  /* as for a batch; a decode header is copied at submit */
   uint64_t tag;          /* caller's cookie, returned in the completion */
+  hipStream_t after;     /* with APAX_REQ_AFTER: the request's kernels start only
+                            after the work enqueued on this stream before the
+                            submit call (inputs, output fills) has finished */
 } apax_request;
+/* apax_request.flags: order the request after the submitter's stream (an event
+ * recorded on `after` at submit, waited on by the slot stream at launch).
+ * Without it the caller must have completed the inputs before submitting. */
+#define APAX_REQ_AFTER 1u
 
 typedef struct apax_completion {
   uint64_t id, tag;

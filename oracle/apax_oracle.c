@@ -94,10 +94,16 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   g->B = (int)B;
   g->G = (int)(B / 4);
   g->nblocks = 1;
+  int64_t ns = 1, nbytes_in;
   for (int i = 0; i < 3; i++) {
     g->nb[i] = (g->n[i] + g->b[i] - 1) / g->b[i];
-    g->nblocks *= g->nb[i];
+    /* counts that do not fit the index types are refused, not wrapped */
+    if (__builtin_mul_overflow(g->nblocks, g->nb[i], &g->nblocks)) return ORC_E_UNSUPPORTED;
+    if (__builtin_mul_overflow(ns, g->n[i], &ns)) return ORC_E_UNSUPPORTED;
   }
+  if (__builtin_mul_overflow(ns, (int64_t)g->esz, &nbytes_in) || nbytes_in > ((int64_t)1 << 56))
+    return ORC_E_UNSUPPORTED;
+  if (g->nblocks > (int64_t)0x7FFFFFFF) return ORC_E_UNSUPPORTED;
   uint32_t allowed = ALLOWED[g->ndim];
   uint32_t m = p->stream_mask ? p->stream_mask : allowed;
   if (m & ~allowed) return ORC_E_INVALID;

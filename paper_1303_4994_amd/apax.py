@@ -75,8 +75,12 @@ class BatchItem(C.Structure):
                 ("h_hdr", C.c_void_p)]
 
 
+REQ_AFTER = 1
+
+
 class Request(C.Structure):
-    _fields_ = [("op", C.c_int32), ("reserved", C.c_uint32), ("item", BatchItem), ("tag", C.c_uint64)]
+    _fields_ = [("op", C.c_int32), ("flags", C.c_uint32), ("item", BatchItem), ("tag", C.c_uint64),
+                ("after", C.c_void_p)]
 
 
 class Completion(C.Structure):
@@ -127,6 +131,7 @@ def _load():
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
     L.apax_decode.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp]
     L.apax_stream_info.argtypes = [vp, u64, P(Params)]
+    L.apax_stream_size.argtypes = [vp, u64, P(u64)]
     L.apax_status_clear.argtypes = [vp, vp]
     L.apax_status.argtypes = [vp, vp]
     L.apax_batch_create.argtypes = [C.c_int, P(BatchItem), C.c_uint32, P(Tune), P(vp), P(u64)]
@@ -420,15 +425,11 @@ def apax_stream_info(hdr: bytes) -> dict:
 
 
 def stream_nbytes(hdr: bytes) -> int:
-    info = apax_stream_info(hdr)
-    payload_words = struct.unpack_from("<Q", hdr, 56)[0]
-    nb = struct.unpack_from("<Q", hdr, 48)[0]
-    if info["mode"] == "fixed_rate":
-        area = 64
-    else:
-        o = 64 + (2 * nb + 7) // 8 * 8 + 8 * ((nb + 63) // 64)
-        area = (o + 15) // 16 * 16
-    return area + 4 * payload_words
+    """Whole stream length from its 64-byte header (apax_stream_size)."""
+    b = (C.c_uint8 * 64).from_buffer_copy(bytes(hdr[:64]))
+    n = C.c_uint64(0)
+    _check(lib.apax_stream_size(C.cast(b, C.c_void_p), 64, C.byref(n)), "apax_stream_size")
+    return int(n.value)
 
 
 def apax_decode(stream_buf: torch.Tensor, nbytes: int | None = None, hdr: bytes | None = None,

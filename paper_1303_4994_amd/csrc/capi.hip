@@ -92,16 +92,23 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   g.G = (int32_t)(B / 4);
   g.rowq = g.b[2] / 4;
   g.plane = g.b[1] * g.rowq;
+  // block counts and sample counts must not wrap: the kernels index blocks
+  // with 31 bits and samples with 64-bit offsets in bytes
   int64_t nb[3];
   g.nblocks = 1;
+  int64_t ns = 1;
   for (int i = 0; i < 3; i++) {
     nb[i] = (n[i] + b[i] - 1) / b[i];
-    g.nblocks *= nb[i];
+    if (__builtin_mul_overflow(g.nblocks, nb[i], &g.nblocks)) return APAX_E_UNSUPPORTED;
+    if (__builtin_mul_overflow(ns, n[i], &ns)) return APAX_E_UNSUPPORTED;
   }
+  int64_t nbytes_in;
+  if (__builtin_mul_overflow(ns, (int64_t)h.esz, &nbytes_in) || nbytes_in > ((int64_t)1 << 56))
+    return APAX_E_UNSUPPORTED;
   g.nbx = nb[2] ? nb[2] : 1;
   g.nby = nb[1] ? nb[1] : 1;
   if (g.nblocks > (int64_t)0x7FFFFFFF) return APAX_E_UNSUPPORTED;
-  h.nsamples = (uint64_t)(n[0] * n[1] * n[2]);
+  h.nsamples = (uint64_t)ns;
   uint32_t allowed = ND_ALLOWED[h.ndim];
   uint32_t m = p->stream_mask ? p->stream_mask : allowed;
   if (m & ~allowed) return APAX_E_INVALID;
@@ -359,6 +366,23 @@ int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
     p.rate = (double)B * 8.0 * h.esz / (32.0 * (double)budget);
   }
   *out = p;
+  return APAX_OK;
+}
+
+int apax_stream_size(const void* h_hdr, uint64_t n, uint64_t* nbytes) {
+  if (!nbytes) return APAX_E_INVALID;
+  apax_params p;
+  const int e = apax_stream_info(h_hdr, n, &p);
+  if (e) return e;
+  HG h;
+  if (setup(&p, h, p.mode == APAX_FIXED_RATE ? (int)(((const uint16_t*)h_hdr)[5]) : -1) != APAX_OK)
+    return APAX_E_CORRUPT;
+  uint64_t words;
+  memcpy(&words, (const uint8_t*)h_hdr + 56, 8);
+  const uint64_t per = h.g.budget ? (uint64_t)h.g.budget : (uint64_t)h.g.maxw;
+  if (words > per * (uint64_t)h.g.nblocks) return APAX_E_CORRUPT;
+  if (h.mode == APAX_FIXED_RATE && words != per * (uint64_t)h.g.nblocks) return APAX_E_CORRUPT;
+  *nbytes = area_offset(h) + 4 * words;
   return APAX_OK;
 }
 
@@ -911,15 +935,17 @@ int apax_signal_monitor(const void* d_x, uint32_t dtype, uint64_t n, apax_monito
   const int sg = (m <= 256 || m >= 768) ? 1 : -1;
   out->stride = k;
   out->sign = sg;
-  // sum_{i >= k} x_i^2 = R0 - head, sum_{i < n - k} x_i^2 = R0 - tail
-  double head = 0.0, tail = 0.0;
-  for (int j = 0; j < k; j++) {
-    head += ends[j] * ends[j];
-    tail += ends[2 * ACF_LAGS - 1 - j] * ends[2 * ACF_LAGS - 1 - j];
-  }
+  // energy in: sum_{i >= k} x_i^2 = R0 - head; energy out: the filtered
+  // samples' squares summed directly on the device
+  double head = 0.0;
+  for (int j = 0; j < k; j++) head += ends[j] * ends[j];
   const double e_in = R[0] - head;
-  double e_out = e_in + (R[0] - tail) - 2.0 * sg * R[k];
-  if (e_out < 0.0) e_out = 0.0;
+  double* d_eout = C.out + (ACF_LAGS + 1);
+  e = hip_err(launch_resid((int)dtype, d_x, (int64_t)n, k, sg, C.partial, d_eout, stream));
+  if (e) return e;
+  double e_out = 0.0;
+  if (hipMemcpyAsync(&e_out, d_eout, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess) return APAX_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return APAX_E_HIP;
   out->gain_db = db(e_in) - db(e_out);
   return APAX_OK;
 }
@@ -1247,6 +1273,7 @@ double now_s() {
 struct SrvReq {
   uint64_t id = 0;
   apax_request r{};
+  hipEvent_t ready = nullptr;  // recorded on the submitter's stream (APAX_REQ_AFTER)
   uint8_t hdr[64];
   uint64_t footprint = 0;
   double t_submit = 0.0;
@@ -1288,6 +1315,7 @@ struct apax_server {
   std::deque<SrvReq> queue;
   std::vector<SrvSlot> slots;
   std::deque<apax_completion> ready;
+  std::vector<hipEvent_t> events;  // free submit events (APAX_REQ_AFTER)
   uint64_t groups = 0;
 };
 
@@ -1309,6 +1337,9 @@ void server_free(apax_server* s) {
     if (sl.done) hipEventDestroy(sl.done);
     if (sl.stream) hipStreamDestroy(sl.stream);
   }
+  for (auto& q : s->queue)
+    if (q.ready) hipEventDestroy(q.ready);
+  for (hipEvent_t ev : s->events) hipEventDestroy(ev);
   delete s;
 }
 
@@ -1322,6 +1353,9 @@ uint64_t solo_ws(const SrvReq& q) {
 }
 
 int server_launch(apax_server* s, SrvSlot& sl) {
+  // the group starts after every submitter's stream point it was ordered after
+  for (const SrvReq& q : sl.reqs)
+    if (q.ready && hipStreamWaitEvent(sl.stream, q.ready, 0) != hipSuccess) return APAX_E_HIP;
   std::vector<apax_batch_item> items[2];
   for (int k = 0; k < 2; k++) sl.which[k].clear();
   sl.solo.clear();
@@ -1431,6 +1465,7 @@ int apax_server_create(uint64_t budget_bytes, uint32_t n_slots, uint32_t max_gro
 
 int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   if (!s || !q || !id || (q->op != APAX_OP_ENCODE && q->op != APAX_OP_DECODE)) return APAX_E_INVALID;
+  if (q->flags & ~APAX_REQ_AFTER) return APAX_E_INVALID;
   SrvReq r;
   r.r = *q;
   HG h;
@@ -1451,6 +1486,16 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   }
   r.footprint = req_footprint(*q, h);
   if (r.footprint > s->budget) return APAX_E_CAPACITY;
+  if (q->flags & APAX_REQ_AFTER) {
+    if (s->events.empty()) {
+      hipEvent_t ev;
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return APAX_E_HIP;
+      s->events.push_back(ev);
+    }
+    r.ready = s->events.back();
+    if (hipEventRecord(r.ready, q->after) != hipSuccess) return APAX_E_HIP;
+    s->events.pop_back();
+  }
   r.id = s->next_id++;
   r.t_submit = now_s();
   *id = r.id;
@@ -1494,6 +1539,8 @@ int apax_server_poll(apax_server* s, apax_completion* done, uint32_t max_done, u
       if (sl.plan[p]) { apax_batch_destroy(sl.plan[p]); sl.plan[p] = nullptr; }
       sl.which[p].clear();
     }
+    for (auto& r : sl.reqs)
+      if (r.ready) s->events.push_back(r.ready);
     sl.reqs.clear();
     sl.busy = false;
   }
@@ -1518,6 +1565,8 @@ int apax_server_poll(apax_server* s, apax_completion* done, uint32_t max_done, u
       }
       for (int p = 0; p < 2; p++)
         if (sl.plan[p]) { apax_batch_destroy(sl.plan[p]); sl.plan[p] = nullptr; }
+      for (auto& r : sl.reqs)
+        if (r.ready) s->events.push_back(r.ready);
       sl.reqs.clear();
       sl.busy = false;
     }

@@ -160,14 +160,19 @@ __device__ __forceinline__ void decode_tile(const DecArgs& A, const int64_t tile
       for (int64_t r = jb + gi; r < j; r += LPB) acc += A.lens[r];
     acc = seg_sum<LPB>(acc);
     if (blk_ok) {
-      off = A.sbo[j >> 6] + (uint64_t)acc;
+      const uint64_t sb = A.sbo[j >> 6];
+      // a superblock offset past the payload is corrupt (checked before the
+      // addition, which could otherwise wrap)
+      if (sb > A.payload_words) bad = true;
+      off = sb > A.payload_words ? A.payload_words : sb + (uint64_t)acc;
       len = A.lens[j];
     }
   } else if (blk_ok) {
     off = (uint64_t)j * (uint64_t)g.budget;
     len = g.budget;
   }
-  if (blk_ok && (len < 1 || (variable && len > g.maxw) || off + (uint64_t)len > A.payload_words)) {
+  if (blk_ok && (bad || len < 1 || (variable && len > g.maxw) || off > A.payload_words ||
+                 (uint64_t)len > A.payload_words - off)) {
     bad = true;
     len = 0;
   }

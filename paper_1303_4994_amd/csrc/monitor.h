@@ -17,5 +17,8 @@ struct AcfArgs {
   double* ends;     // [32]: x[0..15] and x[n - 16..n - 1] (n >= 32; zeros otherwise)
 };
 hipError_t launch_acf(int dtype, AcfArgs& A, hipStream_t s);
+// *out = sum_{n >= k} (x[n] - sg x[n - k])^2 (partial: AcfArgs::partial's region)
+hipError_t launch_resid(int dtype, const void* x, int64_t n, int k, int sg, double* partial, double* out,
+                        hipStream_t s);
 
 }  // namespace apax

@@ -109,6 +109,50 @@ __global__ __launch_bounds__(256) void k_acf_reduce(const double* partial, int n
   if (t == 0) out[k] = s[0];
 }
 
+// Residual energy of the stride filter the monitor selected: sum over
+// n >= k of (x[n] - sg x[n - k])^2, binary64, summed directly (a difference
+// of lag sums would cancel when the filter removes most of the energy).
+// Grid-stride per lane, then one partial per workgroup (slot 0 of the lag
+// sums' record layout, so k_acf_reduce sums them).
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid(const T* __restrict__ x, int64_t n, int k, double sg,
+                                               double* partial) {
+  __shared__ double s[256];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + t + k; i < n; i += (int64_t)gridDim.x * 256) {
+    const double d = (double)x[i] - sg * (double)x[i - k];
+    acc += d * d;
+  }
+  s[t] = acc;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (t < h) s[t] += s[t + h];
+    __syncthreads();
+  }
+  if (t == 0) partial[(int64_t)blockIdx.x * (ACF_LAGS + 1)] = s[0];
+}
+
+hipError_t launch_resid(int dtype, const void* x, int64_t n, int k, int sg, double* partial, double* out,
+                        hipStream_t s) {
+  if (n <= k) return hipSuccess;
+  int64_t nwg = (n + ACF_TILE - 1) / ACF_TILE;
+  if (nwg > ACF_MAX_WGS) nwg = ACF_MAX_WGS;
+  const dim3 grid((unsigned)nwg), block(256);
+  const double sd = (double)sg;
+  switch (dtype) {
+    case DT_I8: hipLaunchKernelGGL(k_resid<int8_t>, grid, block, 0, s, (const int8_t*)x, n, k, sd, partial); break;
+    case DT_I16: hipLaunchKernelGGL(k_resid<int16_t>, grid, block, 0, s, (const int16_t*)x, n, k, sd, partial); break;
+    case DT_I32: hipLaunchKernelGGL(k_resid<int32_t>, grid, block, 0, s, (const int32_t*)x, n, k, sd, partial); break;
+    case DT_F32: hipLaunchKernelGGL(k_resid<float>, grid, block, 0, s, (const float*)x, n, k, sd, partial); break;
+    default: hipLaunchKernelGGL(k_resid<double>, grid, block, 0, s, (const double*)x, n, k, sd, partial); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_acf_reduce, dim3(1), dim3(256), 0, s, (const double*)partial, (int)nwg, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_acf(int dtype, AcfArgs& A, hipStream_t s) {
   if (A.n <= 0) return hipSuccess;
   int64_t nwg = (A.n + ACF_TILE - 1) / ACF_TILE;

@@ -5,8 +5,9 @@ The loop itself (FIFO, admission by HBM budget, slots with resident codec
 state, persistent batch launches per admitted group, event-polled
 completions, latency stamps) runs in libapax.so.  This module keeps the
 tensors of in-flight requests alive and turns completions into dicts.
-Inputs must already be complete on the device when a request is submitted:
-the server's streams do not wait on the submitting stream.
+Each request is ordered after the work enqueued on torch's current stream
+before it was submitted (APAX_REQ_AFTER): the server's slot streams wait on
+an event recorded there at submit.
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ class Server:
 
     # -- submission
     def submit(self, req: A.Request, keep) -> int:
+        req.flags |= A.REQ_AFTER
+        req.after = torch.cuda.current_stream(self.device).cuda_stream
         rid = C.c_uint64()
         A._check(A.lib.apax_server_submit(self.handle, C.byref(req), C.byref(rid)), "apax_server_submit")
         self._live[rid.value] = keep

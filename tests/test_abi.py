@@ -48,6 +48,10 @@ VALIDATION = [
     (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x10}),
     (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x28}),
     (np.int8, (8, 64), {"mode": "lossless", "brick": (32, 2)}),
+    # block and sample counts that would wrap 64-bit products are refused
+    (np.float32, (1099509530628, 67108992, 16), {"mode": "fixed_quality", "brick": (2, 2, 16), "code": 0}),
+    (np.int16, (1 << 40, 1 << 40, 1 << 40), {"mode": "lossless", "brick": (1, 1, 64)}),
+    (np.int16, (1 << 30, 1 << 30), {"mode": "lossless", "brick": (1, 64)}),
 ]
 
 
@@ -84,3 +88,35 @@ def test_stream_info_parses_oracle_streams(A):
     bad[0] ^= 1
     with pytest.raises(A.ApaxError):
         A.apax_stream_info(bytes(bad))
+
+
+def test_stream_header_with_wrapping_counts_is_corrupt(A):
+    """A 64-byte header whose dims make the block count wrap in 64 bits (to a
+    small number that it then also claims) is refused by the host, before any
+    kernel could index past the buffers."""
+    import struct
+    x = np.zeros((4, 4, 32), np.float32)
+    s = bytearray(O.encode(x, {"mode": "fixed_quality", "brick": (2, 2, 16), "code": 0})[:64])
+    struct.pack_into("<QQQ", s, 16, 1099509530628, 67108992, 16)
+    struct.pack_into("<Q", s, 48, 128)          # the wrapped block count
+    with pytest.raises(A.ApaxError) as ei:
+        A.apax_stream_info(bytes(s))
+    assert ei.value.code == A.E_CORRUPT
+    with pytest.raises(A.ApaxError) as ei:
+        A.stream_nbytes(bytes(s))
+    assert ei.value.code == A.E_CORRUPT
+
+
+def test_stream_size_rejects_oversized_payload(A):
+    """apax_stream_size: the payload-word field may not exceed the largest
+    encoding of the blocks (and must equal nblocks * budget in fixed rate)."""
+    import struct
+    x = (np.arange(5000) % 77).astype(np.int16)
+    for params in ({"mode": "lossless", "brick": (64,)},
+                   {"mode": "fixed_rate", "brick": (64,), "rate": 2.0, "code": 0}):
+        s = bytearray(O.encode(x, params)[:64])
+        assert A.stream_nbytes(bytes(s)) == len(O.encode(x, params))
+        struct.pack_into("<Q", s, 56, 1 << 60)
+        with pytest.raises(A.ApaxError) as ei:
+            A.stream_nbytes(bytes(s))
+        assert ei.value.code == A.E_CORRUPT

@@ -543,10 +543,10 @@ def test_signal_monitor(A, dt, n, b, noise):
 
 def test_signal_monitor_every_bin(A):
     """A tone at each of the 512 bins (one segment): the GPU's centre bin,
-    stride and sign equal the oracle's.  The gain agrees to 1e-4 dB up to
-    100 dB; beyond that the residual is at rounding level (the GPU forms it
-    from the lag sums, to about 2e-16 of the energy), so both report at least
-    100 dB."""
+    stride and sign equal the oracle's, and the filter gain agrees to 1e-9
+    relative at every bin, including the bins where the filter cancels the
+    tone to rounding level (both sides sum the filtered samples' squares
+    directly; only the order of the additions differs)."""
     t = np.arange(1024)
     ws = torch.empty(int(A.lib.apax_spectral_workspace_bytes()), dtype=torch.uint8, device=DEV)
     for b in range(1, 513):
@@ -555,10 +555,11 @@ def test_signal_monitor_every_bin(A):
         o = O.signal_monitor(x)
         assert (g["peak_bin"], g["stride"], g["sign"]) == (o["peak_bin"], o["stride"], o["sign"]) == \
             (b,) + O.monitor_stride(b), b
-        if o["gain_db"] <= 100.0:
-            assert abs(g["gain_db"] - o["gain_db"]) < 1e-4, (b, g["gain_db"], o["gain_db"])
+        gv, v = g["gain_db"], o["gain_db"]
+        if math.isinf(v):
+            assert gv == v, (b, gv, v)
         else:
-            assert g["gain_db"] >= 100.0, (b, g["gain_db"], o["gain_db"])
+            assert abs(gv - v) <= 1e-9 * max(1.0, abs(v)), (b, gv, v)
 
 
 def test_signal_monitor_c1_and_edges(A):

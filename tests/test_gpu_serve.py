@@ -1,11 +1,13 @@
 """Serving loop (continuous batching over slots with resident codec state):
-every served result equals the same request run alone, whatever group and
-slot it landed in; admission never exceeds the HBM budget; per-request
-status; requests above the budget are refused at submit."""
+every served result equals the CPU oracle's and the same request run alone,
+whatever group and slot it landed in; admission never exceeds the HBM
+budget; per-request status; requests above the budget are refused at
+submit."""
 import numpy as np
 import pytest
 
 import synth
+from oracle import oracle as O
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -43,10 +45,13 @@ def make_requests(A, n=96, seed=4242):
         buf, nb = A.apax_encode(x, params)            # the standalone result
         n_ = int(nb.item())
         r["ref_stream"] = buf[:n_].cpu().numpy()
+        # the oracle's stream and decode of the same bytes
+        r["orc_stream"] = O.encode(x.cpu().numpy(), params)
         if kind == "decode":
             r["stream"], r["nbytes"] = buf, n_
             r["hdr"] = bytes(r["ref_stream"][:64])
             r["ref_y"] = A.apax_decode(buf, n_).cpu().numpy()
+            r["orc_y"] = O.decode(r["orc_stream"])
         reqs.append(r)
     torch.cuda.synchronize()
     return reqs
@@ -88,10 +93,13 @@ def test_served_results_equal_standalone(A, S):
         if r["kind"] == "encode":
             out, nb = outs[k]
             n_ = int(nb.item())
-            assert np.array_equal(out[:n_].cpu().numpy(), r["ref_stream"]), k
+            got = out[:n_].cpu().numpy()
+            assert np.array_equal(got, r["orc_stream"]), ("served != oracle", k)
+            assert np.array_equal(got, r["ref_stream"]), ("served != alone", k)
         else:
             got = outs[k].cpu().numpy()
-            assert np.array_equal(got.view(np.uint8), r["ref_y"].view(np.uint8)), k
+            assert np.array_equal(got.view(np.uint8), r["orc_y"].view(np.uint8)), ("served != oracle", k)
+            assert np.array_equal(got.view(np.uint8), r["ref_y"].view(np.uint8)), ("served != alone", k)
     srv.close()
 
 
@@ -175,4 +183,6 @@ def test_large_requests_run_alone_with_their_status(A, S):
         if not nonfinite:
             n_ = int(nb.item())
             assert n_ == refs[k].numel() and torch.equal(o[:n_], refs[k]), k
+            if k < 4:  # the first large ones (16-40 MB) also against the oracle
+                assert np.array_equal(o[:n_].cpu().numpy(), O.encode(x.cpu().numpy(), p)), k
     srv.close()

@@ -835,3 +835,169 @@ def test_monitor_white_noise_and_edges():
     assert short["segments"] == 0 and short["acf"][0] == 1.0
     zero = O.signal_monitor(np.zeros(4096))
     assert not zero["acf"].any() and zero["peak_bin"] == 1 and math.isnan(zero["snr_db"])
+
+
+# ---------------------------------------------------------------- profile outputs: curve, mask, tie, stats
+
+def _curve_point_bruteforce(x, params, ct, mask):
+    """(ratio, r) of Window 1's curve point at code ct: every (subsample)
+    block at clamp(ct) to its own bracket, coded with the cheapest allowed
+    stream (verbatim allowed), whole 32-bit words per block; r by fsum."""
+    isint = x.dtype.kind == "i"
+    W, H = (32, 48) if not isint else (8 * x.dtype.itemsize, 32)
+    in_bits = out_bits = 0
+    for j, blk, val in _blocks_of(x, params["brick"]):
+        M = float(np.abs(blk.astype(np.float64))[val].max()) if val.any() else 0.0
+        cf, cc = _py_bracket(M, isint)
+        cj = min(max(ct, cf), cc)
+        a = np.where(val, _quantized_block(blk, cj, isint, False), 0)
+        bits = min(brute.size_model(a, s_, W, H, val) for s_ in range(8) if (mask | 0x81) >> s_ & 1)
+        in_bits += int(val.sum()) * 8 * x.dtype.itemsize
+        out_bits += 32 * ((bits + 31) // 32)
+    return in_bits / out_bits, _py_r(x, params, ct)
+
+
+@pytest.mark.parametrize("dt,shape,params", [
+    (np.float32, (24, 32), {"mode": "fixed_quality", "brick": (8, 8), "target_corr": 0.9999}),
+    (np.float32, (640,), {"mode": "fixed_rate", "brick": (64,), "rate": 4.0}),
+])
+def test_profile_curve_ratio_and_r_bruteforce(dt, shape, params):
+    """Every point of the rate-correlation curve (Window 1): its ratio from
+    an independent size model and its r from exactly rounded sums, at each of
+    the 17 quarter-octave codes around the recommended one."""
+    x = _tiny_input(dt, shape, 31)
+    r = O.profile_dict(O.profile(x, params))
+    codes = [min(max(r["code"] + 4 * (t - 8), -17120), 16383) for t in range(17)]
+    assert [c for c, _, _ in r["curve"]] == codes
+    for c, ratio, rr in r["curve"]:
+        er, err = _curve_point_bruteforce(x, params, c, r["stream_mask"])
+        assert ratio == er, (c, ratio, er)
+        assert abs(rr - err) <= 1e-13, (c, rr, err)
+
+
+def test_profile_mask_threshold_is_one_percent_rounded_up():
+    """Stream mask = {0, 7} and the streams that at least ceil(n_sub / 100)
+    subsample blocks choose: 250 blocks (all in the subsample) need 3; three
+    ramp blocks (stream 2) get in, two constant blocks (stream 1) do not."""
+    B = 64
+    blocks = [np.zeros(B, np.int64) for _ in range(250)]
+    n = np.arange(B)
+    for k in (10, 90, 170):
+        blocks[k] = 5 + 300 * n                     # a ramp: only the second difference vanishes
+    for k in (40, 200):
+        blocks[k] = np.full(B, 9000)                # a constant: the first difference vanishes
+    x = np.concatenate(blocks).astype(np.int16)
+    params = {"mode": "lossless", "brick": (B,)}
+    # each block's cheapest stream, by the independent size model
+    chosen = []
+    for blk in blocks:
+        sizes = {s_: brute.size_model(blk.reshape(1, 1, B), s_, 16, 32) for s_ in (0, 1, 2, 7)}
+        best = min(sizes.values())
+        chosen.append(min(s_ for s_, v in sizes.items() if v == best))
+    assert chosen.count(2) == 3 and chosen.count(1) == 2 and chosen.count(0) == 245
+    r = O.profile_dict(O.profile(x, params))
+    assert r["n_sub"] == 250
+    assert r["stream_mask"] == 0x85, hex(r["stream_mask"])
+    # one more constant block makes stream 1 reach the threshold
+    blocks[120] = np.full(B, -700)
+    r = O.profile_dict(O.profile(np.concatenate(blocks).astype(np.int16), params))
+    assert r["stream_mask"] == 0x87, hex(r["stream_mask"])
+
+
+def _fq_probes(x, params, target):
+    """The fixed-quality bisection replayed on exactly rounded r: every
+    probe's (code, r) and the resulting code."""
+    cf, cc = _py_bracket(float(np.abs(x).max()), False)
+    probes = [(cc, _py_r(x, params, cc))]
+    if probes[0][1] < target:
+        return probes, cc
+    lo, hi = cf, cc
+    while hi - lo > 1:
+        mid = lo + ((hi - lo) >> 1)
+        r = _py_r(x, params, mid)
+        probes.append((mid, r))
+        if r >= target:
+            hi = mid
+        else:
+            lo = mid
+    return probes, hi
+
+
+def test_profile_near_tie_flag():
+    """NEAR_TIE is set exactly when some bisection probe's r lies within
+    1e-11 of the target: targets placed 0.9e-11 and 1.1e-11 from the r of
+    the first inner probe, on both sides, each checked against a replay of
+    every probe."""
+    x = _tiny_input(np.float32, (24, 32), 21)
+    params = {"mode": "fixed_quality", "brick": (8, 8)}
+    cf, cc = _py_bracket(float(np.abs(x).max()), False)
+    r_mid = _py_r(x, params, cf + ((cc - cf) >> 1))
+    seen = set()
+    for off in (-1.1e-11, -0.9e-11, 0.9e-11, 1.1e-11, -3e-9):
+        t = r_mid + off
+        probes, code = _fq_probes(x, params, t)
+        dist = min(abs(r - t) for _, r in probes)
+        assert abs(dist - 1e-11) > 5e-14            # no probe sits on the threshold itself
+        expect = dist < 1e-11
+        got = O.profile_dict(O.profile(x, dict(params, target_corr=t)))
+        assert bool(got["flags"] & O.NEAR_TIE) == expect, (off, dist, probes)
+        assert got["code"] == code and got["n_probes"] == len(probes)
+        seen.add(expect)
+    assert seen == {True, False}
+
+
+@pytest.mark.parametrize("dt,shape,params", [
+    (np.float32, (24, 32), {"mode": "fixed_quality", "brick": (8, 8), "target_corr": 0.9999}),
+    (np.float64, (6, 8, 16), {"mode": "fixed_quality", "brick": (2, 4, 8), "target_corr": 0.99999}),
+    (np.float32, (640,), {"mode": "fixed_rate", "brick": (64,), "rate": 4.0}),
+    (np.int16, (3000,), {"mode": "fixed_rate", "brick": (64,), "rate": 3.0}),
+])
+def test_profile_means_stds_maxd_against_decoded_array(dt, shape, params):
+    """The profile's own metrics pass (means, population standard deviations
+    by two passes, max |d|) equals numpy and exactly rounded sums over the
+    array the oracle decodes at the recommended point."""
+    x = _tiny_input(dt, shape, 41)
+    r = O.profile_dict(O.profile(x, params))
+    enc = dict(params, code=r["code"], stream_mask=r["stream_mask"] & (0x7F if params["mode"] == "fixed_rate" else 0xFF))
+    y = O.decode(O.encode(x, enc)).astype(np.float64)
+    xv = x.astype(np.float64).ravel()
+    yv = y.ravel()
+    d = xv - yv
+    m = r["metrics"]
+    nn = xv.size
+    for name, v in (("x", xv), ("y", yv), ("d", d)):
+        mean = math.fsum(v) / nn
+        std = math.sqrt(math.fsum((v - mean) ** 2) / nn)
+        assert abs(m[f"mean_{name}"] - mean) <= 1e-13 * max(1.0, abs(mean)), (name, m[f"mean_{name}"], mean)
+        assert abs(m[f"std_{name}"] - std) <= 1e-12 * max(1e-300, std), (name, m[f"std_{name}"], std)
+    assert m["max_abs_d"] == float(np.abs(d).max())
+
+
+def test_spectral_floor_is_the_256th_smallest_bin():
+    """Tones at bins 1..511 with seeded amplitudes and phases over exactly one
+    segment.  The periodic Hann window sin^2(pi n / N) = 1/2 - cos(2 pi n / N) / 2
+    turns each bin's DFT X[k] = (N / 2) A_k e^{i phi_k} into
+    X[k] / 2 - X[k - 1] / 4 - X[k + 1] / 4, so the whole spectrum is known in
+    closed form: the floor is its 256th smallest bin (its neighbours in rank
+    differ from it), the peak its largest."""
+    N = 1024
+    rng = np.random.default_rng(77)
+    A = rng.uniform(0.1, 2.0, 513)
+    ph = rng.uniform(0, 2 * np.pi, 513)
+    A[0] = A[512] = 0.0
+    t = np.arange(N)
+    x = np.zeros(N)
+    for b in range(1, 512):
+        x += A[b] * np.cos(2 * np.pi * b * t / N + ph[b])
+    X = np.zeros(515, complex)
+    X[1:514] = (N / 2) * A * np.exp(1j * ph)     # X[1 + k] holds bin k, zero padding either side
+    P = np.abs(X[1:514] / 2 - X[0:513] / 4 - X[2:515] / 4) ** 2
+    # Nyquist: its upper neighbour is bin 513 = the conjugate of bin 511
+    P[512] = abs(-(X[512] + np.conj(X[512])) / 4) ** 2
+    levels = np.sort(P[1:513])
+    assert levels[254] < levels[255] < levels[256]
+    s = O.spectral_metrics(x, np.zeros_like(x))
+    assert abs(s["floor_x"] - 10 * math.log10(levels[255])) < 1e-9
+    assert abs(s["peak_x"] - 10 * math.log10(levels[-1])) < 1e-9
+    mon = O.signal_monitor(x)
+    assert abs(mon["floor_db"] - 10 * math.log10(levels[255])) < 1e-9
