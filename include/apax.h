@@ -265,6 +265,29 @@ int apax_profile_read(const apax_params* p, apax_profile_result* h_out, const vo
 int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
                 uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* Scratch bytes the library holds on each GPU for apax_encode_noalloc. */
+#define APAX_NOALLOC_SCRATCH_BYTES (8ull << 20)
+
+/* apax_encode for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same stream bytes and byte count as apax_encode with the same arguments,
+ * but no workspace argument.  Its scratch (status word, work-queue ticket,
+ * one 8-byte look-back state per tile of 4 waves, one int32 per block with
+ * APAX_FLAG_LAGGED) lives in a library-owned device array of
+ * APAX_NOALLOC_SCRATCH_BYTES (8 MiB) per GPU, which the GPU holds until the
+ * process ends; the call itself allocates nothing (no hipMalloc, no library
+ * allocation).  An array whose scratch would exceed 8 MiB returns
+ * APAX_E_CAPACITY before anything is enqueued (about 4 million blocks
+ * without the lagged choice, 1.4 million with it).  APAX_CODE_PROFILED is not
+ * accepted (APAX_E_INVALID): no profile writes that scratch.
+ * d_status (device int32, may be NULL) receives APAX_OK, APAX_E_NONFINITE or
+ * APAX_E_INTERNAL once the encode has run.  Every call on one GPU shares its
+ * scratch and keeps the last call's contents: calls that overlap in time on
+ * one GPU (two host threads, or two streams) race and give undefined streams.
+ * Asynchronous, enqueued on `stream` on the current device. */
+int apax_encode_noalloc(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
+                        uint64_t* d_nbytes, int32_t* d_status, hipStream_t stream);
+
 /* Decoder.  h_hdr: host copy of the first 64 bytes of the stream (the
  * parameters are taken from it; apax_stream_info parses it); d_stream: the
  * whole stream on the device, nbytes long; d_y: output array (cap bytes).

@@ -129,6 +129,7 @@ def _load():
     L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
+    L.apax_encode_noalloc.argtypes = [vp, P(Params), vp, u64, vp, vp, vp]
     L.apax_decode.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp]
     L.apax_stream_info.argtypes = [vp, u64, P(Params)]
     L.apax_stream_size.argtypes = [vp, u64, P(u64)]
@@ -411,6 +412,21 @@ def apax_encode(x: torch.Tensor, params: dict, out: torch.Tensor | None = None,
         _check(lib.apax_status_clear(_dev_ptr(ws), sp), "apax_status_clear")
     _check(lib.apax_encode(_dev_ptr(x), C.byref(p), _dev_ptr(out), out.numel(),
                            _dev_ptr(nbytes), _dev_ptr(ws), ws.numel(), sp), "apax_encode")
+    return out, nbytes
+
+
+def apax_encode_noalloc(x: torch.Tensor, params: dict, out: torch.Tensor, nbytes: torch.Tensor,
+                        status: torch.Tensor | None = None, stream=None):
+    """Encode x into the caller's buffers with the library's own scratch
+    (no workspace, nothing allocated by the call).  out: uint8 stream buffer
+    of at least apax_encode_bound bytes; nbytes: device int64[1]; status:
+    device int32[1] or None, set to 0 or an APAX_E_* code on the device."""
+    assert x.is_cuda and x.is_contiguous() and out.dtype == torch.uint8
+    p = make_params(x.dtype, tuple(x.shape), params)
+    sp = _stream_ptr(stream)
+    st = _dev_ptr(status) if status is not None else None
+    _check(lib.apax_encode_noalloc(_dev_ptr(x), C.byref(p), _dev_ptr(out), out.numel(),
+                                   _dev_ptr(nbytes), st, sp), "apax_encode_noalloc")
     return out, nbytes
 
 

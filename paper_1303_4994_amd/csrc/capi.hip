@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
+#include <mutex>
 #include <vector>
 
 #include "apax.h"
@@ -404,23 +405,22 @@ int apax_status(const void* d_ws, hipStream_t stream) {
   return APAX_OK;
 }
 
-int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
-                uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
-  HG h;
-  const bool profiled = p && p->code == APAX_CODE_PROFILED;
+}  // extern "C"
+
+namespace {
+
+// Workspace bytes an encode itself uses: the state block (status word,
+// ticket), the look-back states of its tiles and, for the lagged choice,
+// one best stream per block.
+uint64_t enc_need(const HG& h) {
+  return ws_cj_off(h) + (h.lagged ? al256(4 * (uint64_t)h.g.nblocks) : 0);
+}
+
+// apax_encode's work once the parameters are set up and the buffers checked:
+// d_ws holds at least enc_need(h) bytes.
+int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool profiled, void* d_stream,
+                   uint64_t* d_nbytes, void* d_ws, hipStream_t stream) {
   int e;
-  if (profiled) {
-    apax_params q = *p;
-    q.code = 0;  // placeholder; the kernels read the profiled code on the device
-    e = setup(&q, h);
-  } else {
-    e = setup(p, h);
-  }
-  if (e) return e;
-  if (!d_stream || !d_nbytes || !d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
-  if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
-  if (cap < bound_of(h)) return APAX_E_CAPACITY;
-  if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
   EncArgs A;
   memset(&A, 0, sizeof(A));
   A.g = h.g;
@@ -464,6 +464,87 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
     return hip_err(hipGetLastError());
   }
   return hip_err(launch_encode(h.dtype, h.ndim, A, stream));
+}
+
+// ---- scratch of the allocation-free encode: one copy per GPU, held until
+// the process ends.  Host code never passes `scratch` itself to a kernel
+// (on the host it names a stand-in, not device memory); it passes the
+// device address hipGetSymbolAddress returns for the current device.
+constexpr uint64_t NOALLOC_BYTES = APAX_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of the current device's scratch (looked up once per device)
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return APAX_E_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return APAX_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return APAX_OK;
+}
+
+// the encode's device status word as an APAX code, into the caller's word
+__global__ void k_status_code(const uint32_t* status, int32_t* out) {
+  if (threadIdx.x == 0) {
+    const uint32_t st = *status;
+    *out = (st & ST_NONFINITE) ? APAX_E_NONFINITE : ((st & ST_INTERNAL) ? APAX_E_INTERNAL : APAX_OK);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
+                uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  HG h;
+  const bool profiled = p && p->code == APAX_CODE_PROFILED;
+  int e;
+  if (profiled) {
+    apax_params q = *p;
+    q.code = 0;  // placeholder; the kernels read the profiled code on the device
+    e = setup(&q, h);
+  } else {
+    e = setup(p, h);
+  }
+  if (e) return e;
+  if (!d_stream || !d_nbytes || !d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
+  if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
+  if (cap < bound_of(h)) return APAX_E_CAPACITY;
+  if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
+  return encode_enqueue(d_x, p, h, profiled, d_stream, d_nbytes, d_ws, stream);
+}
+
+int apax_encode_noalloc(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
+                        uint64_t* d_nbytes, int32_t* d_status, hipStream_t stream) {
+  if (p && p->code == APAX_CODE_PROFILED) return APAX_E_INVALID;  // no profile writes the scratch
+  HG h;
+  int e = setup(p, h);
+  if (e) return e;
+  if (!d_stream || !d_nbytes || (!d_x && h.nsamples)) return APAX_E_INVALID;
+  if ((uintptr_t)d_stream & 15) return APAX_E_INVALID;
+  if (cap < bound_of(h)) return APAX_E_CAPACITY;
+  if (enc_need(h) > NOALLOC_BYTES) return APAX_E_CAPACITY;  // larger than the library's scratch
+  void* ws = nullptr;
+  if ((e = scratch_of_current_device(&ws))) return e;
+  // the status word starts at zero (a fill kernel: no memset node if captured);
+  // the ticket and look-back states are reset by the encode's own first kernel
+  clear_words((uint32_t*)ws, 1, stream);
+  if ((e = hip_err(hipGetLastError()))) return e;
+  if ((e = encode_enqueue(d_x, p, h, false, d_stream, d_nbytes, ws, stream))) return e;
+  if (d_status) {
+    hipLaunchKernelGGL(k_status_code, dim3(1), dim3(64), 0, stream, (const uint32_t*)ws, d_status);
+    return hip_err(hipGetLastError());
+  }
+  return APAX_OK;
 }
 
 // Header checks and kernel arguments of a decode (no output pointer yet).

@@ -120,3 +120,22 @@ def test_stream_size_rejects_oversized_payload(A):
         with pytest.raises(A.ApaxError) as ei:
             A.stream_nbytes(bytes(s))
         assert ei.value.code == A.E_CORRUPT
+
+
+def test_noalloc_encode_refuses_arrays_beyond_its_scratch(A):
+    """apax_encode_noalloc refuses, on the host and before anything is
+    enqueued, an array whose scratch (8 bytes per tile of look-back state)
+    would exceed the library's 8 MiB array; no GPU call is made."""
+    lib = C.CDLL(A.LIB_PATH)
+    lib.apax_encode_noalloc.argtypes = [C.c_void_p, C.POINTER(A.Params), C.c_void_p, C.c_uint64,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]
+    import torch
+    # 2^32 int16 samples in 256-sample blocks: 2^24 blocks, 2^22 tiles, 32 MiB of states
+    p = A.make_params(torch.int16, (1 << 32,), {"mode": "lossless", "brick": (256,)})
+    fake = C.c_void_p(1 << 20)  # never dereferenced: the call returns first
+    rc = lib.apax_encode_noalloc(fake, C.byref(p), fake, C.c_uint64(2 ** 64 - 1), fake, None, None)
+    assert rc == A.E_CAPACITY
+    # the profiled operating point is refused too (no profile writes the scratch)
+    q = A.make_params(torch.int16, (1000,), {"mode": "lossless", "brick": (256,), "code": A.CODE_PROFILED})
+    rc = lib.apax_encode_noalloc(fake, C.byref(q), fake, C.c_uint64(1 << 20), fake, None, None)
+    assert rc == A.E_INVALID
