@@ -1,8 +1,10 @@
 """Build libapax.so (HIP for gfx950) in-tree with hipcc."""
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -15,10 +17,29 @@ SOURCES = ["capi.hip", "encode.hip", "decode.hip", "profile.hip", "batch_enc.hip
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function",
-         # keep DPP lane moves as separate v_mov_b32_dpp: folding a wave_shr
-         # move into a subtract-reverse gave negated results on gfx950
-         "-mllvm", "-amdgpu-dpp-combine=false"]
+         "-munsafe-fp-atomics", "-I", INC, "-I", CSRC, "-Wall", "-Wno-unused-function"]
+LLVM = "/opt/rocm/llvm/bin"
+# A DPP lane move folded into a subtraction (v_sub*_dpp / v_subrev*_dpp) gave
+# negated results on gfx950, so the sources only ever add a shifted operand
+# (a shifted difference is sent negated); every object is checked for it.
+BAD_DPP = re.compile(r"\bv_sub(?:rev)?[a-z0-9_]*_dpp\b")
+
+
+def _check_dpp(obj):
+    """Disassemble the gfx950 code object of `obj` and refuse subtract-DPP forms."""
+    with tempfile.TemporaryDirectory() as td:
+        fat, co = os.path.join(td, "fat"), os.path.join(td, "co")
+        subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section", f".hip_fatbin={fat}", obj],
+                       check=True, capture_output=True)
+        subprocess.run([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o",
+                        f"--input={fat}", "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", f"--output={co}"],
+                       check=True, capture_output=True)
+        dis = subprocess.run([os.path.join(LLVM, "llvm-objdump"), "-d", co], check=True,
+                             capture_output=True, text=True).stdout
+    bad = sorted(set(BAD_DPP.findall(dis)))
+    if bad:
+        raise RuntimeError(f"{os.path.basename(obj)}: subtract-DPP instructions {bad}; "
+                           "write the shifted operand as an added negation")
 
 
 def _compile(src):
@@ -27,6 +48,7 @@ def _compile(src):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
+    _check_dpp(obj)
     return obj
 
 

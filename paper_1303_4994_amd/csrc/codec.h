@@ -58,40 +58,59 @@ __device__ __forceinline__ double gain_of(int c) {
   return ldexp((double)(16 + (c & 15)), (c >> 4) - 4);
 }
 
-// Largest code in [cmin, cmax] with fl64(M * g(c)) <= lim (M * g(cmin) <=
-// lim holds for every finite M).  The predicate is monotone in c, so an
-// estimate corrected by exact tests gives the answer whatever the estimate.
-// Estimate for lim near 2^L: with M = m 2^e (m in [0.5, 1)) and r = 1/(2m),
-// g(c) = (16 + f) 2^(k-4) fits for k = L - e and f <= 32 r - 16.
-__device__ __forceinline__ int largest_code(double M, double lim, int L, int cmin, int cmax) {
-  if (M == 0.0) return cmax;
-  const int e = __builtin_amdgcn_frexp_exp(M);
-  const double m = __builtin_amdgcn_frexp_mant(M);
-  const double r = __builtin_amdgcn_rcp(2.0 * m);
-  int c = 16 * (L - e) + (int)(32.0 * r - 16.0);
-  c = c > cmax ? cmax : (c < cmin ? cmin : c);
-  while (c < cmax && M * gain_of(c + 1) <= lim) c++;
-  while (c > cmin && !(M * gain_of(c) <= lim)) c--;
-  return c;
-}
-
-// c_floor = largest code with fl64(M g) <= 1/2; c_cap = largest code with
-// fl64(M g) <= 2^31 - 1 (ints: 0).  Scaling by 2^32 (512 codes) is exact, so
-// c_cap is c_floor + 512 or, when the product lands in (2^31 - 1, 2^31],
-// one code less.
-template <typename T>
-__device__ __forceinline__ void bracket(double M, int cmin, int cmax, int& cf, int& cc) {
-  cf = largest_code(M, 0.5, -1, cmin, cmax);
-  if constexpr (Traits<T>::isint) {
-    cc = 0;
-  } else {
-    if (cf + 512 >= cmax) {
-      cc = (cf + 511 >= cmax || M * gain_of(cmax) <= 2147483647.0) ? cmax : cmax - 1;
-      if (!(M * gain_of(cc) <= 2147483647.0)) cc = largest_code(M, 2147483647.0, 31, cmin, cmax);
-    } else {
-      cc = M * gain_of(cf + 512) <= 2147483647.0 ? cf + 512 : cf + 511;
+// Code bracket of a block (Sec. 6 attenuator, reading R18): c_floor = the
+// largest code with fl64(M g(c)) <= 1/2 (every sample quantizes to 0),
+// c_cap = the largest with fl64(M g(c)) <= 2^31 - 1 (no quantized sample
+// leaves 32 bits; integer dtypes: 0), both clamped to [cmin, cmax].
+// Exact integer arithmetic on M = m 2^e (m an integer below 2^53): with
+// v = m (16 + f), M g(c) = v 2^(e + k - 4), so fl64(M g) <= 1/2 reads
+// fl64(v) <= 2^(3 - e - k).  ROUND: v is rounded to 53 bits (binary64 M);
+// otherwise it is exact (m below 2^24 or an integer below 2^31).
+//  * The smallest t with 16 m <= 2^t is t0 = bitlen(m) + 3 (m a power of two)
+//    or + 4; k0 = 3 - e - t0 is the top octave that fits at f = 0, and no
+//    code of octave k0 + 1 fits (2^(t0-1) < 16 m, also after rounding since
+//    16 m - 2^(t0-1) >= 16 exceeds half an ulp for t0 <= 57).
+//  * f = the largest f <= 15 with fl64(m (16 + f)) <= 2^t0, i.e.
+//    m (16 + f) <= 2^t0 + 2^(t0-53) when rounding (the tie rounds to even
+//    2^t0), found by a 4-step binary search.
+//  * g(c + 512) = 2^32 g(c) exactly, so c_cap is c_floor + 512 when
+//    fl64(M g(c_floor)) <= 1/2 - 2^-32 and c_floor + 511 otherwise (the code
+//    below c_floor is at most 31/32 of its gain, far below that bound).
+template <bool ROUND>
+__host__ __device__ __forceinline__ void bracket_me(uint64_t m, int e, int cmin, int cmax, bool isint, int& cf,
+                                                    int& cc) {
+  if (m == 0) {
+    cf = cmax;
+    cc = isint ? 0 : cmax;
+    return;
+  }
+  const int b = 64 - __builtin_clzll(m);
+  const bool p2 = (m & (m - 1)) == 0;
+  const int t0 = b + (p2 ? 3 : 4);
+  const uint64_t X = (1ull << t0) + ((ROUND && t0 >= 53) ? (1ull << (t0 - 53)) : 0ull);
+  uint64_t v = m << 4;
+  int f = 0;
+#pragma unroll
+  for (int s = 3; s >= 0; s--) {
+    const uint64_t cand = v + (m << s);
+    if (cand <= X) {
+      v = cand;
+      f += 1 << s;
     }
   }
+  const int craw = 16 * (3 - e - t0) + f;
+  cf = craw < cmin ? cmin : (craw > cmax ? cmax : craw);
+  if (isint) {
+    cc = 0;
+    return;
+  }
+  // fl64(v) <= 2^t0 - 2^(t0-31): integer bound, plus half an ulp when rounding
+  uint64_t Y;
+  if (t0 >= 54) Y = (1ull << t0) - (1ull << (t0 - 31)) + (ROUND ? (1ull << (t0 - 54)) : 0ull);
+  else if (t0 >= 31) Y = (1ull << t0) - (1ull << (t0 - 31));
+  else Y = (1ull << t0) - 1ull;
+  const int ccraw = craw + (v <= Y ? 512 : 511);
+  cc = ccraw > cmax ? cmax : (ccraw < cf ? cf : ccraw);
 }
 
 __device__ __forceinline__ int clampc(int c, int lo, int hi) { return c < lo ? lo : (c > hi ? hi : c); }
@@ -138,14 +157,17 @@ __device__ __forceinline__ int32_t wrapw(uint32_t v) {
 }
 
 // Exponent of a group (minimal two's-complement width, Sec. 6 BFPE): the
-// highest bit where some sample differs from its next-higher bit.  eps
-// saturates at 31; width(31) is 32 bits when W = 32.
+// widest sample is the largest or the smallest; u = max(mx, ~mn) >= 0 is one
+// bit narrower than the group, except that u = 0 stands for both {0} and a
+// group holding -1, told apart by mn's low bit.  eps saturates at 31;
+// width(31) is 32 bits when W = 32.
 template <int W>
 __device__ __forceinline__ void group_eps(const int32_t v[4], int& eps, int& pw) {
-  uint32_t t = 0;
-#pragma unroll
-  for (int k = 0; k < 4; k++) t |= (uint32_t)v[k] ^ ((uint32_t)v[k] << 1);
-  int w = t ? 32 - __clz((int)t) : 0;
+  const int32_t mx = max(max(v[0], v[1]), max(v[2], v[3]));
+  const int32_t mn = min(min(v[0], v[1]), min(v[2], v[3]));
+  const uint32_t u = (uint32_t)max(mx, ~mn);
+  const uint32_t t = (u << 1) | ((uint32_t)mn & 1u);
+  const int w = 32 - __clz((int)t);
   eps = w > 31 ? 31 : w;
   pw = (W == 32 && w >= 31) ? 32 : w;
 }

@@ -47,19 +47,18 @@ template <typename T, int LPB, int NDIM>
 __global__ __launch_bounds__(WPG * 64) void k_stream_choice(EncArgs A, int32_t* best_st) {
   constexpr int BPW = 64 / LPB;
   using B_ = Blk<T, LPB, NDIM>;
-  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
   const Geo& g = A.g;
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   B_ b;
-  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * 64 : nullptr);
+  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * XCH : nullptr);
   b.template load<false>((const T*)A.x, g);
-  int32_t a[4], v[7][4];
-  int eps[7], pw[7];
+  int32_t a[4];
   Costs C;
   int32_t best;
   b.quantize(0, true, a);
-  b.sizes(g, g.mask, a, v, eps, pw, C);
+  b.costs(g, g.mask, a, C);
   const int st = B_::argmin(C, g.mask, best);
   if (b.blk_ok && b.L.gi == 0) best_st[b.j] = st;
 }

@@ -30,6 +30,15 @@ __device__ __forceinline__ void or_bits(uint32_t* buf, int bitpos, uint32_t val,
   }
 }
 
+// OR the bits of val into the buffer from bit position bitpos on (the two
+// words it may touch; zero bits leave a word unchanged)
+__device__ __forceinline__ void or_word2(uint32_t* buf, int bitpos, uint32_t val) {
+  const uint64_t r = (uint64_t)val << (bitpos & 31);
+  uint32_t* q = buf + (bitpos >> 5);
+  atomicOr(q, (uint32_t)r);
+  atomicOr(q + 1, (uint32_t)(r >> 32));
+}
+
 __device__ __forceinline__ uint32_t low_bits(int32_t v, int n) {
   return n >= 32 ? (uint32_t)v : ((uint32_t)v & ((1u << n) - 1u));
 }
@@ -98,7 +107,7 @@ struct EncShared {
   uint32_t item[RUN];         // batch: item of each tile of the run
   uint32_t nw[RUN][WP * 4];   // words of each block
   uint64_t off[RUN][WP * 4];  // word offset of each block
-  uint4 xch[WP * 64];
+  uint4 xch[WP * XCH];
 };
 
 __device__ __forceinline__ bool profiled_point(const EncArgs& A, const Geo& g, int32_t& code,
@@ -126,115 +135,114 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   profiled_point(A, g, code0, mask0);
   B_ b;
   const int lane = lane_id();
-  b.init(g, (tile * WP + wave) * BPW + lane / LPB, NDIM >= 2 ? sm.xch + wave * 64 : nullptr);
-  b.load((const T*)A.x, g);
+  b.init(g, (tile * WP + wave) * BPW + lane / LPB, NDIM >= 2 ? sm.xch + wave * XCH : nullptr);
+  {
+    T xv4[4];
+    b.fetch((const T*)A.x, g, xv4);
+    if (g.mode == M_LOSSLESS) b.template take<false>(g, xv4);  // code 0: no bracket
+    else b.take(g, xv4);
+  }
   if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
 
   // ---- operating point and stream
-  int c = 0, st = 0;
-  int32_t a[4], v[7][4];
-  int eps[7], pw[7];
+  int c = 0;
+  int32_t a[4];
   Costs C;
   int32_t best;
-  if (g.mode == M_QUALITY) c = clampc(code0, b.cf, b.cc);
-  else if (g.mode == M_RATE) c = clampc(code0, b.cf, b.cc);
+  if (g.mode != M_LOSSLESS) c = clampc(code0, b.cf, b.cc);
   const uint32_t emask = g.mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
   b.quantize(c, g.mode == M_LOSSLESS, a);
-  b.sizes(g, emask, a, v, eps, pw, C);
-  st = B_::argmin(C, emask, best);
+  b.costs(g, emask, a, C);
+  int st = B_::argmin(C, emask, best);
   if (A.lag) {  // lagged choice (lossless): the previous block's best stream,
                 // or verbatim where that would code the block above verbatim size
     st = b.j == 0 ? 0 : (b.blk_ok ? A.lag[b.j - 1] : 0);
+    if constexpr (LPB == 64) st = __builtin_amdgcn_readfirstlane(st);
     best = B_::size_sel(C, st);
     if (best > C.sz[7]) {
       st = 7;
       best = C.sz[7];
     }
   }
+  bool searched = false;
   if (g.mode == M_RATE) {
     const bool need = b.act && best > 32 * g.budget;
     if (__ballot(need)) {
-      // some block of this wave does not fit at its start code: search, then
-      // re-evaluate every block of the wave at its final code
+      // some block of this wave does not fit at its start code: search (the
+      // stream stays the one chosen at the start code), then quantize at the
+      // final code
       c = b.rate_search(g, emask, c, st, need);
+      if constexpr (LPB == 64) c = __builtin_amdgcn_readfirstlane(c);
       b.quantize(c, false, a);
-      b.sizes(g, emask, a, v, eps, pw, C);
-      best = B_::size_sel(C, st);
+      searched = true;
     }
+  }
+  (void)searched;
+  // the chosen stream's values, exponent and payload width at the final code
+  const bool verb = st == 7;  // LPB = 64: wave-uniform
+  int32_t vv[4] = {0, 0, 0, 0};
+  int e = 0, p = 0;
+  if constexpr (LPB == 64) {  // one block per wave: form the chosen stream alone
+    if (!verb) {
+      b.stream_one(g, st, a, vv);
+      b.eps_of(vv, e, p);
+    }
+  } else {  // every lane takes part: the streams move values across lanes
+    int32_t v[7][4];
+    b.streams(g, a, v, emask | 1u);
+    B_::select_stream(st, v, vv);
+    b.eps_of(vv, e, p);
+    if (verb) { e = 0; p = 0; }
   }
   const int nw = !b.blk_ok ? 0 : (g.mode == M_RATE ? g.budget : ((best + 31) >> 5));
 
-  // ---- emit into this segment's LDS buffer
+  // ---- emit into this segment's LDS buffer: zero the words it will hold
   const int seg = b.L.seg, gi = b.L.gi;
   const int stride = g.ldsw;
   uint32_t* buf = lds + ((r * WP + wave) * BPW + seg) * slot;
-  for (int w = 4 * gi; w < stride; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
+  const int nz = nw < stride ? nw : stride;
+  for (int w = 4 * gi; w < nz; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
-  const bool verb = st == 7;
-  int32_t vv[4];
-  B_::select_stream(st, v, vv);
-  int e = B_::pick_int(st, eps);
-  int p = B_::pick_int(st, pw);
-  if (verb) { e = 0; p = 0; }
-
-  const int em1 = (int)shr1((uint32_t)e);
-  const int d = e - em1;
-  const bool pos = b.act && gi >= 1 && !verb;
-  const uint64_t m1 = __ballot(pos && (uint32_t)(d + 1) <= 2u);
-  const uint64_t m2 = __ballot(pos && (uint32_t)(d + 2) <= 4u);
-  const uint64_t vp = __ballot(pos);
+  // JEE tokens of the chosen stream.  Exponent differences: the
+  // predecessor's exponent arrives negated through a DPP add (lane 0 of a
+  // segment gets a value it never uses).
+  const int d = (int)((uint32_t)e + shr1(0u - (uint32_t)e));
+  uint64_t vp;
+  if constexpr (LPB == 64) vp = verb ? 0ull : b.vpos;
+  else vp = __ballot(b.act && gi >= 1 && !verb);
+  const uint64_t m1 = __ballot((uint32_t)(d + 1) <= 2u) & vp;
+  const uint64_t m2 = __ballot((uint32_t)(d + 2) <= 4u) & vp;
   const uint64_t Tm = jee_token_starts(m1);
   const uint64_t starts = Tm | (~m1 & vp);
   const uint64_t ab = ~m2 & vp;
+  const uint64_t pairs = Tm & (m1 >> 1);  // a pair token: its second difference is small too
   const int dnext = (int)shl1((uint32_t)d);
   const int ntot = seg_popc<LPB>(starts, seg) + seg_popc<LPB>(ab, seg);
   const int pay0 = H + 4 * ntot;
   const int pex = (int)seg_scan_add<LPB>((uint32_t)(4 * p)) - 4 * p;
-  if (b.act) {
-    if ((starts >> lane) & 1) {
-      int nib_off = below_in_seg<LPB>(starts, seg) + below_in_seg<LPB>(ab, seg);
-      bool pair = ((Tm >> lane) & 1) && lane < 63 && ((m1 >> (lane + 1)) & 1);
-      bool isabs = (ab >> lane) & 1;
-      uint32_t tok;
-      int len = 4;
-      if (pair) tok = (uint32_t)(3 * (d + 1) + (dnext + 1));
-      else if (isabs) { tok = (uint32_t)(14 + (e >> 4)) | ((uint32_t)(e & 15) << 4); len = 8; }
-      else tok = (uint32_t)(11 + d);
-      or_bits(buf, H + 4 * nib_off, tok, len);
-    }
-    if (!verb) {
-      // the group's 4 fields are contiguous: pack them into 128 bits, then
-      // OR the (up to 5) words they touch
-      if (p > 0) {
-        uint64_t m = p >= 32 ? 0xFFFFFFFFull : ((1ull << p) - 1ull);
-        uint64_t lo = ((uint64_t)(uint32_t)vv[0] & m) | (((uint64_t)(uint32_t)vv[1] & m) << p);
-        uint64_t hi = ((uint64_t)(uint32_t)vv[2] & m) | (((uint64_t)(uint32_t)vv[3] & m) << p);
-        int s2 = 2 * p;  // 2..64
-        uint64_t f0 = s2 >= 64 ? lo : (lo | (hi << s2));
-        uint64_t f1 = s2 >= 64 ? hi : (hi >> (64 - s2));
-        int o = pay0 + pex;
-        int w0 = o >> 5, sh = o & 31;
-        uint32_t wd[5];
-        wd[0] = (uint32_t)(f0 << sh);
-        wd[1] = (uint32_t)((f0 << sh) >> 32);
-        wd[2] = (uint32_t)((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0));
-        wd[3] = (uint32_t)(((f1 << sh) | (sh ? (f0 >> (64 - sh)) : 0)) >> 32);
-        wd[4] = sh ? (uint32_t)(f1 >> (64 - sh)) : 0u;
-        const int nwd = (sh + 4 * p + 31) >> 5;
+  if (__builtin_amdgcn_inverse_ballot_w64(starts)) {
+    const int nib_off = below_in_seg<LPB>(starts, seg) + below_in_seg<LPB>(ab, seg);
+    const bool pr = __builtin_amdgcn_inverse_ballot_w64(pairs), isab = __builtin_amdgcn_inverse_ballot_w64(ab);
+    const uint32_t tabs = (uint32_t)(14 + (e >> 4)) | ((uint32_t)(e & 15) << 4);
+    const uint32_t tok = pr ? (uint32_t)(3 * d + dnext + 4) : (isab ? tabs : (uint32_t)(11 + d));
+    or_word2(buf, H + 4 * nib_off, tok);
+  }
+  if (!verb) {
+    // the 4 fields of the group, p bits each, from bit pay0 + pex on; lanes
+    // with p = 0 (and lanes without a group) OR zeros
+    const uint32_t msk = (uint32_t)(1ull << p) - 1u;
+    const int o = pay0 + pex;
 #pragma unroll
-        for (int i = 0; i < 5; i++)
-          if (i < nwd && wd[i]) atomicOr(&buf[w0 + i], wd[i]);
-      }
-    } else {
+    for (int k = 0; k < 4; k++) or_word2(buf, o + k * p, (uint32_t)vv[k] & msk);
+  } else if (b.act) {
 #pragma unroll
-      for (int k = 0; k < 4; k++) or_bits(buf, H + (4 * gi + k) * W, low_bits(a[k], W), W);
-    }
-    if (gi == 0) {
-      uint32_t cm = H == 32 ? 0x3FFu : 0xFFFFu;
-      uint32_t hdr = (uint32_t)st | ((uint32_t)e << 3) | (((uint32_t)c & cm) << 8);
-      or_bits(buf, 0, hdr, 32);
-    }
+    for (int k = 0; k < 4; k++) or_bits(buf, H + (4 * gi + k) * W, low_bits(a[k], W), W);
+  }
+  if (b.act && gi == 0) {
+    uint32_t cm = H == 32 ? 0x3FFu : 0xFFFFu;
+    uint32_t hdr = (uint32_t)st | ((uint32_t)e << 3) | (((uint32_t)c & cm) << 8);
+    or_bits(buf, 0, hdr, 32);
   }
   if (gi == 0) s_nw[wave * BPW + seg] = (uint32_t)nw;
   __syncthreads();

@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   __shared__ float s_red[WPG][NL][2];
   __shared__ uint64_t s_w[WPG], s_dm[WPG];
   __shared__ uint32_t s_fit[WPG], s_hist[WPG][8];
-  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * 64 : 1];
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
 
   const int ci = blockIdx.y;
   const int nset = A.final_code ? 1 : st->ncodes;
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     const int64_t jj = (t * WPG + wave) * BPW + lane / LPB;
     return jj < A.nbe ? jj * A.jstride : g.nblocks;
   };
-  uint4* xw = NDIM >= 2 ? s_xch + wave * 64 : nullptr;
+  uint4* xw = NDIM >= 2 ? s_xch + wave * XCH : nullptr;
   // the samples of the next tile are fetched while the current one is
   // evaluated (a tile past the end fetches nothing)
   B_ nb;
@@ -443,15 +443,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     }
     if (OP == P_CENTER && A.rule != R_QUALITY) b.template take<false>(g, cv);
     else b.take(g, cv);
-    int32_t a[4], v[7][4];
-    int eps[7], pw[7];
+    int32_t a[4];
     Costs C;
     int32_t best;
     if (OP == P_FITS) {
       // argmin over the mask at the clamped code: fit test + stream histogram
       int c = A.rule == R_LOSSLESS ? 0 : clampc(code, b.cf, b.cc);
       b.quantize(c, A.rule == R_LOSSLESS, a);
-      b.sizes(g, mask, a, v, eps, pw, C);
+      b.costs(g, mask, a, C);
       int s_ = B_::argmin(C, mask, best);
       if (b.blk_ok && b.L.gi == 0 && best <= 32 * g.budget) nfit++;
       if (A.hist) {
@@ -474,7 +473,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
         c = clampc(code, b.cf, b.cc);
         const uint32_t m7 = mask & 0x7Fu;
         b.quantize(c, false, a);
-        b.sizes(g, m7, a, v, eps, pw, C);
+        b.costs(g, m7, a, C);
         int s_ = B_::argmin(C, m7, best);
         bool need = b.act && best > 32 * g.budget;
         if (__ballot(need)) c = b.rate_search(g, g.mask, c, s_, need);
@@ -486,7 +485,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     if (OP == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
-        b.sizes(g, mask, a, v, eps, pw, C);
+        b.costs(g, mask, a, C);
         B_::argmin(C, mask, best);
         nw = (best + 31) >> 5;
       } else {
@@ -504,7 +503,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
 #pragma unroll
     for (int k = 0; k < 4; k++) {
       if (!(b.act && b.valid(k))) continue;
-      double x = b.xd[k];
+      double x = b.xv(k);
       double y;
       if (A.rule == R_LOSSLESS) y = (double)a[k];
       else y = (double)to_out<T>(dequant_rk(a[k], Rq, eq));

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_s2r(S2RArgs A) {
       uint32_t digit = 0;
       uint64_t key = 0;
       if (b.act && b.valid(k)) {
-        const double x = b.xd[k];
+        const double x = b.xv(k);
         const double y = A.rule == R_LOSSLESS ? (double)a[k] : (double)to_out<T>(dequant_rk(a[k], Rq, eq));
         const double d = x - y;
         key = d == 0.0 ? 0x7FF0000000000000ull
