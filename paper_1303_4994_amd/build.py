@@ -40,6 +40,33 @@ def _check_dpp(obj):
     if bad:
         raise RuntimeError(f"{os.path.basename(obj)}: subtract-DPP instructions {bad}; "
                            "write the shifted operand as an added negation")
+    # A DPP lane move reads zero from lanes that are switched off, so none
+    # may run while a divergent branch has narrowed the execution mask: scan
+    # each function in order, tracking whether the last write of exec narrowed
+    # it (saveexec / and / andn2 / xor) or restored it (or / mov); code after
+    # an unconditional branch starts a block reached by jumps only, whose mask
+    # this scan does not follow.
+    narrowed, where = False, []
+    for line in dis.splitlines():
+        t = line.split("//")[0].strip()
+        if t.endswith(">:"):
+            narrowed = False
+            continue
+        ops = t.split()
+        op = next((o for o in ops if o.startswith(("s_", "v_"))), None)
+        if op is None:
+            continue
+        if op in ("s_branch", "s_endpgm", "s_setpc_b64"):
+            narrowed = False
+        elif op.startswith(("s_and_saveexec", "s_andn2_saveexec", "s_xor_saveexec")) or \
+                (op.startswith(("s_and_b64", "s_andn2_b64", "s_xor_b64")) and "exec," in t.split(op, 1)[1][:8]):
+            narrowed = True
+        elif op.startswith(("s_or_b64", "s_or_saveexec", "s_mov_b64")) and "exec" in t.split(op, 1)[1][:8]:
+            narrowed = False
+        elif "_dpp" in op and narrowed:
+            where.append(t)
+    if where:
+        raise RuntimeError(f"{os.path.basename(obj)}: DPP under a narrowed exec mask: {where[:4]}")
 
 
 def _compile(src):

@@ -357,7 +357,7 @@ struct Blk {
   template <bool DENSE>
   __device__ __forceinline__ void streams_t(const Geo& g, const int32_t a[4], int32_t v[7][4],
                                             uint32_t need) const {
-    const uint32_t nd = NDMASK & need;
+    const uint32_t nd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(NDMASK & need));  // wave-uniform
     uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
     uint32_t s[4];
 #pragma unroll
@@ -462,7 +462,7 @@ struct Blk {
   }
   template <bool DENSE>
   __device__ __forceinline__ void costs_t(const Geo& g, uint32_t mask, const int32_t a[4], Costs& C) const {
-    const uint32_t nd = NDMASK & mask;
+    const uint32_t nd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(NDMASK & mask));  // wave-uniform
     const uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
     uint32_t pk[4] = {0u, 0u, 0u, 0u};  // payload widths, streams 2i and 2i+1 in the halves of pk[i]
     int tk[7] = {0, 0, 0, 0, 0, 0, 0};

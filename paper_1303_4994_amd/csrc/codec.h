@@ -194,6 +194,14 @@ __device__ __forceinline__ uint32_t bcast31(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
 }
 
+// Keep a value computed where it is: the compiler may otherwise move a DPP
+// lane move that only feeds one arm of a select into that arm, where lanes
+// outside it are disabled and read as zero.
+__device__ __forceinline__ uint32_t pin(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // inclusive scan (sum mod 2^32) inside segments of LPB lanes
 template <int LPB>
 __device__ __forceinline__ uint32_t seg_scan_add(uint32_t v) {

@@ -127,9 +127,12 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   constexpr int W = Traits<T>::W;
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
+  // wave-uniform by construction (batches read their arguments from memory,
+  // where the compiler cannot see that)
+  const int mode = __builtin_amdgcn_readfirstlane(g.mode);
   uint32_t* s_nw = sm.nw[r];
   const int wave = threadIdx.x >> 6;
-  const bool variable = g.mode != M_RATE;
+  const bool variable = mode != M_RATE;
   int32_t code0;  // operating point, read before the block so the loads overlap
   uint32_t mask0;
   profiled_point(A, g, code0, mask0);
@@ -139,7 +142,7 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   {
     T xv4[4];
     b.fetch((const T*)A.x, g, xv4);
-    if (g.mode == M_LOSSLESS) b.template take<false>(g, xv4);  // code 0: no bracket
+    if (mode == M_LOSSLESS) b.template take<false>(g, xv4);  // code 0: no bracket
     else b.take(g, xv4);
   }
   if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
@@ -149,9 +152,9 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   int32_t a[4];
   Costs C;
   int32_t best;
-  if (g.mode != M_LOSSLESS) c = clampc(code0, b.cf, b.cc);
-  const uint32_t emask = g.mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
-  b.quantize(c, g.mode == M_LOSSLESS, a);
+  if (mode != M_LOSSLESS) c = clampc(code0, b.cf, b.cc);
+  const uint32_t emask = mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
+  b.quantize(c, mode == M_LOSSLESS, a);
   b.costs(g, emask, a, C);
   int st = B_::argmin(C, emask, best);
   if (A.lag) {  // lagged choice (lossless): the previous block's best stream,
@@ -164,8 +167,12 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
       best = C.sz[7];
     }
   }
+  if constexpr (LPB == 64) {
+    st = __builtin_amdgcn_readfirstlane(st);
+    best = __builtin_amdgcn_readfirstlane(best);
+  }
   bool searched = false;
-  if (g.mode == M_RATE) {
+  if (mode == M_RATE) {
     const bool need = b.act && best > 32 * g.budget;
     if (__ballot(need)) {
       // some block of this wave does not fit at its start code: search (the
@@ -194,7 +201,7 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     b.eps_of(vv, e, p);
     if (verb) { e = 0; p = 0; }
   }
-  const int nw = !b.blk_ok ? 0 : (g.mode == M_RATE ? g.budget : ((best + 31) >> 5));
+  const int nw = !b.blk_ok ? 0 : (mode == M_RATE ? g.budget : ((best + 31) >> 5));
 
   // ---- emit into this segment's LDS buffer: zero the words it will hold
   const int seg = b.L.seg, gi = b.L.gi;
@@ -217,7 +224,7 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
   const uint64_t starts = Tm | (~m1 & vp);
   const uint64_t ab = ~m2 & vp;
   const uint64_t pairs = Tm & (m1 >> 1);  // a pair token: its second difference is small too
-  const int dnext = (int)shl1((uint32_t)d);
+  const int dnext = (int)pin(shl1((uint32_t)d));
   const int ntot = seg_popc<LPB>(starts, seg) + seg_popc<LPB>(ab, seg);
   const int pay0 = H + 4 * ntot;
   const int pex = (int)seg_scan_add<LPB>((uint32_t)(4 * p)) - 4 * p;
