@@ -11,8 +11,14 @@ the encoder adopts the profile's code and stream mask on the device
 waits only for the operating point (final after the stream histogram), so
 they overlap the profile's curve, metrics and centred passes.  Inputs are resident in HBM before
 timing; steps rotate over several copies so the 256 MB Infinity Cache cannot
-serve them.  After the timed loop the last profile is read back and the
-decoded field checked against its correlation.  Prints one JSON line.
+serve them.  The timed steps are hipGraphs of that enqueue sequence (one per
+copy; the eager enqueue is timed too and reported beside it), so host launch
+overhead stays out of the GPU's step time.  After the timed loop the last
+profile is read back and the decoded field checked against its correlation,
+and every graph replay's decode against the eager one.  Also timed, outside
+the step: encode and decode of the other workloads (the int16 time series,
+the fp64 3-d field at fixed quality, the same field at 3:1 and 10:1).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -87,21 +93,31 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
         return vals
     f = per_kernel(fetch_csv, "FETCH_SIZE")
     w = per_kernel(write_csv, "WRITE_SIZE")
-    copy_bytes = 64 * 1024 * 1024
+    field = 64 * 1024 * 1024
 
-    def copy_factor(vals):
-        big = [v for k, vs in vals.items() if "copyBuffer" in k or "copy" in k.lower() for v in vs]
-        big = [v for v in big if v * 1024 > copy_bytes / 2]
-        return copy_bytes / (sum(big) / len(big) * 1024) if big else None
-    ff, fw = copy_factor(f), copy_factor(w)
+    def factor(vals, pick):
+        """field bytes / the counter's mean reading (bytes) for the calibration kernel"""
+        big = [v for k, vs in vals.items() if pick(k) for v in vs if v * 1024 > field / 4]
+        return field / (sum(big) / len(big) * 1024) if big else None
+    # reads: the plain copy of the field (its reads are whole 128-byte lines, as
+    # the codec kernels' are); writes: the write-only fill of a field (the
+    # copy's WRITE_SIZE reads about 1.4 times the bytes it writes)
+    copyk = lambda k: "copy" in k.lower() and "apax" not in k
+    ff = factor(f, copyk)
+    fw = factor(w, lambda k: "FillFunctor" in k)
+    f_sum = factor(f, lambda k: "reduce_kernel" in k)
+    w_copy = factor(w, copyk)
     lines = ["# HBM traffic of the codec kernels, C1 workload (4096x4096 fp32, 16x16 bricks, 4:1)",
              f"# command (fetch): {command.format(c='FETCH_SIZE', d='fetch')}",
              f"# command (write): {command.format(c='WRITE_SIZE', d='write')}",
              f"# summary: python3 bench.py --traffic-from {fetch_csv} {write_csv}",
-             "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
-             "# the counter's reading for a plain 64 MiB device copy onto 64 MiB",
+             "# FETCH_SIZE / WRITE_SIZE are KiB per dispatch (raw_* below); the calibrated bytes scale",
+             "# FETCH_SIZE by 64 MiB over its reading for a plain copy of a 64 MiB field and",
+             "# WRITE_SIZE by 64 MiB over its reading for a write-only fill of a 64 MiB field",
+             "# (for reference: the same factors from a read-only sum and from the copy's writes)",
              f"source_sha256: {source_digest()}",
-             f"copy_factor_fetch: {ff}", f"copy_factor_write: {fw}"]
+             f"calibration_factor_fetch: {ff}", f"calibration_factor_write: {fw}",
+             f"reference_factor_fetch_sum: {f_sum}", f"reference_factor_write_copy: {w_copy}"]
     for k in sorted(set(f) | set(w)):
         if not k.startswith("void apax::") and "apax::" not in k:
             continue
@@ -110,7 +126,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
         name = k.split("apax::")[1].split("<")[0]
         fb = fv * 1024 * (ff or 1.0)
         wb = wv * 1024 * (fw or 1.0)
-        lines.append(f"{name}<{k.split('<', 1)[1] if '<' in k else ''}: fetch_bytes={fb:.0f} write_bytes={wb:.0f}")
+        lines.append(f"{name}<{k.split('<', 1)[1] if '<' in k else ''}: fetch_bytes={fb:.0f} write_bytes={wb:.0f} "
+                     f"raw_fetch_KiB={fv:.0f} raw_write_KiB={wv:.0f}")
         key = TRAFFIC_KEYS.get(k.replace("void ", "").split("(")[0].strip())
         if key:
             lines.append(f"{key}_hbm_bytes_per_launch: {fb + wb:.0f}")
@@ -118,11 +135,12 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
     print("\n".join(lines))
 
 
-TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && rocprofv3 --kernel-trace --stats "
-             "-d gpurun_out/kt_c1 -o kt -- python3 bench.py --steps 5 --warmup 1 --no-cpu-baseline")
-INSTMIX_CMD = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES "
-               "SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM SQ_BUSY_CYCLES --output-format csv "
-               "-d gpurun_out/pmc_sq -o p -- python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --copy-probe")
+TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d /root/repo/gpurun_out/kt_c1 "
+             "-o kt -- python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-workloads")
+INSTMIX_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU "
+               "SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM SQ_BUSY_CYCLES --output-format csv "
+               "-d /root/repo/gpurun_out/pmc_sq -o p -- python3 /root/repo/bench.py --steps 2 --warmup 1 "
+               "--no-cpu-baseline --no-workloads --copy-probe")
 
 
 def trace_summary(db_path: str, out_path: str):
@@ -211,17 +229,51 @@ def instmix_summary(csv_path: str, out_path: str):
     print("\n".join(out))
 
 
+def host_cpu():
+    """Model name and logical core count of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cores": os.cpu_count()}
+
+
 def cpu_baseline(x, params):
+    """The oracle (single-threaded C) on the full C1 field: profile, encode and
+    decode each timed, and the whole pass."""
     from oracle import oracle as O
     t0 = time.perf_counter()
     prof = O.profile_dict(O.profile(x, params))
+    t1 = time.perf_counter()
     p = dict(params, code=prof["code"], stream_mask=prof["stream_mask"] & 0x7F)
     s = O.encode(x, p)
+    t2 = time.perf_counter()
     O.decode(s)
-    dt = time.perf_counter() - t0
+    t3 = time.perf_counter()
+    dt = t3 - t0
+    mb = x.nbytes / 1e6
     return {"value": round(x.nbytes / dt / 1e9, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": "the full 4096x4096 fp32 field, one profile+encode+decode pass, "
-                      "single-threaded C oracle", "seconds": round(dt, 3)}
+                      "single-threaded C oracle", "seconds": round(dt, 3),
+            "profile_MBps": round(mb / (t1 - t0), 2), "encode_MBps": round(mb / (t2 - t1), 2),
+            "decode_MBps": round(mb / (t3 - t2), 2), "host": host_cpu()}
+
+
+# The paper's throughput figures for this path (other implementations and
+# hardware: context, not the target)
+PAPER_THROUGHPUT = {
+    "software_encode_MBps": 130, "software_decode_MBps": 170,
+    "software": "one x86 core at the profiler's operating points over the paper's datasets (Sec. 4, Sec. 7)",
+    "table1_software_MBps_per_core": 150, "table1_software": "x86 core, about 50 instructions per sample",
+    "table1_fpga_MBps_per_instance": 600, "table1_fpga": "FPGA netlist, encoder about 4000 and decoder about "
+                                                          "3500 6-input LUTs",
+    "table1_soc_GBps_per_instance": 1.5, "table1_soc": "SoC IP block, encoder + decoder about 220k gates "
+                                                      "(under 0.1 mm^2 in 28 nm)",
+}
 
 
 def cpu_baseline_items(arrays, op, budget_bytes=192 << 20):
@@ -246,6 +298,67 @@ def cpu_baseline_items(arrays, op, budget_bytes=192 << 20):
                       "single-threaded C oracle", "seconds": round(dt, 3)}
 
 
+def codec_workload(A, dev, name, x, params, copies, reps, profile=True):
+    """Encode and decode GB/s (input bytes) of one workload: the operating
+    point from apax_profile (fixed rate / quality), then back-to-back
+    launches over `copies` rotating device copies between HIP events."""
+    import torch
+    dtype = {1: torch.int8, 2: torch.int16, 4: torch.float32, 8: torch.float64}[x.itemsize]
+    if x.dtype.kind == "i" and x.itemsize == 4:
+        dtype = torch.int32
+    xs = [torch.from_numpy(x).to(dev) for _ in range(copies)]
+    ws = A.workspace(dtype, x.shape, params, dev)
+    p = dict(params)
+    prof = None
+    if profile:
+        prof = A.apax_profile(xs[0], params, ws=ws)
+        p = dict(params, code=prof["code"], stream_mask=prof["stream_mask"] & (0x7F if params["mode"] ==
+                                                                                 "fixed_rate" else 0xFF))
+    bound = A.apax_encode_bound(dtype, x.shape, p)
+    bufs = [torch.empty(bound, dtype=torch.uint8, device=dev) for _ in range(copies)]
+    nbs = [torch.empty(1, dtype=torch.int64, device=dev) for _ in range(copies)]
+    ys = [torch.empty_like(xs[0]) for _ in range(copies)]
+    stream = torch.cuda.current_stream()
+    A.apax_status_clear(ws)
+    for k in range(copies):
+        A.apax_encode(xs[k], p, out=bufs[k], nbytes=nbs[k], ws=ws, clear_status=False)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    nb = int(nbs[0].item())
+    hdr = bytes(bufs[0][:64].cpu().numpy().tobytes())
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    for k in range(reps):
+        A.apax_encode(xs[k % copies], p, out=bufs[k % copies], nbytes=nbs[k % copies], ws=ws,
+                      clear_status=False)
+    e1.record(stream)
+    for k in range(reps):
+        A.apax_decode(bufs[k % copies], nb, hdr=hdr, y=ys[k % copies], ws=ws, clear_status=False)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    for k in range(copies):  # every copy gave the same stream and decoded to the same array
+        assert int(nbs[k].item()) == nb and torch.equal(bufs[k][:nb], bufs[0][:nb])
+        assert torch.equal(ys[k], ys[0])
+    if params["mode"] == "lossless":
+        assert torch.equal(ys[0], xs[0])
+    enc_ms, dec_ms = e0.elapsed_time(e1) / reps, e1.elapsed_time(e2) / reps
+    enc = x.nbytes / (enc_ms * 1e-3) / 1e9
+    dec = x.nbytes / (dec_ms * 1e-3) / 1e9
+    out = {"workload": name, "mode": params["mode"], "input_bytes": x.nbytes, "stream_bytes": nb,
+           "ratio": round(x.nbytes / nb, 4), "encode_GBps": round(enc, 2), "decode_GBps": round(dec, 2),
+           "encode_pct_hbm": round(100 * enc / HBM_PEAK_GBPS, 2),
+           "decode_pct_hbm": round(100 * dec / HBM_PEAK_GBPS, 2),
+           "encode_us": round(1e3 * enc_ms, 2), "decode_us": round(1e3 * dec_ms, 2),
+           "copies_rotated": copies, "launches": reps}
+    if prof is not None:
+        out["code"] = prof["code"]
+        out["r"] = prof["metrics"]["r"]
+    del xs, bufs, ys
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +366,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--copies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="c1: skip the C0 / C2 / 3:1 / 10:1 encode and decode lines")
     ap.add_argument("--workload", choices=("c1", "batch", "serve"), default="c1",
                     help="c1: the headline single-array path; batch: many arrays per persistent "
                          "launch vs separate launches; serve: Poisson request stream")
@@ -278,9 +393,9 @@ def main():
         instmix_summary(args.instmix_from, os.path.join(ROOT, "profiles", "pmc_c1_instmix.txt"))
         return
     if args.traffic_from:
-        cmd = ("cd /tmp && export TMPDIR=/tmp && cd /root/repo && timeout -s KILL 150 rocprofv3 --pmc {c} "
-               "--output-format csv -d gpurun_out/pmc_{d} -o p -- python3 bench.py --steps 2 --warmup 1 "
-               "--no-cpu-baseline --copy-probe")
+        cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc {c} --output-format csv "
+               "-d /root/repo/gpurun_out/pmc_{d} -o p -- python3 /root/repo/bench.py --steps 2 --warmup 1 "
+               "--no-cpu-baseline --no-workloads --copy-probe")
         traffic_summary(args.traffic_from[0], args.traffic_from[1],
                         os.path.join(ROOT, "profiles", "traffic_c1.txt"), cmd)
         return
@@ -376,7 +491,45 @@ def main():
     assert prof["code"] == prof0["code"] and prof["stream_mask"] == prof0["stream_mask"]
     for k in range(1, min(R, args.steps)):  # every copy decoded to the same field
         assert torch.equal(ys[k], ys[0])
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step_eager = (t1 - t0) * 1e3 / args.steps
+    # the same steps as hipGraphs (one per input copy, the two streams forked
+    # and joined inside): the host enqueues one graph per step instead of
+    # about twenty kernels, so the step time is the GPU's
+    graph_ok, ms_step = False, ms_step_eager
+    try:
+        y_eager = ys[0].clone()
+        graphs = []
+        for i in range(R):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                cap = torch.cuda.current_stream()
+                A.apax_profile_async_point(xs[i], params, ws, ev_point, stream=cap)
+                codec.wait_event(ev_point)
+                A.apax_adopt_point(ws, ws_enc, stream=codec)
+                A.apax_encode(xs[i], p_dev, out=bufs[i], nbytes=nbt, ws=ws_enc, stream=codec, clear_status=False)
+                A.apax_decode(bufs[i], bound, hdr=step.hdr, y=ys[i], ws=ws_enc, stream=codec, clear_status=False)
+                cap.wait_stream(codec)
+            graphs.append(g)
+        for k in range(args.warmup):
+            graphs[k % R].replay()
+        torch.cuda.synchronize()
+        for i in range(R):
+            ys[i].zero_()
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        for k in range(args.steps):
+            graphs[k % R].replay()
+        torch.cuda.synchronize()
+        g1 = time.perf_counter()
+        assert A.apax_status(ws) == 0 and A.apax_status(ws_enc) == 0
+        # every replayed copy decoded to the eager result
+        for i in range(min(R, args.steps)):
+            assert torch.equal(ys[i], y_eager), f"graph replay of copy {i} differs from the eager step"
+        ms_step = (g1 - g0) * 1e3 / args.steps
+        graph_ok = True
+        del graphs
+    except RuntimeError as exc:  # capture refused: report the eager steps
+        log(f"step graph not used: {exc}")
     # in a step: the profile stream's span (enqueue start to the last pass),
     # and the codec stream's encode and decode
     prof_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
@@ -493,10 +646,12 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4),
+        "ms_per_step_eager": round(ms_step_eager, 4),
+        "step_as_graph": graph_ok,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i32",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "C1: 2-D fp32 field 4096x4096 (GRF, k^-3, [-1e3,1e3] + noise 1e-2), "
                                "fixed rate 4:1, 16x16 bricks, profile + encode + decode per step",
@@ -542,10 +697,38 @@ def main():
                            "note": "Welch spectrum of x and its lags 0..16 autocorrelation; outside the step"},
     }
     if args.copy_probe:
-        # a plain copy of the field: reads and writes exactly input_bytes
+        # counter calibration: a plain copy of the field (reads and writes
+        # input_bytes), a read-only sum over it and a write-only fill of a field
         for _ in range(3):
             ys[0].copy_(xs[1])
+            float(xs[1].sum())
+            ys[0].fill_(0.5)
         torch.cuda.synchronize()
+
+    # the other workloads of the metric, each timed alone (not part of the step):
+    # the lossless int16 time series, the fp64 3-d field at fixed quality, and
+    # the C1 field at 3:1 and 10:1
+    if not args.no_workloads:
+        del xs, bufs, ys
+        torch.cuda.empty_cache()
+        wl = []
+        x0 = synth.sinusoids(1 << 20)
+        wl.append(codec_workload(A, dev, "C0: int16 time series 2^20 samples (2 MiB), lossless, 256-sample "
+                                 "blocks; launch-latency bound at this size", x0,
+                                 {"mode": "lossless", "brick": (256,)}, copies=256, reps=256, profile=False))
+        x0l = synth.sinusoids(1 << 25)
+        wl.append(codec_workload(A, dev, "C0 recipe at 2^25 samples (64 MiB): int16 time series, lossless, "
+                                 "256-sample blocks", x0l, {"mode": "lossless", "brick": (256,)},
+                                 copies=8, reps=max(8, args.steps), profile=False))
+        for rate in (3.0, 10.0):
+            wl.append(codec_workload(A, dev, f"C1 field at {rate:g}:1", x, dict(params, rate=rate),
+                                     copies=8, reps=max(8, args.steps)))
+        x2 = synth.blobs3d()
+        wl.append(codec_workload(A, dev, "C2: fp64 field 256x512x512, fixed quality r >= 0.99996, 4x4x8 bricks",
+                                 x2, {"mode": "fixed_quality", "brick": (4, 4, 8), "target_corr": 0.99996},
+                                 copies=2, reps=8))
+        out["workloads"] = wl
+    out["paper_throughput"] = PAPER_THROUGHPUT
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x, params)
     print(json.dumps(out), flush=True)
@@ -765,6 +948,22 @@ def bench_serve(args):
     for i, v in ref.items():
         got = result(items[i])
         assert got.shape == v.shape and torch.equal(got, v), f"served item {i} differs from its plain call"
+    # the served results of a bounded sample of those items (about 256 MB)
+    # also equal the CPU oracle's stream or decoded array, byte for byte
+    from oracle import oracle as O
+    orc_bytes, orc_items = 0, 0
+    for i in ref:
+        r = items[i]
+        if orc_bytes >= (256 << 20):
+            break
+        got = result(r).cpu().numpy()
+        if r["kind"] == "encode":
+            assert np.array_equal(got, O.encode(r["x"].cpu().numpy(), r["params"])), f"served item {i} != oracle"
+        else:
+            exp = O.decode(r["stream"][: r["nbytes"]].cpu().numpy())
+            assert np.array_equal(got.view(np.uint8), exp.view(np.uint8)), f"served item {i} != oracle"
+        orc_bytes += r["bytes"]
+        orc_items += 1
     total = st["bytes"]
     out = {
         "metric": "served encode/decode GB/s (uncompressed bytes) with p50/p99 latency, 1 GPU",
@@ -782,6 +981,7 @@ def bench_serve(args):
         "plain_GBps": round(T_plain / 1e9, 2),
         "offered_GBps": round(args.rho * T_plain / 1e9, 2),
         "checked_items": len(ref),
+        "oracle_checked_items": orc_items, "oracle_checked_bytes": orc_bytes,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_items([(r["x"], r["params"]) for r in items], "both")

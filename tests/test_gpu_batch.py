@@ -138,3 +138,48 @@ def test_tuner_picks_a_candidate(A, items, tmp_path, monkeypatch):
     best = T.tune(A.OP_ENCODE, arrays, candidates=cands, reps=1)
     assert best in cands
     assert T.tune(A.OP_ENCODE, arrays, candidates=cands, reps=1) == best  # cached
+
+
+def test_batch_large_items_match_oracle(A):
+    """Items of 16-64 MB (one per dtype, from the C0-C2 generators; lossless
+    and fixed rate), batched with small ones: encodes equal the oracle's
+    streams and decodes the oracle's decoded arrays, byte for byte."""
+    pools = synth.Pools(n=1 << 24, seed=77)
+    big = []
+    for i, (dt, gen, mode, nbytes) in enumerate([(np.int16, 0, "lossless", 16 << 20),
+                                                 (np.int32, 1, "fixed_rate", 24 << 20),
+                                                 (np.float32, 1, "fixed_rate", 64 << 20),
+                                                 (np.float64, 2, "fixed_rate", 40 << 20)]):
+        spec = {"dtype": np.dtype(dt), "gen": gen, "n": nbytes // np.dtype(dt).itemsize,
+                "offset": 12345 * (i + 1), "mode": mode, "rate": 3.0 + 2.5 * i}
+        x = pools.item(spec)
+        if mode == "lossless":
+            p = {"mode": "lossless", "brick": (256,)}
+        else:
+            p = {"mode": "fixed_rate", "brick": (256,), "rate": spec["rate"], "code": 0 if dt == np.int32 else 180}
+        big.append((x, p))
+    small = [(synth.sinusoids(3000, seed=11), {"mode": "lossless", "brick": (256,)}),
+             (synth.grf2d(64, 64, seed=12).ravel(), {"mode": "fixed_rate", "brick": (256,), "rate": 5.0,
+                                                    "code": 100})]
+    items = big + small
+    print("large batch items", [(x.dtype.name, x.nbytes) for x, _ in items], flush=True)
+    arrays = [(torch.from_numpy(np.ascontiguousarray(x)).to(DEV), p) for x, p in items]
+    b = A.Batch.encode(arrays)
+    b.run()
+    assert b.status() == 0
+    got = batch_outputs(b)
+    exps = []
+    for i, (x, p) in enumerate(items):
+        exps.append(O.encode(x, p))
+        assert np.array_equal(got[i], exps[i]), (i, x.dtype, p)
+    # the batched decode of the same streams equals the oracle's decode
+    streams = [(torch.from_numpy(g).to(DEV), g.size, bytes(g[:64])) for g in got]
+    d = A.Batch.decode(streams)
+    d.run()
+    assert d.status() == 0
+    torch.cuda.synchronize()
+    for i in range(len(items)):
+        yo = O.decode(exps[i])
+        assert np.array_equal(d.outs[i].cpu().numpy().view(np.uint8), yo.view(np.uint8)), i
+    b.close()
+    d.close()

@@ -331,7 +331,13 @@ def test_c1_full(A):
     assert abs(m["r"] - pg["metrics"]["r"]) < 1e-12
 
 
-def test_c2_full_sampled(A):
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_c2_full_stream_and_decode_equal_oracle(A):
+    """The whole 512 MiB fp64 field: the GPU profile's operating point is the
+    correlation boundary by the oracle's r, and at that point the whole
+    bitstream and the whole decoded array equal the oracle's byte for byte
+    (the oracle's encode and decode take about a minute)."""
     x = synth.blobs3d()
     params = {"mode": "fixed_quality", "brick": (4, 4, 8), "target_corr": 0.99996}
     xg = torch.from_numpy(x).to(DEV)
@@ -351,14 +357,17 @@ def test_c2_full_sampled(A):
     assert n == pg["metrics"]["enc_bytes"]
     got = buf[:n].cpu().numpy()
     st = brute.Stream(got)
-    rng = np.random.default_rng(2)
-    js = np.concatenate([rng.integers(0, st.nblocks, 300), [0, st.nblocks - 1]])
-    for j in js:
-        w, sid, cj, ub = O.encode_block(x, p, int(j))
-        assert np.array_equal(w, st.block(int(j))), int(j)
+    exp = O.encode(x, p)
+    assert got.size == exp.size
+    if not np.array_equal(got, exp):
+        bad = next(j for j in range(st.nblocks) if not np.array_equal(st.block(j), brute.Stream(exp).block(j)))
+        pytest.fail(f"C2 bitstream differs from the oracle's, first at block {bad}")
     y = A.apax_decode(buf, n, ws=ws)
     assert A.apax_status(ws) == 0
     yn = y.cpu().numpy()
+    assert np.array_equal(yn.view(np.uint8), O.decode(exp).view(np.uint8))
+    rng = np.random.default_rng(2)
+    js = np.concatenate([rng.integers(0, st.nblocks, 300), [0, st.nblocks - 1]])
     # sampled bricks decode to DQ(Q(x)) at their own code (numpy, from the header)
     nby, nbx = 512 // 4, 512 // 8
     for j in js[:100]:
