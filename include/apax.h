@@ -271,14 +271,14 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
 /* apax_encode for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same stream bytes and byte count as apax_encode with the same arguments,
- * but no workspace argument.  Its scratch (status word, work-queue ticket,
- * one 8-byte look-back state per tile of 4 waves, one int32 per block with
- * APAX_FLAG_LAGGED) lives in a library-owned device array of
- * APAX_NOALLOC_SCRATCH_BYTES (8 MiB) per GPU, which the GPU holds until the
- * process ends; the call itself allocates nothing (no hipMalloc, no library
- * allocation).  An array whose scratch would exceed 8 MiB returns
- * APAX_E_CAPACITY before anything is enqueued (about 4 million blocks
- * without the lagged choice, 1.4 million with it).  APAX_CODE_PROFILED is not
+ * but no workspace argument.  Its scratch (status word, one byte per block
+ * for the chosen stream and 4 bytes per 64 blocks for their word count, one
+ * int32 per block with APAX_FLAG_LAGGED) lives in a library-owned device
+ * array of APAX_NOALLOC_SCRATCH_BYTES (8 MiB) per GPU, which the GPU holds
+ * until the process ends; the call itself allocates nothing (no hipMalloc,
+ * no library allocation).  An array whose scratch would exceed 8 MiB returns
+ * APAX_E_CAPACITY before anything is enqueued (about 7.9 million blocks
+ * without the lagged choice, 1.6 million with it).  APAX_CODE_PROFILED is not
  * accepted (APAX_E_INVALID): no profile writes that scratch.
  * d_status (device int32, may be NULL) receives APAX_OK, APAX_E_NONFINITE or
  * APAX_E_INTERNAL once the encode has run.  Every call on one GPU shares its

@@ -96,26 +96,29 @@ __device__ __forceinline__ int64_t group_index(const Geo& g, const LaneMap<LPB>&
 }
 
 // Block j of a one-block-per-wave layout lies wholly inside the array, every
-// lane owns a group (G = 64), and its lane offsets fit 32 bits: then sample 0
-// of block j is at `base` and the lane's group at base + off (elements).
+// lane owns a group (G = 64), and its lane offsets fit 31 bits with rows
+// 4-sample aligned (g.dense_ok, set on the host): then sample 0 of block j is
+// at `base` and the lane's group at base + off (elements).
 template <int NDIM, int LPB>
 __device__ __forceinline__ bool dense_block(const Geo& g, const LaneMap<LPB>& L, int64_t j, int64_t& base,
                                             uint32_t& off) {
   if constexpr (LPB != 64) {
     return false;
   } else {
-    j = ((int64_t)__builtin_amdgcn_readfirstlane((int)(j >> 32)) << 32) |
-        (uint32_t)__builtin_amdgcn_readfirstlane((int)j);
-    if (g.G != 64 || j >= g.nblocks) return false;
-    int64_t bz = 0, by = 0, bx = j;
-    if constexpr (NDIM > 1) brick_of(g, j, bz, by, bx);
-    const int64_t X = bx * g.b[2], Y = by * g.b[1], Z = bz * g.b[0];
-    if (X + g.b[2] > g.n[2] || Y + g.b[1] > g.n[1] || Z + g.b[0] > g.n[0]) return false;
-    // the farthest lane offset of a brick must fit 32 bits
-    const int64_t span = ((int64_t)(g.b[0] - 1) * g.n[1] + (g.b[1] - 1)) * g.n[2] + g.b[2];
-    if (span >= (1ll << 31)) return false;
-    base = (Z * g.n[1] + Y) * g.n[2] + X;
-    off = (uint32_t)(((int64_t)L.z * g.n[1] + L.y) * g.n[2] + 4 * L.xq);
+    const uint32_t jj = (uint32_t)__builtin_amdgcn_readfirstlane((int)j);  // j < 2^31
+    if (!g.dense_ok || g.G != 64 || (int64_t)jj >= g.nblocks) return false;
+    if constexpr (NDIM == 1) {
+      if ((int64_t)jj >= (int64_t)g.fbx) return false;
+      base = (int64_t)jj * g.b[2];
+    } else {
+      const uint32_t t = fdiv(jj, g.nbx_m, g.nbx_s);
+      const uint32_t bx = jj - t * (uint32_t)g.nbx;
+      const uint32_t bz = fdiv(t, g.nby_m, g.nby_s);
+      const uint32_t by = t - bz * (uint32_t)g.nby;
+      if (bx >= (uint32_t)g.fbx || by >= (uint32_t)g.fby || bz >= (uint32_t)g.fbz) return false;
+      base = (int64_t)bz * g.sz + (int64_t)by * g.sy + (int64_t)bx * g.b[2];
+    }
+    off = ((uint32_t)L.z * (uint32_t)g.n[1] + (uint32_t)L.y) * (uint32_t)g.n[2] + 4u * (uint32_t)L.xq;
     return true;
   }
 }
@@ -220,9 +223,9 @@ struct Blk {
   __device__ __forceinline__ void fetch(const T* __restrict__ x, const Geo& g, T v[4]) {
     int64_t base;
     uint32_t off;
-    // dense: a whole block per wave, every group 4 aligned samples (x and
-    // rows 16-byte aligned for the vector loads); wave-uniform
-    const bool aligned = (((uintptr_t)x) & (4 * sizeof(T) - 1)) == 0 && (NDIM == 1 || (g.n[2] & 3) == 0);
+    // dense: a whole block per wave, every group 4 aligned samples (x 16-byte
+    // aligned for the vector loads); wave-uniform
+    const bool aligned = (((uintptr_t)x) & (4 * sizeof(T) - 1)) == 0;
     if (aligned && dense_block<NDIM, LPB>(g, L, j, base, off)) {
       dense = true;
       nvalid = 4;

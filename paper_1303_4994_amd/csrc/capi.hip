@@ -142,6 +142,15 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
   }
   if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not implemented on the GPU
+  g.sz = (int64_t)g.b[0] * g.n[1] * g.n[2];
+  g.sy = (int64_t)g.b[1] * g.n[2];
+  g.fbx = (int32_t)(g.n[2] / g.b[2]);
+  g.fby = (int32_t)(g.n[1] / g.b[1]);
+  g.fbz = (int32_t)(g.n[0] / g.b[0]);
+  {
+    const int64_t span = ((int64_t)(g.b[0] - 1) * g.n[1] + (g.b[1] - 1)) * g.n[2] + g.b[2];
+    g.dense_ok = span < ((int64_t)1 << 31) && (h.ndim == 1 || g.n[2] % 4 == 0);
+  }
   magic(g.nbx, g.nbx_m, g.nbx_s);
   magic(g.nby, g.nby_m, g.nby_s);
   magic(g.rowq, g.rowq_m, g.rowq_s);
@@ -197,12 +206,13 @@ uint64_t partial_bytes(const HG& h) {
                             8 * (uint64_t)encode_tiles(h.g));
 }
 
-uint64_t ws_tile_off() { return al256(sizeof(PState)); }
-uint64_t ws_cj_off(const HG& h) { return ws_tile_off() + al256(8 * tiles_enc(h)); }
+// [PState][chosen stream per block][words per superblock][int32 per block][partials]
+uint64_t ws_bst_off(const HG& h) { (void)h; return al256(sizeof(PState)); }
+uint64_t ws_ssum_off(const HG& h) { return ws_bst_off(h) + al256((uint64_t)h.g.nblocks); }
+uint64_t ws_cj_off(const HG& h) { return ws_ssum_off(h) + al256(4 * (((uint64_t)h.g.nblocks + 63) / 64)); }
 uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
 uint64_t ws_need(const HG& h) { return ws_part_off(h) + partial_bytes(h); }
 
-uint64_t* tile_state_ptr(void* ws) { return (uint64_t*)((uint8_t*)ws + ws_tile_off()); }
 void* partials_ptr(void* ws, const HG& h) { return (uint8_t*)ws + ws_part_off(h); }
 int32_t* cj_ptr(void* ws, const HG& h) { return (int32_t*)((uint8_t*)ws + ws_cj_off(h)); }
 
@@ -409,9 +419,9 @@ int apax_status(const void* d_ws, hipStream_t stream) {
 
 namespace {
 
-// Workspace bytes an encode itself uses: the state block (status word,
-// ticket), the look-back states of its tiles and, for the lagged choice,
-// one best stream per block.
+// Workspace bytes an encode itself uses: the state block (status word), one
+// chosen stream per block and one word count per superblock of 64 blocks
+// (variable-size modes) and, for the lagged choice, one best stream per block.
 uint64_t enc_need(const HG& h) {
   return ws_cj_off(h) + (h.lagged ? al256(4 * (uint64_t)h.g.nblocks) : 0);
 }
@@ -433,7 +443,8 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
   A.d_nbytes = d_nbytes;
   A.status = &((PState*)d_ws)->status;
   A.ticket = &((PState*)d_ws)->ticket;
-  A.tile_state = tile_state_ptr(d_ws);
+  A.bst = (uint8_t*)d_ws + ws_bst_off(h);
+  A.ssum = (uint32_t*)((uint8_t*)d_ws + ws_ssum_off(h));
   make_header(p, h, A.hdr);
   if (h.mode != APAX_FIXED_RATE) {
     A.zpad[0] = (uint64_t)(64 + 2 * (uint64_t)h.g.nblocks);
@@ -536,7 +547,7 @@ int apax_encode_noalloc(const void* d_x, const apax_params* p, void* d_stream, u
   void* ws = nullptr;
   if ((e = scratch_of_current_device(&ws))) return e;
   // the status word starts at zero (a fill kernel: no memset node if captured);
-  // the ticket and look-back states are reset by the encode's own first kernel
+  // the superblock counts are reset by the encode's own first kernel
   clear_words((uint32_t*)ws, 1, stream);
   if ((e = hip_err(hipGetLastError()))) return e;
   if ((e = encode_enqueue(d_x, p, h, false, d_stream, d_nbytes, ws, stream))) return e;

@@ -43,6 +43,12 @@ struct Geo {
   // n / d = (n * m) >> sh for n < 2^31 (divisors nbx, nby, rowq, plane)
   uint32_t nbx_m, nby_m, rowq_m, plane_m;
   int32_t nbx_s, nby_s, rowq_s, plane_s;
+  // whole bricks: element strides of one brick step along z and y (x: b[2]),
+  // number of bricks that lie wholly inside the array per axis, and whether
+  // a brick's lane offsets fit 31 bits with every row 4-sample aligned
+  int64_t sz, sy;
+  int32_t fbx, fby, fbz;
+  int32_t dense_ok;
 };
 
 // Division of a numerator below 2^31 by a divisor known on the host

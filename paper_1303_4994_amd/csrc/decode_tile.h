@@ -408,7 +408,7 @@ __device__ __forceinline__ void decode_tile64(const DecArgs& A, const int64_t ti
   // ---- dequantize and store
   int64_t base;
   uint32_t doff;
-  const bool aligned = (((uintptr_t)A.y) & (4 * sizeof(T) - 1)) == 0 && (NDIM == 1 || (g.n[2] & 3) == 0);
+  const bool aligned = (((uintptr_t)A.y) & (4 * sizeof(T) - 1)) == 0;
   const bool dense = aligned && dense_block<NDIM, 64>(g, L, j, base, doff);
   int nvalid = 4;
   int64_t idx = 0;

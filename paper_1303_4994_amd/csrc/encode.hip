@@ -6,16 +6,131 @@
 
 namespace apax {
 
-__global__ void k_encode_reset(uint32_t* ticket, uint32_t* status_unused, uint64_t* tile_state,
-                               int64_t ntiles) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *ticket = 0;
-  for (; i < ntiles; i += (int64_t)gridDim.x * blockDim.x) tile_state[i] = 0;
-  (void)status_unused;
+// zero the superblock word counts of a variable-size encode
+__global__ void k_encode_reset(uint32_t* ssum, int64_t nsuper) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsuper; i += (int64_t)gridDim.x * blockDim.x)
+    ssum[i] = 0;
 }
 
-// VAR: variable-size modes (runs of RUN tiles from the ticket, look-back);
-// else fixed rate (one tile per workgroup, offsets known up front).
+// Variable-size modes, first pass (one tile per workgroup): each block's
+// analysis -- operating point, quantization, every allowed stream costed --
+// gives its chosen stream and word count; the counts go to the stream's
+// block-length index and are summed per superblock of 64 blocks.
+template <typename T, int LPB, int NDIM>
+__global__ __launch_bounds__(WPG * 64) void k_encode_size(EncArgs A) {
+  constexpr int BPW = 64 / LPB;
+  using B_ = Blk<T, LPB, NDIM>;
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
+  const Geo& g = A.g;
+  const int mode = __builtin_amdgcn_readfirstlane(g.mode);
+  int32_t code0;
+  uint32_t mask0;
+  profiled_point(A, g, code0, mask0);
+  const int wave = threadIdx.x >> 6;
+  B_ b;
+  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane_id() / LPB,
+         NDIM >= 2 ? s_xch + wave * XCH : nullptr);
+  int c, st;
+  int32_t best, a[4];
+  analyze_block<T, LPB, NDIM>(A, b, mode, code0, mask0, c, st, best, a);
+  if (b.blk_ok && b.L.gi == 0) {
+    const uint32_t nw = (uint32_t)((best + 31) >> 5);
+    A.lens[b.j] = (uint16_t)nw;
+    A.bst[b.j] = (uint8_t)st;
+    atomicAdd(&A.ssum[b.j >> 6], nw);
+  }
+}
+
+// Variable-size modes: superblock word offsets (exclusive running sum of the
+// superblock counts, one workgroup, fixed order), the payload size in the
+// stream header and the stream's byte count.
+__global__ __launch_bounds__(1024) void k_encode_scan(EncArgs A, int64_t nsuper) {
+  __shared__ uint64_t s_part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nsuper + 1023) / 1024;
+  const int64_t lo = t * per, hi = lo + per < nsuper ? lo + per : nsuper;
+  uint64_t sum = 0;
+  for (int64_t i = lo; i < hi; i++) sum += A.ssum[i];
+  s_part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint64_t v = t >= o ? s_part[t - o] : 0;
+    __syncthreads();
+    s_part[t] += v;
+    __syncthreads();
+  }
+  uint64_t acc = s_part[t] - sum;
+  for (int64_t i = lo; i < hi; i++) {
+    A.sbo[i] = acc;
+    acc += A.ssum[i];
+  }
+  if (t == 1023) {
+    const uint64_t total = s_part[1023];
+    *reinterpret_cast<uint64_t*>(A.out_base + 56) = total;
+    *A.d_nbytes = A.area + 4 * total;
+  }
+}
+
+// Variable-size modes, second pass (one tile per workgroup): each block is
+// quantized again at its operating point, its chosen stream (first pass)
+// assembled in LDS and stored at its offset: the superblock's offset plus the
+// lengths of the blocks before it in the superblock.  Tile 0 writes the
+// stream header.
+template <typename T, int LPB, int NDIM>
+__global__ __launch_bounds__(WPG * 64) void k_encode_emit(EncArgs A) {
+  constexpr int BPW = 64 / LPB;
+  using B_ = Blk<T, LPB, NDIM>;
+  const uint32_t* hsrc =
+      (const uint32_t*)((const uint8_t*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(EncArgs, hdr));
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
+  const Geo& g = A.g;
+  const int mode = __builtin_amdgcn_readfirstlane(g.mode);
+  int32_t code0;
+  uint32_t mask0;
+  profiled_point(A, g, code0, mask0);
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  if (blockIdx.x == 0 && wave == 0) write_stream_header(A, hsrc, true);
+  B_ b;
+  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * XCH : nullptr);
+  {
+    T xv4[4];
+    b.fetch((const T*)A.x, g, xv4);
+    if (mode == M_LOSSLESS) b.template take<false>(g, xv4);
+    else b.take(g, xv4);
+  }
+  const int c = mode == M_LOSSLESS ? 0 : clampc(code0, b.cf, b.cc);
+  int32_t a[4];
+  b.quantize(c, mode == M_LOSSLESS, a);
+  const int seg = b.L.seg, gi = b.L.gi;
+  const int64_t j = b.j;
+  int st = b.blk_ok ? (int)A.bst[j] : 0;
+  int nw = b.blk_ok ? (int)A.lens[j] : 0;
+  // offset: superblock offset + lengths of the blocks before j in its superblock
+  const int64_t jb = (j >> 6) << 6;
+  uint32_t acc = 0;
+  if (b.blk_ok)
+    for (int64_t r = jb + gi; r < j; r += LPB) acc += A.lens[r];
+  acc = (uint32_t)seg_sum<LPB>((int32_t)acc);
+  uint64_t off = b.blk_ok ? A.sbo[j >> 6] + (uint64_t)acc : 0;
+  if constexpr (LPB == 64) {
+    st = __builtin_amdgcn_readfirstlane(st);
+    nw = __builtin_amdgcn_readfirstlane(nw);
+  }
+  uint32_t* buf = lds + (wave * BPW + seg) * g.ldsw;
+  emit_block<T, LPB, NDIM>(g, b, c, st, mask0, a, buf, nw);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t* dst = A.out_words + off;
+  const int stride = g.ldsw;
+  for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
+}
+
+// Fixed rate: one workgroup per tile, block j at j * budget words.  (VAR is
+// kept for the template's shape; variable-size single arrays use the size /
+// scan / emit kernels below.)
 template <typename T, int LPB, int NDIM, int WP, bool VAR>
 __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
   constexpr int BPW = 64 / LPB;
@@ -24,13 +139,8 @@ __global__ __launch_bounds__(WP * 64) void k_encode(EncArgs A) {
       (const uint32_t*)((const uint8_t*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(EncArgs, hdr));
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ EncShared<WP> sm;
-  if constexpr (VAR) {
-    if (threadIdx.x == 0) sm.tile = (int64_t)atomicAdd(A.ticket, (uint32_t)RUN);
-    __syncthreads();
-    const int64_t t0 = sm.tile;
-    const int64_t left = A.ntiles - t0;
-    encode_run<T, LPB, NDIM, WP>(A, hsrc, t0, left < RUN ? (int)left : RUN, sm, lds);
-  } else {
+  static_assert(!VAR, "variable-size single arrays use k_encode_size / k_encode_scan / k_encode_emit");
+  {
     const int64_t t = blockIdx.x;
     encode_analyze<T, LPB, NDIM, WP>(A, t, 0, A.g.ldsw, sm, lds);
     if ((threadIdx.x >> 6) == 0) {
@@ -95,14 +205,18 @@ hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   constexpr int BPW = 64 / LPB;
-  const bool variable = A.g.mode != M_RATE;
-  const int run = variable ? RUN : 1;
-  size_t lds = (size_t)run * WPG * BPW * A.g.ldsw * 4;
-  const int64_t grid = (A.ntiles + run - 1) / run;
-  if (variable)
-    hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG, true>), dim3((unsigned)grid), dim3(WPG * 64), lds, s, A);
-  else
-    hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG, false>), dim3((unsigned)grid), dim3(WPG * 64), lds, s, A);
+  const size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
+  const unsigned grid = (unsigned)A.ntiles;
+  if (A.g.mode == M_RATE) {
+    hipLaunchKernelGGL((k_encode<T, LPB, NDIM, WPG, false>), dim3(grid), dim3(WPG * 64), lds, s, A);
+    return hipGetLastError();
+  }
+  const int64_t nsuper = (A.g.nblocks + 63) / 64;
+  const int64_t nb = (nsuper + 255) / 256;
+  hipLaunchKernelGGL(k_encode_reset, dim3((unsigned)(nb > 1024 ? 1024 : nb)), dim3(256), 0, s, A.ssum, nsuper);
+  hipLaunchKernelGGL((k_encode_size<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), 0, s, A);
+  hipLaunchKernelGGL(k_encode_scan, dim3(1), dim3(1024), 0, s, A, nsuper);
+  hipLaunchKernelGGL((k_encode_emit<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
 }
 
@@ -133,12 +247,6 @@ int64_t encode_tiles(const Geo& g) { return encode_tiles_wp(g, WPG); }
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s) {
   A.ntiles = encode_tiles(A.g);
   if (A.ntiles == 0) return hipSuccess;
-  if (A.g.mode != M_RATE) {
-    int64_t nb = (A.ntiles + 255) / 256;
-    unsigned grid = (unsigned)(nb > 1024 ? 1024 : (nb < 1 ? 1 : nb));
-    hipLaunchKernelGGL(k_encode_reset, dim3(grid), dim3(256), 0, s, A.ticket, A.status,
-                       A.tile_state, A.ntiles);
-  }
   switch (dtype) {
     case DT_I8: return launch_nd<int8_t>(A, ndim, s);
     case DT_I16: return launch_nd<int16_t>(A, ndim, s);

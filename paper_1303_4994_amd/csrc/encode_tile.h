@@ -115,48 +115,27 @@ __device__ __forceinline__ bool profiled_point(const EncArgs& A, const Geo& g, i
   return operating_point(A.sel, A.status, g.cmin, g.cmax, g.code, g.mask, code, mask);
 }
 
-// Phase 1 for one tile (WP waves x 64/LPB blocks) of one array: analyse
-// every block, assemble it in LDS region r of the run (block slots of
-// `slot` >= g.ldsw words, the same for every tile of a run), record the
-// block word counts and publish the tile's count (variable-size modes).
-template <typename T, int LPB, int NDIM, int WP>
-__device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t tile, const int r,
-                                               const int slot, EncShared<WP>& sm, uint32_t* lds) {
-  constexpr int BPW = 64 / LPB;
-  constexpr int H = Traits<T>::H;
-  constexpr int W = Traits<T>::W;
+// Analysis of one block (the wave segment's): samples, bracket, operating
+// point c, quantized samples a, chosen stream st and its size best (bits);
+// fixed rate: after the cap-and-descend search (c final, a at c).
+template <typename T, int LPB, int NDIM>
+__device__ __forceinline__ void analyze_block(const EncArgs& A, Blk<T, LPB, NDIM>& b, int mode, int code0,
+                                              uint32_t emask, int& c, int& st, int32_t& best, int32_t a[4]) {
   using B_ = Blk<T, LPB, NDIM>;
   const Geo& g = A.g;
-  // wave-uniform by construction (batches read their arguments from memory,
-  // where the compiler cannot see that)
-  const int mode = __builtin_amdgcn_readfirstlane(g.mode);
-  uint32_t* s_nw = sm.nw[r];
-  const int wave = threadIdx.x >> 6;
-  const bool variable = mode != M_RATE;
-  int32_t code0;  // operating point, read before the block so the loads overlap
-  uint32_t mask0;
-  profiled_point(A, g, code0, mask0);
-  B_ b;
-  const int lane = lane_id();
-  b.init(g, (tile * WP + wave) * BPW + lane / LPB, NDIM >= 2 ? sm.xch + wave * XCH : nullptr);
   {
     T xv4[4];
     b.fetch((const T*)A.x, g, xv4);
     if (mode == M_LOSSLESS) b.template take<false>(g, xv4);  // code 0: no bracket
     else b.take(g, xv4);
   }
-  if (__ballot(b.act && b.nonfinite) && lane == 0) atomicOr(A.status, ST_NONFINITE);
-
-  // ---- operating point and stream
-  int c = 0;
-  int32_t a[4];
-  Costs C;
-  int32_t best;
+  if (__ballot(b.act && b.nonfinite) && lane_id() == 0) atomicOr(A.status, ST_NONFINITE);
+  c = 0;
   if (mode != M_LOSSLESS) c = clampc(code0, b.cf, b.cc);
-  const uint32_t emask = mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
   b.quantize(c, mode == M_LOSSLESS, a);
+  Costs C;
   b.costs(g, emask, a, C);
-  int st = B_::argmin(C, emask, best);
+  st = B_::argmin(C, emask, best);
   if (A.lag) {  // lagged choice (lossless): the previous block's best stream,
                 // or verbatim where that would code the block above verbatim size
     st = b.j == 0 ? 0 : (b.blk_ok ? A.lag[b.j - 1] : 0);
@@ -171,7 +150,6 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     st = __builtin_amdgcn_readfirstlane(st);
     best = __builtin_amdgcn_readfirstlane(best);
   }
-  bool searched = false;
   if (mode == M_RATE) {
     const bool need = b.act && best > 32 * g.budget;
     if (__ballot(need)) {
@@ -181,11 +159,20 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
       c = b.rate_search(g, emask, c, st, need);
       if constexpr (LPB == 64) c = __builtin_amdgcn_readfirstlane(c);
       b.quantize(c, false, a);
-      searched = true;
     }
   }
-  (void)searched;
-  // the chosen stream's values, exponent and payload width at the final code
+}
+
+// One block's encoding at code c with stream st, assembled in the segment's
+// LDS buffer `buf` (its nw words zeroed first): header | JEE tokens | BFPE
+// payload (verbatim: the W-bit samples).  Every lane of the wave takes part.
+template <typename T, int LPB, int NDIM>
+__device__ __forceinline__ void emit_block(const Geo& g, const Blk<T, LPB, NDIM>& b, int c, int st, uint32_t emask,
+                                           const int32_t a[4], uint32_t* buf, int nw) {
+  constexpr int H = Traits<T>::H;
+  constexpr int W = Traits<T>::W;
+  using B_ = Blk<T, LPB, NDIM>;
+  // the chosen stream's values, exponent and payload width
   const bool verb = st == 7;  // LPB = 64: wave-uniform
   int32_t vv[4] = {0, 0, 0, 0};
   int e = 0, p = 0;
@@ -201,15 +188,15 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     b.eps_of(vv, e, p);
     if (verb) { e = 0; p = 0; }
   }
-  const int nw = !b.blk_ok ? 0 : (mode == M_RATE ? g.budget : ((best + 31) >> 5));
-
-  // ---- emit into this segment's LDS buffer: zero the words it will hold
+  // zero the words the block will hold (this wave's own buffer: LDS
+  // accesses of one wave complete in order)
   const int seg = b.L.seg, gi = b.L.gi;
   const int stride = g.ldsw;
-  uint32_t* buf = lds + ((r * WP + wave) * BPW + seg) * slot;
   const int nz = nw < stride ? nw : stride;
   for (int w = 4 * gi; w < nz; w += 4 * LPB) *reinterpret_cast<uint4*>(buf + w) = make_uint4(0, 0, 0, 0);
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
   // JEE tokens of the chosen stream.  Exponent differences: the
   // predecessor's exponent arrives negated through a DPP add (lane 0 of a
@@ -251,6 +238,38 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     uint32_t hdr = (uint32_t)st | ((uint32_t)e << 3) | (((uint32_t)c & cm) << 8);
     or_bits(buf, 0, hdr, 32);
   }
+}
+
+// Phase 1 for one tile (WP waves x 64/LPB blocks) of one array: analyse
+// every block, assemble it in LDS region r of the run (block slots of
+// `slot` >= g.ldsw words, the same for every tile of a run), record the
+// block word counts and publish the tile's count (variable-size modes).
+template <typename T, int LPB, int NDIM, int WP>
+__device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t tile, const int r,
+                                               const int slot, EncShared<WP>& sm, uint32_t* lds) {
+  constexpr int BPW = 64 / LPB;
+  using B_ = Blk<T, LPB, NDIM>;
+  const Geo& g = A.g;
+  // wave-uniform by construction (batches read their arguments from memory,
+  // where the compiler cannot see that)
+  const int mode = __builtin_amdgcn_readfirstlane(g.mode);
+  uint32_t* s_nw = sm.nw[r];
+  const int wave = threadIdx.x >> 6;
+  const bool variable = mode != M_RATE;
+  int32_t code0;  // operating point, read before the block so the loads overlap
+  uint32_t mask0;
+  profiled_point(A, g, code0, mask0);
+  B_ b;
+  const int lane = lane_id();
+  b.init(g, (tile * WP + wave) * BPW + lane / LPB, NDIM >= 2 ? sm.xch + wave * XCH : nullptr);
+  const uint32_t emask = mode == M_RATE ? (mask0 & 0x7Fu) : mask0;
+  int c, st;
+  int32_t best, a[4];
+  analyze_block<T, LPB, NDIM>(A, b, mode, code0, emask, c, st, best, a);
+  const int nw = !b.blk_ok ? 0 : (mode == M_RATE ? g.budget : ((best + 31) >> 5));
+  const int seg = b.L.seg, gi = b.L.gi;
+  uint32_t* buf = lds + ((r * WP + wave) * BPW + seg) * slot;
+  emit_block<T, LPB, NDIM>(g, b, c, st, emask, a, buf, nw);
   if (gi == 0) s_nw[wave * BPW + seg] = (uint32_t)nw;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -258,6 +277,32 @@ __device__ __forceinline__ void encode_analyze(const EncArgs& A, const int64_t t
     for (int i = 0; i < WP * BPW; i++) agg += s_nw[i];
     sm.agg[r] = agg;
     if (variable) lb_publish(A.tile_state, tile, agg);
+  }
+}
+
+// The stream header (lanes 0-15 of the calling wave, one word each, read
+// from `hsrc`: the argument block in memory, so no scalar registers are held
+// for it across the kernel) and the index padding; in variable-size modes
+// words 14-15 (the payload size) and the byte count are written by whoever
+// knows the total.
+__device__ __forceinline__ void write_stream_header(const EncArgs& A, const uint32_t* hsrc, bool variable) {
+  const Geo& g = A.g;
+  const int lane = lane_id();
+  if (lane >= 16) return;
+  uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
+  uint32_t w = hsrc[lane];
+  if (A.sel && (lane == 2 || lane == 3)) {  // operating point adopted on the device
+    int32_t code0;
+    uint32_t mask0;
+    const bool ok = profiled_point(A, g, code0, mask0);
+    if (!ok && lane == 2) atomicOr(A.status, ST_NOPROFILE);
+    w = lane == 2 ? ((w & ~0xFF00u) | ((mask0 & 0xFFu) << 8)) : (uint32_t)code0;
+  }
+  if (lane < 14 || !variable) h[lane] = w;
+  if (lane == 0) {
+    for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
+    for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
+    if (!variable) *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
   }
 }
 
@@ -282,27 +327,7 @@ __device__ __forceinline__ void encode_place(const EncArgs& A, const uint32_t* h
   } else {
     base = (uint64_t)tile * (WP * BPW) * (uint64_t)g.budget;
   }
-  if (tile == 0 && lane < 16) {
-    // the stream header, one word per lane, read from `hsrc` (the argument
-    // block in memory: no scalar registers held for it across the kernel);
-    // in variable-size modes words 14-15 (the payload size) come with the
-    // last tile
-    uint32_t* h = reinterpret_cast<uint32_t*>(A.out_base);
-    uint32_t w = hsrc[lane];
-    if (A.sel && (lane == 2 || lane == 3)) {  // operating point adopted on the device
-      int32_t code0;
-      uint32_t mask0;
-      const bool ok = profiled_point(A, g, code0, mask0);
-      if (!ok && lane == 2) atomicOr(A.status, ST_NOPROFILE);
-      w = lane == 2 ? ((w & ~0xFF00u) | ((mask0 & 0xFFu) << 8)) : (uint32_t)code0;
-    }
-    if (lane < 14 || !variable) h[lane] = w;
-    if (lane == 0) {
-      for (uint64_t i = A.zpad[0]; i < A.zpad[1]; i++) A.out_base[i] = 0;
-      for (uint64_t i = A.zpad[2]; i < A.zpad[3]; i++) A.out_base[i] = 0;
-      if (!variable) *A.d_nbytes = A.area + 4 * (uint64_t)g.budget * (uint64_t)g.nblocks;
-    }
-  }
+  if (tile == 0) write_stream_header(A, hsrc, variable);
   if (lane == 0) {
     uint64_t acc = base;
     for (int i = 0; i < WP * BPW; i++) {

@@ -26,6 +26,8 @@ struct EncArgs {
   uint64_t zpad[4];      // byte ranges [0,1) and [2,3) of index padding to zero
   const int32_t* sel;    // {code, stream mask} a profile left in the workspace, or null
   const int32_t* lag;    // lagged stream choice: each block's own best stream, or null
+  uint8_t* bst;          // variable-size modes, single array: each block's chosen stream
+  uint32_t* ssum;        // variable-size modes, single array: words per superblock of 64 blocks
   Geo g;
 };
 

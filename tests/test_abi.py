@@ -130,7 +130,7 @@ def test_noalloc_encode_refuses_arrays_beyond_its_scratch(A):
     lib.apax_encode_noalloc.argtypes = [C.c_void_p, C.POINTER(A.Params), C.c_void_p, C.c_uint64,
                                         C.c_void_p, C.c_void_p, C.c_void_p]
     import torch
-    # 2^32 int16 samples in 256-sample blocks: 2^24 blocks, 2^22 tiles, 32 MiB of states
+    # 2^32 int16 samples in 256-sample blocks: 2^24 blocks, 16 MiB of chosen streams
     p = A.make_params(torch.int16, (1 << 32,), {"mode": "lossless", "brick": (256,)})
     fake = C.c_void_p(1 << 20)  # never dereferenced: the call returns first
     rc = lib.apax_encode_noalloc(fake, C.byref(p), fake, C.c_uint64(2 ** 64 - 1), fake, None, None)

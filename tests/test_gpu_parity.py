@@ -638,6 +638,7 @@ def test_overlapped_handoff(A):
     ev = torch.cuda.Event()
     A.apax_profile_async_point(xg, params, ws, ev)
     codec.wait_event(ev)
+    A.apax_status_clear(ws2, stream=codec)  # a fresh workspace's status word is undefined
     A.apax_adopt_point(ws, ws2, stream=codec)
     buf, nb = A.apax_encode(xg, dict(params, code=A.CODE_PROFILED), ws=ws2, stream=codec, clear_status=False)
     torch.cuda.synchronize()
