@@ -52,7 +52,9 @@ enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2 };
 enum {
   APAX_OK = 0,
   APAX_E_INVALID = -1,     /* bad parameters */
-  APAX_E_UNSUPPORTED = -2, /* valid request the library does not implement (lossless floats, blocks above 256 samples) */
+  APAX_E_UNSUPPORTED = -2, /* valid request the library does not implement (lossless floats; blocks above
+                              256 samples in the profiler, batches and the server, or on a device whose
+                              workgroups get too little LDS for them) */
   APAX_E_CAPACITY = -3,    /* output or workspace buffer too small */
   APAX_E_CORRUPT = -4,     /* stream fails validation */
   APAX_E_NONFINITE = -5,   /* NaN or Inf in the input */
@@ -134,7 +136,8 @@ int apax_encode_bound(const apax_params* p, uint64_t* bytes);
 int apax_workspace_size(const apax_params* p, uint64_t* bytes);
 
 /* Sec. 4 profiler.  d_x: input array (p->dtype, p->dims).  Synchronous:
- * fills *h_out on return.  p->code is ignored. */
+ * fills *h_out on return.  p->code is ignored.  Blocks of at most 256
+ * samples (larger: APAX_E_UNSUPPORTED). */
 int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* h_out,
                  void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 
@@ -261,7 +264,9 @@ int apax_profile_read(const apax_params* p, apax_profile_result* h_out, const vo
 /* Sec. 6 encoder.  Writes the whole stream (header, index, blocks) to
  * d_stream (cap bytes, >= apax_encode_bound) and its byte length to
  * *d_nbytes (device uint64).  Asynchronous.  Non-finite input sets
- * APAX_E_NONFINITE in the workspace status. */
+ * APAX_E_NONFINITE in the workspace status.  Every block size of Sec. 6
+ * (64..16384 samples); blocks above 256 samples run one workgroup per block
+ * with the block in LDS (up to about 120 KB of it per workgroup at 16384). */
 int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t cap,
                 uint64_t* d_nbytes, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
 

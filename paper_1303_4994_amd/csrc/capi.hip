@@ -13,6 +13,7 @@
 #include "kernels.h"
 #include "monitor.h"
 #include "spectra.h"
+#include "wide.h"
 
 using namespace apax;
 
@@ -141,7 +142,6 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (h.mode == APAX_FIXED_QUALITY && forced_budget < 0) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
   }
-  if (g.G > 64) return APAX_E_UNSUPPORTED;  // blocks above 256 samples: not implemented on the GPU
   g.sz = (int64_t)g.b[0] * g.n[1] * g.n[2];
   g.sy = (int64_t)g.b[1] * g.n[2];
   g.fbx = (int32_t)(g.n[2] / g.b[2]);
@@ -426,6 +426,20 @@ uint64_t enc_need(const HG& h) {
   return ws_cj_off(h) + (h.lagged ? al256(4 * (uint64_t)h.g.nblocks) : 0);
 }
 
+// Blocks above 256 samples run one workgroup per block with the block staged
+// in LDS; the current device must give a workgroup that much.
+bool wide_fits(const Geo& g) {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  int v = dev >= 0 && dev < 64 ? cache[dev] : 0;
+  if (v == 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
+    if (dev >= 0 && dev < 64) cache[dev] = v;
+  }
+  return wide_lds_bytes(g) + sizeof(WideShared) + 256 <= (size_t)v;
+}
+
 // apax_encode's work once the parameters are set up and the buffers checked:
 // d_ws holds at least enc_need(h) bytes.
 int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool profiled, void* d_stream,
@@ -453,9 +467,13 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
     A.zpad[3] = A.area;
   }
   if (profiled) A.sel = ((PState*)d_ws)->sel;
+  const bool wide = h.g.G > 64;
+  if (wide && h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
   if (h.lagged && h.g.nblocks) {
     int32_t* best = cj_ptr(d_ws, h);  // each block's own best stream
-    if ((e = hip_err(launch_stream_choice(h.dtype, h.ndim, A, best, stream)))) return e;
+    if ((e = hip_err(wide ? launch_wide_choice(h.dtype, h.ndim, A, best, stream)
+                          : launch_stream_choice(h.dtype, h.ndim, A, best, stream))))
+      return e;
     A.lag = best;
   }
   if (h.g.nblocks == 0) {
@@ -474,7 +492,7 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
     hipLaunchKernelGGL(k_header_only, dim3(1), dim3(64), 0, stream, Hd);
     return hip_err(hipGetLastError());
   }
-  return hip_err(launch_encode(h.dtype, h.ndim, A, stream));
+  return hip_err(wide ? launch_wide_encode(h.dtype, h.ndim, A, stream) : launch_encode(h.dtype, h.ndim, A, stream));
 }
 
 // ---- scratch of the allocation-free encode: one copy per GPU, held until
@@ -597,6 +615,10 @@ int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* 
   if (!d_y && h.nsamples) return APAX_E_INVALID;
   if (cap < h.nsamples * (uint64_t)h.esz) return APAX_E_CAPACITY;
   A.y = d_y;
+  if (h.g.G > 64) {
+    if (h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
+    return hip_err(launch_wide_decode(h.dtype, h.ndim, A, stream));
+  }
   return hip_err(launch_decode(h.dtype, h.ndim, A, stream));
 }
 
@@ -610,6 +632,10 @@ int apax_decode_dot(const void* h_hdr, const void* d_stream, uint64_t nbytes, co
   if (h.g.nblocks == 0) {
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_out, 2);
     return hip_err(hipGetLastError());
+  }
+  if (h.g.G > 64) {
+    if (!wide_fits(h.g)) return APAX_E_UNSUPPORTED;
+    return hip_err(launch_wide_decode_dot(h.dtype, h.ndim, A, d_w, (double*)partials_ptr(d_ws, h), d_out, stream));
   }
   return hip_err(launch_decode_dot(h.dtype, h.ndim, A, d_w, (double*)partials_ptr(d_ws, h), d_out, stream));
 }
@@ -639,6 +665,7 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
   q.code = 0;
   int e = setup(&q, h);
   if (e) return e;
+  if (h.g.G > 64) return APAX_E_UNSUPPORTED;  // the profile passes hold a block in one wave
   if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
   if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
@@ -1104,7 +1131,7 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
     int e;
     if (op == APAX_OP_ENCODE) {
       if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
-      if (h.lagged) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
+      if (h.lagged || h.g.G > 64) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
       if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
         delete b;
         return batch_error(APAX_E_INVALID, i);
@@ -1116,6 +1143,7 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
       uint16_t budget;
       memcpy(&budget, (const uint8_t*)it.h_hdr + 10, 2);
       if ((e = setup(&q, h, q.mode == APAX_FIXED_RATE ? budget : -1))) { delete b; return batch_error(e, i); }
+      if (h.g.G > 64) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
       uint64_t pw;
       memcpy(&pw, (const uint8_t*)it.h_hdr + 56, 8);
       uint64_t area = area_offset(h);
@@ -1564,7 +1592,7 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   int e;
   if (q->op == APAX_OP_ENCODE) {
     if ((e = setup(&q->item.p, h))) return e;
-    if (h.lagged) return APAX_E_UNSUPPORTED;  // served encodes may share a batch launch
+    if (h.lagged || h.g.G > 64) return APAX_E_UNSUPPORTED;  // served encodes may share a batch launch
     if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
     memset(r.hdr, 0, 64);
   } else {
@@ -1573,6 +1601,7 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
     uint16_t budget;
     memcpy(&budget, (const uint8_t*)q->item.h_hdr + 10, 2);
     if ((e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1))) return e;
+    if (h.g.G > 64) return APAX_E_UNSUPPORTED;
     memcpy(r.hdr, q->item.h_hdr, 64);
     r.r.item.h_hdr = nullptr;
   }

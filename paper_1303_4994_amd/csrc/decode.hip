@@ -74,6 +74,10 @@ __global__ __launch_bounds__(256) void k_dot_reduce(const double* partial, int64
   }
 }
 
+void launch_dot_reduce(const double* partial, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), 0, s, partial, n, out);
+}
+
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_dot_t(const DecArgs& A, const void* w, double* partial, hipStream_t s) {
   constexpr int BPW = 64 / LPB;

@@ -202,6 +202,16 @@ hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* 
 }
 
 // ------------------------------------------------------------ launcher
+void launch_encode_reset(uint32_t* ssum, int64_t nsuper, hipStream_t s) {
+  const int64_t nb = (nsuper + 255) / 256;
+  hipLaunchKernelGGL(k_encode_reset, dim3((unsigned)(nb > 1024 ? 1024 : (nb < 1 ? 1 : nb))), dim3(256), 0, s,
+                     ssum, nsuper);
+}
+
+void launch_encode_scan(const EncArgs& A, int64_t nsuper, hipStream_t s) {
+  hipLaunchKernelGGL(k_encode_scan, dim3(1), dim3(1024), 0, s, A, nsuper);
+}
+
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   constexpr int BPW = 64 / LPB;
@@ -212,10 +222,9 @@ static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
     return hipGetLastError();
   }
   const int64_t nsuper = (A.g.nblocks + 63) / 64;
-  const int64_t nb = (nsuper + 255) / 256;
-  hipLaunchKernelGGL(k_encode_reset, dim3((unsigned)(nb > 1024 ? 1024 : nb)), dim3(256), 0, s, A.ssum, nsuper);
+  launch_encode_reset(A.ssum, nsuper, s);
   hipLaunchKernelGGL((k_encode_size<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), 0, s, A);
-  hipLaunchKernelGGL(k_encode_scan, dim3(1), dim3(1024), 0, s, A, nsuper);
+  launch_encode_scan(A, nsuper, s);
   hipLaunchKernelGGL((k_encode_emit<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
 }
@@ -238,6 +247,7 @@ int lpb_of(const Geo& g) { return g.G <= 16 ? 16 : (g.G <= 32 ? 32 : 64); }
 
 
 int64_t encode_tiles_wp(const Geo& g, int wp) {
+  if (g.G > 64) return g.nblocks;  // blocks above 256 samples: one workgroup each
   int64_t per = (int64_t)wp * (64 / lpb_of(g));
   return (g.nblocks + per - 1) / per;
 }

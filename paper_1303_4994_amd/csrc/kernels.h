@@ -223,6 +223,18 @@ hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 // each block's own best stream into best[nblocks] (lossless; the lagged choice)
 hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
+// variable-size encodes: zero the superblock sums; their exclusive scan, the
+// payload size in the stream header and the byte count
+void launch_encode_reset(uint32_t* ssum, int64_t nsuper, hipStream_t s);
+void launch_encode_scan(const EncArgs& A, int64_t nsuper, hipStream_t s);
+// sum of n binary64 partials in index order into *out
+void launch_dot_reduce(const double* partial, int64_t n, double* out, hipStream_t s);
+// blocks of more than 256 samples (G > 64): one workgroup per block
+hipError_t launch_wide_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
+hipError_t launch_wide_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
+hipError_t launch_wide_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
+hipError_t launch_wide_decode_dot(int dtype, int ndim, DecArgs& A, const void* w, double* partial, double* out,
+                                  hipStream_t s);
 // decode-on-read dot product (partial: one double per tile) and the plain one
 hipError_t launch_decode_dot(int dtype, int ndim, DecArgs& A, const void* w, double* partial, double* out,
                              hipStream_t s);

@@ -48,6 +48,12 @@ VALIDATION = [
     (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x10}),
     (np.int8, (8, 64), {"mode": "lossless", "brick": (2, 32), "stream_mask": 0x28}),
     (np.int8, (8, 64), {"mode": "lossless", "brick": (32, 2)}),
+    # blocks above 256 samples, up to 16384 (Sec. 6)
+    (np.int16, (100000,), {"mode": "lossless", "brick": (16384,)}),
+    (np.int16, (100000,), {"mode": "lossless", "brick": (16388,)}),
+    (np.float32, (300, 300), {"mode": "fixed_rate", "brick": (128, 128), "rate": 4.0}),
+    (np.float64, (8, 64, 64), {"mode": "fixed_quality", "brick": (16, 32, 32), "code": 0}),
+    (np.int8, (8, 64, 64), {"mode": "fixed_rate", "brick": (4, 16, 16), "rate": 2.0, "code": 0}),
     # block and sample counts that would wrap 64-bit products are refused
     (np.float32, (1099509530628, 67108992, 16), {"mode": "fixed_quality", "brick": (2, 2, 16), "code": 0}),
     (np.int16, (1 << 40, 1 << 40, 1 << 40), {"mode": "lossless", "brick": (1, 1, 64)}),
