@@ -51,6 +51,7 @@ typedef struct {
   int64_t nblocks;
   uint32_t mask;   /* effective stream mask for this mode */
   int budget;      /* fixed-rate words per block, 0 otherwise */
+  int target;      /* adaptive rate: target words per block, 0 otherwise */
   int cmin, cmax;  /* admissible gain codes */
   int code;
 } geom;
@@ -64,7 +65,7 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   if (!p || p->size != sizeof(orc_params)) return ORC_E_INVALID;
   if (p->dtype < ORC_I8 || p->dtype > ORC_F64) return ORC_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return ORC_E_INVALID;
-  if (p->mode > ORC_FIXED_QUALITY) return ORC_E_INVALID;
+  if (p->mode > ORC_ADAPTIVE_RATE) return ORC_E_INVALID;
   if (p->flags & ~ORC_FLAG_LAGGED) return ORC_E_INVALID;
   if ((p->flags & ORC_FLAG_LAGGED) && p->mode != ORC_LOSSLESS) return ORC_E_INVALID;
   g->dtype = (int)p->dtype;
@@ -135,6 +136,18 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   }
   if (g->mode == ORC_FIXED_QUALITY) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return ORC_E_INVALID;
+  }
+  if (g->mode == ORC_ADAPTIVE_RATE) {
+    /* target words per block, from the rate as in fixed rate (reading) */
+    double words;
+    if (forced_budget >= 0) {
+      words = forced_budget;
+    } else {
+      if (!(p->rate > 0.0) || !isfinite(p->rate)) return ORC_E_INVALID;
+      words = floor((double)g->B * 8.0 * g->esz / (p->rate * 32.0));
+    }
+    if (words < 1.0 || words > 65535.0) return ORC_E_INVALID;
+    g->target = (int)words;
   }
   return ORC_OK;
 }
@@ -660,7 +673,8 @@ static int check_finite(const geom* g, const void* x) {
 
 static oprule rule_of(const geom* g) {
   oprule r;
-  r.rule = g->mode;
+  /* adaptive rate codes each block as fixed quality at its requested code */
+  r.rule = g->mode == ORC_ADAPTIVE_RATE ? ORC_FIXED_QUALITY : g->mode;
   r.code = g->code;
   r.mask = g->mask;
   r.lag_st = -1;
@@ -684,6 +698,11 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
   oprule r = rule_of(&g);
   const int lagged = (p->flags & ORC_FLAG_LAGGED) != 0;
   if (lagged) r.lag_st = 0;  /* block 0: stream 0 */
+  /* adaptive rate: the controller's window and state (a requested code) */
+  const int adapt = g.mode == ORC_ADAPTIVE_RATE;
+  const int lo = g.code - ORC_ADAPT_HALF < g.cmin ? g.cmin : g.code - ORC_ADAPT_HALF;
+  const int hi = g.code + ORC_ADAPT_HALF - 1 > g.cmax ? g.cmax : g.code + ORC_ADAPT_HALF - 1;
+  int state = g.code;
   uint64_t wpos = 0;
   int cap_words = g.budget ? g.budget : max_block_words(&g);
   uint8_t* lens = o + 64;
@@ -692,9 +711,17 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
     uint32_t* w = (uint32_t*)(void*)(o + area + 4 * wpos);
     int st, cj;
     int64_t bits;
+    if (adapt) r.code = state;
     int nw = do_block(&g, x, j, &r, &s, w, cap_words, &st, &cj, &bits, NULL);
     if (nw < 0) { scratch_free(&s); return ORC_E_INVALID; }
     if (lagged) r.lag_st = st;
+    if (adapt) {
+      /* feedback: one code step towards the target packet size */
+      if (nw < g.target) state += 1;
+      else if (nw > g.target) state -= 1;
+      if (state < lo) state = lo;
+      if (state > hi) state = hi;
+    }
     if (g.mode != ORC_FIXED_RATE) {
       if (j % 64 == 0) put64(sbo + 8 * (j / 64), wpos);
       put16(lens + 2 * j, (uint16_t)nw);
@@ -708,7 +735,7 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
   o[7] = (uint8_t)g.mode;
   o[8] = (uint8_t)g.ndim;
   o[9] = (uint8_t)g.mask;
-  put16(o + 10, (uint16_t)g.budget);
+  put16(o + 10, (uint16_t)(adapt ? g.target : g.budget));
   put32(o + 12, (uint32_t)g.code);
   for (int i = 0; i < 3; i++) put64(o + 16 + 8 * i, i < (int)p->ndim ? p->dims[i] : 0);
   for (int i = 0; i < 3; i++) put16(o + 40 + 2 * i, (uint16_t)(i < (int)p->ndim ? p->brick[i] : 0));
@@ -740,7 +767,7 @@ static int parse_header(const uint8_t* b, uint64_t nbytes, orc_params* p, geom* 
   if (get16(b + 46) != 0) return ORC_E_CORRUPT;
   p->code = (int32_t)get32(b + 12);
   int budget = get16(b + 10);
-  if (p->mode == ORC_FIXED_RATE) {
+  if (p->mode == ORC_FIXED_RATE || p->mode == ORC_ADAPTIVE_RATE) {
     uint32_t B = 1;
     for (int i = 0; i < (int)p->ndim; i++) B *= p->brick[i];
     static const int esz[6] = {0, 1, 2, 4, 4, 8};
@@ -751,7 +778,7 @@ static int parse_header(const uint8_t* b, uint64_t nbytes, orc_params* p, geom* 
     p->rate = 0.0;
   }
   p->target_corr = 0.5;
-  int e = setup_geom_b(p, g, p->mode == ORC_FIXED_RATE ? budget : -1);
+  int e = setup_geom_b(p, g, (p->mode == ORC_FIXED_RATE || p->mode == ORC_ADAPTIVE_RATE) ? budget : -1);
   if (e) return ORC_E_CORRUPT;
   if (g->mask != p->stream_mask) return ORC_E_CORRUPT;
   if (get64(b + 48) != (uint64_t)g->nblocks) return ORC_E_CORRUPT;
@@ -1045,6 +1072,7 @@ static int64_t fits_count(pctx* P, int c) {
 int orc_profile(const void* x, const orc_params* p, orc_profile_result* res) {
   geom g;
   orc_params q = *p;
+  if (q.mode == ORC_ADAPTIVE_RATE) return ORC_E_UNSUPPORTED; /* the loop sets its own codes */
   if (q.mode != ORC_LOSSLESS) q.code = 0; /* the profiler chooses the code */
   int e = setup_geom(&q, &g);
   if (e) return e;

@@ -27,7 +27,19 @@ extern "C" {
 #endif
 
 enum { ORC_I8 = 1, ORC_I16 = 2, ORC_I32 = 3, ORC_F32 = 4, ORC_F64 = 5 };
-enum { ORC_LOSSLESS = 0, ORC_FIXED_RATE = 1, ORC_FIXED_QUALITY = 2 };
+enum { ORC_LOSSLESS = 0, ORC_FIXED_RATE = 1, ORC_FIXED_QUALITY = 2, ORC_ADAPTIVE_RATE = 3 };
+
+/* ORC_ADAPTIVE_RATE (Sec. 6, the attenuator under an adaptive loop that
+ * converges to the desired packet size), reading: a target of
+ * T = floor(B * 8 * esz / (rate * 32)) words per block (1..65535) and a start
+ * code c0 (p->code).  The controller's state is a requested code in the
+ * window [lo, hi] = [max(cmin, c0 - 32), min(cmax, c0 + 31)], starting at c0.
+ * Blocks are visited in order; block j is coded as in fixed quality at
+ * clamp(state, c_floor_j, c_cap_j) (best stream, verbatim allowed) and takes
+ * n_j words; then the state steps by +1 if n_j < T, -1 if n_j > T, 0 if
+ * equal, clamped to the window.  The stream container is the variable-size
+ * one; its header carries T in the budget field and c0 in the code field. */
+#define ORC_ADAPT_HALF 32
 enum {
   ORC_OK = 0,
   ORC_E_INVALID = -1,
@@ -43,13 +55,13 @@ typedef struct {
   uint32_t size;        /* sizeof(orc_params) */
   uint32_t dtype;       /* ORC_I8 .. ORC_F64 */
   uint32_t ndim;        /* 1..3 */
-  uint32_t mode;        /* ORC_LOSSLESS, ORC_FIXED_RATE, ORC_FIXED_QUALITY */
+  uint32_t mode;        /* ORC_LOSSLESS, ORC_FIXED_RATE, ORC_FIXED_QUALITY, ORC_ADAPTIVE_RATE */
   uint64_t dims[3];     /* slow -> fast, first ndim entries used */
   uint32_t brick[3];    /* slow -> fast, first ndim entries used */
   uint32_t stream_mask; /* bit s allows stream s; 0 = every stream of ndim */
-  double rate;          /* fixed-rate: input bits per encoded bit */
+  double rate;          /* fixed / adaptive rate: input bits per encoded bit */
   double target_corr;   /* fixed-quality: correlation target */
-  int32_t code;         /* gain code (fixed-rate start code / fixed-quality code) */
+  int32_t code;         /* gain code (fixed-rate / adaptive start code, fixed-quality code) */
   uint32_t flags;       /* ORC_FLAG_LAGGED: lossless only */
 } orc_params;
 

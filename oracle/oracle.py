@@ -1,7 +1,7 @@
 """ctypes binding of the CPU oracle (test infrastructure only).
 
 Everything here works on host numpy arrays.  Parameters are plain dicts:
-    {"mode": "lossless" | "fixed_rate" | "fixed_quality",
+    {"mode": "lossless" | "fixed_rate" | "fixed_quality" | "adaptive_rate",
      "brick": (..), "stream_mask": 0, "rate": 4.0, "target_corr": 0.99999,
      "code": 0}
 The array's dtype and shape give the dtype and dims.
@@ -15,7 +15,8 @@ import numpy as np
 from . import build as _build
 
 I8, I16, I32, F32, F64 = 1, 2, 3, 4, 5
-LOSSLESS, FIXED_RATE, FIXED_QUALITY = 0, 1, 2
+LOSSLESS, FIXED_RATE, FIXED_QUALITY, ADAPTIVE_RATE = 0, 1, 2, 3
+ADAPT_HALF = 32  # the adaptive loop's window: start code - 32 .. start code + 31
 E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE = -1, -2, -3, -4, -5
 NEAR_TIE = 1
 NCURVE = 17
@@ -23,7 +24,8 @@ NCURVE = 17
 DTYPES = {np.dtype(np.int8): I8, np.dtype(np.int16): I16, np.dtype(np.int32): I32,
           np.dtype(np.float32): F32, np.dtype(np.float64): F64}
 NP_OF = {v: k for k, v in DTYPES.items()}
-MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY}
+MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY,
+         "adaptive_rate": ADAPTIVE_RATE}
 
 
 class OracleError(RuntimeError):
