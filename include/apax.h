@@ -47,8 +47,23 @@ extern "C" {
 /* dtypes (the integer and float types of the paper's Table 2) */
 enum { APAX_I8 = 1, APAX_I16 = 2, APAX_I32 = 3, APAX_F32 = 4, APAX_F64 = 5 };
 /* modes: lossless (integers only, unit gain), fixed rate (per-block word
- * budget, Sec. 6 "compressed packet size"), fixed quality (correlation target) */
-enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2 };
+ * budget, Sec. 6 "compressed packet size"), fixed quality (correlation
+ * target), adaptive rate (Sec. 6: the attenuator's gain under a feedback loop
+ * that converges to the desired packet size).
+ * Adaptive rate: a target of T = floor(B * 8 * esz / (rate * 32)) words per
+ * block (1..65535) and a start code c0 = p->code.  The controller's state is a
+ * requested code in [max(cmin, c0 - APAX_ADAPT_HALF), min(cmax, c0 +
+ * APAX_ADAPT_HALF - 1)], starting at c0; blocks are coded in order, block j
+ * as in fixed quality at clamp(state, c_floor_j, c_cap_j) (best stream,
+ * verbatim allowed) in n_j words, after which the state steps by +1 if
+ * n_j < T, -1 if n_j > T, 0 if equal, clamped to the window.  The stream is
+ * the variable-size container (its header holds T in the budget field and c0
+ * in the code field) and decodes like any other.  The loop runs as a parallel
+ * scan over per-block transition maps, exactly reproducing the sequential
+ * order.  Not accepted by the profiler, batches, the server or
+ * APAX_CODE_PROFILED (APAX_E_UNSUPPORTED). */
+enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2, APAX_ADAPTIVE_RATE = 3 };
+#define APAX_ADAPT_HALF 32
 enum {
   APAX_OK = 0,
   APAX_E_INVALID = -1,     /* bad parameters */
@@ -75,7 +90,7 @@ typedef struct apax_params {
   uint32_t size;        /* = sizeof(apax_params) */
   uint32_t dtype;       /* APAX_I8 .. APAX_F64 */
   uint32_t ndim;        /* 1..3 */
-  uint32_t mode;        /* APAX_LOSSLESS / APAX_FIXED_RATE / APAX_FIXED_QUALITY */
+  uint32_t mode;        /* APAX_LOSSLESS / APAX_FIXED_RATE / APAX_FIXED_QUALITY / APAX_ADAPTIVE_RATE */
   uint64_t dims[3];     /* array extent, slow -> fast; first ndim entries used */
   uint32_t brick[3];    /* block (brick) extent, slow -> fast; product B in
                            [64, 16384], B % 4 == 0 (Sec. 6), brick[ndim-1] % 4 == 0 */

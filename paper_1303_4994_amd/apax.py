@@ -6,7 +6,7 @@ compute runs in the HIP library: if libapax.so is missing this module raises
 at import time -- there is no CPU fallback.
 
 Parameters are dicts:
-    {"mode": "lossless" | "fixed_rate" | "fixed_quality",
+    {"mode": "lossless" | "fixed_rate" | "fixed_quality" | "adaptive_rate",
      "brick": (..), "stream_mask": 0, "rate": 4.0, "target_corr": 0.99999,
      "code": 0}
 dtype and dims come from the tensor.
@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapax.so")
 
 I8, I16, I32, F32, F64 = 1, 2, 3, 4, 5
-LOSSLESS, FIXED_RATE, FIXED_QUALITY = 0, 1, 2
+LOSSLESS, FIXED_RATE, FIXED_QUALITY, ADAPTIVE_RATE = 0, 1, 2, 3
 OK, E_INVALID, E_UNSUPPORTED, E_CAPACITY, E_CORRUPT, E_NONFINITE, E_HIP, E_INTERNAL = \
     0, -1, -2, -3, -4, -5, -6, -7
 NEAR_TIE = 1
@@ -34,7 +34,8 @@ CODE_PROFILED = -(1 << 31)  # apax_encode: adopt the code and mask of the profil
 _DT = {torch.int8: I8, torch.int16: I16, torch.int32: I32, torch.float32: F32,
        torch.float64: F64}
 _TORCH_OF = {v: k for k, v in _DT.items()}
-_MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY}
+_MODES = {"lossless": LOSSLESS, "fixed_rate": FIXED_RATE, "fixed_quality": FIXED_QUALITY,
+          "adaptive_rate": ADAPTIVE_RATE}
 
 
 class ApaxError(RuntimeError):

@@ -58,12 +58,18 @@ void magic(int64_t d, uint32_t& m, int32_t& sh) {
 
 // Validation of apax_params (the rules of include/apax.h).  forced_budget >= 0
 // takes the fixed-rate budget from a stream header instead of the rate.
+// the budget field of a stream header as setup()'s forced budget: fixed rate
+// (words per block) and adaptive rate (target words per block) only
+int header_budget(uint32_t mode, int budget) {
+  return (mode == APAX_FIXED_RATE || mode == APAX_ADAPTIVE_RATE) ? budget : -1;
+}
+
 int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   memset(&h, 0, sizeof(h));
   if (!p || p->size != sizeof(apax_params)) return APAX_E_INVALID;
   if (p->dtype < APAX_I8 || p->dtype > APAX_F64) return APAX_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return APAX_E_INVALID;
-  if (p->mode > APAX_FIXED_QUALITY) return APAX_E_INVALID;
+  if (p->mode > APAX_ADAPTIVE_RATE) return APAX_E_INVALID;
   if (p->flags & ~APAX_FLAG_LAGGED) return APAX_E_INVALID;
   if ((p->flags & APAX_FLAG_LAGGED) && p->mode != APAX_LOSSLESS) return APAX_E_INVALID;
   h.lagged = (p->flags & APAX_FLAG_LAGGED) != 0;
@@ -142,6 +148,22 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (h.mode == APAX_FIXED_QUALITY && forced_budget < 0) {
     if (!(p->target_corr > 0.0 && p->target_corr <= 1.0)) return APAX_E_INVALID;
   }
+  g.target = g.alo = g.awd = 0;
+  if (h.mode == APAX_ADAPTIVE_RATE) {
+    // target words per block (from the rate as in fixed rate) and the
+    // controller's window of requested codes around the start code
+    double words;
+    if (forced_budget >= 0) {
+      words = forced_budget;
+    } else {
+      if (!(p->rate > 0.0) || !isfinite(p->rate)) return APAX_E_INVALID;
+      words = floor((double)g.B * 8.0 * h.esz / (p->rate * 32.0));
+    }
+    if (words < 1.0 || words > 65535.0) return APAX_E_INVALID;
+    g.target = (int32_t)words;
+    g.alo = std::max(g.cmin, g.code - APAX_ADAPT_HALF);
+    g.awd = std::min(g.cmax, g.code + APAX_ADAPT_HALF - 1) - g.alo + 1;
+  }
   g.sz = (int64_t)g.b[0] * g.n[1] * g.n[2];
   g.sy = (int64_t)g.b[1] * g.n[2];
   g.fbx = (int32_t)(g.n[2] / g.b[2]);
@@ -184,7 +206,7 @@ void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
   b[7] = (uint8_t)h.mode;
   b[8] = (uint8_t)h.ndim;
   b[9] = (uint8_t)h.g.mask;
-  put16(10, (uint16_t)h.g.budget);
+  put16(10, (uint16_t)(h.mode == APAX_ADAPTIVE_RATE ? h.g.target : h.g.budget));
   put32(12, (uint32_t)h.g.code);
   for (int i = 0; i < 3; i++) put64(16 + 8 * i, i < h.ndim ? p->dims[i] : 0);
   for (int i = 0; i < 3; i++) put16(40 + 2 * i, (uint16_t)(i < h.ndim ? p->brick[i] : 0));
@@ -211,7 +233,9 @@ uint64_t ws_bst_off(const HG& h) { (void)h; return al256(sizeof(PState)); }
 uint64_t ws_ssum_off(const HG& h) { return ws_bst_off(h) + al256((uint64_t)h.g.nblocks); }
 uint64_t ws_cj_off(const HG& h) { return ws_ssum_off(h) + al256(4 * (((uint64_t)h.g.nblocks + 63) / 64)); }
 uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
-uint64_t ws_need(const HG& h) { return ws_part_off(h) + partial_bytes(h); }
+// adaptive rate: the controller's maps and states after the per-block codes
+uint64_t adapt_need(const HG& h) { return h.mode == APAX_ADAPTIVE_RATE ? adapt_bytes(h.g.nblocks) : 0; }
+uint64_t ws_need(const HG& h) { return ws_part_off(h) + std::max(partial_bytes(h), adapt_need(h)); }
 
 void* partials_ptr(void* ws, const HG& h) { return (uint8_t*)ws + ws_part_off(h); }
 int32_t* cj_ptr(void* ws, const HG& h) { return (int32_t*)((uint8_t*)ws + ws_cj_off(h)); }
@@ -363,15 +387,15 @@ int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
     else if (dims[i] || brick[i]) return APAX_E_CORRUPT;
   }
   p.target_corr = 0.5;
-  if (p.mode == APAX_FIXED_RATE) {
+  if (p.mode == APAX_FIXED_RATE || p.mode == APAX_ADAPTIVE_RATE) {
     if (budget == 0) return APAX_E_CORRUPT;
   } else if (budget != 0) {
     return APAX_E_CORRUPT;
   }
   HG h;
-  if (setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1) != APAX_OK) return APAX_E_CORRUPT;
+  if (setup(&p, h, header_budget(p.mode, budget)) != APAX_OK) return APAX_E_CORRUPT;
   if (h.g.mask != p.stream_mask || (uint64_t)h.g.nblocks != nblocks) return APAX_E_CORRUPT;
-  if (p.mode == APAX_FIXED_RATE) {
+  if (p.mode == APAX_FIXED_RATE || p.mode == APAX_ADAPTIVE_RATE) {
     uint32_t B = 1;
     for (int i = 0; i < (int)p.ndim; i++) B *= p.brick[i];
     p.rate = (double)B * 8.0 * h.esz / (32.0 * (double)budget);
@@ -386,7 +410,7 @@ int apax_stream_size(const void* h_hdr, uint64_t n, uint64_t* nbytes) {
   const int e = apax_stream_info(h_hdr, n, &p);
   if (e) return e;
   HG h;
-  if (setup(&p, h, p.mode == APAX_FIXED_RATE ? (int)(((const uint16_t*)h_hdr)[5]) : -1) != APAX_OK)
+  if (setup(&p, h, header_budget(p.mode, ((const uint16_t*)h_hdr)[5])) != APAX_OK)
     return APAX_E_CORRUPT;
   uint64_t words;
   memcpy(&words, (const uint8_t*)h_hdr + 56, 8);
@@ -423,6 +447,7 @@ namespace {
 // chosen stream per block and one word count per superblock of 64 blocks
 // (variable-size modes) and, for the lagged choice, one best stream per block.
 uint64_t enc_need(const HG& h) {
+  if (h.mode == APAX_ADAPTIVE_RATE) return ws_part_off(h) + adapt_need(h);
   return ws_cj_off(h) + (h.lagged ? al256(4 * (uint64_t)h.g.nblocks) : 0);
 }
 
@@ -475,6 +500,12 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
                           : launch_stream_choice(h.dtype, h.ndim, A, best, stream))))
       return e;
     A.lag = best;
+  }
+  if (h.mode == APAX_ADAPTIVE_RATE && h.g.nblocks) {
+    // the loop's requested code of every block, then the encode at those codes
+    int32_t* bcode = cj_ptr(d_ws, h);
+    if ((e = hip_err(launch_adapt(h.dtype, h.ndim, A, (uint8_t*)d_ws + ws_part_off(h), bcode, stream)))) return e;
+    A.bcode = bcode;
   }
   if (h.g.nblocks == 0) {
     HdrArgs Hd;
@@ -537,6 +568,7 @@ int apax_encode(const void* d_x, const apax_params* p, void* d_stream, uint64_t 
   HG h;
   const bool profiled = p && p->code == APAX_CODE_PROFILED;
   int e;
+  if (profiled && p->mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;  // needs its start code
   if (profiled) {
     apax_params q = *p;
     q.code = 0;  // placeholder; the kernels read the profiled code on the device
@@ -584,7 +616,7 @@ static int decode_setup(const void* h_hdr, const void* d_stream, uint64_t nbytes
   if (e) return e;
   uint16_t budget;
   memcpy(&budget, (const uint8_t*)h_hdr + 10, 2);
-  e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1);
+  e = setup(&p, h, header_budget(p.mode, budget));
   if (e) return e == APAX_E_UNSUPPORTED ? e : APAX_E_CORRUPT;
   if (!d_stream || !d_ws) return APAX_E_INVALID;
   if (((uintptr_t)d_stream & 15) || ((uintptr_t)d_ws & 15)) return APAX_E_INVALID;
@@ -666,6 +698,7 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
   int e = setup(&q, h);
   if (e) return e;
   if (h.g.G > 64) return APAX_E_UNSUPPORTED;  // the profile passes hold a block in one wave
+  if (h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;  // the loop sets its own codes
   if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
   if (ws_bytes < ws_need(h)) return APAX_E_CAPACITY;
@@ -1131,7 +1164,7 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
     int e;
     if (op == APAX_OP_ENCODE) {
       if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
-      if (h.lagged || h.g.G > 64) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
+      if (h.lagged || h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
       if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
         delete b;
         return batch_error(APAX_E_INVALID, i);
@@ -1142,8 +1175,8 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
       if (!it.h_hdr || (e = apax_stream_info(it.h_hdr, 64, &q))) { delete b; return batch_error(APAX_E_CORRUPT, i); }
       uint16_t budget;
       memcpy(&budget, (const uint8_t*)it.h_hdr + 10, 2);
-      if ((e = setup(&q, h, q.mode == APAX_FIXED_RATE ? budget : -1))) { delete b; return batch_error(e, i); }
-      if (h.g.G > 64) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
+      if ((e = setup(&q, h, header_budget(q.mode, budget)))) { delete b; return batch_error(e, i); }
+      if (h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
       uint64_t pw;
       memcpy(&pw, (const uint8_t*)it.h_hdr + 56, 8);
       uint64_t area = area_offset(h);
@@ -1592,7 +1625,8 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   int e;
   if (q->op == APAX_OP_ENCODE) {
     if ((e = setup(&q->item.p, h))) return e;
-    if (h.lagged || h.g.G > 64) return APAX_E_UNSUPPORTED;  // served encodes may share a batch launch
+    // served encodes may share a batch launch
+    if (h.lagged || h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
     if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
     memset(r.hdr, 0, 64);
   } else {
@@ -1600,8 +1634,8 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
     if (!q->item.h_hdr || apax_stream_info(q->item.h_hdr, 64, &p)) return APAX_E_CORRUPT;
     uint16_t budget;
     memcpy(&budget, (const uint8_t*)q->item.h_hdr + 10, 2);
-    if ((e = setup(&p, h, p.mode == APAX_FIXED_RATE ? budget : -1))) return e;
-    if (h.g.G > 64) return APAX_E_UNSUPPORTED;
+    if ((e = setup(&p, h, header_budget(p.mode, budget)))) return e;
+    if (h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
     memcpy(r.hdr, q->item.h_hdr, 64);
     r.r.item.h_hdr = nullptr;
   }

@@ -14,7 +14,7 @@
 namespace apax {
 
 enum { DT_I8 = 1, DT_I16 = 2, DT_I32 = 3, DT_F32 = 4, DT_F64 = 5 };
-enum { M_LOSSLESS = 0, M_RATE = 1, M_QUALITY = 2 };
+enum { M_LOSSLESS = 0, M_RATE = 1, M_QUALITY = 2, M_ADAPT = 3 };
 enum : uint32_t { ST_NONFINITE = 1u, ST_CORRUPT = 2u, ST_INTERNAL = 4u, ST_NOPROFILE = 8u };
 
 template <typename T> struct Traits;
@@ -49,6 +49,9 @@ struct Geo {
   int64_t sz, sy;
   int32_t fbx, fby, fbz;
   int32_t dense_ok;
+  // adaptive rate: target words per block, the controller's window of
+  // requested codes [alo, alo + awd)
+  int32_t target, alo, awd, pad_;
 };
 
 // Division of a numerator below 2^31 by a divisor known on the host
@@ -153,6 +156,15 @@ __device__ __forceinline__ T to_out(double y) {
     r = r < lo ? lo : (r > hi ? hi : r);
     return (T)(int32_t)r;
   }
+}
+
+// Adaptive rate (Sec. 6 feedback loop): the controller's next state for a
+// block of n words at state w: one step towards the target T, inside the
+// window of wd states.
+__device__ __forceinline__ uint8_t adapt_next(int w, int n, int T, int wd) {
+  int s = w + (n < T ? 1 : (n > T ? -1 : 0));
+  s = s < 0 ? 0 : (s > wd - 1 ? wd - 1 : s);
+  return (uint8_t)s;
 }
 
 // ------------------------------------------------------------ W-bit wrap

@@ -6,6 +6,14 @@
 
 namespace apax {
 
+// adaptive rate: the block's own requested code (wave-uniform with one block
+// per wave)
+template <int LPB>
+__device__ __forceinline__ void block_code(const EncArgs& A, bool ok, int64_t j, int32_t& code0) {
+  code0 = ok ? A.bcode[j] : 0;
+  if constexpr (LPB == 64) code0 = __builtin_amdgcn_readfirstlane(code0);
+}
+
 // zero the superblock word counts of a variable-size encode
 __global__ void k_encode_reset(uint32_t* ssum, int64_t nsuper) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsuper; i += (int64_t)gridDim.x * blockDim.x)
@@ -30,6 +38,7 @@ __global__ __launch_bounds__(WPG * 64) void k_encode_size(EncArgs A) {
   B_ b;
   b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane_id() / LPB,
          NDIM >= 2 ? s_xch + wave * XCH : nullptr);
+  if (A.bcode) block_code<LPB>(A, b.blk_ok, b.j, code0);
   int c, st;
   int32_t best, a[4];
   analyze_block<T, LPB, NDIM>(A, b, mode, code0, mask0, c, st, best, a);
@@ -94,6 +103,7 @@ __global__ __launch_bounds__(WPG * 64) void k_encode_emit(EncArgs A) {
   if (blockIdx.x == 0 && wave == 0) write_stream_header(A, hsrc, true);
   B_ b;
   b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * XCH : nullptr);
+  if (A.bcode) block_code<LPB>(A, b.blk_ok, b.j, code0);
   {
     T xv4[4];
     b.fetch((const T*)A.x, g, xv4);

@@ -28,6 +28,7 @@ struct EncArgs {
   const int32_t* lag;    // lagged stream choice: each block's own best stream, or null
   uint8_t* bst;          // variable-size modes, single array: each block's chosen stream
   uint32_t* ssum;        // variable-size modes, single array: words per superblock of 64 blocks
+  const int32_t* bcode;  // adaptive rate: each block's requested code, or null
   Geo g;
 };
 
@@ -233,6 +234,12 @@ void launch_dot_reduce(const double* partial, int64_t n, double* out, hipStream_
 hipError_t launch_wide_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
 hipError_t launch_wide_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
 hipError_t launch_wide_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);
+hipError_t launch_wide_table(int dtype, int ndim, const EncArgs& A, uint8_t* tab, hipStream_t s);
+// adaptive rate: the controller's state of every block (the loop as a scan
+// over per-block transition maps) as requested codes into bcode; `region`
+// holds adapt_bytes(nblocks)
+uint64_t adapt_bytes(int64_t nblocks);
+hipError_t launch_adapt(int dtype, int ndim, const EncArgs& A, void* region, int32_t* bcode, hipStream_t s);
 hipError_t launch_wide_decode_dot(int dtype, int ndim, DecArgs& A, const void* w, double* partial, double* out,
                                   hipStream_t s);
 // decode-on-read dot product (partial: one double per tile) and the plain one

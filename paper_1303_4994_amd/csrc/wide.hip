@@ -7,7 +7,7 @@
 
 namespace apax {
 
-enum { WK_RATE = 0, WK_SIZE = 1, WK_EMIT = 2, WK_CHOICE = 3 };
+enum { WK_RATE = 0, WK_SIZE = 1, WK_EMIT = 2, WK_CHOICE = 3, WK_TABLE = 4 };
 
 template <typename T, int NDIM>
 struct WEnc {
@@ -343,9 +343,11 @@ struct WEnc {
 // One block per workgroup.  KIND: WK_RATE fixed rate (search and store at
 // j * budget), WK_SIZE variable-size first pass (length, chosen stream,
 // superblock sums), WK_EMIT second pass (store at the block's offset),
-// WK_CHOICE the lagged choice's first pass (each block's own best stream).
+// WK_CHOICE the lagged choice's first pass (each block's own best stream into
+// aux, int32 per block), WK_TABLE the adaptive rate's transition map of the
+// block (aux: 64 bytes per block).
 template <typename T, int NDIM, int KIND>
-__global__ __launch_bounds__(WIDE_MAXT) void k_wide_enc(EncArgs A, int32_t* best_st) {
+__global__ __launch_bounds__(WIDE_MAXT) void k_wide_enc(EncArgs A, void* aux) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ WideShared sh;
   const uint32_t* hsrc =
@@ -356,6 +358,7 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_enc(EncArgs A, int32_t* best
   int32_t code0;
   uint32_t mask0;
   profiled_point(A, g, code0, mask0);
+  if (A.bcode) code0 = A.bcode[j];  // adaptive rate: the block's own requested code
   if ((KIND == WK_RATE || KIND == WK_EMIT) && j == 0 && threadIdx.x < 64)
     write_stream_header(A, hsrc, KIND == WK_EMIT);
   WEnc<T, NDIM> b;
@@ -368,7 +371,25 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_enc(EncArgs A, int32_t* best
   if constexpr (KIND == WK_CHOICE) {
     int32_t best;
     const int st = b.choose(g.mask, best);
-    if (threadIdx.x == 0) best_st[j] = st;
+    if (threadIdx.x == 0) static_cast<int32_t*>(aux)[j] = st;
+  } else if constexpr (KIND == WK_TABLE) {
+    uint8_t* row = static_cast<uint8_t*>(aux) + 64 * j;
+    int cprev = 0x7FFFFFFF, nprev = 0;
+    for (int w = 0; w < 64; w++) {
+      if (w >= g.awd) {
+        if (threadIdx.x == 0) row[w] = (uint8_t)w;
+        continue;
+      }
+      const int c = clampc(g.alo + w, b.cf, b.cc);
+      if (c != cprev) {
+        b.quantize(c, false);
+        int32_t best;
+        b.choose(g.mask, best);
+        nprev = (best + 31) >> 5;
+        cprev = c;
+      }
+      if (threadIdx.x == 0) row[w] = adapt_next(w, nprev, g.target, g.awd);
+    }
   } else if constexpr (KIND == WK_RATE) {
     const uint32_t emask = mask0 & 0x7Fu;
     int32_t best;
@@ -745,7 +766,7 @@ static hipError_t wide_lds_attr(K kernel, size_t lds) {
 }
 
 template <typename T, int NDIM, int KIND>
-static hipError_t wide_enc_t(const EncArgs& A, int32_t* best, hipStream_t s) {
+static hipError_t wide_enc_t(const EncArgs& A, void* best, hipStream_t s) {
   const size_t lds = wide_lds_bytes(A.g);
   hipError_t e = wide_lds_attr(k_wide_enc<T, NDIM, KIND>, lds);
   if (e != hipSuccess) return e;
@@ -789,6 +810,24 @@ static hipError_t wide_choice_t(const EncArgs& A, int ndim, int32_t* best, hipSt
   if (ndim == 1) return wide_enc_t<T, 1, WK_CHOICE>(A, best, s);
   if (ndim == 2) return wide_enc_t<T, 2, WK_CHOICE>(A, best, s);
   return wide_enc_t<T, 3, WK_CHOICE>(A, best, s);
+}
+
+template <typename T>
+static hipError_t wide_table_t(const EncArgs& A, int ndim, uint8_t* tab, hipStream_t s) {
+  if (ndim == 1) return wide_enc_t<T, 1, WK_TABLE>(A, tab, s);
+  if (ndim == 2) return wide_enc_t<T, 2, WK_TABLE>(A, tab, s);
+  return wide_enc_t<T, 3, WK_TABLE>(A, tab, s);
+}
+
+hipError_t launch_wide_table(int dtype, int ndim, const EncArgs& A, uint8_t* tab, hipStream_t s) {
+  if (A.g.nblocks == 0) return hipSuccess;
+  switch (dtype) {
+    case DT_I8: return wide_table_t<int8_t>(A, ndim, tab, s);
+    case DT_I16: return wide_table_t<int16_t>(A, ndim, tab, s);
+    case DT_I32: return wide_table_t<int32_t>(A, ndim, tab, s);
+    case DT_F32: return wide_table_t<float>(A, ndim, tab, s);
+    default: return wide_table_t<double>(A, ndim, tab, s);
+  }
 }
 
 hipError_t launch_wide_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s) {

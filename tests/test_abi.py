@@ -54,6 +54,12 @@ VALIDATION = [
     (np.float32, (300, 300), {"mode": "fixed_rate", "brick": (128, 128), "rate": 4.0}),
     (np.float64, (8, 64, 64), {"mode": "fixed_quality", "brick": (16, 32, 32), "code": 0}),
     (np.int8, (8, 64, 64), {"mode": "fixed_rate", "brick": (4, 16, 16), "rate": 2.0, "code": 0}),
+    # adaptive rate (Sec. 6 feedback loop): target words from the rate
+    (np.float32, (64, 64), {"mode": "adaptive_rate", "brick": (16, 16), "rate": 4.0, "code": 20}),
+    (np.float32, (64, 64), {"mode": "adaptive_rate", "brick": (16, 16), "rate": 400.0, "code": 20}),
+    (np.float64, (64, 64), {"mode": "adaptive_rate", "brick": (16, 16), "rate": 4.0, "code": 16384}),
+    (np.int16, (5000,), {"mode": "adaptive_rate", "brick": (64,), "rate": 2.0, "code": -600}),
+    (np.int16, (5000,), {"mode": "adaptive_rate", "brick": (64,), "rate": 2.0, "code": -6}),
     # block and sample counts that would wrap 64-bit products are refused
     (np.float32, (1099509530628, 67108992, 16), {"mode": "fixed_quality", "brick": (2, 2, 16), "code": 0}),
     (np.int16, (1 << 40, 1 << 40, 1 << 40), {"mode": "lossless", "brick": (1, 1, 64)}),
@@ -84,7 +90,8 @@ def test_validation_and_bound_match_oracle(A, dt, shape, params):
 def test_stream_info_parses_oracle_streams(A):
     x = np.arange(3000, dtype=np.int16).reshape(30, 100) // 3
     for params in ({"mode": "lossless", "brick": (4, 16)},
-                   {"mode": "fixed_rate", "brick": (4, 16), "rate": 3.0, "code": -20}):
+                   {"mode": "fixed_rate", "brick": (4, 16), "rate": 3.0, "code": -20},
+                   {"mode": "adaptive_rate", "brick": (4, 16), "rate": 3.0, "code": -20}):
         s = O.encode(x, params)
         info = A.apax_stream_info(bytes(s[:64]))
         assert info["shape"] == x.shape and info["brick"] == params["brick"]

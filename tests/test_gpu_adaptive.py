@@ -1,0 +1,122 @@
+"""GPU parity of the adaptive-rate mode (Sec. 6: the attenuator's gain under a
+feedback loop towards the packet size).  The library runs the sequential loop
+as a parallel scan over per-block transition maps; its streams must equal the
+oracle's block-by-block loop byte for byte and decode identically, for every
+dtype, 1-/2-/3-d bricks, blocks above 256 samples, windows clipped at the code
+range, and the 4096^2 fp32 field at 4:1."""
+import numpy as np
+import pytest
+
+import brute
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1303_4994_amd import apax
+    return apax
+
+
+def smooth(dt, shape, seed):
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(seed)
+    t = np.arange(n)
+    v = np.sin(2 * np.pi * 0.004 * t) + 0.2 * np.sin(2 * np.pi * 0.05 * t) + 0.01 * rng.standard_normal(n)
+    v = v * (1.0 + 0.8 * np.sin(2 * np.pi * t / n))
+    if np.dtype(dt).kind == "i":
+        return np.rint(v / np.abs(v).max() * 0.4 * np.iinfo(dt).max).astype(dt).reshape(shape)
+    return (v * 50.0).astype(dt).reshape(shape)
+
+
+CASES = [
+    ("f32-1d-B64", np.float32, (64 * 300 + 20,), {"brick": (64,), "rate": 4.0, "code": 40}),
+    ("f64-2d-8x8", np.float64, (70, 90), {"brick": (8, 8), "rate": 6.0, "code": 250}),
+    ("i16-1d-B128", np.int16, (128 * 200,), {"brick": (128,), "rate": 3.0, "code": -2}),
+    ("i32-3d-2x4x8", np.int32, (12, 20, 24), {"brick": (2, 4, 8), "rate": 2.5, "code": -30}),
+    ("i8-2d-8x16", np.int8, (60, 64), {"brick": (8, 16), "rate": 1.5, "code": -4}),
+    ("f32-2d-16x16", np.float32, (300, 260), {"brick": (16, 16), "rate": 4.0, "code": 23}),
+    ("f32-1d-B512-wide", np.float32, (512 * 40 + 30,), {"brick": (512,), "rate": 5.0, "code": 60}),
+    ("f64-3d-8x16x16-wide", np.float64, (20, 40, 50), {"brick": (8, 16, 16), "rate": 8.0, "code": 200}),
+    ("f32-1d-top-of-range", np.float32, (64 * 100,), {"brick": (64,), "rate": 0.1, "code": 16380}),
+    ("f32-1d-one-word-target", np.float32, (64 * 100,), {"brick": (64,), "rate": 64.0, "code": -17100}),
+    ("i16-1d-many-groups", np.int16, (64 * 70000,), {"brick": (64,), "rate": 3.0, "code": -40}),
+]
+
+
+def roundtrip(A, x, params):
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, tuple(x.shape), params, DEV)
+    buf, nb = A.apax_encode(xg, params, ws=ws)
+    assert A.apax_status(ws) == 0
+    n = int(nb.item())
+    got = buf[:n].cpu().numpy()
+    y = A.apax_decode(buf, n, ws=ws)
+    assert A.apax_status(ws) == 0
+    return got, y.cpu().numpy()
+
+
+def first_block_diff(got, exp):
+    sg, se = brute.Stream(got), brute.Stream(exp)
+    for j in range(se.nblocks):
+        if not np.array_equal(sg.block(j), se.block(j)):
+            return j, sg.lens[j], se.lens[j], [hex(int(w)) for w in sg.block(j)[:2]], [hex(int(w)) for w in se.block(j)[:2]]
+    return None
+
+
+@pytest.mark.parametrize("name,dt,shape,params", CASES, ids=[c[0] for c in CASES])
+def test_adaptive_equals_oracle_loop(A, name, dt, shape, params):
+    print(f"case {name}", flush=True)
+    x = smooth(dt, shape, 5)
+    p = dict(params, mode="adaptive_rate")
+    exp = O.encode(x, p)
+    got, y = roundtrip(A, x, p)
+    if got.size != exp.size or not np.array_equal(got, exp):
+        pytest.fail(f"stream differs ({got.size} vs {exp.size} bytes), first block {first_block_diff(got, exp)}")
+    assert np.array_equal(y.view(np.uint8), O.decode(exp).view(np.uint8))
+
+
+@pytest.mark.timeout(900)
+def test_adaptive_full_field(A):
+    """The 4096^2 fp32 field (16x16 bricks) at a 4:1 target from code 23:
+    65536 blocks, so the scan composes two levels of maps."""
+    x = synth.grf2d(4096, 4096)
+    p = {"mode": "adaptive_rate", "brick": (16, 16), "rate": 4.0, "code": 23}
+    print("case 4096^2 adaptive", flush=True)
+    exp = O.encode(x, p)
+    got, y = roundtrip(A, x, p)
+    assert got.size == exp.size and np.array_equal(got, exp), first_block_diff(got, exp)
+    assert np.array_equal(y.view(np.uint8), O.decode(exp).view(np.uint8))
+    st = brute.Stream(got)
+    tail = np.array(st.lens[len(st.lens) // 2:], np.float64)
+    assert abs(tail.mean() - st.budget) <= 0.1 * st.budget  # the loop holds the target
+
+
+def test_adaptive_noalloc_and_refusals(A):
+    x = smooth(np.float32, (64 * 500,), 2)
+    p = {"mode": "adaptive_rate", "brick": (64,), "rate": 4.0, "code": 40}
+    xg = torch.from_numpy(x).to(DEV)
+    exp = O.encode(x, p)
+    bound = A.apax_encode_bound(xg.dtype, tuple(x.shape), p)
+    out = torch.zeros(bound, dtype=torch.uint8, device=DEV)
+    nb = torch.zeros(1, dtype=torch.int64, device=DEV)
+    st = torch.zeros(1, dtype=torch.int32, device=DEV)
+    torch.cuda.synchronize()
+    A.apax_encode_noalloc(xg, p, out, nb, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert np.array_equal(out[: int(nb.item())].cpu().numpy(), exp)
+    for call in (lambda: A.apax_profile(xg, p),
+                 lambda: A.apax_encode(xg, dict(p, code=A.CODE_PROFILED)),
+                 lambda: A.Batch.encode([(xg, p)])):
+        with pytest.raises(A.ApaxError) as e:
+            call()
+        assert e.value.code == A.E_UNSUPPORTED
