@@ -52,6 +52,7 @@ typedef struct {
   uint32_t mask;   /* effective stream mask for this mode */
   int budget;      /* fixed-rate words per block, 0 otherwise */
   int target;      /* adaptive rate: target words per block, 0 otherwise */
+  int fk, fneg;    /* filter stream: stride (0: none) and sign (1: x[n] + x[n-k]) */
   int cmin, cmax;  /* admissible gain codes */
   int code;
 } geom;
@@ -66,8 +67,12 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   if (p->dtype < ORC_I8 || p->dtype > ORC_F64) return ORC_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return ORC_E_INVALID;
   if (p->mode > ORC_ADAPTIVE_RATE) return ORC_E_INVALID;
-  if (p->flags & ~ORC_FLAG_LAGGED) return ORC_E_INVALID;
+  if (p->flags & ~(ORC_FLAG_LAGGED | ORC_FILTER(31, 1))) return ORC_E_INVALID;
   if ((p->flags & ORC_FLAG_LAGGED) && p->mode != ORC_LOSSLESS) return ORC_E_INVALID;
+  /* filter stream: 1-d only, stride 1..16, a sign only with a stride */
+  g->fk = (int)ORC_FILTER_K(p->flags);
+  g->fneg = (p->flags & ORC_FILTER_NEG) ? 1 : 0;
+  if (g->fk > 16 || (g->fneg && !g->fk) || (g->fk && p->ndim != 1)) return ORC_E_INVALID;
   g->dtype = (int)p->dtype;
   g->mode = (int)p->mode;
   g->ndim = (int)p->ndim;
@@ -105,7 +110,7 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   if (__builtin_mul_overflow(ns, (int64_t)g->esz, &nbytes_in) || nbytes_in > ((int64_t)1 << 56))
     return ORC_E_UNSUPPORTED;
   if (g->nblocks > (int64_t)0x7FFFFFFF) return ORC_E_UNSUPPORTED;
-  uint32_t allowed = ALLOWED[g->ndim];
+  uint32_t allowed = ALLOWED[g->ndim] | (g->fk ? 0x08u : 0u);
   uint32_t m = p->stream_mask ? p->stream_mask : allowed;
   if (m & ~allowed) return ORC_E_INVALID;
   if (g->mode == ORC_FIXED_RATE)
@@ -257,18 +262,31 @@ static void diff_axis(const int64_t* f, int64_t* o, const int64_t* b, int axis) 
   }
 }
 
-/* Candidate stream s of a brick (reading): 0 samples, 1 dx, 2 dx dx, 3 dy,
- * 4 dz, 5 dx dy, 6 dx dy dz, all modulo 2^W. Stream 7 (verbatim) is not a
- * transform. tmp must hold 2 B values. */
+/* Filter stream of a 1-d block: v[p] = a[p] - sgn a[p - k] (0 before the
+ * block's start). */
+static void filter_block(const int64_t* a, int64_t* v, int64_t B, int k, int neg) {
+  for (int64_t p = 0; p < B; p++) {
+    int64_t prev = p >= k ? a[p - k] : 0;
+    v[p] = neg ? a[p] + prev : a[p] - prev;
+  }
+}
+
+/* Candidate stream s of a brick (reading): 0 samples, 1 dx, 2 dx dx, 3 dy
+ * (1-d arrays with a filter: the filter stream), 4 dz, 5 dx dy, 6 dx dy dz,
+ * all modulo 2^W. Stream 7 (verbatim) is not a transform. tmp must hold 2 B
+ * values. */
 static void make_stream(const int64_t* a, int64_t* v, int64_t* tmp, const int64_t* b, int W,
-                        int s) {
+                        int s, int fk, int fneg) {
   int64_t B = b[0] * b[1] * b[2];
   int64_t* t1 = tmp;
   int64_t* t2 = tmp + B;
   switch (s) {
     case 1: diff_axis(a, v, b, 2); break;
     case 2: diff_axis(a, t1, b, 2); diff_axis(t1, v, b, 2); break;
-    case 3: diff_axis(a, v, b, 1); break;
+    case 3:
+      if (fk) filter_block(a, v, B, fk, fneg);
+      else diff_axis(a, v, b, 1);
+      break;
     case 4: diff_axis(a, v, b, 0); break;
     case 5: diff_axis(a, t1, b, 1); diff_axis(t1, v, b, 2); break;
     case 6: diff_axis(a, t1, b, 0); diff_axis(t1, t2, b, 1); diff_axis(t2, v, b, 2); break;
@@ -287,7 +305,16 @@ static void sum_axis(int64_t* f, const int64_t* b, int axis, int W) {
   }
 }
 
-static void unmake_stream(int64_t* v, const int64_t* b, int W, int s) {
+/* Inverse of the filter: a[p] = v[p] + sgn a[p - k], in increasing p. */
+static void unfilter_block(int64_t* v, int64_t B, int k, int neg, int W) {
+  for (int64_t p = k; p < B; p++) v[p] = wrapW(neg ? v[p] - v[p - k] : v[p] + v[p - k], W);
+}
+
+static void unmake_stream(int64_t* v, const int64_t* b, int W, int s, int fk, int fneg) {
+  if (s == 3 && fk) {
+    unfilter_block(v, b[0] * b[1] * b[2], fk, fneg, W);
+    return;
+  }
   switch (s) {
     case 1: sum_axis(v, b, 2, W); break;
     case 2: sum_axis(v, b, 2, W); sum_axis(v, b, 2, W); break;
@@ -454,7 +481,7 @@ static void quantize_block(const geom* g, scratch* s, int c) {
  * stream values in s->v, the exponents in s->eps and the tokens in s->nib. */
 static int64_t cost_stream(const geom* g, scratch* s, int st, int* nnib) {
   if (st == 7) { *nnib = 0; return (int64_t)g->H + (int64_t)g->B * g->W; }
-  make_stream(s->a, s->v, s->tmp, g->b, g->W, st);
+  make_stream(s->a, s->v, s->tmp, g->b, g->W, st, g->fk, g->fneg);
   for (int p = 0; p < g->B; p++)
     if (!s->valid[p]) s->v[p] = 0; /* absent positions carry 0 (reading) */
   int64_t bits = g->H;
@@ -739,7 +766,8 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
   put32(o + 12, (uint32_t)g.code);
   for (int i = 0; i < 3; i++) put64(o + 16 + 8 * i, i < (int)p->ndim ? p->dims[i] : 0);
   for (int i = 0; i < 3; i++) put16(o + 40 + 2 * i, (uint16_t)(i < (int)p->ndim ? p->brick[i] : 0));
-  put16(o + 46, 0);
+  o[46] = (uint8_t)g.fk;  /* filter stream: stride and sign (0 0: none) */
+  o[47] = (uint8_t)g.fneg;
   put64(o + 48, (uint64_t)g.nblocks);
   put64(o + 56, wpos);
   *nbytes = area + 4 * wpos;
@@ -764,7 +792,8 @@ static int parse_header(const uint8_t* b, uint64_t nbytes, orc_params* p, geom* 
     if (i < (int)p->ndim) { p->dims[i] = d; p->brick[i] = k; }
     else if (d != 0 || k != 0) return ORC_E_CORRUPT;
   }
-  if (get16(b + 46) != 0) return ORC_E_CORRUPT;
+  if (b[46] > 16 || b[47] > 1 || (b[47] && !b[46])) return ORC_E_CORRUPT;
+  if (b[46]) p->flags |= ORC_FILTER(b[46], b[47]);
   p->code = (int32_t)get32(b + 12);
   int budget = get16(b + 10);
   if (p->mode == ORC_FIXED_RATE || p->mode == ORC_ADAPTIVE_RATE) {
@@ -844,7 +873,7 @@ static int decode_block(const geom* g, const uint32_t* w, int nwords, scratch* s
       for (int k = 0; k < 4; k++) s->v[4 * gi + k] = sext(get_bits(&br, pw), pw);
     }
     if (br.err) return ORC_E_CORRUPT;
-    unmake_stream(s->v, g->b, g->W, st);
+    unmake_stream(s->v, g->b, g->W, st, g->fk, g->fneg);
     memcpy(s->a, s->v, sizeof(int64_t) * g->B);
   }
   if (br.err) return ORC_E_CORRUPT;
@@ -1333,9 +1362,34 @@ int orc_stream_values(const int64_t* a, const uint32_t* brick, int32_t W, int32_
   int64_t* aw = malloc(sizeof(int64_t) * (size_t)B);
   if (!tmp || !aw) { free(tmp); free(aw); return ORC_E_INVALID; }
   for (int64_t p = 0; p < B; p++) aw[p] = wrapW(a[p], W);
-  make_stream(aw, v, tmp, b, W, s == 7 ? 0 : s);
+  make_stream(aw, v, tmp, b, W, s == 7 ? 0 : s, 0, 0);
   free(tmp);
   free(aw);
+  return ORC_OK;
+}
+
+int orc_stream_values_f(const int64_t* a, const uint32_t* brick, int32_t W, int32_t s, int32_t fk,
+                        int32_t fneg, int64_t* v) {
+  int64_t b[3] = {brick[0], brick[1], brick[2]};
+  int64_t B = b[0] * b[1] * b[2];
+  if (s < 0 || s > 7 || B <= 0 || fk < 0 || fk > 16) return ORC_E_INVALID;
+  int64_t* tmp = malloc(sizeof(int64_t) * 2 * (size_t)B);
+  int64_t* aw = malloc(sizeof(int64_t) * (size_t)B);
+  if (!tmp || !aw) { free(tmp); free(aw); return ORC_E_INVALID; }
+  for (int64_t p = 0; p < B; p++) aw[p] = wrapW(a[p], W);
+  make_stream(aw, v, tmp, b, W, s == 7 ? 0 : s, fk, fneg);
+  free(tmp);
+  free(aw);
+  return ORC_OK;
+}
+
+int orc_stream_inverse(const int64_t* v, const uint32_t* brick, int32_t W, int32_t s, int32_t fk,
+                       int32_t fneg, int64_t* a) {
+  int64_t b[3] = {brick[0], brick[1], brick[2]};
+  int64_t B = b[0] * b[1] * b[2];
+  if (s < 0 || s > 7 || B <= 0 || fk < 0 || fk > 16) return ORC_E_INVALID;
+  for (int64_t p = 0; p < B; p++) a[p] = wrapW(v[p], W);
+  if (s != 7) unmake_stream(a, b, W, s, fk, fneg);
   return ORC_OK;
 }
 

@@ -71,6 +71,17 @@ typedef struct {
  * block's header still names the stream it uses, so decoding is unchanged. */
 #define ORC_FLAG_LAGGED 1u
 
+/* Filter stream (Sec. 5 oversampling / Sec. 6 redundancy remover: filtered
+ * versions of the attenuated series, the signal monitor's centre frequency
+ * telling which nearby samples of a modulated waveform are correlated),
+ * reading: 1-d arrays only, stream id 3 (unused by 1-d derivatives) becomes
+ * v[p] = a[p] - s a[p - k] inside the block (a[p - k] = 0 before the block's
+ * start), k = 1..16 and s = +1 or -1 from p->flags = ORC_FILTER(k, s < 0);
+ * the stream header records k and s (bytes 46, 47). */
+#define ORC_FILTER(k, neg) ((((uint32_t)(k)) << 8) | ((neg) ? 0x2000u : 0u))
+#define ORC_FILTER_K(flags) (((flags) >> 8) & 0x1Fu)
+#define ORC_FILTER_NEG 0x2000u
+
 typedef struct {
   double r, one_minus_r, snr_db, rms_pct, rms_db;
   double mean_x, mean_y, mean_d, std_x, std_y, std_d, max_abs_d;
@@ -115,6 +126,11 @@ int orc_encode_block(const void* x, const orc_params* p, int64_t j, uint32_t* wo
                      int32_t* used_bits);
 int orc_stream_values(const int64_t* a, const uint32_t* brick, int32_t W, int32_t s,
                       int64_t* v);
+/* the same with a filter (fk = 0: none; fneg: s = -1) and the inverse */
+int orc_stream_values_f(const int64_t* a, const uint32_t* brick, int32_t W, int32_t s, int32_t fk,
+                        int32_t fneg, int64_t* v);
+int orc_stream_inverse(const int64_t* v, const uint32_t* brick, int32_t W, int32_t s, int32_t fk,
+                       int32_t fneg, int64_t* a);
 int orc_group_eps(const int64_t* v, int32_t G, int32_t W, int32_t* eps);
 int orc_jee_tokens(const int32_t* eps, int32_t G, uint8_t* nibbles, int32_t* n_nibbles);
 int orc_stats(const double* x, const double* y, uint64_t n, orc_metrics* m);

@@ -85,6 +85,8 @@ def lib():
                                        P(C.c_int32)]
         L.orc_stream_values.argtypes = [vp, vp, C.c_int32, C.c_int32, vp]
         L.orc_group_eps.argtypes = [vp, C.c_int32, C.c_int32, vp]
+        L.orc_stream_values_f.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.orc_stream_inverse.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
         L.orc_jee_tokens.argtypes = [vp, C.c_int32, vp, P(C.c_int32)]
         L.orc_stats.argtypes = [vp, vp, C.c_uint64, P(Metrics)]
         L.orc_corr_at.argtypes = [vp, P(Params), C.c_int32, P(C.c_double)]
@@ -113,7 +115,15 @@ def make_params(x_or_dtype, shape, params) -> Params:
     p.target_corr = float(params.get("target_corr", 0.99999))
     p.code = int(params.get("code", 0))
     p.flags = 1 if params.get("lagged", False) else 0  # ORC_FLAG_LAGGED
+    f = params.get("filter")  # (stride k, sign s): the stream x[n] - s x[n-k] (1-d)
+    if f:
+        p.flags |= filter_flags(*f)
     return p
+
+
+def filter_flags(k: int, sign: int) -> int:
+    """ORC_FILTER(k, sign < 0)."""
+    return (int(k) << 8) | (0x2000 if sign < 0 else 0)
 
 
 def _check(rc, what):
@@ -211,6 +221,28 @@ def stream_values(a: np.ndarray, brick, W: int, s: int) -> np.ndarray:
     v = np.zeros_like(a)
     _check(lib().orc_stream_values(_ptr(a), _ptr(b), int(W), int(s), _ptr(v)), "stream_values")
     return v
+
+
+def stream_values_f(a: np.ndarray, brick, W: int, s: int, k: int, sign: int) -> np.ndarray:
+    """Stream s with the filter (k, sign) (k = 0: none)."""
+    a = np.ascontiguousarray(a, np.int64).ravel()
+    b = np.ones(3, np.uint32)
+    b[3 - len(brick):] = brick
+    v = np.zeros_like(a)
+    _check(lib().orc_stream_values_f(_ptr(a), _ptr(b), int(W), int(s), int(k), 1 if sign < 0 else 0, _ptr(v)),
+           "stream_values_f")
+    return v
+
+
+def stream_inverse(v: np.ndarray, brick, W: int, s: int, k: int = 0, sign: int = 1) -> np.ndarray:
+    """The decoder's inverse of stream s (with the filter (k, sign) for s = 3 in 1-d)."""
+    v = np.ascontiguousarray(v, np.int64).ravel()
+    b = np.ones(3, np.uint32)
+    b[3 - len(brick):] = brick
+    a = np.zeros_like(v)
+    _check(lib().orc_stream_inverse(_ptr(v), _ptr(b), int(W), int(s), int(k), 1 if sign < 0 else 0, _ptr(a)),
+           "stream_inverse")
+    return a
 
 
 def group_eps(v: np.ndarray, W: int) -> np.ndarray:

@@ -191,3 +191,16 @@ def requests(n: int, seed: int | None = None, lo_bytes: int = 64 << 10,
         spec["gap_u"] = float(rng.uniform())
         out.append(spec)
     return out
+
+
+def modulated(dt, n: int, seed: int, b: int, noise: float = 0.01) -> np.ndarray:
+    """A carrier at bin b of 1024 (b / 1024 cycles per sample) under a slow
+    envelope, plus white noise; integers scaled to 90 % of the dtype's range."""
+    rng = np.random.default_rng(seed)
+    t = np.arange(n)
+    env = 1.0 + 0.3 * np.sin(2 * np.pi * t / 5000.0)
+    s = env * np.cos(2 * np.pi * b * t / 1024 + 0.7) + noise * rng.standard_normal(n)
+    dt = np.dtype(dt)
+    if dt.kind == "i":
+        return np.rint(s / np.abs(s).max() * 0.9 * np.iinfo(dt).max).astype(dt)
+    return (s * 3.0).astype(dt)
