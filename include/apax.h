@@ -104,7 +104,7 @@ typedef struct apax_params {
                            start code / fixed-quality code (from apax_profile);
                            ignored in lossless mode.  ints: [-512, 0];
                            floats: [-17120, 16383] */
-  uint32_t flags;       /* 0, or APAX_FLAG_LAGGED (lossless only) */
+  uint32_t flags;       /* APAX_FLAG_LAGGED (lossless only) | APAX_FILTER(k, neg) (1-d) */
 } apax_params;
 
 /* apax_params.flags: the streaming hardware's lagged stream choice (Sec. 6):
@@ -113,6 +113,19 @@ typedef struct apax_params {
  * Lossless mode only; the stream format is unchanged (each block header
  * names its stream).  Not accepted by batches. */
 #define APAX_FLAG_LAGGED 1u
+
+/* apax_params.flags: the filter stream (Sec. 5 oversampling, Sec. 6: the
+ * redundancy remover's filtered versions of the series, the signal monitor's
+ * centre frequency telling which nearby samples of a modulated waveform are
+ * correlated).  1-d arrays only: stream id 3 (unused by 1-d derivatives)
+ * becomes v[n] = a[n] - s a[n - k] inside the block (a before the block's
+ * start counts as 0), k = 1..16, s = +1 or -1 (neg), typically the stride and
+ * sign apax_signal_monitor reports; allowed in every mode and mixed with the
+ * other streams by the usual fewest-bits choice.  The stream header records
+ * k and s (bytes 46, 47), so decoding needs no parameter.  Other ndim, k > 16
+ * or a sign without a stride: APAX_E_INVALID. */
+#define APAX_FILTER(k, neg) ((((uint32_t)(k)) << 8) | ((neg) ? 0x2000u : 0u))
+#define APAX_FILTER_NEG 0x2000u
 
 typedef struct apax_metrics {
   double r, one_minus_r;   /* Sec. 4 correlation (uncentered, as printed) */

@@ -206,7 +206,15 @@ def _make_params(dtype: torch.dtype, shape, params: dict) -> Params:
     p.target_corr = float(params.get("target_corr", 0.99999))
     p.code = int(params.get("code", 0))
     p.flags = FLAG_LAGGED if params.get("lagged", False) else 0
+    f = params.get("filter")  # (stride k, sign s): the 1-d filter stream x[n] - s x[n-k]
+    if f:
+        p.flags |= filter_flags(*f)
     return p
+
+
+def filter_flags(k: int, sign: int) -> int:
+    """APAX_FILTER(k, sign < 0)."""
+    return (int(k) << 8) | (0x2000 if sign < 0 else 0)
 
 
 def _stream_ptr(stream):
@@ -438,7 +446,8 @@ def apax_stream_info(hdr: bytes) -> dict:
     names = {v: k for k, v in _MODES.items()}
     return {"dtype": _TORCH_OF[p.dtype], "shape": tuple(int(p.dims[i]) for i in range(p.ndim)),
             "mode": names[p.mode], "brick": tuple(int(p.brick[i]) for i in range(p.ndim)),
-            "stream_mask": p.stream_mask, "rate": p.rate, "code": p.code}
+            "stream_mask": p.stream_mask, "rate": p.rate, "code": p.code,
+            "filter": ((p.flags >> 8) & 0x1F, -1 if p.flags & 0x2000 else 1) if (p.flags >> 8) & 0x1F else None}
 
 
 def stream_nbytes(hdr: bytes) -> int:

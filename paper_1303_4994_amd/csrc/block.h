@@ -176,7 +176,9 @@ struct Blk {
   static constexpr int W = Traits<T>::W;
   static constexpr int H = Traits<T>::H;
   static constexpr bool ISINT = Traits<T>::isint;
-  static constexpr uint32_t NDMASK = NDIM == 1 ? 0x07u : (NDIM == 2 ? 0x2Fu : 0x7Fu);
+  // 1-d: stream 3 is the filter stream (allowed by the mask only when the
+  // array has one)
+  static constexpr uint32_t NDMASK = NDIM == 1 ? 0x0Fu : (NDIM == 2 ? 0x2Fu : 0x7Fu);
   static constexpr int BIG = 0x7FFFFFFF;
 
   LaneMap<LPB> L;
@@ -321,6 +323,14 @@ struct Blk {
     o[3] = s[3] - s[2];
   }
 
+  // the filter stream x[n] - s x[n-k] of the 1-d block (Sec. 5 / Sec. 6)
+  __device__ __forceinline__ void filt(const Geo& g, const uint32_t s_[4], uint32_t o[4]) const {
+    uint32_t pv[4];
+    back_by(s_, L.gi, g.fk, pv);
+#pragma unroll
+    for (int k = 0; k < 4; k++) o[k] = g.fneg ? s_[k] + pv[k] : s_[k] - pv[k];
+  }
+
   // the y (and z) predecessors through the wave's LDS exchange
   __device__ __forceinline__ void exchange(const uint32_t A[4], uint32_t Q[4], uint32_t R[4], uint32_t RQ[4],
                                            bool needz) const {
@@ -375,6 +385,13 @@ struct Blk {
       if (nd & 4u) {
         xdiff(d, s);
         finish<DENSE>(s, v[2]);
+      }
+    }
+    if constexpr (NDIM == 1) {
+      if (nd & 8u) {
+        uint32_t F[4];
+        filt(g, A, F);
+        finish<DENSE>(F, v[3]);
       }
     }
     if (NDIM >= 2 && (nd & 0x78u)) {
@@ -486,6 +503,13 @@ struct Blk {
         uint32_t s2[4];
         xdiff(d, s2);
         cost1(2, s2);
+      }
+    }
+    if constexpr (NDIM == 1) {
+      if (nd & 8u) {
+        uint32_t F[4];
+        filt(g, A, F);
+        cost1(3, F);
       }
     }
     if (NDIM >= 2 && (nd & 0x78u)) {

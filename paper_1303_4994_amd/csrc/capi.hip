@@ -70,8 +70,11 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (p->dtype < APAX_I8 || p->dtype > APAX_F64) return APAX_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return APAX_E_INVALID;
   if (p->mode > APAX_ADAPTIVE_RATE) return APAX_E_INVALID;
-  if (p->flags & ~APAX_FLAG_LAGGED) return APAX_E_INVALID;
+  if (p->flags & ~(APAX_FLAG_LAGGED | APAX_FILTER(31, 1))) return APAX_E_INVALID;
   if ((p->flags & APAX_FLAG_LAGGED) && p->mode != APAX_LOSSLESS) return APAX_E_INVALID;
+  // filter stream: 1-d only, stride 1..16, a sign only with a stride
+  const int fk = (int)((p->flags >> 8) & 0x1Fu), fneg = (p->flags & APAX_FILTER_NEG) ? 1 : 0;
+  if (fk > 16 || (fneg && !fk) || (fk && p->ndim != 1)) return APAX_E_INVALID;
   h.lagged = (p->flags & APAX_FLAG_LAGGED) != 0;
   static const int ESZ[6] = {0, 1, 2, 4, 4, 8};
   static const int WQ[6] = {0, 8, 16, 32, 32, 32};
@@ -117,7 +120,9 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   g.nby = nb[1] ? nb[1] : 1;
   if (g.nblocks > (int64_t)0x7FFFFFFF) return APAX_E_UNSUPPORTED;
   h.nsamples = (uint64_t)ns;
-  uint32_t allowed = ND_ALLOWED[h.ndim];
+  uint32_t allowed = ND_ALLOWED[h.ndim] | (fk ? 0x08u : 0u);
+  g.fk = fk;
+  g.fneg = fneg;
   uint32_t m = p->stream_mask ? p->stream_mask : allowed;
   if (m & ~allowed) return APAX_E_INVALID;
   m = h.mode == APAX_FIXED_RATE ? ((m | 1u) & 0x7Fu) : (m | 0x81u);
@@ -210,6 +215,8 @@ void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
   put32(12, (uint32_t)h.g.code);
   for (int i = 0; i < 3; i++) put64(16 + 8 * i, i < h.ndim ? p->dims[i] : 0);
   for (int i = 0; i < 3; i++) put16(40 + 2 * i, (uint16_t)(i < h.ndim ? p->brick[i] : 0));
+  b[46] = (uint8_t)h.g.fk;  // filter stream: stride and sign (0 0: none)
+  b[47] = (uint8_t)h.g.fneg;
   put64(48, (uint64_t)h.g.nblocks);
   put64(56, h.mode == APAX_FIXED_RATE ? (uint64_t)h.g.budget * (uint64_t)h.g.nblocks : 0);
   memcpy(hdr, b, 64);
@@ -370,9 +377,11 @@ int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
   memcpy(&code, b + 12, 4);
   memcpy(dims, b + 16, 24);
   memcpy(brick, b + 40, 6);
-  memcpy(&rsv, b + 46, 2);
+  memcpy(&rsv, b + 46, 2);  // filter stream: stride, sign
   memcpy(&nblocks, b + 48, 8);
-  if (magic != MAGIC || ver != 1 || rsv != 0) return APAX_E_CORRUPT;
+  if (magic != MAGIC || ver != 1) return APAX_E_CORRUPT;
+  const uint32_t hk = b[46], hn = b[47];
+  if (hk > 16 || hn > 1 || (hn && !hk)) return APAX_E_CORRUPT;
   apax_params p;
   memset(&p, 0, sizeof(p));
   p.size = sizeof(p);
@@ -381,6 +390,7 @@ int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
   p.ndim = b[8];
   p.stream_mask = b[9];
   p.code = code;
+  p.flags = hk ? APAX_FILTER(hk, hn) : 0u;
   if (p.ndim < 1 || p.ndim > 3) return APAX_E_CORRUPT;
   for (int i = 0; i < 3; i++) {
     if (i < (int)p.ndim) { p.dims[i] = dims[i]; p.brick[i] = brick[i]; }

@@ -51,7 +51,9 @@ struct Geo {
   int32_t dense_ok;
   // adaptive rate: target words per block, the controller's window of
   // requested codes [alo, alo + awd)
-  int32_t target, alo, awd, pad_;
+  int32_t target, alo, awd;
+  // filter stream (1-d): stride (0: none) and sign (1: x[n] + x[n-k])
+  int32_t fk, fneg;
 };
 
 // Division of a numerator below 2^31 by a divisor known on the host
@@ -165,6 +167,35 @@ __device__ __forceinline__ uint8_t adapt_next(int w, int n, int T, int wd) {
   int s = w + (n < T ? 1 : (n > T ? -1 : 0));
   s = s < 0 ? 0 : (s > wd - 1 ? wd - 1 : s);
   return (uint8_t)s;
+}
+
+// Values D positions back in a block held 4 samples per lane (lane gi of a
+// segment holds positions 4 gi .. 4 gi + 3): o[m] = v at position 4 gi + m - D
+// of the same block, 0 before the block's start.  D is wave-uniform; every
+// lane of the wave must take part (lane shuffles).
+__device__ __forceinline__ void back_by(const uint32_t v[4], int gi, int D, uint32_t o[4]) {
+#pragma unroll
+  for (int m = 0; m < 4; m++) {
+    const int dl = (D - m + 3) >> 2;  // lanes back
+    const int r = (m - D) & 3;        // sample of the source lane
+    const uint32_t sv = r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3]));
+    const uint32_t pv = (uint32_t)__shfl_up((int)sv, (unsigned)(dl < 64 ? dl : 63), 64);
+    o[m] = gi >= dl ? pv : 0u;
+  }
+}
+
+// Inverse of the filter stream over a block of n samples (4 per lane):
+// a[p] = v[p] + s a[p - k], as log-step sums over multiples of k (the first
+// step carries the sign, the later ones its square).
+__device__ __forceinline__ void unfilter(uint32_t r[4], int gi, int k, int neg, int n) {
+  bool first = true;
+  for (int D = k; D < n; D <<= 1) {
+    uint32_t o[4];
+    back_by(r, gi, D, o);
+#pragma unroll
+    for (int m = 0; m < 4; m++) r[m] = (first && neg) ? r[m] - o[m] : r[m] + o[m];
+    first = false;
+  }
 }
 
 // ------------------------------------------------------------ W-bit wrap

@@ -394,6 +394,7 @@ __device__ __forceinline__ void decode_tile64(const DecArgs& A, const int64_t ti
   }
 
   // ---- undo the derivative stream (running sums, mod 2^W); st is wave-uniform
+  if (NDIM == 1 && st == 3) unfilter(r, gi, g.fk, g.fneg, 4 * g.G);
   if (st == 1 || st == 2 || st == 5 || st == 6) undo_x64(r, L.xq, g.rowq);
   if (st == 2) undo_x64(r, L.xq, g.rowq);
   uint4* xch = sm.xch + wave * XCH;
@@ -655,6 +656,15 @@ __device__ __forceinline__ void decode_tile(const DecArgs& A, const int64_t tile
   // ---- undo the derivative stream (running sums, mod 2^W)
   {
     uint32_t u[4] = {r[0], r[1], r[2], r[3]};
+    if constexpr (NDIM == 1) {
+      if (g.fk) {  // the filter stream (every lane takes part; segments with st 3 keep it)
+        unfilter(u, gi, g.fk, g.fneg, 4 * g.G);
+#pragma unroll
+        for (int k = 0; k < 4; k++) r[k] = st == 3 ? u[k] : r[k];
+#pragma unroll
+        for (int k = 0; k < 4; k++) u[k] = r[k];
+      }
+    }
     const bool dx1 = st == 1 || st == 2 || st == 5 || st == 6;
     sum_x<LPB>(u, L.xq, g.rowq);
 #pragma unroll

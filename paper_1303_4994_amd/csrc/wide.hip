@@ -14,7 +14,7 @@ struct WEnc {
   static constexpr int W = Traits<T>::W;
   static constexpr int H = Traits<T>::H;
   static constexpr bool ISINT = Traits<T>::isint;
-  static constexpr uint32_t NDMASK = NDIM == 1 ? 0x07u : (NDIM == 2 ? 0x2Fu : 0x7Fu);
+  static constexpr uint32_t NDMASK = NDIM == 1 ? 0x0Fu : (NDIM == 2 ? 0x2Fu : 0x7Fu);  // 1-d: 3 = filter
   using S = typename std::conditional<ISINT, int32_t, double>::type;
 
   const Geo* g;
@@ -117,6 +117,16 @@ struct WEnc {
     qc = c;
   }
 
+  // the filter stream x[n] - s x[n-k] of group gi of a 1-d block (Sec. 5 / Sec. 6)
+  __device__ __forceinline__ void group_filter(int gi, const uint32_t P[6], uint32_t u[4]) const {
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+      const int p = 4 * gi + m;
+      const uint32_t prev = p >= g->fk ? qa[p - g->fk] : 0u;
+      u[m] = g->fneg ? P[m + 2] + prev : P[m + 2] - prev;
+    }
+  }
+
   // values of stream st (0..6) for group gi: wrapped to W bits, 0 past the edge
   __device__ __forceinline__ void group_stream(int st, int gi, int32_t v[4]) const {
     int z, y, xq;
@@ -130,7 +140,8 @@ struct WEnc {
     if (bit & 0x50u) wide_row6(qa, *g, z - 1, y, xq, Z);
     if (bit & 0x40u) wide_row6(qa, *g, z - 1, y - 1, xq, ZY);
     uint32_t u[4];
-    wide_stream(st, P, Y, Z, ZY, u);
+    if (NDIM == 1 && st == 3) group_filter(gi, P, u);
+    else wide_stream(st, P, Y, Z, ZY, u);
 #pragma unroll
     for (int k = 0; k < 4; k++) v[k] = k < nv ? wrapw<W>(u[k]) : 0;
   }
@@ -157,7 +168,8 @@ struct WEnc {
       for (int st = 0; st < 7; st++) {
         if (!((need >> st) & 1u)) continue;
         uint32_t u[4];
-        wide_stream(st, P, Y, Z, ZY, u);
+        if (NDIM == 1 && st == 3) group_filter(gi, P, u);
+        else wide_stream(st, P, Y, Z, ZY, u);
         int32_t v[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) v[k] = k < nv ? wrapw<W>(u[k]) : 0;
@@ -709,7 +721,36 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
       __syncthreads();
     }
   };
+  // the filter stream's inverse a[p] = v[p] + s a[p - k]: log-step sums over
+  // multiples of k (the first step carries the sign)
+  auto run_filter = [&]() {
+    bool first = true;
+    for (int D = g.fk; D < g.B; D <<= 1) {
+      uint32_t nv[WIDE_GPT][4];
+#pragma unroll
+      for (int q = 0; q < WIDE_GPT; q++) {
+        const int gi = p0 + q;
+        if (q >= C || gi >= G) continue;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const int p = 4 * gi + k;
+          const uint32_t prev = p >= D ? v[p - D] : 0u;
+          nv[q][k] = (first && g.fneg) ? v[p] - prev : v[p] + prev;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < WIDE_GPT; q++) {
+        const int gi = p0 + q;
+        if (q >= C || gi >= G) continue;
+        *reinterpret_cast<uint4*>(v + 4 * gi) = make_uint4(nv[q][0], nv[q][1], nv[q][2], nv[q][3]);
+      }
+      __syncthreads();
+      first = false;
+    }
+  };
   if (!ubad) {
+    if (NDIM == 1 && st == 3) run_filter();
     if (st == 1 || st == 2 || st == 5 || st == 6) run_sum(2);
     if (st == 2) run_sum(2);
     if (NDIM >= 2 && (st == 3 || st == 5 || st == 6)) run_sum(1);
