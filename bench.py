@@ -3,13 +3,15 @@
 noise 1e-2) at a fixed 4:1 rate with the profiler's attenuation, 16x16 bricks,
 on one MI355X.
 
-One step = one pass of the whole hot path over one field: apax_profile
-(operating point, stream mask, curve, metrics) -> apax_encode at the
-profiled operating point -> apax_decode, enqueued with no host round trip:
-the encoder adopts the profile's code and stream mask on the device
-(APAX_CODE_PROFILED).  The encode and decode run on a second stream that
-waits only for the operating point (final after the stream histogram), so
-they overlap the profile's curve, metrics and centred passes.  Inputs are resident in HBM before
+One step = one pass of the whole hot path over one field: the profile
+(operating point, stream mask, metrics, curve) and the encode at the profiled
+operating point in one launch sequence (apax_profile_encode_async: the
+profile's metrics pass runs the encoder's per-block gain search and stream
+choice and records them, and the encode after it only quantizes, forms each
+block's stream and packs -- the same bytes as apax_encode with
+APAX_CODE_PROFILED), then apax_decode, enqueued with no host round trip.  The
+decode runs on a second stream from the `encoded` event on, overlapping the
+profile's centred and curve passes.  Inputs are resident in HBM before
 timing; steps rotate over several copies so the 256 MB Infinity Cache cannot
 serve them.  The timed steps are hipGraphs of that enqueue sequence (one per
 copy; the eager enqueue is timed too and reported beside it), so host launch
@@ -164,13 +166,14 @@ def trace_summary(db_path: str, out_path: str):
            f"# command: {TRACE_CMD}",
            f"# summary: python3 bench.py --trace-from {db_path}",
            "# durations in microseconds; per bench step: k_clear; k_pmax + k_pmax_reduce; 3 bisection probes",
-           "# k_profile<.., 2> + k_reduce<2, false>; histogram k_profile<.., 2> + k_reduce<2, true>; curve",
-           "# k_profile<.., 4> + k_reduce<4, false>; metrics k_profile<.., 1> + k_reduce<1, false>; centred",
-           "# k_profile<.., 3> + k_reduce<3, false>; k_encode; k_decode.  The run also times back-to-back",
-           "# encode/decode launches, event-bracketed profiles and the calls outside the step.",
-           "# The encode and decode of a step run on a second stream, overlapping the profile's curve,",
-           "# metrics and centred passes; iso_avg_us is the mean over launches with no other kernel",
-           "# running (the per-launch figure bench.py reports)",
+           "# k_profile<.., 2> + k_reduce<2, false>; histogram k_profile<.., 2> + k_reduce<2, true>; metrics",
+           "# k_profile<.., 1> + k_reduce<1, false>; k_encode_blocks (the encode from the metrics pass's",
+           "# per-block codes and streams); centred k_profile<.., 3> + k_reduce<3, false>; curve",
+           "# k_profile<.., 4> + k_reduce<4, false>; and k_decode on a second stream from the encode on,",
+           "# overlapping the centred and curve passes.  The run also times back-to-back standalone",
+           "# k_encode / k_decode launches, event-bracketed profiles and the calls outside the step;",
+           "# iso_avg_us is the mean over launches with no other kernel running (the per-launch figure",
+           "# bench.py reports)",
            f"{'kernel':52s} {'calls':>6s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'total_us':>9s} "
            f"{'iso_n':>6s} {'iso_avg_us':>10s}"]
     for k, v in sorted(every.items(), key=lambda kv: -sum(kv[1])):
@@ -428,65 +431,59 @@ def main():
     stream = torch.cuda.current_stream()
 
     p_dev = dict(params, code=A.CODE_PROFILED)
-    # two streams: the profile on `stream`; the encode and decode on `codec`,
-    # which waits only for the operating point (final after the stream
-    # histogram) and so overlaps the profile's curve, metrics and centred
-    # passes.  The codec stream has its own workspace; the next profile waits
-    # until the point has been copied out of the profile's workspace.
+    # two streams: the profile and the encode on `stream` in one launch
+    # sequence (apax_profile_encode_async: the encode is taken from the
+    # metrics pass's per-block results and enqueued right after that pass);
+    # the decode on `codec`, from the `encoded` event on, overlapping the
+    # profile's centred and curve passes.  The decode has its own workspace.
     codec = torch.cuda.Stream()
-    ws_enc = A.workspace(torch.float32, x.shape, params, dev)
-    ev_point = torch.cuda.Event()
-    ev_adopted = torch.cuda.Event()
+    ws_dec = A.workspace(torch.float32, x.shape, params, dev)
+    ev_enc = torch.cuda.Event()
 
     def step(i, ev=None):
         xi = xs[i % R]
-        if i > 0:
-            stream.wait_event(ev_adopted)
         if ev is not None:
             ev[0].record(stream)
-        A.apax_profile_async_point(xi, params, ws, ev_point, stream=stream)
+        A.apax_profile_encode_async(xi, params, ws, out=bufs[i % R], nbytes=nbt, encoded=ev_enc, stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        codec.wait_event(ev_point)
-        A.apax_adopt_point(ws, ws_enc, stream=codec)
-        ev_adopted.record(codec)
+        codec.wait_event(ev_enc)
         if ev is not None:
             ev[2].record(codec)
-        A.apax_encode(xi, p_dev, out=bufs[i % R], nbytes=nbt, ws=ws_enc, stream=codec, clear_status=False)
-        if ev is not None:
-            ev[3].record(codec)
-        A.apax_decode(bufs[i % R], bound, hdr=step.hdr, y=ys[i % R], ws=ws_enc, stream=codec,
+        A.apax_decode(bufs[i % R], bound, hdr=step.hdr, y=ys[i % R], ws=ws_dec, stream=codec,
                       clear_status=False)
         if ev is not None:
-            ev[4].record(codec)
+            ev[3].record(codec)
 
-    # first pass: the device hand-off (across workspaces and streams) gives
-    # the stream of an encode at the host-read operating point, byte for
-    # byte; its header serves the decodes (the decoder compares it with each
-    # stream's own header on the device)
+    # first pass: the fused profile + encode writes the stream of an encode at
+    # the host-read operating point, byte for byte; its header serves the
+    # decodes (the decoder compares it with each stream's own header on the
+    # device)
     prof0 = A.apax_profile(xs[0], params, ws=ws)
     p0 = dict(params, code=prof0["code"], stream_mask=prof0["stream_mask"] & 0x7F)
     A.apax_encode(xs[0], p0, out=bufs[0], nbytes=nbt, ws=ws)
     torch.cuda.synchronize()
     step.hdr = bytes(bufs[0][:64].cpu().numpy().tobytes())
+    A.apax_status_clear(ws)
+    A.apax_status_clear(ws_dec)
     step(1)
     torch.cuda.synchronize()
-    assert A.apax_status(ws) == 0 and A.apax_status(ws_enc) == 0
+    assert A.apax_status(ws) == 0 and A.apax_status(ws_dec) == 0
     assert int(nbt.item()) == bound
     assert torch.equal(bufs[0], bufs[1 % R])
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
-    assert A.apax_status(ws) == 0 and A.apax_status(ws_enc) == 0
+    assert A.apax_status(ws) == 0 and A.apax_status(ws_dec) == 0
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(k, evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    assert A.apax_status(ws) == 0 and A.apax_status(ws_enc) == 0
+    assert A.apax_status(ws) == 0 and A.apax_status(ws_dec) == 0
     prof = A.apax_profile_read(xs[(args.steps - 1) % R], params, ws)
     assert prof["code"] == prof0["code"] and prof["stream_mask"] == prof0["stream_mask"]
     for k in range(1, min(R, args.steps)):  # every copy decoded to the same field
@@ -503,11 +500,9 @@ def main():
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 cap = torch.cuda.current_stream()
-                A.apax_profile_async_point(xs[i], params, ws, ev_point, stream=cap)
-                codec.wait_event(ev_point)
-                A.apax_adopt_point(ws, ws_enc, stream=codec)
-                A.apax_encode(xs[i], p_dev, out=bufs[i], nbytes=nbt, ws=ws_enc, stream=codec, clear_status=False)
-                A.apax_decode(bufs[i], bound, hdr=step.hdr, y=ys[i], ws=ws_enc, stream=codec, clear_status=False)
+                A.apax_profile_encode_async(xs[i], params, ws, out=bufs[i], nbytes=nbt, encoded=ev_enc, stream=cap)
+                codec.wait_event(ev_enc)
+                A.apax_decode(bufs[i], bound, hdr=step.hdr, y=ys[i], ws=ws_dec, stream=codec, clear_status=False)
                 cap.wait_stream(codec)
             graphs.append(g)
         for k in range(args.warmup):
@@ -521,7 +516,7 @@ def main():
             graphs[k % R].replay()
         torch.cuda.synchronize()
         g1 = time.perf_counter()
-        assert A.apax_status(ws) == 0 and A.apax_status(ws_enc) == 0
+        assert A.apax_status(ws) == 0 and A.apax_status(ws_dec) == 0
         # every replayed copy decoded to the eager result
         for i in range(min(R, args.steps)):
             assert torch.equal(ys[i], y_eager), f"graph replay of copy {i} differs from the eager step"
@@ -533,8 +528,7 @@ def main():
     # in a step: the profile stream's span (enqueue start to the last pass),
     # and the codec stream's encode and decode
     prof_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    enc_in_step = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
-    dec_in_step = sum(e[3].elapsed_time(e[4]) for e in evs) / args.steps
+    dec_in_step = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
 
     # per-launch kernel time: back-to-back launches over the rotating copies,
     # HIP events on the launch stream around the whole run
@@ -657,8 +651,9 @@ def main():
                                "fixed rate 4:1, 16x16 bricks, profile + encode + decode per step",
                    "input_bytes": nbytes_in, "stream_bytes": bound, "copies_rotated": R,
                    "attenuation_arith": "f64", "stats_arith": "f32 float-float",
-                   "streams": "profile on one stream; encode + decode on a second, from the "
-                              "operating point on (overlapping the curve, metrics and centred passes)"},
+                   "streams": "profile and encode on one stream (the encode from the metrics pass's "
+                              "per-block codes and streams, right after that pass); decode on a second, "
+                              "overlapping the centred and curve passes"},
         "encode_GBps": round(enc_gbps, 2),
         "decode_GBps": round(dec_gbps, 2),
         "encode_pct_hbm": round(100 * enc_gbps / HBM_PEAK_GBPS, 2),

@@ -185,6 +185,24 @@ int apax_profile_async(const void* d_x, const apax_params* p, void* d_ws, uint64
 int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                              hipStream_t stream, hipEvent_t point_ready);
 
+/* Profile and encode of one array in one launch sequence on `stream` (the
+ * Sec. 4 profiler feeding the Sec. 6 encoder): the profile as
+ * apax_profile_async, and the stream of d_x at the profiled operating point
+ * (the bytes apax_encode writes with p->code = APAX_CODE_PROFILED) into
+ * d_stream / *d_nbytes.  The encode is taken from the profile's metrics pass,
+ * which already runs the encoder's per-block analysis at that point (fixed
+ * rate: each block's gain search; every mode: each block's stream choice
+ * and size): it records each block's code and stream, and the encode only
+ * quantizes, forms that stream and packs.  `encoded` (optional) is recorded
+ * on `stream` as soon as the stream is complete, before the profile's
+ * centred and curve passes, so a decode on another stream can overlap them.
+ * p->code is ignored; d_ws holds the profile as after apax_profile_async.
+ * Blocks of at most 256 samples; the lagged choice runs the plain encode
+ * after the profile. */
+int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                              void* d_stream, uint64_t cap, uint64_t* d_nbytes, hipStream_t stream,
+                              hipEvent_t encoded);
+
 /* Copies the operating point of the profile in d_ws_from into d_ws_to
  * (enqueued on `stream`), so an encode with APAX_CODE_PROFILED can run on its
  * own workspace while d_ws_from goes on with the profile. */

@@ -475,12 +475,9 @@ bool wide_fits(const Geo& g) {
   return wide_lds_bytes(g) + sizeof(WideShared) + 256 <= (size_t)v;
 }
 
-// apax_encode's work once the parameters are set up and the buffers checked:
-// d_ws holds at least enc_need(h) bytes.
-int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool profiled, void* d_stream,
-                   uint64_t* d_nbytes, void* d_ws, hipStream_t stream) {
-  int e;
-  EncArgs A;
+// The encoder's kernel arguments for array d_x, stream d_stream, workspace d_ws.
+void enc_args(const void* d_x, const apax_params* p, const HG& h, bool profiled, void* d_stream,
+              uint64_t* d_nbytes, void* d_ws, EncArgs& A) {
   memset(&A, 0, sizeof(A));
   A.g = h.g;
   A.x = d_x;
@@ -502,6 +499,15 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
     A.zpad[3] = A.area;
   }
   if (profiled) A.sel = ((PState*)d_ws)->sel;
+}
+
+// apax_encode's work once the parameters are set up and the buffers checked:
+// d_ws holds at least enc_need(h) bytes.
+int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool profiled, void* d_stream,
+                   uint64_t* d_nbytes, void* d_ws, hipStream_t stream) {
+  int e;
+  EncArgs A;
+  enc_args(d_x, p, h, profiled, d_stream, d_nbytes, d_ws, A);
   const bool wide = h.g.G > 64;
   if (wide && h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
   if (h.lagged && h.g.nblocks) {
@@ -719,9 +725,15 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
 // result stays in the workspace's PState.
 // ev (optional): 2 * APAX_NPASS events, a pair around the kernel of each
 // pass that runs (bit of *ran set)
+// enc (optional): an encode of the same array at the profiled operating
+// point, enqueued right after the metrics pass from that pass's per-block
+// results (the encoder's own per-block search and stream choice, run there);
+// `encoded` is recorded once it is complete, before the centred and curve
+// passes.
 static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
                            hipEvent_t* ev = nullptr, uint32_t* ran = nullptr,
-                           hipEvent_t point_ready = nullptr) {
+                           hipEvent_t point_ready = nullptr, EncArgs* enc = nullptr,
+                           hipEvent_t encoded = nullptr) {
   int e;
   if (ran) *ran = 0;
   auto pair = [&](int pass) -> hipEvent_t* {
@@ -777,11 +789,16 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     A.final_code = (flags & 2) != 0;
     A.curve = (flags & 4) != 0;
     A.store_cj = (flags & 8) != 0;
+    if ((flags & 16) && enc) {
+      A.bst = enc->bst;
+      A.lens = enc->lens;
+      A.ssum = enc->ssum;
+    }
     A.C = C;
     A.C.step = next;
     return hip_err(launch_profile(h.dtype, h.ndim, A, stream, pair(pass)));
   };
-  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8 };
+  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16 };
 
   // whole profile, asynchronously: clear, max |x| (-> bracket), bisection
   // batches, histogram at the chosen code (-> mask, curve codes), curve
@@ -801,9 +818,17 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     }
     if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL, APAX_PASS_HIST))) return e;
     if (point_ready && hipEventRecord(point_ready, stream) != hipSuccess) return APAX_E_HIP;
-    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_METRICS, F_CURVE, APAX_PASS_CURVE))) return e;
-    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE, APAX_PASS_METRICS))) return e;
+    // metrics at the operating point (fixed rate: each block's code kept
+    // for the centred pass), then the encode that may follow it, the
+    // centred sums and the curve
+    if (enc && !fr) launch_encode_reset(enc->ssum, (g.nblocks + 63) / 64, stream);
+    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC, APAX_PASS_METRICS))) return e;
+    if (enc) {
+      if ((e = hip_err(launch_encode_profiled(h.dtype, h.ndim, *enc, cj_ptr(d_ws, h), stream)))) return e;
+      if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
+    }
     if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL, APAX_PASS_CENTRED))) return e;
+    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_KEEP_CURVE, F_CURVE, APAX_PASS_CURVE))) return e;
   } else {
     if ((e = ctl(C_INIT))) return e;
     if ((e = ctl(C_MASK))) return e;
@@ -1127,6 +1152,29 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
   int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
   if (e) return e;
   return profile_enqueue(d_x, p, h, d_ws, stream, nullptr, nullptr, point_ready);
+}
+
+int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
+                              void* d_stream, uint64_t cap, uint64_t* d_nbytes, hipStream_t stream,
+                              hipEvent_t encoded) {
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  if (!d_stream || !d_nbytes || ((uintptr_t)d_stream & 15)) return APAX_E_INVALID;
+  if (cap < bound_of(h)) return APAX_E_CAPACITY;
+  apax_params q = *p;
+  q.code = 0;  // the header's code and mask are the profile's, written on the device
+  if (h.lagged || h.g.nblocks == 0) {
+    // the lagged choice codes block j with block j-1's stream, which the
+    // metrics pass does not record: the profile, then the plain encode
+    if ((e = profile_enqueue(d_x, p, h, d_ws, stream))) return e;
+    if ((e = encode_enqueue(d_x, &q, h, true, d_stream, d_nbytes, d_ws, stream))) return e;
+    if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
+    return APAX_OK;
+  }
+  EncArgs A;
+  enc_args(d_x, &q, h, true, d_stream, d_nbytes, d_ws, A);
+  return profile_enqueue(d_x, p, h, d_ws, stream, nullptr, nullptr, nullptr, &A, encoded);
 }
 
 int apax_adopt_point(const void* d_ws_from, void* d_ws_to, hipStream_t stream) {

@@ -142,7 +142,7 @@ __host__ __device__ inline PParts pparts(void* base, int64_t R) {
 constexpr int PPART_BYTES = 8 * NSUM + 8 + 8 + 4 + 4 * 8;  // per record
 
 // control steps of the profile (run by the last workgroup of a launch)
-enum { C_NONE = -1, C_INIT = 0, C_DECIDE = 1, C_MASK = 2, C_CURVE = 3, C_METRICS = 4, C_MEANS = 5 };
+enum { C_NONE = -1, C_INIT = 0, C_DECIDE = 1, C_MASK = 2, C_CURVE = 3, C_KEEP_CURVE = 4, C_MEANS = 5 };
 struct CtlArgs {
   PState* st;
   int step, mode, isint, depth, cmin, cmax;
@@ -166,6 +166,12 @@ struct ProfArgs {
   int mask_sel;               // 0 st->mask_probe, 1 st->mask_out (+0x81), 2 metrics mask
   int final_code;             // evaluate st->code (one code) instead of st->codes[]
   int curve;                  // P_STATS: only the four sums of r and the word count
+  // metrics pass of a profile that encodes next (else null): each block's
+  // chosen stream, and in variable-size modes its length (into the stream's
+  // index) and its superblock's word sum -- the encoder's first pass
+  uint8_t* bst;
+  uint16_t* lens;
+  uint32_t* ssum;
   CtlArgs C;                  // control step run by the reduce kernel (C.step, C_NONE: none)
   Geo g;
 };
@@ -221,6 +227,10 @@ hipError_t launch_decode_batch(int lpb, int ndim, int wp, const BatchArgs& B, in
                                size_t lds, hipStream_t s);
 hipError_t launch_batch_reset(uint32_t* ticket, uint64_t* tile_state, int64_t n, hipStream_t s);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
+// the encode of a profiled array from its metrics pass's per-block results:
+// fixed rate from each block's code (cj) and stream (A.bst); variable-size
+// modes from the lengths, streams and superblock sums it left (scan + emit)
+hipError_t launch_encode_profiled(int dtype, int ndim, EncArgs& A, const int32_t* cj, hipStream_t s);
 // each block's own best stream into best[nblocks] (lossless; the lagged choice)
 hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);

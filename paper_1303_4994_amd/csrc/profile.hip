@@ -478,7 +478,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
         bool need = b.act && best > 32 * g.budget;
         if (__ballot(need)) c = b.rate_search(g, g.mask, c, s_, need);
         else have_a = true;
-        if (A.store_cj && b.blk_ok && b.L.gi == 0) A.cj[b.j] = c;
+        if (A.store_cj && b.blk_ok && b.L.gi == 0) {
+          A.cj[b.j] = c;
+          if (A.bst) A.bst[b.j] = (uint8_t)s_;  // the encoder's choice at this block
+        }
       }
     }
     if (!have_a) b.quantize(c, A.rule == R_LOSSLESS, a);
@@ -486,8 +489,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
       int nw;
       if (A.rule != R_RATE) {
         b.costs(g, mask, a, C);
-        B_::argmin(C, mask, best);
+        const int s_ = B_::argmin(C, mask, best);
         nw = (best + 31) >> 5;
+        if (A.bst && b.blk_ok && b.L.gi == 0) {  // the encoder's size pass, done here
+          A.bst[b.j] = (uint8_t)s_;
+          A.lens[b.j] = (uint16_t)nw;
+          atomicAdd(&A.ssum[b.j >> 6], (uint32_t)nw);
+        }
       } else {
         nw = g.budget;
       }
@@ -746,10 +754,13 @@ __device__ void ctl_step(const CtlArgs& C) {
         st->curve_codes[t] = ct;
       }
       st->ncodes = NCURVE;
+      // the metrics pass (at st->code alone) comes next, then the centred
+      // and curve passes; codes[] keeps the curve codes until then
+      st->maxbits[1] = 0;
       ctl_zero(st);
       break;
     }
-    case C_METRICS: {  // after the curve: keep it, set up the metrics pass
+    case C_KEEP_CURVE: {  // after the curve pass: keep its sums
       for (int t = 0; t < NCURVE; t++) {
         st->curve_sums[t][0] = st->sums[t][S_XX];
         st->curve_sums[t][1] = st->sums[t][S_YY];
@@ -757,9 +768,6 @@ __device__ void ctl_step(const CtlArgs& C) {
         st->curve_sums[t][3] = st->sums[t][S_DS];
         st->curve_words[t] = st->words[t];
       }
-      st->codes[0] = st->code; st->ncodes = 1;
-      st->maxbits[1] = 0;
-      ctl_zero(st);
       break;
     }
     case C_MEANS: {  // after the metrics pass: keep it, means for the centred pass
@@ -769,7 +777,6 @@ __device__ void ctl_step(const CtlArgs& C) {
       st->mean[0] = ldexp(st->sums[0][S_X], st->escale) / n;
       st->mean[1] = ldexp(st->sums[0][S_Y], st->escale) / n;
       st->mean[2] = ldexp(st->sums[0][S_D], st->escale) / n;
-      st->codes[0] = st->code; st->ncodes = 1;
       break;
     }
   }

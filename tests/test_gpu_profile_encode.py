@@ -1,0 +1,111 @@
+"""apax_profile_encode_async (the profiler feeding the encoder, Sec. 4 -> Sec. 6,
+the encode taken from the metrics pass's per-block results) against the
+separate calls: the same profile result and the same stream bytes as
+apax_profile_async followed by apax_encode with APAX_CODE_PROFILED, in every
+mode, 1-/2-/3-d, the lagged choice, an empty array and the 4096^2 fp32 field;
+and the stream decodes to the oracle's decode of the oracle's encode at the
+profiled point."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1303_4994_amd import apax
+    return apax
+
+
+def field(dt, shape, seed):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    t = np.arange(n)
+    base = (np.sin(2 * np.pi * 0.013 * t) * 0.9 + 0.05 * rng.standard_normal(n)).reshape(shape)
+    base = base.cumsum(axis=-1) / 4
+    if np.dtype(dt).kind == "i":
+        return np.rint(base / np.abs(base).max() * 0.45 * np.iinfo(dt).max).astype(dt)
+    return (base * 1e2).astype(dt)
+
+
+CASES = [
+    ("f32-2d-16x16-fr", np.float32, (300, 260), {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}),
+    ("f32-1d-B128-fr", np.float32, (6000,), {"mode": "fixed_rate", "brick": (128,), "rate": 4.0}),
+    ("i8-1d-B64-fr", np.int8, (7000,), {"mode": "fixed_rate", "brick": (64,), "rate": 2.0}),
+    ("f64-3d-4x4x8-fq", np.float64, (9, 33, 40), {"mode": "fixed_quality", "brick": (4, 4, 8)}),
+    ("f32-2d-4x16-fq", np.float32, (70, 64), {"mode": "fixed_quality", "brick": (4, 16)}),
+    ("i16-1d-B256-lossless", np.int16, (50000 + 37,), {"mode": "lossless", "brick": (256,)}),
+    ("i32-3d-2x4x8-lossless", np.int32, (7, 20, 24), {"mode": "lossless", "brick": (2, 4, 8)}),
+    ("i16-1d-lagged", np.int16, (20000,), {"mode": "lossless", "brick": (64,), "lagged": True}),
+    ("f32-1d-filter-fr", np.float32, (64 * 300,), {"mode": "fixed_rate", "brick": (64,), "rate": 4.0,
+                                                    "filter": (1, -1)}),
+]
+
+
+def separate(A, xg, params):
+    ws = A.workspace(xg.dtype, tuple(xg.shape), params, DEV)
+    A.apax_status_clear(ws)
+    A.apax_profile_async(xg, params, ws)
+    buf, nb = A.apax_encode(xg, dict(params, code=A.CODE_PROFILED), ws=ws, clear_status=False)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    return buf[: int(nb.item())].cpu().numpy(), A.apax_profile_read(xg, params, ws)
+
+
+def fused(A, xg, params):
+    ws = A.workspace(xg.dtype, tuple(xg.shape), params, DEV)
+    A.apax_status_clear(ws)
+    ev = torch.cuda.Event()
+    buf, nb = A.apax_profile_encode_async(xg, params, ws, encoded=ev)
+    ev.synchronize()
+    n = int(nb.item())
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    return buf, n, A.apax_profile_read(xg, params, ws)
+
+
+@pytest.mark.parametrize("name,dt,shape,params", CASES, ids=[c[0] for c in CASES])
+def test_fused_equals_separate(A, name, dt, shape, params):
+    print(f"case {name}", flush=True)
+    params = dict(params, target_corr=0.9999)
+    x = field(dt, shape, 3)
+    xg = torch.from_numpy(x).to(DEV)
+    ref, pref = separate(A, xg, params)
+    buf, n, pf = fused(A, xg, params)
+    got = buf[:n].cpu().numpy()
+    assert pf == pref
+    assert got.size == ref.size and np.array_equal(got, ref)
+    # the oracle at the same operating point decodes to the same values
+    mode = params["mode"]
+    p = {k: v for k, v in params.items() if k != "lagged" or mode == "lossless"}
+    p = dict(p, code=pf["code"], stream_mask=pf["stream_mask"] & (0x7F if mode == "fixed_rate" else 0xFF))
+    y = A.apax_decode(buf, n).cpu().numpy()
+    assert np.array_equal(y.view(np.uint8), O.decode(O.encode(x, p)).view(np.uint8))
+
+
+def test_fused_empty(A):
+    xg = torch.zeros((0,), dtype=torch.float32, device=DEV)
+    p = {"mode": "fixed_rate", "brick": (64,), "rate": 4.0}
+    buf, n, pf = fused(A, xg, p)
+    ref, pref = separate(A, xg, p)
+    assert np.array_equal(buf[:n].cpu().numpy(), ref) and pf == pref
+
+
+@pytest.mark.timeout(600)
+def test_fused_full_field(A):
+    x = synth.grf2d(4096, 4096)
+    xg = torch.from_numpy(x).to(DEV)
+    p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    ref, pref = separate(A, xg, p)
+    buf, n, pf = fused(A, xg, p)
+    assert pf == pref
+    assert n == ref.size and torch.equal(buf[:n].cpu(), torch.from_numpy(ref))
