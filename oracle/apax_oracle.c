@@ -46,7 +46,8 @@ typedef struct {
   int isint;
   int64_t n[3]; /* array extent, z y x (leading 1 for lower ndim)             */
   int64_t b[3]; /* brick extent, z y x                                         */
-  int B, G;     /* samples and 4-sample groups per block                       */
+  int B, G;     /* samples and exponent groups per block                       */
+  int N;        /* samples per exponent group: 4, or 8 with ORC_FLAG_GROUP8     */
   int64_t nb[3];
   int64_t nblocks;
   uint32_t mask;   /* effective stream mask for this mode */
@@ -67,7 +68,7 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
   if (p->dtype < ORC_I8 || p->dtype > ORC_F64) return ORC_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return ORC_E_INVALID;
   if (p->mode > ORC_ADAPTIVE_RATE) return ORC_E_INVALID;
-  if (p->flags & ~(ORC_FLAG_LAGGED | ORC_FILTER(31, 1))) return ORC_E_INVALID;
+  if (p->flags & ~(ORC_FLAG_LAGGED | ORC_FILTER(31, 1) | ORC_FLAG_GROUP8)) return ORC_E_INVALID;
   if ((p->flags & ORC_FLAG_LAGGED) && p->mode != ORC_LOSSLESS) return ORC_E_INVALID;
   /* filter stream: 1-d only, stride 1..16, a sign only with a stride */
   g->fk = (int)ORC_FILTER_K(p->flags);
@@ -93,12 +94,13 @@ static int setup_geom_b(const orc_params* p, geom* g, int forced_budget) {
     B *= p->brick[i];
   }
   if (B < 64 || B > 16384 || B % 4 != 0) return ORC_E_INVALID;
-  if (g->b[2] % 4 != 0) return ORC_E_INVALID; /* reading: groups never straddle rows */
+  g->N = (p->flags & ORC_FLAG_GROUP8) ? 8 : 4;
+  if (g->b[2] % g->N != 0 || B % g->N != 0) return ORC_E_INVALID; /* reading: groups never straddle rows */
   for (int i = 0; i < 3; i++) {
     if (g->n[i] < 0 || g->n[i] > ((int64_t)1 << 40)) return ORC_E_INVALID;
   }
   g->B = (int)B;
-  g->G = (int)(B / 4);
+  g->G = (int)(B / g->N);
   g->nblocks = 1;
   int64_t ns = 1, nbytes_in;
   for (int i = 0; i < 3; i++) {
@@ -338,12 +340,13 @@ static int width_of(int64_t v) {
   return n + 1;
 }
 
-/* Exponent code of a group: the width of its widest sample (0 if all four
- * are zero), saturated at 31 (reading: code 31 means 32 bits when W = 32). */
-static int group_eps(const int64_t* v4) {
+/* Exponent code of a group of n samples: the width of its widest sample (0
+ * if all are zero), saturated at 31 (reading: code 31 means 32 bits when
+ * W = 32). */
+static int group_eps(const int64_t* v, int n) {
   int w = 0;
-  for (int k = 0; k < 4; k++) {
-    int t = width_of(v4[k]);
+  for (int k = 0; k < n; k++) {
+    int t = width_of(v[k]);
     if (t > w) w = t;
   }
   return w > 31 ? 31 : w;
@@ -486,8 +489,8 @@ static int64_t cost_stream(const geom* g, scratch* s, int st, int* nnib) {
     if (!s->valid[p]) s->v[p] = 0; /* absent positions carry 0 (reading) */
   int64_t bits = g->H;
   for (int i = 0; i < g->G; i++) {
-    s->eps[i] = group_eps(s->v + 4 * i);
-    bits += 4 * payload_width(s->eps[i], g->W);
+    s->eps[i] = group_eps(s->v + g->N * i, g->N);
+    bits += g->N * payload_width(s->eps[i], g->W);
   }
   *nnib = jee_tokens(s->eps, g->G, s->nib);
   return bits + 4 * (int64_t)(*nnib);
@@ -575,7 +578,7 @@ static int64_t emit_block(const geom* g, scratch* s, int st, int c, int nnib, ui
     for (int t = 0; t < nnib; t++) put_bits(&bw, s->bnib[t], 4);
     for (int i = 0; i < g->G; i++) {
       int pw = payload_width(s->beps[i], g->W);
-      for (int k = 0; k < 4; k++) put_bits(&bw, (uint64_t)s->best[4 * i + k], pw);
+      for (int k = 0; k < g->N; k++) put_bits(&bw, (uint64_t)s->best[g->N * i + k], pw);
     }
   }
   return bw.pos;
@@ -760,7 +763,7 @@ int orc_encode(const void* x, const orc_params* p, void* out, uint64_t cap, uint
   put16(o + 4, 1);
   o[6] = (uint8_t)g.dtype;
   o[7] = (uint8_t)g.mode;
-  o[8] = (uint8_t)g.ndim;
+  o[8] = (uint8_t)(g.ndim | (g.N == 8 ? 0x10 : 0)); /* bit 4: groups of 8 */
   o[9] = (uint8_t)g.mask;
   put16(o + 10, (uint16_t)(adapt ? g.target : g.budget));
   put32(o + 12, (uint32_t)g.code);
@@ -783,7 +786,9 @@ static int parse_header(const uint8_t* b, uint64_t nbytes, orc_params* p, geom* 
   p->size = sizeof(orc_params);
   p->dtype = b[6];
   p->mode = b[7];
-  p->ndim = b[8];
+  p->ndim = b[8] & 0x0F;
+  if (b[8] & 0xE0) return ORC_E_CORRUPT;
+  if (b[8] & 0x10) p->flags |= ORC_FLAG_GROUP8;
   p->stream_mask = b[9];
   if (p->ndim < 1 || p->ndim > 3) return ORC_E_CORRUPT;
   for (int i = 0; i < 3; i++) {
@@ -870,7 +875,7 @@ static int decode_block(const geom* g, const uint32_t* w, int nwords, scratch* s
     }
     for (int gi = 0; gi < g->G; gi++) {
       int pw = payload_width(s->eps[gi], g->W);
-      for (int k = 0; k < 4; k++) s->v[4 * gi + k] = sext(get_bits(&br, pw), pw);
+      for (int k = 0; k < g->N; k++) s->v[g->N * gi + k] = sext(get_bits(&br, pw), pw);
     }
     if (br.err) return ORC_E_CORRUPT;
     unmake_stream(s->v, g->b, g->W, st, g->fk, g->fneg);
@@ -1395,7 +1400,13 @@ int orc_stream_inverse(const int64_t* v, const uint32_t* brick, int32_t W, int32
 
 int orc_group_eps(const int64_t* v, int32_t G, int32_t W, int32_t* eps) {
   (void)W;
-  for (int i = 0; i < G; i++) eps[i] = group_eps(v + 4 * i);
+  for (int i = 0; i < G; i++) eps[i] = group_eps(v + 4 * i, 4);
+  return ORC_OK;
+}
+
+int orc_group_eps_n(const int64_t* v, int32_t G, int32_t n, int32_t* eps) {
+  if (n < 1) return ORC_E_INVALID;
+  for (int i = 0; i < G; i++) eps[i] = group_eps(v + (int64_t)n * i, n);
   return ORC_OK;
 }
 

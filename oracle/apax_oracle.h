@@ -78,6 +78,13 @@ typedef struct {
  * v[p] = a[p] - s a[p - k] inside the block (a[p - k] = 0 before the block's
  * start), k = 1..16 and s = +1 or -1 from p->flags = ORC_FILTER(k, s < 0);
  * the stream header records k and s (bytes 46, 47). */
+/* Groups of 8 (Sec. 6: one exponent per group of N = 4 or 8 samples),
+ * reading: p->flags |= ORC_FLAG_GROUP8 gives every exponent (and its JEE
+ * position) 8 consecutive samples of a brick row; B and the brick's x extent
+ * must be multiples of 8.  The stream header records it in bit 4 of the
+ * ndim byte (byte 8). */
+#define ORC_FLAG_GROUP8 0x4000u
+
 #define ORC_FILTER(k, neg) ((((uint32_t)(k)) << 8) | ((neg) ? 0x2000u : 0u))
 #define ORC_FILTER_K(flags) (((flags) >> 8) & 0x1Fu)
 #define ORC_FILTER_NEG 0x2000u
@@ -132,6 +139,8 @@ int orc_stream_values_f(const int64_t* a, const uint32_t* brick, int32_t W, int3
 int orc_stream_inverse(const int64_t* v, const uint32_t* brick, int32_t W, int32_t s, int32_t fk,
                        int32_t fneg, int64_t* a);
 int orc_group_eps(const int64_t* v, int32_t G, int32_t W, int32_t* eps);
+/* exponents of G groups of n samples each */
+int orc_group_eps_n(const int64_t* v, int32_t G, int32_t n, int32_t* eps);
 int orc_jee_tokens(const int32_t* eps, int32_t G, uint8_t* nibbles, int32_t* n_nibbles);
 int orc_stats(const double* x, const double* y, uint64_t n, orc_metrics* m);
 int orc_corr_at(const void* x, const orc_params* p, int32_t code, double* r);

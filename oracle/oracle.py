@@ -118,6 +118,8 @@ def make_params(x_or_dtype, shape, params) -> Params:
     f = params.get("filter")  # (stride k, sign s): the stream x[n] - s x[n-k] (1-d)
     if f:
         p.flags |= filter_flags(*f)
+    if int(params.get("group", 4)) == 8:  # ORC_FLAG_GROUP8: 8 samples per exponent
+        p.flags |= 0x4000
     return p
 
 

@@ -106,17 +106,17 @@ def unstream_np(v3, s: int, W: int):
     return wrap(v, W)
 
 
-def size_model(a3, s: int, W: int, H: int, valid3=None) -> int:
+def size_model(a3, s: int, W: int, H: int, valid3=None, n: int = 4) -> int:
     """Bits of a block coded with stream s: header + minimal JEE tokens +
-    BFPE payload (4 samples per exponent)."""
+    BFPE payload (n samples per exponent)."""
     B = a3.size
     if s == 7:
         return H + B * W
     v = stream_np(a3, s, W).ravel()
     if valid3 is not None:
         v = np.where(np.asarray(valid3).ravel(), v, 0)
-    eps = [eps_of(v[4 * i:4 * i + 4]) for i in range(B // 4)]
-    return H + jee_min_bits(eps) + sum(4 * pw_of(e, W) for e in eps)
+    eps = [eps_of(v[n * i:n * i + n]) for i in range(B // n)]
+    return H + jee_min_bits(eps) + sum(n * pw_of(e, W) for e in eps)
 
 
 # ---------------------------------------------------------------- gain grid
@@ -190,8 +190,9 @@ class BitReader:
         return r
 
 
-def parse_block(words, isint: bool, G: int, W: int):
-    """Return (stream, eps0, code, eps list, nibbles, payload values, bits used)."""
+def parse_block(words, isint: bool, G: int, W: int, n: int = 4):
+    """Return (stream, eps0, code, eps list, nibbles, payload values, bits used)
+    of a block of G exponent groups of n samples."""
     br = BitReader(words)
     s = br.get(3)
     eps0 = br.get(5)
@@ -199,7 +200,7 @@ def parse_block(words, isint: bool, G: int, W: int):
     rsv = br.get(14 if isint else 24)
     assert rsv == 0
     if s == 7:
-        vals = [br.sget(W) for _ in range(4 * G)]
+        vals = [br.sget(W) for _ in range(n * G)]
         return s, eps0, code, None, [], vals, br.pos
     nib = []
     eps = [eps0]
@@ -218,5 +219,5 @@ def parse_block(words, isint: bool, G: int, W: int):
     vals = []
     for e in eps:
         p = pw_of(e, W)
-        vals += [br.sget(p) for _ in range(4)]
+        vals += [br.sget(p) for _ in range(n)]
     return s, eps0, code, eps, nib, vals, br.pos

@@ -258,12 +258,13 @@ def _check_blocks(x, params, s):
     lossless = params["mode"] == "lossless"
     mask = st.mask
     brick = params["brick"]
-    G = int(np.prod(brick)) // 4
+    n = params.get("group", 4)
+    G = int(np.prod(brick)) // n
     for j, blk, val in _blocks_of(x, brick):
         words = st.block(j)
-        sid, eps0, code, eps, nib, vals, used = brute.parse_block(words, isint, G, W)
+        sid, eps0, code, eps, nib, vals, used = brute.parse_block(words, isint, G, W, n)
         a = np.where(val, _quantized_block(blk, code, isint, lossless), 0)
-        sizes = {s_: brute.size_model(a, s_, W, H, val) for s_ in range(8) if mask >> s_ & 1}
+        sizes = {s_: brute.size_model(a, s_, W, H, val, n) for s_ in range(8) if mask >> s_ & 1}
         if params["mode"] != "fixed_rate":
             best = min(sizes.values())
             assert sid == min(k for k, v in sizes.items() if v == best), (j, sizes, sid)
@@ -292,6 +293,12 @@ CASES = [
     (np.float64, (20, 24), {"mode": "fixed_rate", "brick": (8, 8), "rate": 6.0, "code": 300}),
     (np.int16, (900,), {"mode": "fixed_rate", "brick": (64,), "rate": 3.0, "code": 0}),
     (np.int32, (12, 12), {"mode": "fixed_quality", "brick": (4, 16), "code": -40}),
+    # groups of 8 samples per exponent (Sec. 6 "groups of 4 or 8")
+    (np.int16, (1000,), {"mode": "lossless", "brick": (64,), "group": 8}),
+    (np.int32, (5, 9, 16), {"mode": "lossless", "brick": (2, 4, 8), "group": 8}),
+    (np.float32, (33, 40), {"mode": "fixed_quality", "brick": (4, 16), "code": 40, "group": 8}),
+    (np.float64, (20, 24), {"mode": "fixed_rate", "brick": (8, 8), "rate": 6.0, "code": 300, "group": 8}),
+    (np.int8, (700,), {"mode": "fixed_rate", "brick": (128,), "rate": 2.0, "code": 0, "group": 8}),
 ]
 
 
@@ -351,11 +358,12 @@ def test_decode_is_dq_of_q_and_error_bound(dt, shape, params):
     if params["mode"] == "lossless":
         assert np.array_equal(x, y)
         return
-    G = int(np.prod(params["brick"])) // 4
+    n = params.get("group", 4)
+    G = int(np.prod(params["brick"])) // n
     W = W_OF[x.dtype]
     for (j, blk, val), (_, yblk, _) in zip(_blocks_of(x, params["brick"]),
                                           _blocks_of(y, params["brick"])):
-        code = brute.parse_block(st.block(j), isint, G, W)[2]
+        code = brute.parse_block(st.block(j), isint, G, W, n)[2]
         a = _quantized_block(blk, code, isint, False)
         yd = brute.dequant_np(a, code)
         if x.dtype == np.float32:
@@ -395,14 +403,14 @@ def _py_bracket(M, isint):
     return largest(0.5), (0 if isint else largest(2 ** 31 - 1))
 
 
-def _py_fixed_rate(blk, val, cp, mask, budget_bits, W, H, isint):
+def _py_fixed_rate(blk, val, cp, mask, budget_bits, W, H, isint, n=4):
     M = float(np.abs(blk.astype(np.float64))[val].max()) if val.any() else 0.0
     cf, cc = _py_bracket(M, isint)
     c = min(max(cp, cf), cc)
 
     def size(s_, c_):
         a = np.where(val, np.rint(blk.astype(np.float64) * brute.gain(c_)).astype(np.int64), 0)
-        return brute.size_model(a, s_, W, H, val)
+        return brute.size_model(a, s_, W, H, val, n)
     sizes = {s_: size(s_, c) for s_ in range(7) if mask >> s_ & 1}
     best = min(sizes.values())
     s_star = min(k for k, v in sizes.items() if v == best)
@@ -431,14 +439,15 @@ def test_fixed_rate_search_replicated(dt, shape, params):
     st = brute.Stream(s)
     isint = x.dtype.kind == "i"
     W, H = W_OF[x.dtype], (32 if isint else 48)
-    G = int(np.prod(params["brick"])) // 4
+    n = params.get("group", 4)
+    G = int(np.prod(params["brick"])) // n
     bpb = 8 * x.dtype.itemsize * int(np.prod(params["brick"]))
     assert st.budget == math.floor(bpb / (params["rate"] * 32))
     for j, blk, val in _blocks_of(x, params["brick"]):
         assert len(st.block(j)) == st.budget
-        sid, _, code, *_ = brute.parse_block(st.block(j), isint, G, W)
+        sid, _, code, *_ = brute.parse_block(st.block(j), isint, G, W, n)
         exp_c, exp_s = _py_fixed_rate(blk, val, params["code"], st.mask, 32 * st.budget, W, H,
-                                      isint)
+                                      isint, n)
         assert (code, sid) == (exp_c, exp_s), j
 
 
