@@ -104,7 +104,7 @@ typedef struct apax_params {
                            start code / fixed-quality code (from apax_profile);
                            ignored in lossless mode.  ints: [-512, 0];
                            floats: [-17120, 16383] */
-  uint32_t flags;       /* APAX_FLAG_LAGGED (lossless only) | APAX_FILTER(k, neg) (1-d) */
+  uint32_t flags;       /* APAX_FLAG_LAGGED (lossless only) | APAX_FILTER(k, neg) (1-d) | APAX_FLAG_GROUP8 */
 } apax_params;
 
 /* apax_params.flags: the streaming hardware's lagged stream choice (Sec. 6):
@@ -124,6 +124,15 @@ typedef struct apax_params {
  * other streams by the usual fewest-bits choice.  The stream header records
  * k and s (bytes 46, 47), so decoding needs no parameter.  Other ndim, k > 16
  * or a sign without a stride: APAX_E_INVALID. */
+/* apax_params.flags: groups of 8 samples per exponent (Sec. 6: one exponent
+ * per group of N = 4 or 8 samples; default 4).  Every exponent and JEE
+ * position then covers 8 consecutive samples of a brick row: the block size
+ * and the brick's x extent must be multiples of 8 (else APAX_E_INVALID).  The
+ * stream header records it in bit 4 of the ndim byte (byte 8).  Encoded and
+ * decoded by the one-workgroup-per-block kernels; not accepted by the
+ * profiler, batches or the server (APAX_E_UNSUPPORTED). */
+#define APAX_FLAG_GROUP8 0x4000u
+
 #define APAX_FILTER(k, neg) ((((uint32_t)(k)) << 8) | ((neg) ? 0x2000u : 0u))
 #define APAX_FILTER_NEG 0x2000u
 

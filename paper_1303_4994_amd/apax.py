@@ -210,6 +210,8 @@ def _make_params(dtype: torch.dtype, shape, params: dict) -> Params:
     f = params.get("filter")  # (stride k, sign s): the 1-d filter stream x[n] - s x[n-k]
     if f:
         p.flags |= filter_flags(*f)
+    if int(params.get("group", 4)) == 8:  # APAX_FLAG_GROUP8: 8 samples per exponent
+        p.flags |= 0x4000
     return p
 
 
@@ -470,7 +472,8 @@ def apax_stream_info(hdr: bytes) -> dict:
     return {"dtype": _TORCH_OF[p.dtype], "shape": tuple(int(p.dims[i]) for i in range(p.ndim)),
             "mode": names[p.mode], "brick": tuple(int(p.brick[i]) for i in range(p.ndim)),
             "stream_mask": p.stream_mask, "rate": p.rate, "code": p.code,
-            "filter": ((p.flags >> 8) & 0x1F, -1 if p.flags & 0x2000 else 1) if (p.flags >> 8) & 0x1F else None}
+            "filter": ((p.flags >> 8) & 0x1F, -1 if p.flags & 0x2000 else 1) if (p.flags >> 8) & 0x1F else None,
+            "group": 8 if p.flags & 0x4000 else 4}
 
 
 def stream_nbytes(hdr: bytes) -> int:

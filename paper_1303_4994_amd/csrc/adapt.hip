@@ -156,7 +156,7 @@ hipError_t launch_adapt(int dtype, int ndim, const EncArgs& A, void* region, int
     p += ((uint64_t)m[l] + 255) / 256 * 256;
   }
   hipError_t e;
-  if (g.G > 64) e = launch_wide_table(dtype, ndim, A, tabs[0], s);
+  if (g.G > 64 || g.gq == 2) e = launch_wide_table(dtype, ndim, A, tabs[0], s);
   else {
     switch (dtype) {
       case DT_I8: e = table_nd<int8_t>(A, ndim, tabs[0], s); break;

@@ -70,7 +70,7 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   if (p->dtype < APAX_I8 || p->dtype > APAX_F64) return APAX_E_INVALID;
   if (p->ndim < 1 || p->ndim > 3) return APAX_E_INVALID;
   if (p->mode > APAX_ADAPTIVE_RATE) return APAX_E_INVALID;
-  if (p->flags & ~(APAX_FLAG_LAGGED | APAX_FILTER(31, 1))) return APAX_E_INVALID;
+  if (p->flags & ~(APAX_FLAG_LAGGED | APAX_FILTER(31, 1) | APAX_FLAG_GROUP8)) return APAX_E_INVALID;
   if ((p->flags & APAX_FLAG_LAGGED) && p->mode != APAX_LOSSLESS) return APAX_E_INVALID;
   // filter stream: 1-d only, stride 1..16, a sign only with a stride
   const int fk = (int)((p->flags >> 8) & 0x1Fu), fneg = (p->flags & APAX_FILTER_NEG) ? 1 : 0;
@@ -98,6 +98,9 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
   }
   if (B < 64 || B > 16384 || B % 4 != 0 || b[2] % 4 != 0) return APAX_E_INVALID;
   Geo& g = h.g;
+  // groups of 8 samples per exponent: B and the brick rows multiples of 8
+  g.gq = (p->flags & APAX_FLAG_GROUP8) ? 2 : 1;
+  if (g.gq == 2 && (B % 8 != 0 || b[2] % 8 != 0)) return APAX_E_INVALID;
   for (int i = 0; i < 3; i++) { g.n[i] = n[i]; g.b[i] = (int32_t)b[i]; }
   g.B = (int32_t)B;
   g.G = (int32_t)(B / 4);
@@ -146,7 +149,7 @@ int setup(const apax_params* p, HG& h, int forced_budget = -1) {
       if (!(p->rate > 0.0) || !isfinite(p->rate)) return APAX_E_INVALID;
       words = floor((double)g.B * 8.0 * h.esz / (p->rate * 32.0));
     }
-    int min_words = (h.H + 4 * (g.G / 2) + 31) / 32;
+    int min_words = (h.H + 4 * (g.G / g.gq / 2) + 31) / 32;
     if (words < min_words || words > 65535.0) return APAX_E_INVALID;
     g.budget = (int32_t)words;
   }
@@ -209,7 +212,7 @@ void make_header(const apax_params* p, const HG& h, uint32_t hdr[16]) {
   put16(4, 1);
   b[6] = (uint8_t)h.dtype;
   b[7] = (uint8_t)h.mode;
-  b[8] = (uint8_t)h.ndim;
+  b[8] = (uint8_t)(h.ndim | (h.g.gq == 2 ? 0x10 : 0));  // bit 4: groups of 8
   b[9] = (uint8_t)h.g.mask;
   put16(10, (uint16_t)(h.mode == APAX_ADAPTIVE_RATE ? h.g.target : h.g.budget));
   put32(12, (uint32_t)h.g.code);
@@ -387,10 +390,11 @@ int apax_stream_info(const void* h_hdr, uint64_t n, apax_params* out) {
   p.size = sizeof(p);
   p.dtype = b[6];
   p.mode = b[7];
-  p.ndim = b[8];
+  p.ndim = b[8] & 0x0Fu;
+  if (b[8] & 0xE0u) return APAX_E_CORRUPT;
   p.stream_mask = b[9];
   p.code = code;
-  p.flags = hk ? APAX_FILTER(hk, hn) : 0u;
+  p.flags = (hk ? APAX_FILTER(hk, hn) : 0u) | ((b[8] & 0x10u) ? APAX_FLAG_GROUP8 : 0u);
   if (p.ndim < 1 || p.ndim > 3) return APAX_E_CORRUPT;
   for (int i = 0; i < 3; i++) {
     if (i < (int)p.ndim) { p.dims[i] = dims[i]; p.brick[i] = brick[i]; }
@@ -508,7 +512,7 @@ int encode_enqueue(const void* d_x, const apax_params* p, const HG& h, bool prof
   int e;
   EncArgs A;
   enc_args(d_x, p, h, profiled, d_stream, d_nbytes, d_ws, A);
-  const bool wide = h.g.G > 64;
+  const bool wide = h.g.G > 64 || h.g.gq == 2;
   if (wide && h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
   if (h.lagged && h.g.nblocks) {
     int32_t* best = cj_ptr(d_ws, h);  // each block's own best stream
@@ -663,7 +667,7 @@ int apax_decode(const void* h_hdr, const void* d_stream, uint64_t nbytes, void* 
   if (!d_y && h.nsamples) return APAX_E_INVALID;
   if (cap < h.nsamples * (uint64_t)h.esz) return APAX_E_CAPACITY;
   A.y = d_y;
-  if (h.g.G > 64) {
+  if (h.g.G > 64 || h.g.gq == 2) {
     if (h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
     return hip_err(launch_wide_decode(h.dtype, h.ndim, A, stream));
   }
@@ -681,7 +685,7 @@ int apax_decode_dot(const void* h_hdr, const void* d_stream, uint64_t nbytes, co
     hipLaunchKernelGGL(k_clear, dim3(1), dim3(64), 0, stream, (uint32_t*)d_out, 2);
     return hip_err(hipGetLastError());
   }
-  if (h.g.G > 64) {
+  if (h.g.G > 64 || h.g.gq == 2) {
     if (!wide_fits(h.g)) return APAX_E_UNSUPPORTED;
     return hip_err(launch_wide_decode_dot(h.dtype, h.ndim, A, d_w, (double*)partials_ptr(d_ws, h), d_out, stream));
   }
@@ -713,7 +717,8 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
   q.code = 0;
   int e = setup(&q, h);
   if (e) return e;
-  if (h.g.G > 64) return APAX_E_UNSUPPORTED;  // the profile passes hold a block in one wave
+  // the profile passes hold a block of groups of 4 in one wave
+  if (h.g.G > 64 || h.g.gq == 2) return APAX_E_UNSUPPORTED;
   if (h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;  // the loop sets its own codes
   if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
@@ -1222,7 +1227,10 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
     int e;
     if (op == APAX_OP_ENCODE) {
       if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
-      if (h.lagged || h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
+      if (h.lagged || h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) {
+        delete b;
+        return batch_error(APAX_E_UNSUPPORTED, i);
+      }
       if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
         delete b;
         return batch_error(APAX_E_INVALID, i);
@@ -1234,7 +1242,10 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
       uint16_t budget;
       memcpy(&budget, (const uint8_t*)it.h_hdr + 10, 2);
       if ((e = setup(&q, h, header_budget(q.mode, budget)))) { delete b; return batch_error(e, i); }
-      if (h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) { delete b; return batch_error(APAX_E_UNSUPPORTED, i); }
+      if (h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) {
+        delete b;
+        return batch_error(APAX_E_UNSUPPORTED, i);
+      }
       uint64_t pw;
       memcpy(&pw, (const uint8_t*)it.h_hdr + 56, 8);
       uint64_t area = area_offset(h);
@@ -1684,7 +1695,7 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   if (q->op == APAX_OP_ENCODE) {
     if ((e = setup(&q->item.p, h))) return e;
     // served encodes may share a batch launch
-    if (h.lagged || h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
+    if (h.lagged || h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
     if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
     memset(r.hdr, 0, 64);
   } else {
@@ -1693,7 +1704,7 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
     uint16_t budget;
     memcpy(&budget, (const uint8_t*)q->item.h_hdr + 10, 2);
     if ((e = setup(&p, h, header_budget(p.mode, budget)))) return e;
-    if (h.g.G > 64 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
+    if (h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
     memcpy(r.hdr, q->item.h_hdr, 64);
     r.r.item.h_hdr = nullptr;
   }

@@ -54,6 +54,8 @@ struct Geo {
   int32_t target, alo, awd;
   // filter stream (1-d): stride (0: none) and sign (1: x[n] + x[n-k])
   int32_t fk, fneg;
+  // groups of 4 per exponent: 1, or 2 for groups of 8 samples
+  int32_t gq, pad_;
 };
 
 // Division of a numerator below 2^31 by a divisor known on the host

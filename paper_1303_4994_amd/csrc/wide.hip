@@ -147,47 +147,60 @@ struct WEnc {
   }
 
   // bits of every stream in `need` (a subset of 0x7F) at the quantized block;
-  // returns their sum (with one stream: its bits)
+  // returns their sum (with one stream: its bits).  Exponent positions of
+  // g->gq groups of 4 (groups of 4 or 8 samples, Sec. 6); each thread takes
+  // CP consecutive positions.
   __device__ __forceinline__ int32_t cost(uint32_t need) {
     need &= NDMASK;
-    const int G = g->G, C = wg.C, p0 = tid * C;
+    const int G = g->G, gq = g->gq, NP = G / gq;
+    const int CP = (NP + wg.nt - 1) / wg.nt, pp0 = tid * CP;
     int32_t pay[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int q = 0; q < C; q++) {
-      const int gi = p0 + q;
-      if (gi >= G) break;
-      int z, y, xq;
-      wg.coords(*g, gi, z, y, xq);
-      int64_t idx;
-      const int nv = wg.nvalid(*g, z, y, xq, idx);
-      uint32_t P[6], Y[6] = {0, 0, 0, 0, 0, 0}, Z[6] = {0, 0, 0, 0, 0, 0}, ZY[6] = {0, 0, 0, 0, 0, 0};
-      wide_row6(qa, *g, z, y, xq, P);
-      if (need & 0x68u) wide_row6(qa, *g, z, y - 1, xq, Y);
-      if (need & 0x50u) wide_row6(qa, *g, z - 1, y, xq, Z);
-      if (need & 0x40u) wide_row6(qa, *g, z - 1, y - 1, xq, ZY);
+    for (int q = 0; q < CP; q++) {
+      const int pos = pp0 + q;
+      if (pos >= NP) break;
+      int em[7] = {0, 0, 0, 0, 0, 0, 0}, pm[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (int r = 0; r < gq; r++) {
+        const int gi = pos * gq + r;
+        int z, y, xq;
+        wg.coords(*g, gi, z, y, xq);
+        int64_t idx;
+        const int nv = wg.nvalid(*g, z, y, xq, idx);
+        uint32_t P[6], Y[6] = {0, 0, 0, 0, 0, 0}, Z[6] = {0, 0, 0, 0, 0, 0}, ZY[6] = {0, 0, 0, 0, 0, 0};
+        wide_row6(qa, *g, z, y, xq, P);
+        if (need & 0x68u) wide_row6(qa, *g, z, y - 1, xq, Y);
+        if (need & 0x50u) wide_row6(qa, *g, z - 1, y, xq, Z);
+        if (need & 0x40u) wide_row6(qa, *g, z - 1, y - 1, xq, ZY);
+#pragma unroll
+        for (int st = 0; st < 7; st++) {
+          if (!((need >> st) & 1u)) continue;
+          uint32_t u[4];
+          if (NDIM == 1 && st == 3) group_filter(gi, P, u);
+          else wide_stream(st, P, Y, Z, ZY, u);
+          int32_t v[4];
+#pragma unroll
+          for (int k = 0; k < 4; k++) v[k] = k < nv ? wrapw<W>(u[k]) : 0;
+          int e, pw;
+          group_eps<W>(v, e, pw);
+          em[st] = max(em[st], e);
+          pm[st] = max(pm[st], pw);
+        }
+      }
 #pragma unroll
       for (int st = 0; st < 7; st++) {
         if (!((need >> st) & 1u)) continue;
-        uint32_t u[4];
-        if (NDIM == 1 && st == 3) group_filter(gi, P, u);
-        else wide_stream(st, P, Y, Z, ZY, u);
-        int32_t v[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = k < nv ? wrapw<W>(u[k]) : 0;
-        int e, pw;
-        group_eps<W>(v, e, pw);
-        eps[st * G + gi] = (uint8_t)e;
-        pay[st] += 4 * pw;
+        eps[st * G + pos] = (uint8_t)em[st];
+        pay[st] += 4 * gq * pm[st];
       }
     }
     wg_sum<7>(pay, *sh);  // its barriers also publish the exponent rows
     int32_t last[7];
 #pragma unroll
-    for (int st = 0; st < 7; st++) last[st] = ((need >> st) & 1u) ? wide_last_big(eps + st * G, G, p0, C) : -1;
+    for (int st = 0; st < 7; st++) last[st] = ((need >> st) & 1u) ? wide_last_big(eps + st * G, NP, pp0, CP) : -1;
     wg_excl_max<7>(last, *sh);
     int32_t nib[7];
 #pragma unroll
     for (int st = 0; st < 7; st++)
-      nib[st] = ((need >> st) & 1u) ? wide_jee_count(eps + st * G, G, p0, C, last[st]) : 0;
+      nib[st] = ((need >> st) & 1u) ? wide_jee_count(eps + st * G, NP, pp0, CP, last[st]) : 0;
     wg_sum<7>(nib, *sh);
     int32_t sum = 0;
 #pragma unroll
@@ -247,42 +260,58 @@ struct WEnc {
   }
 
   // the block's encoding at code c (quantized in qa) with stream st, nw words
-  // stored at dst (words past the LDS buffer are zero padding)
+  // stored at dst (words past the LDS buffer are zero padding).  The thread
+  // takes CP consecutive exponent positions, i.e. their gq * CP groups of 4.
   __device__ __forceinline__ void emit(int c, int st, int nw, uint32_t* __restrict__ dst) {
-    const int G = g->G, C = wg.C, p0 = tid * C;
+    const int G = g->G, gq = g->gq, NP = G / gq;
+    const int CP = (NP + wg.nt - 1) / wg.nt, pp0 = tid * CP, q0 = pp0 * gq, nq = CP * gq;
     const bool verb = st == 7;
     uint8_t* e7 = eps + 7 * G;
     uint32_t vv[WIDE_GPT][4];
-    int32_t pwv[WIDE_GPT];
+    int32_t pwq[WIDE_GPT];  // payload width of each group's position
     int32_t pay = 0;
 #pragma unroll
-    for (int q = 0; q < WIDE_GPT; q++) {
-      const int gi = p0 + q;
-      pwv[q] = 0;
+    for (int lq = 0; lq < WIDE_GPT; lq++) {
+      const int gi = q0 + lq;
+      pwq[lq] = 0;
 #pragma unroll
-      for (int k = 0; k < 4; k++) vv[q][k] = 0u;
-      if (q >= C || gi >= G) continue;
+      for (int k = 0; k < 4; k++) vv[lq][k] = 0u;
+      if (lq >= nq || gi >= G) continue;
       if (verb) {
         const uint4 a = *reinterpret_cast<const uint4*>(qa + 4 * gi);
-        vv[q][0] = a.x; vv[q][1] = a.y; vv[q][2] = a.z; vv[q][3] = a.w;
+        vv[lq][0] = a.x; vv[lq][1] = a.y; vv[lq][2] = a.z; vv[lq][3] = a.w;
       } else {
         int32_t v[4];
         group_stream(st, gi, v);
         int e, pw;
         group_eps<W>(v, e, pw);
-        e7[gi] = (uint8_t)e;
-        pwv[q] = pw;
-        pay += 4 * pw;
+        pwq[lq] = (e << 8) | pw;  // combined per position below
 #pragma unroll
-        for (int k = 0; k < 4; k++) vv[q][k] = (uint32_t)v[k];
+        for (int k = 0; k < 4; k++) vv[lq][k] = (uint32_t)v[k];
+      }
+    }
+    if (!verb) {  // exponent and width of each position: the widest of its groups
+#pragma unroll
+      for (int lq = 0; lq < WIDE_GPT; lq++) {
+        // gq = 2: groups lq & ~1 and lq | 1 share a position (the even one
+        // already holds the pair's maximum when the odd one comes)
+        const int a = lq & ~1, b = (lq | 1) < WIDE_GPT ? (lq | 1) : lq;
+        const int m = gq == 1 ? pwq[lq] : max(pwq[a], pwq[b]);
+        const bool head = gq == 1 || (lq & 1) == 0;
+        const int pos = pp0 + (gq == 1 ? lq : (lq >> 1));
+        if (head && lq < nq && pos < NP) {
+          e7[pos] = (uint8_t)(m >> 8);
+          pay += 4 * gq * (m & 0xFF);
+        }
+        pwq[lq] = m;
       }
     }
     int32_t s1[1] = {pay}, t1[1];
     wg_excl_sum<1>(s1, t1, *sh);  // its barriers publish row 7 and end the reads of qa
     int32_t payoff = s1[0];
-    int32_t last[1] = {verb ? -1 : wide_last_big(e7, G, p0, C)};
+    int32_t last[1] = {verb ? -1 : wide_last_big(e7, NP, pp0, CP)};
     wg_excl_max<1>(last, *sh);
-    int32_t n1[1] = {verb ? 0 : wide_jee_count(e7, G, p0, C, last[0])}, ntot[1];
+    int32_t n1[1] = {verb ? 0 : wide_jee_count(e7, NP, pp0, CP, last[0])}, ntot[1];
     wg_excl_sum<1>(n1, ntot, *sh);
     const int e0 = verb ? 0 : (int)e7[0];
     uint32_t* buf = qa;
@@ -292,9 +321,9 @@ struct WEnc {
     if (!verb) {
       // JEE tokens of the thread's positions
       int lst = last[0], noff = n1[0];
-      for (int q = 0; q < C; q++) {
-        const int i = p0 + q;
-        if (i >= G) break;
+      for (int q = 0; q < CP; q++) {
+        const int i = pp0 + q;
+        if (i >= NP) break;
         if (i == 0) {
           lst = 0;
           continue;
@@ -303,7 +332,7 @@ struct WEnc {
         const int ad = d < 0 ? -d : d;
         if (ad <= 1) {
           if ((i - lst) & 1) {
-            const int d2 = i + 1 < G ? (int)e7[i + 1] - (int)e7[i] : 9;
+            const int d2 = i + 1 < NP ? (int)e7[i + 1] - (int)e7[i] : 9;
             const bool pair = d2 >= -1 && d2 <= 1;
             const uint32_t tok = pair ? (uint32_t)(3 * (d + 1) + (d2 + 1)) : (uint32_t)(11 + d);
             or_word2(buf, H + 4 * noff, tok);
@@ -321,25 +350,26 @@ struct WEnc {
           }
         }
       }
-      // BFPE payload: 4 fields of pw bits per group
-      const int pay0 = H + 4 * ntot[0];
-      int o = pay0 + payoff;
+      // BFPE payload: 4 gq fields of pw bits per position, its groups in order
+      int o = H + 4 * ntot[0] + payoff;
 #pragma unroll
-      for (int q = 0; q < WIDE_GPT; q++) {
-        const int pw = pwv[q];
-        if (pw == 0) continue;
-        const uint32_t msk = (uint32_t)((1ull << pw) - 1u);
+      for (int lq = 0; lq < WIDE_GPT; lq++) {
+        if (lq >= nq || q0 + lq >= G) break;
+        const int pw = pwq[lq] & 0xFF;
+        if (pw) {
+          const uint32_t msk = (uint32_t)((1ull << pw) - 1u);
 #pragma unroll
-        for (int k = 0; k < 4; k++) or_word2(buf, o + k * pw, vv[q][k] & msk);
+          for (int k = 0; k < 4; k++) or_word2(buf, o + k * pw, vv[lq][k] & msk);
+        }
         o += 4 * pw;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < WIDE_GPT; q++) {
-        const int gi = p0 + q;
-        if (q >= C || gi >= G) break;
+      for (int lq = 0; lq < WIDE_GPT; lq++) {
+        const int gi = q0 + lq;
+        if (lq >= nq || gi >= G) break;
 #pragma unroll
-        for (int k = 0; k < 4; k++) or_word2(buf, H + (4 * gi + k) * W, low_bits((int32_t)vv[q][k], W));
+        for (int k = 0; k < 4; k++) or_word2(buf, H + (4 * gi + k) * W, low_bits((int32_t)vv[lq][k], W));
       }
     }
     if (tid == 0) {
@@ -455,6 +485,9 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
   WGeo wg;
   wg.init(g, j);
   const int nt = wg.nt, G = g.G, C = wg.C, p0 = tid * C;
+  // exponent positions (groups of 4 or 8 samples: gq groups of 4 each); the
+  // thread takes CP consecutive positions, i.e. groups q0 .. q0 + nq - 1
+  const int gq = g.gq, NP = G / gq, CP = (NP + nt - 1) / nt, pp0 = tid * CP, q0 = pp0 * gq, nq = CP * gq;
   const int mode = g.mode;
   const bool variable = mode != M_RATE;
   uint32_t* buf = lds;
@@ -523,7 +556,7 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
   // ---- JEE tokens: starts, positions, token area length
   int tend = 0;
   if (!verb && !ubad) {
-    const int K = 2 * (G - 1);                 // nibbles the tokens can take at most
+    const int K = 2 * (NP - 1);                 // nibbles the tokens can take at most
     const int avail = (32 * len - H) / 4;      // nibbles before the block's end
     const int Kw = K < avail ? K : avail;
     const int NC = (K + nt - 1) / nt;          // nibbles per thread
@@ -560,7 +593,7 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
       int pos = 1 + np[0];
       for (int q = 0; q < NC; q++) {
         const int k = k0 + q;
-        if (k >= Kw || pos > G - 1) break;
+        if (k >= Kw || pos > NP - 1) break;
         const int t = nib(k);
         const bool start = ((k - last - 1) & 1) == 0;
         if (t < 14) last = k;
@@ -568,9 +601,9 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
         int cover = 1, nn = 1;
         if (t <= 8) {
           cover = 2;
-          if (pos + 1 > G - 1) bad = true;
+          if (pos + 1 > NP - 1) bad = true;
           info[pos] = rel(t / 3 - 1);
-          if (pos + 1 <= G - 1) info[pos + 1] = rel(t % 3 - 1);
+          if (pos + 1 <= NP - 1) info[pos + 1] = rel(t % 3 - 1);
         } else if (t <= 13) {
           info[pos] = rel(t - 11);
         } else {
@@ -581,13 +614,13 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
             info[pos] = (2 << 16) | ((t - 14) * 16 + nib(k + 1));
           }
         }
-        if (pos + cover > G - 1 && pos <= G - 1) sh.tend = k + nn;  // the token that covers position G - 1
+        if (pos + cover > NP - 1 && pos <= NP - 1) sh.tend = k + nn;  // the token that covers the last position
         pos += cover;
       }
     }
     __syncthreads();
     tend = sh.tend;
-    if (tend < 0) ubad = true;  // the tokens end before position G - 1
+    if (tend < 0) ubad = true;  // the tokens end before the last position
   }
 
   // ---- exponents: running sums of the differences, restarted by absolute tokens
@@ -596,9 +629,9 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
   for (int q = 0; q < WIDE_GPT; q++) pwv[q] = 0;
   if (!verb && !ubad) {
     int32_t rs[1] = {0};
-    for (int q = 0; q < C; q++) {
-      const int i = p0 + q;
-      if (i >= G || i == 0) continue;
+    for (int q = 0; q < CP; q++) {
+      const int i = pp0 + q;
+      if (i >= NP || i == 0) continue;
       const int32_t v = info[i];
       if ((v >> 16) == 1) rs[0] += (int16_t)(v & 0xFFFF);
     }
@@ -608,9 +641,9 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
     int32_t key[1] = {-1};
     {
       int32_t s = rs[0];
-      for (int q = 0; q < C; q++) {
-        const int i = p0 + q;
-        if (i >= G) break;
+      for (int q = 0; q < CP; q++) {
+        const int i = pp0 + q;
+        if (i >= NP) break;
         if (i == 0) {
           key[0] = e0 + 32768;
           continue;
@@ -624,8 +657,8 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
     int32_t s = rs[0], kk = key[0];
 #pragma unroll
     for (int q = 0; q < WIDE_GPT; q++) {
-      const int i = p0 + q;
-      if (q >= C || i >= G) break;
+      const int i = pp0 + q;
+      if (q >= CP || i >= NP) break;
       int eps;
       if (i == 0) {
         eps = e0;
@@ -644,10 +677,10 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
       pwv[q] = (W == 32 && e == 31) ? 32 : e;
     }
   }
-  // ---- payload offsets and extraction
+  // ---- payload offsets and extraction (4 gq fields of a position's width)
   int32_t po[1] = {0};
 #pragma unroll
-  for (int q = 0; q < WIDE_GPT; q++) po[0] += 4 * pwv[q];
+  for (int q = 0; q < WIDE_GPT; q++) po[0] += 4 * gq * pwv[q];
   int32_t ptot[1];
   wg_excl_sum<1>(po, ptot, sh);
   const int pay0 = H + 4 * tend;
@@ -657,21 +690,24 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
   {
     int o = pay0 + po[0];
 #pragma unroll
-    for (int q = 0; q < WIDE_GPT; q++) {
-      const int gi = p0 + q;
+    for (int lq = 0; lq < WIDE_GPT; lq++) {
+      const int gi = q0 + lq;
+      int pq = 0;  // width of the group's position
+#pragma unroll
+      for (int q = 0; q < WIDE_GPT; q++) pq = q == lq / gq ? pwv[q] : pq;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        const int width = verb ? W : pwv[q];
-        const int bit = verb ? H + (4 * gi + k) * W : o + k * pwv[q];
+        const int width = verb ? W : pq;
+        const int bit = verb ? H + (4 * gi + k) * W : o + k * pq;
         int wd = bit >> 5;
         wd = wd < 0 ? 0 : (wd > stride - 2 ? stride - 2 : wd);
         const uint64_t both = ((uint64_t)buf[wd + 1] << 32) | buf[wd];
         const uint32_t raw = (uint32_t)(both >> (bit & 31));
-        r[q][k] = (ubad || q >= C || gi >= G || width == 0)
-                      ? 0u
-                      : (width >= 32 ? raw : (uint32_t)(((int32_t)(raw << (32 - width))) >> (32 - width)));
+        r[lq][k] = (ubad || lq >= nq || gi >= G || width == 0)
+                       ? 0u
+                       : (width >= 32 ? raw : (uint32_t)(((int32_t)(raw << (32 - width))) >> (32 - width)));
       }
-      o += 4 * pwv[q];
+      o += 4 * pq;
     }
   }
   // padding after the last used bit must be zero
@@ -685,10 +721,10 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wide_dec(DecArgs A, const T* __re
   __syncthreads();  // the words are read: the buffer takes the values
   uint32_t* v = lds;
 #pragma unroll
-  for (int q = 0; q < WIDE_GPT; q++) {
-    const int gi = p0 + q;
-    if (q < C && gi < G)
-      *reinterpret_cast<uint4*>(v + 4 * gi) = make_uint4(r[q][0], r[q][1], r[q][2], r[q][3]);
+  for (int lq = 0; lq < WIDE_GPT; lq++) {
+    const int gi = q0 + lq;
+    if (lq < nq && gi < G)
+      *reinterpret_cast<uint4*>(v + 4 * gi) = make_uint4(r[lq][0], r[lq][1], r[lq][2], r[lq][3]);
   }
   __syncthreads();
 

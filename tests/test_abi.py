@@ -60,6 +60,12 @@ VALIDATION = [
     (np.float64, (64, 64), {"mode": "adaptive_rate", "brick": (16, 16), "rate": 4.0, "code": 16384}),
     (np.int16, (5000,), {"mode": "adaptive_rate", "brick": (64,), "rate": 2.0, "code": -600}),
     (np.int16, (5000,), {"mode": "adaptive_rate", "brick": (64,), "rate": 2.0, "code": -6}),
+    # groups of 8 samples per exponent (Sec. 6)
+    (np.int16, (5000,), {"mode": "lossless", "brick": (64,), "group": 8}),
+    (np.int16, (5000,), {"mode": "lossless", "brick": (68,), "group": 8}),
+    (np.float32, (64, 64), {"mode": "fixed_rate", "brick": (4, 16), "rate": 4.0, "group": 8}),
+    (np.float32, (64, 64), {"mode": "fixed_rate", "brick": (4, 12), "rate": 4.0, "group": 8}),
+    (np.int8, (64, 64), {"mode": "fixed_rate", "brick": (8, 8), "rate": 7.9, "group": 8}),
     # block and sample counts that would wrap 64-bit products are refused
     (np.float32, (1099509530628, 67108992, 16), {"mode": "fixed_quality", "brick": (2, 2, 16), "code": 0}),
     (np.int16, (1 << 40, 1 << 40, 1 << 40), {"mode": "lossless", "brick": (1, 1, 64)}),
@@ -91,7 +97,8 @@ def test_stream_info_parses_oracle_streams(A):
     x = np.arange(3000, dtype=np.int16).reshape(30, 100) // 3
     for params in ({"mode": "lossless", "brick": (4, 16)},
                    {"mode": "fixed_rate", "brick": (4, 16), "rate": 3.0, "code": -20},
-                   {"mode": "adaptive_rate", "brick": (4, 16), "rate": 3.0, "code": -20}):
+                   {"mode": "adaptive_rate", "brick": (4, 16), "rate": 3.0, "code": -20},
+                   {"mode": "lossless", "brick": (4, 16), "group": 8}):
         s = O.encode(x, params)
         info = A.apax_stream_info(bytes(s[:64]))
         assert info["shape"] == x.shape and info["brick"] == params["brick"]

@@ -1,0 +1,160 @@
+"""GPU parity of groups of 8 samples per exponent (Sec. 6: N = 4 or 8):
+streams and decodes byte-identical to the oracle for every dtype, 1-/2-/3-d
+bricks, every mode, blocks of 64..16384 samples, ragged edges, with the
+filter stream, the lagged choice and the adaptive loop; the decode-on-read
+consumer; corrupt blocks flagged exactly where the oracle refuses them."""
+import numpy as np
+import pytest
+
+import brute
+import synth
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def A():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1303_4994_amd import apax
+    return apax
+
+
+def field(dt, shape, seed, kind="smooth"):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    dt = np.dtype(dt)
+    if kind == "noise":
+        if dt.kind == "i":
+            info = np.iinfo(dt)
+            return rng.integers(info.min, info.max, n, endpoint=True).astype(dt).reshape(shape)
+        return rng.standard_normal(n).astype(dt).reshape(shape)
+    t = np.arange(n)
+    base = (np.sin(2 * np.pi * 0.003 * t) + 0.2 * np.sin(2 * np.pi * 0.05 * t)
+            + 0.02 * rng.standard_normal(n)).reshape(shape)
+    for ax in range(len(shape)):
+        base = base.cumsum(axis=ax) / 8
+    if dt.kind == "i":
+        return np.rint(base / np.abs(base).max() * 0.45 * np.iinfo(dt).max).astype(dt)
+    return (base * 1e2).astype(dt)
+
+
+CASES = [
+    ("i16-1d-B64-lossless", np.int16, (64 * 300 + 40,), {"mode": "lossless", "brick": (64,)}, "smooth"),
+    ("i16-1d-B256-lossless", np.int16, (256 * 100 + 8,), {"mode": "lossless", "brick": (256,)}, "smooth"),
+    ("i32-1d-B512-noise", np.int32, (512 * 20 + 24,), {"mode": "lossless", "brick": (512,)}, "noise"),
+    ("i8-2d-8x8-lossless", np.int8, (60, 70), {"mode": "lossless", "brick": (8, 8)}, "smooth"),
+    ("i32-3d-2x4x8-lossless", np.int32, (9, 17, 30), {"mode": "lossless", "brick": (2, 4, 8)}, "smooth"),
+    ("f32-2d-16x16-fr", np.float32, (300, 260), {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0, "code": 60},
+     "smooth"),
+    ("f64-3d-4x4x16-fq", np.float64, (17, 30, 50), {"mode": "fixed_quality", "brick": (4, 4, 16), "code": 250},
+     "smooth"),
+    ("f32-1d-B16384-fr-top", np.float32, (16384 * 3 + 504,), {"mode": "fixed_rate", "brick": (16384,), "rate": 5.0,
+                                                             "code": 16383}, "noise"),
+    ("f64-2d-64x64-fr", np.float64, (200, 150), {"mode": "fixed_rate", "brick": (64, 64), "rate": 6.0, "code": 300},
+     "smooth"),
+    ("i16-2d-8x16-fr", np.int16, (90, 100), {"mode": "fixed_rate", "brick": (8, 16), "rate": 3.0, "code": 0},
+     "smooth"),
+    ("f32-1d-B128-fr-bigbudget", np.float32, (5000,), {"mode": "fixed_rate", "brick": (128,), "rate": 0.5,
+                                                       "code": 300}, "noise"),
+    ("f32-1d-B256-adaptive", np.float32, (256 * 200,), {"mode": "adaptive_rate", "brick": (256,), "rate": 4.0,
+                                                        "code": 60}, "smooth"),
+]
+
+
+def roundtrip(A, x, params):
+    xg = torch.from_numpy(x).to(DEV)
+    ws = A.workspace(xg.dtype, tuple(x.shape), params, DEV)
+    buf, nb = A.apax_encode(xg, params, ws=ws)
+    assert A.apax_status(ws) == 0
+    n = int(nb.item())
+    got = buf[:n].cpu().numpy()
+    y = A.apax_decode(buf, n, ws=ws)
+    assert A.apax_status(ws) == 0
+    return got, y.cpu().numpy()
+
+
+def check(A, x, params):
+    exp = O.encode(x, params)
+    got, y = roundtrip(A, x, params)
+    if got.size != exp.size or not np.array_equal(got, exp):
+        sg, se = brute.Stream(got), brute.Stream(exp)
+        j = next((j for j in range(se.nblocks) if not np.array_equal(sg.block(j), se.block(j))), None)
+        pytest.fail(f"stream differs ({got.size} vs {exp.size} bytes), first block {j}")
+    assert np.array_equal(y.view(np.uint8), O.decode(exp).view(np.uint8))
+    if params["mode"] == "lossless":
+        assert np.array_equal(y, x)
+    return exp
+
+
+@pytest.mark.parametrize("name,dt,shape,params,kind", CASES, ids=[c[0] for c in CASES])
+def test_group8_equals_oracle(A, name, dt, shape, params, kind):
+    print(f"case {name}", flush=True)
+    x = field(dt, shape, 5, kind)
+    exp = check(A, x, dict(params, group=8))
+    assert exp[8] & 0x10
+
+
+def test_group8_filter_lagged_dot(A):
+    x = synth.modulated(np.int16, 40000, 3, 512, noise=0.002)
+    check(A, x, {"mode": "lossless", "brick": (256,), "group": 8, "filter": (1, -1)})
+    check(A, x, {"mode": "lossless", "brick": (128,), "group": 8, "lagged": True})
+    xf = field(np.float32, (120, 96), 9)
+    w = field(np.float32, (120, 96), 10, "noise")
+    p = {"mode": "fixed_rate", "brick": (8, 16), "rate": 4.0, "code": 60, "group": 8}
+    xg, wg = torch.from_numpy(xf).to(DEV), torch.from_numpy(w).to(DEV)
+    buf, nb = A.apax_encode(xg, p)
+    n = int(nb.item())
+    got = float(A.apax_decode_dot(buf, n, bytes(buf[:64].cpu().numpy().tobytes()), wg).item())
+    y = O.decode(O.encode(xf, p)).astype(np.float64).ravel()
+    wd = w.astype(np.float64).ravel()
+    assert abs(got - float(np.dot(y, wd))) <= 1e-12 * float(np.abs(y * wd).sum()) + 1e-300
+
+
+def test_group8_corrupt_blocks_flagged_as_the_oracle(A):
+    x = field(np.int16, (256 * 12 + 40,), 3)
+    params = {"mode": "lossless", "brick": (256,), "group": 8}
+    exp = O.encode(x, params)
+    st = brute.Stream(exp)
+    ws = A.workspace(torch.int16, x.shape, params, DEV)
+
+    def decode(buf):
+        g = torch.from_numpy(buf).to(DEV)
+        A.apax_status_clear(ws)
+        y = A.apax_decode(g, buf.size, hdr=bytes(exp[:64]), ws=ws)
+        return A.apax_status(ws), y.cpu().numpy()
+
+    rng = np.random.default_rng(12)
+    nflag = 0
+    for t in range(30):
+        bad = exp.copy()
+        j = int(rng.integers(0, st.nblocks))
+        w = int(rng.integers(0, st.lens[j]))
+        bit = int(rng.integers(0, 32))
+        bad[st.area + 4 * (st.offsets[j] + w) + bit // 8] ^= np.uint8(1 << (bit % 8))
+        yo = np.zeros_like(x)
+        orc = O.decode_rc(bad, yo)
+        print(f"flip block {j} word {w} bit {bit}: oracle rc {orc}", flush=True)
+        rc, y = decode(bad)
+        if orc == O.E_CORRUPT:
+            assert rc == A.E_CORRUPT, (j, w, bit)
+            nflag += 1
+        else:
+            assert orc == 0 and rc == 0 and np.array_equal(y, yo), (j, w, bit, orc, rc)
+    assert nflag > 0
+
+
+def test_group8_refused_where_unsupported(A):
+    x = torch.from_numpy(field(np.float32, (4096,), 1)).to(DEV)
+    p = {"mode": "fixed_rate", "brick": (64,), "rate": 4.0, "group": 8}
+    with pytest.raises(A.ApaxError) as e:
+        A.apax_profile(x, p)
+    assert e.value.code == A.E_UNSUPPORTED
+    with pytest.raises(A.ApaxError) as e:
+        A.Batch.encode([(x, dict(p, code=10))])
+    assert e.value.code == A.E_UNSUPPORTED
