@@ -60,16 +60,17 @@ enum { APAX_I8 = 1, APAX_I16 = 2, APAX_I32 = 3, APAX_F32 = 4, APAX_F64 = 5 };
  * the variable-size container (its header holds T in the budget field and c0
  * in the code field) and decodes like any other.  The loop runs as a parallel
  * scan over per-block transition maps, exactly reproducing the sequential
- * order.  Not accepted by the profiler, batches, the server or
- * APAX_CODE_PROFILED (APAX_E_UNSUPPORTED). */
+ * order.  Not accepted by the profiler or APAX_CODE_PROFILED
+ * (APAX_E_UNSUPPORTED): the loop sets its own codes.  Batches and the server
+ * run such items as single calls. */
 enum { APAX_LOSSLESS = 0, APAX_FIXED_RATE = 1, APAX_FIXED_QUALITY = 2, APAX_ADAPTIVE_RATE = 3 };
 #define APAX_ADAPT_HALF 32
 enum {
   APAX_OK = 0,
   APAX_E_INVALID = -1,     /* bad parameters */
-  APAX_E_UNSUPPORTED = -2, /* valid request the library does not implement (lossless floats; blocks above
-                              256 samples in the profiler, batches and the server, or on a device whose
-                              workgroups get too little LDS for them) */
+  APAX_E_UNSUPPORTED = -2, /* valid request the library does not implement (lossless floats; the
+                              profiler in adaptive rate; blocks above 256 samples or groups of 8 on a
+                              device whose workgroups get too little LDS for them) */
   APAX_E_CAPACITY = -3,    /* output or workspace buffer too small */
   APAX_E_CORRUPT = -4,     /* stream fails validation */
   APAX_E_NONFINITE = -5,   /* NaN or Inf in the input */
@@ -111,7 +112,7 @@ typedef struct apax_params {
  * block j is coded with the stream that was best for block j-1 (block 0:
  * stream 0), as an encoder that decides after the block has streamed out.
  * Lossless mode only; the stream format is unchanged (each block header
- * names its stream).  Not accepted by batches. */
+ * names its stream).  Batches and the server run such items as single calls. */
 #define APAX_FLAG_LAGGED 1u
 
 /* apax_params.flags: the filter stream (Sec. 5 oversampling, Sec. 6: the
@@ -129,8 +130,8 @@ typedef struct apax_params {
  * position then covers 8 consecutive samples of a brick row: the block size
  * and the brick's x extent must be multiples of 8 (else APAX_E_INVALID).  The
  * stream header records it in bit 4 of the ndim byte (byte 8).  Encoded and
- * decoded by the one-workgroup-per-block kernels; not accepted by the
- * profiler, batches or the server (APAX_E_UNSUPPORTED). */
+ * decoded, and profiled, by the one-workgroup-per-block kernels; batches and
+ * the server run such items as single calls. */
 #define APAX_FLAG_GROUP8 0x4000u
 
 #define APAX_FILTER(k, neg) ((((uint32_t)(k)) << 8) | ((neg) ? 0x2000u : 0u))
@@ -206,8 +207,9 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
  * on `stream` as soon as the stream is complete, before the profile's
  * centred and curve passes, so a decode on another stream can overlap them.
  * p->code is ignored; d_ws holds the profile as after apax_profile_async.
- * Blocks of at most 256 samples; the lagged choice runs the plain encode
- * after the profile. */
+ * The lagged choice, blocks of more than 256 samples and groups of 8 run the
+ * plain encode after the profile (their passes record no per-block
+ * choices). */
 int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                               void* d_stream, uint64_t cap, uint64_t* d_nbytes, hipStream_t stream,
                               hipEvent_t encoded);
@@ -380,7 +382,10 @@ const char* apax_strerror(int code);
  * one persistent kernel launch per block-shape class (one launch when every
  * item has the same ndim and a block of 129..256 samples), optionally
  * replayed as a hipGraph.  Each item's output is byte-identical to a
- * separate apax_encode / apax_decode call.  Launch geometry (waves per
+ * separate apax_encode / apax_decode call.  Items the shared launch does not
+ * take (blocks of more than 256 samples, groups of 8, the lagged choice,
+ * adaptive rate) run in the same batch run as single-array calls, each with
+ * its own region of the batch workspace and its own status word.  Launch geometry (waves per
  * workgroup, persistent workgroups per CU, tiles taken per work-queue
  * ticket) never changes any output; an autotuner chooses it. */
 enum { APAX_OP_ENCODE = 0, APAX_OP_DECODE = 1 };
@@ -430,8 +435,11 @@ void apax_batch_destroy(apax_batch* b);
  * every free slot while the in-flight footprint (input bytes + output
  * capacity of each admitted request) stays within the HBM budget, and
  * launches each admitted group on the slot's own stream: requests of 16 MB
- * and more as single apax_encode / apax_decode calls (each with its own
- * status word), the rest as one persistent batch.  Groups on different slots
+ * and more, and those no shared launch takes (blocks of more than 256
+ * samples, groups of 8, the lagged choice, adaptive rate; their workspace
+ * must fit the slot's, else APAX_E_CAPACITY at submit), as single
+ * apax_encode / apax_decode calls (each with its own status word), the rest
+ * as one persistent batch.  Groups on different slots
  * overlap on the device; a request that
  * arrives while others run is admitted as soon as a slot and budget free up.
  * Codec state stays on the device: each slot owns resident workspaces

@@ -13,7 +13,7 @@ INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libapax.so")
 SOURCES = ["capi.hip", "encode.hip", "decode.hip", "profile.hip", "batch_enc.hip", "batch_dec.hip",
-           "s2r.hip", "spectra.hip", "monitor.hip", "wide.hip", "adapt.hip"]
+           "s2r.hip", "spectra.hip", "monitor.hip", "wide.hip", "adapt.hip", "profile_wide.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
          "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

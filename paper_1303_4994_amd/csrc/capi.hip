@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <deque>
 #include <mutex>
@@ -261,6 +262,10 @@ void clear_words(uint32_t* p, int nwords, hipStream_t s) {
   if (nwords > 0) hipLaunchKernelGGL(k_clear, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s, p, nwords);
 }
 
+__global__ void k_copy_word(uint32_t* dst, const uint32_t* src) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 // OR the per-item status words of a batch into the workspace status word
 __global__ void k_fold_status(const uint32_t* item_status, uint32_t n, uint32_t* status) {
   uint32_t acc = 0;
@@ -318,6 +323,12 @@ struct apax_batch {
   std::vector<apax_batch_item> items;
   std::vector<HG> geo;
   std::vector<BatchClass> classes;
+  // items the shared launch does not take (blocks of more than 64 groups,
+  // groups of 8, the lagged choice, adaptive rate): single-array calls in
+  // the same run, each with its own workspace region and copy of the header
+  std::vector<uint32_t> solo;
+  std::vector<uint64_t> solo_off;
+  std::vector<std::array<uint8_t, 64>> solo_hdr;
   uint64_t ws_bytes = 0;
   uint64_t istat_off = 0;       // per-item status words in the workspace
   void* d_ws = nullptr;
@@ -467,7 +478,8 @@ uint64_t enc_need(const HG& h) {
 
 // Blocks above 256 samples run one workgroup per block with the block staged
 // in LDS; the current device must give a workgroup that much.
-bool wide_fits(const Geo& g) {
+// extra: static LDS of the kernel beyond WideShared (the profile passes' wave partials)
+bool wide_fits(const Geo& g, size_t extra = 256) {
   static int cache[64] = {0};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
@@ -476,7 +488,7 @@ bool wide_fits(const Geo& g) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
     if (dev >= 0 && dev < 64) cache[dev] = v;
   }
-  return wide_lds_bytes(g) + sizeof(WideShared) + 256 <= (size_t)v;
+  return wide_lds_bytes(g) + sizeof(WideShared) + extra <= (size_t)v;
 }
 
 // The encoder's kernel arguments for array d_x, stream d_stream, workspace d_ws.
@@ -717,8 +729,9 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
   q.code = 0;
   int e = setup(&q, h);
   if (e) return e;
-  // the profile passes hold a block of groups of 4 in one wave
-  if (h.g.G > 64 || h.g.gq == 2) return APAX_E_UNSUPPORTED;
+  // blocks of more than 64 groups (or groups of 8) take one workgroup each,
+  // staged in LDS beside the wave partials of the pass
+  if ((h.g.G > 64 || h.g.gq == 2) && h.g.nblocks && !wide_fits(h.g, 2048)) return APAX_E_UNSUPPORTED;
   if (h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;  // the loop sets its own codes
   if (!d_ws || (!d_x && h.nsamples)) return APAX_E_INVALID;
   if ((uintptr_t)d_ws & 15) return APAX_E_INVALID;
@@ -945,6 +958,9 @@ int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, doub
   HG h;
   int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
   if (e) return e;
+  // one workgroup per block: the block in LDS beside the digit histogram
+  if ((h.g.G > 64 || h.g.gq == 2) && h.g.nblocks && !wide_fits(h.g, S2R_HIST_BYTES + 256))
+    return APAX_E_UNSUPPORTED;
   *h_ratio = NAN;
   *h_db = NAN;
   if (h.nsamples == 0) return APAX_OK;
@@ -1169,9 +1185,10 @@ int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws,
   if (cap < bound_of(h)) return APAX_E_CAPACITY;
   apax_params q = *p;
   q.code = 0;  // the header's code and mask are the profile's, written on the device
-  if (h.lagged || h.g.nblocks == 0) {
+  if (h.lagged || h.g.nblocks == 0 || h.g.G > 64 || h.g.gq == 2) {
     // the lagged choice codes block j with block j-1's stream, which the
-    // metrics pass does not record: the profile, then the plain encode
+    // metrics pass does not record, and the one-workgroup-per-block passes
+    // record no per-block choices: the profile, then the plain encode
     if ((e = profile_enqueue(d_x, p, h, d_ws, stream))) return e;
     if ((e = encode_enqueue(d_x, &q, h, true, d_stream, d_nbytes, d_ws, stream))) return e;
     if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
@@ -1227,25 +1244,26 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
     int e;
     if (op == APAX_OP_ENCODE) {
       if ((e = setup(&it.p, h))) { delete b; return batch_error(e, i); }
-      if (h.lagged || h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) {
-        delete b;
-        return batch_error(APAX_E_UNSUPPORTED, i);
-      }
       if (!it.d_out || !it.d_nbytes || (!it.d_in && h.nsamples) || ((uintptr_t)it.d_out & 15)) {
         delete b;
         return batch_error(APAX_E_INVALID, i);
       }
       if (it.cap < bound_of(h)) { delete b; return batch_error(APAX_E_CAPACITY, i); }
+      if (h.lagged || h.mode == APAX_ADAPTIVE_RATE || h.g.G > 64 || h.g.gq == 2) {
+        if ((h.g.G > 64 || h.g.gq == 2) && h.g.nblocks && !wide_fits(h.g)) {
+          delete b;
+          return batch_error(APAX_E_UNSUPPORTED, i);
+        }
+        b->solo.push_back(i);
+        b->solo_hdr.push_back({});
+        continue;
+      }
     } else {
       apax_params q;
       if (!it.h_hdr || (e = apax_stream_info(it.h_hdr, 64, &q))) { delete b; return batch_error(APAX_E_CORRUPT, i); }
       uint16_t budget;
       memcpy(&budget, (const uint8_t*)it.h_hdr + 10, 2);
       if ((e = setup(&q, h, header_budget(q.mode, budget)))) { delete b; return batch_error(e, i); }
-      if (h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) {
-        delete b;
-        return batch_error(APAX_E_UNSUPPORTED, i);
-      }
       uint64_t pw;
       memcpy(&pw, (const uint8_t*)it.h_hdr + 56, 8);
       uint64_t area = area_offset(h);
@@ -1253,6 +1271,16 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
       if (it.in_bytes < area || (it.in_bytes - area) / 4 < pw) { delete b; return batch_error(APAX_E_CORRUPT, i); }
       if (h.mode == APAX_FIXED_RATE && pw != (uint64_t)h.g.budget * (uint64_t)h.g.nblocks) { delete b; return batch_error(APAX_E_CORRUPT, i); }
       if (it.cap < h.nsamples * (uint64_t)h.esz) { delete b; return batch_error(APAX_E_CAPACITY, i); }
+      if (h.mode == APAX_ADAPTIVE_RATE || h.g.G > 64 || h.g.gq == 2) {
+        if ((h.g.G > 64 || h.g.gq == 2) && h.g.nblocks && !wide_fits(h.g)) {
+          delete b;
+          return batch_error(APAX_E_UNSUPPORTED, i);
+        }
+        b->solo.push_back(i);
+        b->solo_hdr.emplace_back();
+        memcpy(b->solo_hdr.back().data(), it.h_hdr, 64);
+        continue;
+      }
     }
     int lpb = lpb_of(h.g);
     BatchClass* c = nullptr;
@@ -1285,6 +1313,10 @@ int apax_batch_create(int op, const apax_batch_item* h_items, uint32_t n, const 
   off += tab;
   b->istat_off = off;
   off += al256(4 * (uint64_t)std::max<uint32_t>(n, 1));
+  for (uint32_t i : b->solo) {
+    b->solo_off.push_back(off);
+    off += al256(ws_need(b->geo[i]));
+  }
   for (auto& c : b->classes) {
     c.ticket_off = off;
     off += 256;
@@ -1381,6 +1413,7 @@ int batch_upload_from(apax_batch* b, void* d_ws, uint64_t ws_bytes, hipStream_t 
   }
   clear_words((uint32_t*)d_ws, 1, stream);
   clear_words((uint32_t*)(ws + b->istat_off), (int)b->items.size(), stream);
+  for (uint64_t o : b->solo_off) clear_words((uint32_t*)(ws + o), 1, stream);
   return hip_err(hipGetLastError());
 }
 
@@ -1432,6 +1465,30 @@ int apax_batch_run(apax_batch* b, hipStream_t stream) {
     if (b->op == APAX_OP_ENCODE) e = hip_err(launch_encode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     else e = hip_err(launch_decode_batch(c.lpb, c.ndim, wp, B, c.grid, lds, stream));
     if (e) return e;
+  }
+  for (size_t k = 0; k < b->solo.size(); k++) {
+    const uint32_t i = b->solo[k];
+    const apax_batch_item& it = b->items[i];
+    const HG& h = b->geo[i];
+    uint8_t* sws = ws + b->solo_off[k];
+    const uint64_t swb = ws_need(h);
+    int e;
+    if (b->op == APAX_OP_ENCODE) {
+      e = encode_enqueue(it.d_in, &it.p, h, false, it.d_out, it.d_nbytes, sws, stream);
+    } else {
+      HG hd;
+      DecArgs A;
+      e = decode_setup(b->solo_hdr[k].data(), it.d_in, it.in_bytes, sws, swb, hd, A);
+      if (!e) {
+        A.y = it.d_out;
+        e = hip_err(hd.g.G > 64 || hd.g.gq == 2 ? launch_wide_decode(hd.dtype, hd.ndim, A, stream)
+                                                 : launch_decode(hd.dtype, hd.ndim, A, stream));
+      }
+    }
+    if (e) return e;
+    hipLaunchKernelGGL(k_copy_word, dim3(1), dim3(64), 0, stream, (uint32_t*)(ws + b->istat_off) + i,
+                       (const uint32_t*)sws);
+    if ((e = hip_err(hipGetLastError()))) return e;
   }
   if (!b->items.empty()) {
     hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(256), 0, stream, (const uint32_t*)(ws + b->istat_off),
@@ -1499,6 +1556,7 @@ struct SrvReq {
   uint8_t hdr[64];
   uint64_t footprint = 0;
   double t_submit = 0.0;
+  bool alone = false;  // runs as a single call whatever its size (no shared launch takes it)
 };
 
 struct SrvSlot {
@@ -1543,10 +1601,6 @@ struct apax_server {
 
 namespace {
 
-__global__ void k_copy_word(uint32_t* dst, const uint32_t* src) {
-  if (threadIdx.x == 0) *dst = *src;
-}
-
 void server_free(apax_server* s) {
   for (auto& sl : s->slots) {
     if (sl.stream) hipStreamSynchronize(sl.stream);
@@ -1584,7 +1638,7 @@ int server_launch(apax_server* s, SrvSlot& sl) {
   for (uint32_t i = 0; i < sl.reqs.size(); i++) {
     const SrvReq& q = sl.reqs[i];
     const int k = q.r.op == APAX_OP_ENCODE ? 0 : 1;
-    const uint64_t w = q.footprint - q.r.item.cap >= SOLO_BYTES ? solo_ws(q) : 0;
+    const uint64_t w = q.alone || q.footprint - q.r.item.cap >= SOLO_BYTES ? solo_ws(q) : 0;
     if (w && w <= s->ws_bytes) {
       sl.solo.push_back(i);
       continue;
@@ -1694,9 +1748,8 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
   int e;
   if (q->op == APAX_OP_ENCODE) {
     if ((e = setup(&q->item.p, h))) return e;
-    // served encodes may share a batch launch
-    if (h.lagged || h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
     if (q->item.cap < bound_of(h)) return APAX_E_CAPACITY;
+    r.alone = h.lagged || h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE;
     memset(r.hdr, 0, 64);
   } else {
     apax_params p;
@@ -1704,9 +1757,14 @@ int apax_server_submit(apax_server* s, const apax_request* q, uint64_t* id) {
     uint16_t budget;
     memcpy(&budget, (const uint8_t*)q->item.h_hdr + 10, 2);
     if ((e = setup(&p, h, header_budget(p.mode, budget)))) return e;
-    if (h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE) return APAX_E_UNSUPPORTED;
+    r.alone = h.g.G > 64 || h.g.gq == 2 || h.mode == APAX_ADAPTIVE_RATE;
     memcpy(r.hdr, q->item.h_hdr, 64);
     r.r.item.h_hdr = nullptr;
+  }
+  // requests no shared launch takes run alone in the slot's codec workspace
+  if (r.alone) {
+    if ((h.g.G > 64 || h.g.gq == 2) && h.g.nblocks && !wide_fits(h.g)) return APAX_E_UNSUPPORTED;
+    if (ws_need(h) > s->ws_bytes) return APAX_E_CAPACITY;
   }
   r.footprint = req_footprint(*q, h);
   if (r.footprint > s->budget) return APAX_E_CAPACITY;

@@ -262,6 +262,8 @@ int64_t prof_wgs(int64_t ntiles, int ncodes);
 // ev (optional): events recorded just before and just after the pass kernel
 // (its one-workgroup reduce follows outside the pair)
 hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev = nullptr);
+// the pass kernel for blocks of more than 64 groups or groups of 8 (A.nwg set)
+hipError_t launch_wide_profile(int dtype, int ndim, const ProfArgs& A, hipStream_t s);
 hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,
                        hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_ctl(const CtlArgs& C, hipStream_t s);

@@ -115,8 +115,7 @@ def test_adaptive_noalloc_and_refusals(A):
     assert int(st.item()) == 0
     assert np.array_equal(out[: int(nb.item())].cpu().numpy(), exp)
     for call in (lambda: A.apax_profile(xg, p),
-                 lambda: A.apax_encode(xg, dict(p, code=A.CODE_PROFILED)),
-                 lambda: A.Batch.encode([(xg, p)])):
+                 lambda: A.apax_encode(xg, dict(p, code=A.CODE_PROFILED))):
         with pytest.raises(A.ApaxError) as e:
             call()
         assert e.value.code == A.E_UNSUPPORTED

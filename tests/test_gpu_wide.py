@@ -179,14 +179,3 @@ def test_wide_corrupt_blocks_flagged_as_the_oracle(A):
             assert orc == 0 and rc == 0, (j, w, bit, orc, rc)
             assert np.array_equal(y, yo), (j, w, bit)
     assert nflag > 0
-
-
-def test_wide_refused_where_unsupported(A):
-    x = torch.from_numpy(field(np.float32, (4096,), 1)).to(DEV)
-    p = {"mode": "fixed_rate", "brick": (1024,), "rate": 4.0}
-    with pytest.raises(A.ApaxError) as e:
-        A.apax_profile(x, p)
-    assert e.value.code == A.E_UNSUPPORTED
-    with pytest.raises(A.ApaxError) as e:
-        A.Batch.encode([(x, dict(p, code=10))])
-    assert e.value.code == A.E_UNSUPPORTED
