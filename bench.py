@@ -650,7 +650,7 @@ def main():
         "config": {"workload": "C1: 2-D fp32 field 4096x4096 (GRF, k^-3, [-1e3,1e3] + noise 1e-2), "
                                "fixed rate 4:1, 16x16 bricks, profile + encode + decode per step",
                    "input_bytes": nbytes_in, "stream_bytes": bound, "copies_rotated": R,
-                   "attenuation_arith": "f64", "stats_arith": "f32 float-float",
+                   "attenuation_arith": "f64", "stats_arith": "f64",
                    "streams": "profile and encode on one stream (the encode from the metrics pass's "
                               "per-block codes and streams, right after that pass); decode on a second, "
                               "overlapping the centred and curve passes"},

@@ -117,7 +117,7 @@ struct PState {
 // field (record r = code * nwg + workgroup, R records), reduced in a fixed
 // order by the one-workgroup reduce kernel that follows the pass.
 struct PParts {
-  float2* s;          // [NSUM][R] float-float sums
+  double* s;          // [NSUM][R] binary64 sums
   uint64_t* words;    // [R] encoded words
   uint64_t* dmax;     // [R] max |d| (binary64 bits)
   uint32_t* nfit;     // [R] blocks that fit the budget
@@ -127,7 +127,7 @@ struct PParts {
 __host__ __device__ inline PParts pparts(void* base, int64_t R) {
   PParts P;
   uint8_t* b = (uint8_t*)base;
-  P.s = (float2*)b;
+  P.s = (double*)b;
   b += 8 * NSUM * R;
   P.words = (uint64_t*)b;
   b += 8 * R;

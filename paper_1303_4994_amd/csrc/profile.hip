@@ -3,16 +3,15 @@
 // Every pass visits blocks with the encoder's own per-block machinery
 // (bracket, quantizer, stream sizes, fixed-rate search), so the profiler sees
 // exactly what the encoder will produce.  Persistent workgroups loop over
-// tiles; each lane accumulates its statistics in FP32 float-float pairs
-// (TwoSum, Knuth; renormalised with Fast2Sum), every binary64 term split
-// exactly into hi + lo first and scaled by a power of two chosen from max|x|
-// so FP32 never overflows.  Lanes reduce once per workgroup (wave
-// butterflies, then LDS) into a partial record; a one-workgroup kernel then
+// tiles; each lane accumulates its statistics in binary64 (the terms scaled
+// by a power of two chosen from max|x|, which is exact).  Lanes reduce once
+// per workgroup (wave butterflies, then LDS) into a partial record; a
+// one-workgroup kernel then
 // reduces the records in a fixed order, so results are deterministic, and
 // runs the next control step of the profile.  No global atomics in the
 // passes.  grid.y indexes the gain codes evaluated in one launch.
 #include "block.h"
-#include "ff.h"
+#include "totals.h"
 #include "kernels.h"
 
 namespace apax {
@@ -24,6 +23,19 @@ __device__ void ctl_step(const CtlArgs& C);
 __device__ __forceinline__ void st_copy(uint32_t* dst, const uint32_t* src) {
   constexpr int NW = (int)(sizeof(PState) / 4);
   for (int i = threadIdx.x; i < NW; i += blockDim.x) dst[i] = src[i];
+}
+
+// The state back from LDS, except the status and ticket words: other
+// kernels only ever change those atomically, and a write-back of the copy
+// taken at the start would undo such a change.
+__device__ __forceinline__ void st_copy_back(PState* dst, const PState* src) {
+  constexpr int NW = (int)(sizeof(PState) / 4);
+  constexpr int W0 = (int)(offsetof(PState, maxbits) / 4);
+  static_assert(offsetof(PState, status) == 0 && offsetof(PState, ticket) == 4 && W0 == 2,
+                "status and ticket lead the state");
+  const uint32_t* s = (const uint32_t*)src;
+  uint32_t* d = (uint32_t*)dst;
+  for (int i = W0 + threadIdx.x; i < NW; i += blockDim.x) d[i] = s[i];
 }
 
 
@@ -153,13 +165,16 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
       nfa |= s_nf[w] != 0;
     }
     s_st.maxbits[0] = k;
-    if (nfa) s_st.status |= ST_NONFINITE;
+    if (nfa) {
+      s_st.status |= ST_NONFINITE;
+      atomicOr(&C.st->status, ST_NONFINITE);
+    }
     CtlArgs D = C;
     D.st = &s_st;
     ctl_step(D);
   }
   __syncthreads();
-  st_copy((uint32_t*)C.st, (const uint32_t*)&s_st);
+  st_copy_back(C.st, &s_st);
 }
 
 // ---------------------------------------------------------------- block passes
@@ -180,7 +195,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
   constexpr bool DMAX = OPK == P_STATS;
   constexpr bool FITS = OPK == P_FITS;
   constexpr int U = OPK == P_CURVE ? 16 : 8;
-  __shared__ float s_ff[4][NSA][2];
+  __shared__ double s_ff[4][NSA];
   __shared__ uint64_t s_c64[4][2];
   __shared__ uint32_t s_c32[4][9];
   const int mc = A.maxcodes;  // <= MAXCODES, so every code gets Lc >= 8 lanes
@@ -192,13 +207,13 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
   const int k = (int)threadIdx.x % Lc;
   const bool in_code = ci < mc;
   const int64_t r0 = (int64_t)(in_code ? ci : 0) * nwg;
-  FF acc[NSA];
+  double acc[NSA];
 #pragma unroll
-  for (int i = 0; i < NSA; i++) acc[i] = {0.f, 0.f};
+  for (int i = 0; i < NSA; i++) acc[i] = 0.0;
   uint64_t w = 0, dm = 0;
   uint32_t fit = 0, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   auto batch = [&](const int64_t q0, const bool copy_state) {
-    float2 v[NSA][U];
+    double v[NSA][U];
     uint64_t wv[U], dv[U];
     uint32_t fv[U], hv[8][U];
 #pragma unroll
@@ -206,7 +221,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
       const int64_t q = q0 + (int64_t)u * Lc;
       const bool in = in_code && q < nwg;
 #pragma unroll
-      for (int i = 0; i < NS; i++) v[i][u] = in ? P.s[(int64_t)(I0 + i) * P.R + r0 + q] : float2{0.f, 0.f};
+      for (int i = 0; i < NS; i++) v[i][u] = in ? P.s[(int64_t)(I0 + i) * P.R + r0 + q] : 0.0;
       if (WORDS) wv[u] = in ? P.words[r0 + q] : 0;
       if (DMAX) dv[u] = in ? P.dmax[r0 + q] : 0;
       if (FITS) fv[u] = in ? P.nfit[r0 + q] : 0;
@@ -219,7 +234,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
 #pragma unroll
     for (int u = 0; u < U; u++) {
 #pragma unroll
-      for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], FF{v[i][u].x, v[i][u].y});
+      for (int i = 0; i < NS; i++) acc[i] += v[i][u];
       if (WORDS) w += wv[u];
       if (DMAX) dm = dv[u] > dm ? dv[u] : dm;
       if (FITS) fit += fv[u];
@@ -239,7 +254,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
   const int Lw = Lc < 64 ? Lc : 64;
   for (int o = 1; o < Lw; o <<= 1) {
 #pragma unroll
-    for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], ff_shfl_xor(acc[i], o));
+    for (int i = 0; i < NS; i++) acc[i] += __shfl_xor(acc[i], o, 64);
     if (WORDS) w += (uint64_t)__shfl_xor((unsigned long long)w, o, 64);
     if (DMAX) {
       const uint64_t d2 = (uint64_t)__shfl_xor((unsigned long long)dm, o, 64);
@@ -256,7 +271,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-      for (int i = 0; i < NS; i++) { s_ff[wave][i][0] = acc[i].hi; s_ff[wave][i][1] = acc[i].lo; }
+      for (int i = 0; i < NS; i++) s_ff[wave][i] = acc[i];
       s_c64[wave][0] = w;
       s_c64[wave][1] = dm;
       s_c32[wave][0] = fit;
@@ -268,7 +283,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
       const int wb = (int)threadIdx.x >> 6, nw = Lc / 64;
       for (int j = 1; j < nw; j++) {
 #pragma unroll
-        for (int i = 0; i < NS; i++) acc[i] = ff_add(acc[i], FF{s_ff[wb + j][i][0], s_ff[wb + j][i][1]});
+        for (int i = 0; i < NS; i++) acc[i] += s_ff[wb + j][i];
         w += s_c64[wb + j][0];
         dm = s_c64[wb + j][1] > dm ? s_c64[wb + j][1] : dm;
         fit += s_c32[wb + j][0];
@@ -279,7 +294,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
   }
   if (ci < ncodes && k == 0) {
 #pragma unroll
-    for (int i = 0; i < NS; i++) S->sums[ci][I0 + i] = (double)acc[i].hi + (double)acc[i].lo;
+    for (int i = 0; i < NS; i++) S->sums[ci][I0 + i] = acc[i];
     if (FITS) S->fits[ci] = fit;
     if (HIST && ci == 0) {
       for (int t = 0; t < 8; t++) S->hist[t] = h[t];
@@ -303,7 +318,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   const Geo& g = A.g;
   PState* st = A.st;
   constexpr int NL = S_CXX;  // accumulator slots; the centred pass uses slots S_XX..S_DD
-  __shared__ float s_red[WPG][NL][2];
+  __shared__ double s_red[WPG][NL];
   __shared__ uint64_t s_w[WPG], s_dm[WPG];
   __shared__ uint32_t s_fit[WPG], s_hist[WPG][8];
   __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
@@ -328,12 +343,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   constexpr int L1 = OP == P_STATS ? NL : (OP == P_CENTER ? S_DS : 0);
   constexpr int NA = L1 > L0 ? L1 - L0 : 1;
   // each lane sums its groups' binary64 terms over up to 64 tiles, then
-  // moves the partial (scaled by a power of two) into the FP32 float-float
-  // accumulators that every further reduction level uses; those are only
-  // touched by these moves, so they live in LDS (one slot per thread)
-  __shared__ float2 s_acc[NA][WPG * 64];
+  // adds the partial (scaled by a power of two) to the accumulators that
+  // every further reduction level uses; those are only touched by these
+  // adds, so they live in LDS (one slot per thread)
+  __shared__ double s_acc[NA][WPG * 64];
 #pragma unroll
-  for (int i = 0; i < NA; i++) s_acc[i][threadIdx.x] = float2{0.f, 0.f};
+  for (int i = 0; i < NA; i++) s_acc[i][threadIdx.x] = 0.0;
   double lacc[NL];
 #pragma unroll
   for (int i = 0; i < NL; i++) lacc[i] = 0.0;
@@ -341,9 +356,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   auto flush = [&]() {
 #pragma unroll
     for (int i = L0; i < L1; i++) {
-      const float2 v = s_acc[i - L0][threadIdx.x];
-      const FF a = ff_add(FF{v.x, v.y}, ff_of(lacc[i] * (i < S_XX ? s1 : s2)));
-      s_acc[i - L0][threadIdx.x] = float2{a.hi, a.lo};
+      s_acc[i - L0][threadIdx.x] += lacc[i] * (i < S_XX ? s1 : s2);
     }
 #pragma unroll
     for (int i = 0; i < NL; i++) lacc[i] = 0.0;
@@ -435,8 +448,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
       }
       if (b.blk_ok && b.L.gi == 0) wsum += (unsigned long long)nw;
     }
-    // the group's terms are summed in binary64 first (4 terms, relative error
-    // ~1e-16), then added to the FP32 float-float accumulators
+    // the group's terms are summed first (4 terms), then added to the
+    // lane's partial
     double t[NL];
 #pragma unroll
     for (int i = 0; i < NL; i++) t[i] = 0.0;
@@ -477,14 +490,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
 
   // ---- workgroup partial record
   if constexpr (L1 > L0) {
-    FF part[L1 - L0];
+    double part[L1 - L0];
 #pragma unroll
-    for (int i = 0; i < L1 - L0; i++) part[i] = FF{s_acc[i][threadIdx.x].x, s_acc[i][threadIdx.x].y};
-    const FF tot = wave_totals<L1 - L0>(part, lane);
+    for (int i = 0; i < L1 - L0; i++) part[i] = s_acc[i][threadIdx.x];
+    const double tot = wave_totals<L1 - L0>(part, lane);
     const int idx = wave_totals_index<L1 - L0>(lane);
     if (lane < 8 && idx < L1 - L0) {
-      s_red[wave][L0 + idx][0] = tot.hi;
-      s_red[wave][L0 + idx][1] = tot.lo;
+      s_red[wave][L0 + idx] = tot;
     }
   }
 #pragma unroll
@@ -507,10 +519,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   if (threadIdx.x < NL) {
     const int i = threadIdx.x;
     if (i >= L0 && i < L1) {
-      FF tt = {s_red[0][i][0], s_red[0][i][1]};
-      for (int w = 1; w < WPG; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
+      double tt = s_red[0][i];
+      for (int w = 1; w < WPG; w++) tt += s_red[w][i];
       const int si = OP == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
-      P.s[(int64_t)si * P.R + r] = float2{tt.hi, tt.lo};
+      P.s[(int64_t)si * P.R + r] = tt;
     }
   } else if (threadIdx.x == 64) {
     uint64_t ww = 0, dm = 0;
@@ -544,7 +556,7 @@ __global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
     ctl_step(C);
   }
   __syncthreads();
-  st_copy((uint32_t*)A.st, (const uint32_t*)&s_st);
+  st_copy_back(A.st, &s_st);
 }
 
 // ---------------------------------------------------------------- control
@@ -560,21 +572,23 @@ __device__ int ctl_largest(double M, double lim, int cmin, int cmax) {
 }
 
 // pre-order nodes of the bisection decision tree of the next `depth` steps
-__device__ int ctl_tree(int lo, int hi, int depth, int32_t* out, int n) {
-  int slo[8], shi[8], sd[8], sp = 0;
-  slo[0] = lo; shi[0] = hi; sd[0] = depth; sp = 1;
-  while (sp > 0 && n < MAXCODES) {
-    --sp;
-    int l = slo[sp], h = shi[sp], d = sd[sp];
-    if (d == 0 || h - l <= 1) continue;
-    int mid = l + ((h - l) >> 1);
-    out[n++] = mid;
-    // push right first so the left subtree comes next (pre-order)
-    if (sp + 2 <= 8) {
-      slo[sp] = mid; shi[sp] = h; sd[sp] = d - 1; sp++;
-      slo[sp] = l; shi[sp] = mid; sd[sp] = d - 1; sp++;
-    }
+// (a node, then its left and right subtrees), depth <= D; unrolled at
+// compile time, so no stack array (a dynamically indexed local array becomes
+// compare-and-select chains on the one thread that runs this)
+template <int D>
+__device__ __forceinline__ void ctl_tree_rec(int l, int h, int d, int32_t* out, int& n) {
+  if (d == 0 || h - l <= 1 || n >= MAXCODES) return;
+  const int mid = l + ((h - l) >> 1);
+  out[n++] = mid;
+  if constexpr (D > 1) {
+    ctl_tree_rec<D - 1>(l, mid, d - 1, out, n);
+    ctl_tree_rec<D - 1>(mid, h, d - 1, out, n);
   }
+}
+
+constexpr int CTL_MAX_DEPTH = 4;  // 15 nodes + the cap fit MAXCODES
+__device__ int ctl_tree(int lo, int hi, int depth, int32_t* out, int n) {
+  ctl_tree_rec<CTL_MAX_DEPTH>(lo, hi, depth < CTL_MAX_DEPTH ? depth : CTL_MAX_DEPTH, out, n);
   return n;
 }
 
@@ -621,24 +635,24 @@ __device__ void ctl_step(const CtlArgs& C) {
     case C_DECIDE: {
       if (st->done || st->ncodes == 0) { st->ncodes = 0; break; }
       const int n = st->ncodes;
-      bool pred[MAXCODES], near[MAXCODES];
+      // the predicate and the tie flag of every probed code, as bit masks
+      uint32_t pred = 0, near = 0;
       for (int i = 0; i < n; i++) {
         if (fr) {
-          pred[i] = st->fits[i] >= st->need;
-          near[i] = false;
+          pred |= (st->fits[i] >= st->need ? 1u : 0u) << i;
         } else {
           double r;
           r_from(st->sums[i], r);
-          pred[i] = r >= C.target;
-          near[i] = fabs(r - C.target) < 1e-11;
+          pred |= (r >= C.target ? 1u : 0u) << i;
+          near |= (fabs(r - C.target) < 1e-11 ? 1u : 0u) << i;
         }
       }
       int k = 0;
       if (st->first) {
         st->first = 0;
         st->n_probes++;
-        if (near[0]) st->flags |= 1;
-        if (fr ? pred[0] : !pred[0]) {  // all fit at the cap / target unreachable
+        if (near & 1u) st->flags |= 1;
+        if (fr ? (pred & 1u) : !(pred & 1u)) {  // all fit at the cap / target unreachable
           st->code = st->cc; st->done = 1; st->ncodes = 0;
           break;
         }
@@ -650,9 +664,10 @@ __device__ void ctl_step(const CtlArgs& C) {
         while (k < n && st->probe[k] != mid) k++;
         if (k >= n) break;
         st->n_probes++;
-        if (near[k]) st->flags |= 1;
-        if (fr) { if (pred[k]) lo = mid; else hi = mid; }
-        else { if (pred[k]) hi = mid; else lo = mid; }
+        if ((near >> k) & 1u) st->flags |= 1;
+        const bool pk = (pred >> k) & 1u;
+        if (fr) { if (pk) lo = mid; else hi = mid; }
+        else { if (pk) hi = mid; else lo = mid; }
       }
       st->lo = lo; st->hi = hi;
       ctl_zero(st);

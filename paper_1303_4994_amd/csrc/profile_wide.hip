@@ -7,7 +7,7 @@
 // evaluated in one launch) and writes the same per-(code, workgroup) partial
 // record as the one-wave passes; the same one-workgroup kernel reduces the
 // records in a fixed order and runs the next control step.
-#include "ff.h"
+#include "totals.h"
 #include "kernels.h"
 #include "wide_enc.h"
 
@@ -20,7 +20,7 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wprofile(ProfArgs A) {
   constexpr int OP = OPK == P_CURVE ? P_STATS : OPK;
   constexpr int NL = S_CXX;  // accumulator slots; the centred pass uses slots S_XX..S_DD
   constexpr int MAXW = WIDE_MAXT / 64;
-  __shared__ float s_red[MAXW][NL][2];
+  __shared__ double s_red[MAXW][NL];
   __shared__ uint64_t s_dm[MAXW];
   A.curve = OPK == P_CURVE;
   if (OPK == P_CURVE) A.rule = R_QUALITY;  // curve codes are fixed per block
@@ -48,19 +48,18 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wprofile(ProfArgs A) {
   // the metrics pass, so it needs no bracket (nor does a lossless pass)
   const bool bracket = !(lossless || (OP == P_CENTER && A.rule == R_RATE));
 
-  // each thread sums its groups' binary64 terms over up to 64 blocks (at
-  // most 1024 terms, relative error ~1e-13), then
-  // moves the partial (scaled by a power of two) into FP32 float-float
-  FF acc[NA];
+  // each thread sums its groups' binary64 terms over up to 64 blocks, then
+  // adds the partial (scaled by a power of two) to its accumulators
+  double acc[NA];
 #pragma unroll
-  for (int i = 0; i < NA; i++) acc[i] = FF{0.f, 0.f};
+  for (int i = 0; i < NA; i++) acc[i] = 0.0;
   double lacc[NL];
 #pragma unroll
   for (int i = 0; i < NL; i++) lacc[i] = 0.0;
   int lcount = 0;
   auto flush = [&]() {
 #pragma unroll
-    for (int i = L0; i < L1; i++) acc[i - L0] = ff_add(acc[i - L0], ff_of(lacc[i] * (i < S_XX ? s1 : s2)));
+    for (int i = L0; i < L1; i++) acc[i - L0] += lacc[i] * (i < S_XX ? s1 : s2);
 #pragma unroll
     for (int i = 0; i < NL; i++) lacc[i] = 0.0;
     lcount = 0;
@@ -174,12 +173,9 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wprofile(ProfArgs A) {
   // ---- workgroup partial record (waves in order, then the record)
   const int nwv = wg_nwaves();
   if constexpr (L1 > L0) {
-    const FF tot = wave_totals<L1 - L0>(acc, lane);
+    const double tot = wave_totals<L1 - L0>(acc, lane);
     const int idx = wave_totals_index<L1 - L0>(lane);
-    if (lane < 8 && idx < L1 - L0) {
-      s_red[wave][L0 + idx][0] = tot.hi;
-      s_red[wave][L0 + idx][1] = tot.lo;
-    }
+    if (lane < 8 && idx < L1 - L0) s_red[wave][L0 + idx] = tot;
   }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
@@ -193,10 +189,10 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wprofile(ProfArgs A) {
   if (tid < NL) {
     const int i = tid;
     if (i >= L0 && i < L1) {
-      FF tt = {s_red[0][i][0], s_red[0][i][1]};
-      for (int w = 1; w < nwv; w++) tt = ff_add(tt, FF{s_red[w][i][0], s_red[w][i][1]});
+      double tt = s_red[0][i];
+      for (int w = 1; w < nwv; w++) tt += s_red[w][i];
       const int si = OP == P_CENTER ? i - S_XX + S_CXX : i;  // sum index of the slot
-      P.s[(int64_t)si * P.R + r] = float2{tt.hi, tt.lo};
+      P.s[(int64_t)si * P.R + r] = tt;
     }
   }
   if (tid == 0) {
