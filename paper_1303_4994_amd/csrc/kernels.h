@@ -166,6 +166,10 @@ struct ProfArgs {
   int mask_sel;               // 0 st->mask_probe, 1 st->mask_out (+0x81), 2 metrics mask
   int final_code;             // evaluate st->code (one code) instead of st->codes[]
   int curve;                  // P_STATS: only the four sums of r and the word count
+  // several codes per launch: a 1-D grid of nwg * maxcodes workgroups whose
+  // ids are spread so the workgroups of every code that visit the same
+  // tiles share an XCD (and its L2), which then fetches those tiles once
+  int xcd_map;
   // metrics pass of a profile that encodes next (else null): each block's
   // chosen stream, and in variable-size modes its length (into the stream's
   // index) and its superblock's word sum -- the encoder's first pass

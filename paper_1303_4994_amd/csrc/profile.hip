@@ -323,9 +323,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   __shared__ uint32_t s_fit[WPG], s_hist[WPG][8];
   __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
 
-  const int ci = blockIdx.y;
+  // (workgroup of the code, code): blockIdx, or with the XCD map, id =
+  // ((q * maxcodes + code) * 8 + x) for workgroup 8 q + x of the code --
+  // consecutive ids go to consecutive XCDs, so every id of workgroup 8 q + x
+  // lands on XCD x, and the codes' workgroups over the same tiles run there
+  // close together
+  int64_t wgx;
+  int ci;
+  if (A.xcd_map) {
+    const uint32_t id = blockIdx.x, k = id >> 3;
+    ci = (int)(k % (uint32_t)A.maxcodes);
+    wgx = (int64_t)(k / (uint32_t)A.maxcodes) * 8 + (id & 7u);
+  } else {
+    wgx = blockIdx.x;
+    ci = blockIdx.y;
+  }
   const int nset = A.final_code ? 1 : st->ncodes;
-  const int ncodes = nset < (int)gridDim.y ? nset : (int)gridDim.y;
+  const int ncodes = nset < A.maxcodes ? nset : A.maxcodes;
   if (ci >= ncodes) return;  // uniform per workgroup
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
@@ -377,9 +391,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   // evaluated (a tile past the end fetches nothing)
   B_ nb;
   T nv[4];
-  nb.init(g, block_of(blockIdx.x), xw);
+  nb.init(g, block_of(wgx), xw);
   nb.fetch((const T*)A.x, g, nv);
-  for (int64_t tile = blockIdx.x; tile < A.ntiles; tile += A.nwg) {
+  for (int64_t tile = wgx; tile < A.ntiles; tile += A.nwg) {
     B_ b = nb;
     T cv[4];
 #pragma unroll
@@ -514,8 +528,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     for (int t = 0; t < 8; t++) s_hist[wave][t] = hcnt[t];
   }
   __syncthreads();
-  const PParts P = pparts(A.parts, (int64_t)gridDim.y * A.nwg);
-  const int64_t r = (int64_t)ci * A.nwg + blockIdx.x;
+  const PParts P = pparts(A.parts, (int64_t)A.maxcodes * A.nwg);
+  const int64_t r = (int64_t)ci * A.nwg + wgx;
   if (threadIdx.x < NL) {
     const int i = threadIdx.x;
     if (i >= L0 && i < L1) {
@@ -749,7 +763,8 @@ int64_t prof_wgs(int64_t ntiles, int ncodes) {
 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
-  const dim3 grid((unsigned)A.nwg, A.maxcodes), block(WPG * 64);
+  const dim3 grid = A.xcd_map ? dim3((unsigned)(A.nwg * A.maxcodes), 1) : dim3((unsigned)A.nwg, A.maxcodes);
+  const dim3 block(WPG * 64);
   if (A.op == P_FITS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_FITS>), grid, block, 0, s, A);
   else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CURVE>), grid, block, 0, s, A);
   else if (A.op == P_STATS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_STATS>), grid, block, 0, s, A);
@@ -776,6 +791,14 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEv
   const bool wide = A.g.G > 64 || A.g.gq == 2;
   A.ntiles = wide ? A.nbe : prof_tiles(A.g, A.nbe);
   A.nwg = prof_wgs(A.ntiles, A.maxcodes);
+  // several codes over the same tiles: whole groups of 8 workgroups per
+  // code, mapped onto the XCDs (the one-workgroup-per-block passes keep the
+  // 2-D grid)
+  A.xcd_map = 0;
+  if (!wide && A.maxcodes > 1 && A.nwg >= 8) {
+    A.nwg = A.nwg / 8 * 8;
+    A.xcd_map = 1;
+  }
   if (A.ntiles == 0) return hipSuccess;
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
