@@ -24,11 +24,11 @@ __global__ void k_encode_reset(uint32_t* ssum, int64_t nsuper) {
 // analysis -- operating point, quantization, every allowed stream costed --
 // gives its chosen stream and word count; the counts go to the stream's
 // block-length index and are summed per superblock of 64 blocks.
-template <typename T, int LPB, int NDIM>
-__global__ __launch_bounds__(WPG * 64) void k_encode_size(EncArgs A) {
+template <typename T, int LPB, int NDIM, int WP>
+__global__ __launch_bounds__(WP * 64) void k_encode_size(EncArgs A) {
   constexpr int BPW = 64 / LPB;
   using B_ = Blk<T, LPB, NDIM>;
-  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
+  __shared__ uint4 s_xch[NDIM >= 2 ? WP * XCH : 1];
   const Geo& g = A.g;
   const int mode = __builtin_amdgcn_readfirstlane(g.mode);
   int32_t code0;
@@ -36,17 +36,33 @@ __global__ __launch_bounds__(WPG * 64) void k_encode_size(EncArgs A) {
   profiled_point(A, g, code0, mask0);
   const int wave = threadIdx.x >> 6;
   B_ b;
-  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane_id() / LPB,
+  b.init(g, ((int64_t)blockIdx.x * WP + wave) * BPW + lane_id() / LPB,
          NDIM >= 2 ? s_xch + wave * XCH : nullptr);
   if (A.bcode) block_code<LPB>(A, b.blk_ok, b.j, code0);
   int c, st;
   int32_t best, a[4];
   analyze_block<T, LPB, NDIM>(A, b, mode, code0, mask0, c, st, best, a);
+  uint32_t nw = 0;
   if (b.blk_ok && b.L.gi == 0) {
-    const uint32_t nw = (uint32_t)((best + 31) >> 5);
+    nw = (uint32_t)((best + 31) >> 5);
     A.lens[b.j] = (uint16_t)nw;
     A.bst[b.j] = (uint8_t)st;
-    atomicAdd(&A.ssum[b.j >> 6], nw);
+  }
+  // the workgroup's blocks are consecutive and inside one superblock (64 is
+  // a multiple of WPG * BPW): one add per workgroup, not one per block (the
+  // adds of a superblock's blocks to one word serialize at the memory side)
+  static_assert(64 % (WP * BPW) == 0, "a workgroup's blocks lie in one superblock");
+  __shared__ uint32_t s_nw[WP];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nw += __shfl_xor(nw, o, 64);
+  if (lane_id() == 0) s_nw[wave] = nw;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < WP; w++) t += s_nw[w];
+    const int64_t j0 = (int64_t)blockIdx.x * WP * BPW;
+    if (t) atomicAdd(&A.ssum[j0 >> 6], t);
   }
 }
 
@@ -277,7 +293,11 @@ static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   }
   const int64_t nsuper = (A.g.nblocks + 63) / 64;
   launch_encode_reset(A.ssum, nsuper, s);
-  hipLaunchKernelGGL((k_encode_size<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), 0, s, A);
+  // first pass: up to 16 waves per workgroup (16 to 64 blocks), so each
+  // superblock word takes at most 4 adds
+  constexpr int SWP = 64 / BPW > 16 ? 16 : 64 / BPW;
+  const unsigned sgrid = (unsigned)((A.g.nblocks + SWP * BPW - 1) / (SWP * BPW));
+  hipLaunchKernelGGL((k_encode_size<T, LPB, NDIM, SWP>), dim3(sgrid), dim3(SWP * 64), 0, s, A);
   launch_encode_scan(A, nsuper, s);
   hipLaunchKernelGGL((k_encode_emit<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();
