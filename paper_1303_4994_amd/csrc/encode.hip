@@ -293,9 +293,11 @@ static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
   }
   const int64_t nsuper = (A.g.nblocks + 63) / 64;
   launch_encode_reset(A.ssum, nsuper, s);
-  // first pass: up to 16 waves per workgroup (16 to 64 blocks), so each
-  // superblock word takes at most 4 adds
-  constexpr int SWP = 64 / BPW > 16 ? 16 : 64 / BPW;
+  // first pass: 1-d blocks (few registers) with up to 16 waves per
+  // workgroup, so each superblock word takes at most 4 adds; 2-/3-d blocks
+  // keep 4 waves, as 16-wave workgroups would not fill a SIMD's wave slots at
+  // their register counts
+  constexpr int SWP = NDIM == 1 ? (64 / BPW > 16 ? 16 : 64 / BPW) : WPG;
   const unsigned sgrid = (unsigned)((A.g.nblocks + SWP * BPW - 1) / (SWP * BPW));
   hipLaunchKernelGGL((k_encode_size<T, LPB, NDIM, SWP>), dim3(sgrid), dim3(SWP * 64), 0, s, A);
   launch_encode_scan(A, nsuper, s);
