@@ -552,6 +552,77 @@ struct Blk {
     C.sz[7] = ((mask >> 7) & 1) ? H + g.B * W : BIG;
   }
 
+  // Fixed-rate fit test (this lane's block): whether some stream of `mask`
+  // codes the block in at most `lim` bits, i.e. min over the mask <= lim.
+  // The streams are tried most-likely-smallest first (the verbatim size
+  // needs no work; then the highest-order derivatives of the brick's
+  // dimension) and the test stops once every block of the wave fits.
+  __device__ __forceinline__ bool fits(const Geo& g, uint32_t mask, const int32_t a[4], int lim) const {
+    return dense ? fits_t<true>(g, mask, a, lim) : fits_t<false>(g, mask, a, lim);
+  }
+  template <bool DENSE>
+  __device__ __forceinline__ bool fits_t(const Geo& g, uint32_t mask, const int32_t a[4], int lim) const {
+    const uint32_t nd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(NDMASK & mask));  // wave-uniform
+    const uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
+    bool fit = ((mask >> 7) & 1) && H + g.B * W <= lim;
+    // true once every lane's block fits (wave-uniform)
+    auto done = [&]() { return __ballot(blk_ok && !fit) == 0; };
+    auto try1 = [&](const uint32_t s[4]) {
+      int32_t v[4];
+      finish<DENSE>(s, v);
+      int e, p;
+      eps_of<DENSE>(v, e, p);
+      const int tk = token_nibbles(e);
+      const uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)p), L.seg);
+      fit = fit || H + 4 * tk + 4 * (int)tot <= lim;
+      return done();
+    };
+    if (done()) return fit;
+    uint32_t d[4];
+    if (nd & 6u) xdiff(A, d);
+    if (NDIM >= 2 && (nd & 0x78u)) {
+      uint32_t Q[4], R[4], RQ[4], f[4];
+      exchange(A, Q, R, RQ, (nd & 0x50u) != 0);
+#pragma unroll
+      for (int k = 0; k < 4; k++) f[k] = A[k] - Q[k];
+      if (NDIM == 3 && (nd & 0x50u)) {
+        uint32_t h[4], u[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          h[k] = A[k] - R[k];
+          u[k] = f[k] - R[k] + RQ[k];  // dz dy a
+        }
+        if (nd & 0x40u) {
+          uint32_t s6[4];
+          xdiff(u, s6);
+          if (try1(s6)) return fit;
+        }
+        if ((nd & 0x10u) && try1(h)) return fit;
+      }
+      if (nd & 0x20u) {
+        uint32_t s5[4];
+        xdiff(f, s5);
+        if (try1(s5)) return fit;
+      }
+      if ((nd & 8u) && try1(f)) return fit;
+    }
+    if ((nd & 2u) && try1(d)) return fit;
+    if (nd & 4u) {
+      uint32_t s2[4];
+      xdiff(d, s2);
+      if (try1(s2)) return fit;
+    }
+    if constexpr (NDIM == 1) {
+      if (nd & 8u) {
+        uint32_t F[4];
+        filt(g, A, F);
+        if (try1(F)) return fit;
+      }
+    }
+    if (nd & 1u) try1(A);
+    return fit;
+  }
+
   // size of one stream from its values (segment-uniform)
   __device__ __forceinline__ int size_vals(const int32_t vv[4], int& e, int& p) const {
     eps_of(vv, e, p);

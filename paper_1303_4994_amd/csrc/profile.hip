@@ -411,6 +411,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
       // argmin over the mask at the clamped code: fit test + stream histogram
       int c = A.rule == R_LOSSLESS ? 0 : clampc(code, b.cf, b.cc);
       b.quantize(c, A.rule == R_LOSSLESS, a);
+      if (!A.hist) {  // bisection probe: the fit test alone
+        if (b.fits(g, mask, a, 32 * g.budget) && b.blk_ok && b.L.gi == 0) nfit++;
+        continue;
+      }
       b.costs(g, mask, a, C);
       int s_ = B_::argmin(C, mask, best);
       if (b.blk_ok && b.L.gi == 0 && best <= 32 * g.budget) nfit++;
