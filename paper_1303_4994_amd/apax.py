@@ -120,7 +120,7 @@ def _load():
     L.apax_profile_async.argtypes = [vp, P(Params), vp, u64, vp]
     L.apax_profile_async_point.argtypes = [vp, P(Params), vp, u64, vp, vp]
     L.apax_adopt_point.argtypes = [vp, vp, vp]
-    L.apax_profile_encode_async.argtypes = [vp, P(Params), vp, u64, vp, u64, vp, vp, vp]
+    L.apax_profile_encode_async.argtypes = [vp, P(Params), vp, u64, vp, u64, vp, vp, vp, vp, vp]
     L.apax_s2r_margin.argtypes = [vp, P(Params), P(C.c_double), P(C.c_double), vp, u64, vp]
     L.apax_decode_dot.argtypes = [vp, vp, u64, vp, vp, vp, u64, vp]
     L.apax_dot.argtypes = [vp, vp, C.c_uint32, u64, vp, vp, u64, vp]
@@ -428,12 +428,15 @@ def apax_encode(x: torch.Tensor, params: dict, out: torch.Tensor | None = None,
 
 
 def apax_profile_encode_async(x: torch.Tensor, params: dict, ws: torch.Tensor, out: torch.Tensor | None = None,
-                              nbytes: torch.Tensor | None = None, encoded=None, stream=None):
+                              nbytes: torch.Tensor | None = None, encoded=None, stream=None, side=None,
+                              forked=None):
     """Profile x and encode it at the profiled operating point in one launch
     sequence (the encode from the profile's per-block results); records the
-    torch.cuda.Event `encoded` once the stream is complete.  Returns (stream
-    buffer, device int64 byte length); the profile stays in ws
-    (apax_profile_read)."""
+    torch.cuda.Event `encoded` once the stream is complete.  side (a
+    torch.cuda.Stream) with forked (a torch.cuda.Event): the profile's centred
+    and curve passes run on `side` beside the encode; join `side` before
+    reading the profile.  Returns (stream buffer, device int64 byte length);
+    the profile stays in ws (apax_profile_read)."""
     assert x.is_cuda and x.is_contiguous()
     p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
     bound = C.c_uint64()
@@ -443,8 +446,10 @@ def apax_profile_encode_async(x: torch.Tensor, params: dict, ws: torch.Tensor, o
     if nbytes is None:
         nbytes = torch.empty(1, dtype=torch.int64, device=x.device)
     ev = _event_ptr(encoded) if encoded is not None else None
+    sd = _stream_ptr(side) if side is not None else None
+    fk = _event_ptr(forked) if forked is not None else None
     _check(lib.apax_profile_encode_async(_dev_ptr(x), C.byref(p), _dev_ptr(ws), ws.numel(), _dev_ptr(out),
-                                         out.numel(), _dev_ptr(nbytes), _stream_ptr(stream), ev),
+                                         out.numel(), _dev_ptr(nbytes), _stream_ptr(stream), ev, sd, fk),
            "apax_profile_encode_async")
     return out, nbytes
 

@@ -747,12 +747,16 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
 // point, enqueued right after the metrics pass from that pass's per-block
 // results (the encoder's own per-block search and stream choice, run there);
 // `encoded` is recorded once it is complete, before the centred and curve
-// passes.
+// passes.  side (optional, with the event `forked`): the centred and curve
+// passes run on `side` from the end of the metrics pass on, beside the
+// encode on `stream`.
 static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
                            hipEvent_t* ev = nullptr, uint32_t* ran = nullptr,
                            hipEvent_t point_ready = nullptr, EncArgs* enc = nullptr,
-                           hipEvent_t encoded = nullptr) {
+                           hipEvent_t encoded = nullptr, hipStream_t side = nullptr,
+                           hipEvent_t forked = nullptr) {
   int e;
+  hipStream_t ps = stream;  // the stream of the passes still to come
   if (ran) *ran = 0;
   auto pair = [&](int pass) -> hipEvent_t* {
     if (!ev) return nullptr;
@@ -787,7 +791,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
   C.nsub = (uint64_t)sub_n;
   C.nsamples = h.nsamples;
   C.target = p->target_corr;
-  auto ctl = [&](int step) { C.step = step; return hip_err(launch_ctl(C, stream)); };
+  auto ctl = [&](int step) { C.step = step; return hip_err(launch_ctl(C, ps)); };
   // one pass over blocks; its last workgroup reduces and runs control step `next`
   auto run = [&](int op, int rl, int mask_sel, bool sub, int maxcodes, int next, int flags, int pass) -> int {
     ProfArgs A;
@@ -814,7 +818,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     }
     A.C = C;
     A.C.step = next;
-    return hip_err(launch_profile(h.dtype, h.ndim, A, stream, pair(pass)));
+    return hip_err(launch_profile(h.dtype, h.ndim, A, ps, pair(pass)));
   };
   enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16 };
 
@@ -841,6 +845,11 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     // centred sums and the curve
     if (enc && !fr) launch_encode_reset(enc->ssum, (g.nblocks + 63) / 64, stream);
     if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC, APAX_PASS_METRICS))) return e;
+    if (side) {
+      if (hipEventRecord(forked, stream) != hipSuccess || hipStreamWaitEvent(side, forked, 0) != hipSuccess)
+        return APAX_E_HIP;
+      ps = side;
+    }
     if (enc) {
       if ((e = hip_err(launch_encode_profiled(h.dtype, h.ndim, *enc, cj_ptr(d_ws, h), stream)))) return e;
       if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
@@ -1177,11 +1186,12 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
 
 int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws, uint64_t ws_bytes,
                               void* d_stream, uint64_t cap, uint64_t* d_nbytes, hipStream_t stream,
-                              hipEvent_t encoded) {
+                              hipEvent_t encoded, hipStream_t side, hipEvent_t forked) {
   HG h;
   int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
   if (e) return e;
   if (!d_stream || !d_nbytes || ((uintptr_t)d_stream & 15)) return APAX_E_INVALID;
+  if (side && (!forked || side == stream)) return APAX_E_INVALID;
   if (cap < bound_of(h)) return APAX_E_CAPACITY;
   apax_params q = *p;
   q.code = 0;  // the header's code and mask are the profile's, written on the device
@@ -1196,7 +1206,7 @@ int apax_profile_encode_async(const void* d_x, const apax_params* p, void* d_ws,
   }
   EncArgs A;
   enc_args(d_x, &q, h, true, d_stream, d_nbytes, d_ws, A);
-  return profile_enqueue(d_x, p, h, d_ws, stream, nullptr, nullptr, nullptr, &A, encoded);
+  return profile_enqueue(d_x, p, h, d_ws, stream, nullptr, nullptr, nullptr, &A, encoded, side, forked);
 }
 
 int apax_adopt_point(const void* d_ws_from, void* d_ws_to, hipStream_t stream) {

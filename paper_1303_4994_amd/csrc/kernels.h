@@ -92,7 +92,8 @@ struct PState {
   uint64_t maxbits[2];      // max|x|, max|d| (binary64 bits, non-negative)
   int32_t cf, cc, escale, code;      // whole-array bracket, statistics scale, result code
   int32_t lo, hi, done, n_probes;    // bisection state
-  int32_t flags, ncodes, first, pad0;
+  int32_t flags, ncodes, first;
+  int32_t centred;  // 1: the centred sums came from the raw moments (no centred pass)
   uint32_t mask_probe, mask_out, need, pad1;
   int32_t sel[2];           // operating point for the encoder: code, encoder stream mask
   int32_t codes[MAXCODES];  // codes evaluated by the next probe launch

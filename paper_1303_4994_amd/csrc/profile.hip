@@ -341,6 +341,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   const int nset = A.final_code ? 1 : st->ncodes;
   const int ncodes = nset < A.maxcodes ? nset : A.maxcodes;
   if (ci >= ncodes) return;  // uniform per workgroup
+  if (OP == P_CENTER && st->centred) return;  // the metrics pass's moments gave the centred sums
   const int wave = threadIdx.x >> 6;
   const int lane = lane_id();
   const int code = A.final_code ? st->code : st->codes[ci];
@@ -565,6 +566,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
 // pass, then its control step.
 template <int OPK, bool HIST>
 __global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
+  if (OPK == P_CENTER && A.st->centred) return;  // no centred pass ran
   __shared__ PState s_st;
   reduce_recs<OPK, HIST>(A, &s_st);
   __syncthreads();
@@ -618,6 +620,8 @@ __device__ void r_from(const double* S, double& r) {
   double dn = sds / (nx + ny);
   r = 1.0 - (sdd - dn * dn) / (2.0 * nx * ny);
 }
+
+constexpr double CENTRED_K = 1000.0;
 
 __device__ void ctl_zero(PState* st) {
   for (int i = 0; i < MAXCODES; i++) { st->fits[i] = 0; st->words[i] = 0; }
@@ -744,6 +748,22 @@ __device__ void ctl_step(const CtlArgs& C) {
       st->mean[0] = ldexp(st->sums[0][S_X], st->escale) / n;
       st->mean[1] = ldexp(st->sums[0][S_Y], st->escale) / n;
       st->mean[2] = ldexp(st->sums[0][S_D], st->escale) / n;
+      // The centred sums S2 - S^2 / n from the raw moments, where that is
+      // well conditioned: mean^2 <= CENTRED_K var for x, y and d (or every
+      // term zero).  The binary64 sums carry relative errors below ~4e-14 (of
+      // S2, and of sum |x| for S), so the variance's relative error stays
+      // below 4e-14 (1 + 3 CENTRED_K) ~ 1.2e-10; otherwise the centred pass
+      // sums (x - mean)^2 itself.
+      auto direct = [&](int is, int iq, int ic) -> bool {
+        const double S = st->sums[0][is], Q = st->sums[0][iq];
+        const double m2n = S * (S / n);
+        const double c = Q - m2n;
+        if (Q == 0.0) { st->sums[0][ic] = 0.0; return true; }
+        if (c > 0.0 && m2n <= CENTRED_K * c) { st->sums[0][ic] = c; return true; }
+        return false;
+      };
+      const bool dx = direct(S_X, S_XX, S_CXX), dy = direct(S_Y, S_YY, S_CYY), dd = direct(S_D, S_DD, S_CDD);
+      st->centred = dx && dy && dd ? 1 : 0;
       break;
     }
   }

@@ -30,6 +30,7 @@ __global__ __launch_bounds__(WIDE_MAXT) void k_wprofile(ProfArgs A) {
   const int nset = A.final_code ? 1 : st->ncodes;
   const int ncodes = nset < (int)gridDim.y ? nset : (int)gridDim.y;
   if (ci >= ncodes) return;  // uniform per workgroup
+  if (OP == P_CENTER && st->centred) return;  // the metrics pass's moments gave the centred sums
   const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
   const int code = A.final_code ? st->code : st->codes[ci];
   const int escale = st->escale;

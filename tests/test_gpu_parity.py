@@ -119,6 +119,25 @@ def test_small_profile(A, name, dt, shape, params, kind):
     check_profile(pg, po, x, y)
 
 
+@pytest.mark.parametrize("offset", [0.0, 3e2, 1e4, 1e6])
+def test_profile_std_with_offset(A, offset):
+    """Standard deviations of x, y and d on fields whose mean is 0 to 1e6
+    times their spread: the profile takes the centred sums from the raw
+    moments when mean^2 <= 1000 var, else from its centred pass; both stay
+    within 1e-9 of the oracle's two-pass values."""
+    x = (tiny(np.float64, (96, 160), 4) + offset).astype(np.float64)
+    pp = {"mode": "fixed_quality", "brick": (8, 16), "target_corr": 0.9999}
+    pg = A.apax_profile(torch.from_numpy(x).to(DEV), pp)
+    po = O.profile_dict(O.profile(x, pp))
+    _, y = decoded_at(x, pp, po)
+    check_profile(pg, po, x, y)
+    xi = tiny(np.int16, (5000,), 6).astype(np.int32) + int(offset)
+    pl = {"mode": "lossless", "brick": (64,)}
+    pg = A.apax_profile(torch.from_numpy(xi).to(DEV), pl)
+    po = O.profile_dict(O.profile(xi, pl))
+    check_profile(pg, po, xi, xi)
+
+
 def test_determinism(A):
     x = tiny(np.float32, (256, 384), 3)
     params = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0, "code": 150}

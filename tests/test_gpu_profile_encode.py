@@ -61,11 +61,19 @@ def separate(A, xg, params):
     return buf[: int(nb.item())].cpu().numpy(), A.apax_profile_read(xg, params, ws)
 
 
-def fused(A, xg, params):
+def fused(A, xg, params, side=False):
+    """side: the profile's last passes on a second stream, joined before the
+    profile is read."""
     ws = A.workspace(xg.dtype, tuple(xg.shape), params, DEV)
     A.apax_status_clear(ws)
     ev = torch.cuda.Event()
-    buf, nb = A.apax_profile_encode_async(xg, params, ws, encoded=ev)
+    main = torch.cuda.current_stream()
+    if side:
+        s2, fk = torch.cuda.Stream(), torch.cuda.Event()
+        buf, nb = A.apax_profile_encode_async(xg, params, ws, encoded=ev, stream=main, side=s2, forked=fk)
+        main.wait_stream(s2)
+    else:
+        buf, nb = A.apax_profile_encode_async(xg, params, ws, encoded=ev)
     ev.synchronize()
     n = int(nb.item())
     torch.cuda.synchronize()
@@ -73,14 +81,15 @@ def fused(A, xg, params):
     return buf, n, A.apax_profile_read(xg, params, ws)
 
 
+@pytest.mark.parametrize("side", [False, True], ids=["one-stream", "side-stream"])
 @pytest.mark.parametrize("name,dt,shape,params", CASES, ids=[c[0] for c in CASES])
-def test_fused_equals_separate(A, name, dt, shape, params):
-    print(f"case {name}", flush=True)
+def test_fused_equals_separate(A, name, dt, shape, params, side):
+    print(f"case {name} side {side}", flush=True)
     params = dict(params, target_corr=0.9999)
     x = field(dt, shape, 3)
     xg = torch.from_numpy(x).to(DEV)
     ref, pref = separate(A, xg, params)
-    buf, n, pf = fused(A, xg, params)
+    buf, n, pf = fused(A, xg, params, side)
     got = buf[:n].cpu().numpy()
     assert pf == pref
     assert got.size == ref.size and np.array_equal(got, ref)
@@ -106,6 +115,56 @@ def test_fused_full_field(A):
     xg = torch.from_numpy(x).to(DEV)
     p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
     ref, pref = separate(A, xg, p)
-    buf, n, pf = fused(A, xg, p)
-    assert pf == pref
-    assert n == ref.size and torch.equal(buf[:n].cpu(), torch.from_numpy(ref))
+    for side in (False, True):
+        buf, n, pf = fused(A, xg, p, side)
+        assert pf == pref
+        assert n == ref.size and torch.equal(buf[:n].cpu(), torch.from_numpy(ref))
+
+
+def test_side_stream_graph_replays(A):
+    """The forked sequence (profile, encode and a decode on one stream, the
+    last profile passes on a second) captured as one hipGraph and replayed
+    three times, eager work and synchronizations between the replays: every
+    replay gives the eager profile, stream and decode."""
+    x = synth.grf2d(512, 768, seed=synth.seed_of(1, 5))
+    xg = torch.from_numpy(x).to(DEV)
+    p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    ref, pref = separate(A, xg, p)
+    ws = A.workspace(xg.dtype, tuple(xg.shape), p, DEV)
+    ws_dec = A.workspace(xg.dtype, tuple(xg.shape), p, DEV)
+    out = torch.empty(ref.size + 64, dtype=torch.uint8, device=DEV)
+    nb = torch.empty(1, dtype=torch.int64, device=DEV)
+    y = torch.empty_like(xg)
+    s2, fk = torch.cuda.Stream(), torch.cuda.Event()
+    A.apax_status_clear(ws)
+    A.apax_status_clear(ws_dec)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        cap = torch.cuda.current_stream()
+        A.apax_profile_encode_async(xg, p, ws, out=out, nbytes=nb, stream=cap, side=s2, forked=fk)
+        A.apax_decode(out, ref.size, hdr=bytes(ref[:64]), y=y, ws=ws_dec, stream=cap, clear_status=False)
+        cap.wait_stream(s2)
+    y_ref = O.decode(ref)
+    for rep in range(3):
+        out.fill_(0xAB)
+        y.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert A.apax_status(ws) == 0 and A.apax_status(ws_dec) == 0
+        assert int(nb.item()) == ref.size
+        assert np.array_equal(out[: ref.size].cpu().numpy(), ref), rep
+        assert np.array_equal(y.cpu().numpy().view(np.uint8), y_ref.view(np.uint8)), rep
+        assert A.apax_profile_read(xg, p, ws) == pref, rep
+
+
+def test_side_stream_refused_when_malformed(A):
+    xg = torch.zeros(4096, dtype=torch.float32, device=DEV)
+    p = {"mode": "fixed_rate", "brick": (64,), "rate": 4.0}
+    ws = A.workspace(xg.dtype, tuple(xg.shape), p, DEV)
+    main = torch.cuda.Stream()  # not the null stream, which reads as "no side stream"
+    for side, fk in ((main, torch.cuda.Event()), (torch.cuda.Stream(), None)):
+        with pytest.raises(A.ApaxError) as e:
+            A.apax_profile_encode_async(xg, p, ws, stream=main, side=side, forked=fk)
+        assert e.value.code == A.E_INVALID
