@@ -139,17 +139,20 @@ def traffic_summary(fetch_csv: str, write_csv: str, out_path: str, command: str)
 
 TRACE_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d /root/repo/gpurun_out/kt_c1 "
              "-o kt -- python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-workloads")
+TRACE_WL_CMD = ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats -d /root/repo/gpurun_out/kt_wl "
+                "-o kt -- python3 /root/repo/bench.py --steps 2 --warmup 1 --no-cpu-baseline")
 INSTMIX_CMD = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU "
                "SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM SQ_BUSY_CYCLES --output-format csv "
                "-d /root/repo/gpurun_out/pmc_sq -o p -- python3 /root/repo/bench.py --steps 2 --warmup 1 "
                "--no-cpu-baseline --no-workloads --copy-probe")
 
 
-def trace_summary(db_path: str, out_path: str):
+def trace_summary(db_path: str, out_path: str, workloads: bool = False):
     """Per-kernel durations from a rocprofv3 kernel-trace results database:
     all launches, and the launches that ran alone (the step overlaps two
     streams, so launches that shared the GPU run longer), plus one step's
-    launch sequence."""
+    launch sequence.  workloads: the trace of a whole bench run (the step and
+    the other workloads' encode and decode kernels)."""
     import collections
     import sqlite3
     rows = list(sqlite3.connect(db_path).execute("select name, start, end from kernels order by start"))
@@ -162,6 +165,27 @@ def trace_summary(db_path: str, out_path: str):
         if latest <= a and nxt >= b:
             alone[nm].append((b - a) / 1e3)
         latest = max(latest, b)
+    if workloads:
+        out = ["# rocprofv3 kernel trace of a whole bench run: the C1 step and, timed alone, the encode and",
+               "# decode kernels of the int16 time series (2 MiB and 64 MiB, lossless, 256-sample blocks:",
+               "# <short, 64, 1>), the C1 field at 3:1 and 10:1 (<float, 64, 2>) and the fp64 3-d field at",
+               "# fixed quality (<double, 32, 3>, 4x4x8 bricks); variable-size encodes run",
+               "# k_encode_reset, k_encode_size, k_encode_scan, k_encode_emit",
+               f"# command: {TRACE_WL_CMD}",
+               f"# summary: python3 bench.py --trace-workloads-from {db_path}",
+               "# durations in microseconds; iso_avg_us: launches with no other kernel running",
+               f"{'kernel':52s} {'calls':>6s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'total_us':>9s} "
+               f"{'iso_n':>6s} {'iso_avg_us':>10s}"]
+        for k, v in sorted(every.items(), key=lambda kv: -sum(kv[1])):
+            if "apax::" not in k:
+                continue
+            w = alone.get(k, [])
+            ia = f"{sum(w) / len(w):10.2f}" if w else f"{'-':>10s}"
+            out.append(f"{k[:52]:52s} {len(v):6d} {sum(v) / len(v):8.2f} {min(v):8.2f} {max(v):8.2f} "
+                       f"{sum(v):9.1f} {len(w):6d} {ia}")
+        open(out_path, "w").write("\n".join(out) + "\n")
+        print("\n".join(out))
+        return
     out = ["# rocprofv3 kernel trace, C1 bench (4096x4096 fp32, 16x16 bricks, fixed rate 4:1)",
            f"# command: {TRACE_CMD}",
            f"# summary: python3 bench.py --trace-from {db_path}",
@@ -423,6 +447,8 @@ def main():
                     help="c1: also run a plain 64 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--trace-from", metavar="RESULTS_DB",
                     help="write profiles/kernels_c1_bench.txt from a rocprofv3 kernel-trace results database")
+    ap.add_argument("--trace-workloads-from", metavar="RESULTS_DB",
+                    help="write profiles/kernels_workloads.txt from the kernel trace of a whole bench run")
     ap.add_argument("--instmix-from", metavar="COUNTER_CSV",
                     help="write profiles/pmc_c1_instmix.txt from a rocprofv3 --pmc SQ counter CSV")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -430,6 +456,10 @@ def main():
     args = ap.parse_args()
     if args.trace_from:
         trace_summary(args.trace_from, os.path.join(ROOT, "profiles", "kernels_c1_bench.txt"))
+        return
+    if args.trace_workloads_from:
+        trace_summary(args.trace_workloads_from, os.path.join(ROOT, "profiles", "kernels_workloads.txt"),
+                      workloads=True)
         return
     if args.instmix_from:
         instmix_summary(args.instmix_from, os.path.join(ROOT, "profiles", "pmc_c1_instmix.txt"))
