@@ -210,11 +210,13 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
  * The lagged choice, blocks of more than 256 samples and groups of 8 run the
  * plain encode after the profile (their passes record no per-block
  * choices). */
-/* side (optional, else null): a second stream for the profile's last passes.
- * Then `forked` (an event the caller owns) is recorded on `stream` at the end
- * of the metrics pass, `side` waits for it, and the centred and curve passes
- * run on `side` while the encode (and whatever the caller enqueues after it
- * on `stream`, such as a decode of the stream) runs on `stream`.  The profile
+/* side (optional, else null): a second stream for two of the profile's
+ * passes.  Then `forked` (an event the caller owns) is recorded on `stream`
+ * at the end of the stream-histogram pass, `side` waits for it and runs the
+ * curve pass beside the metrics pass; `forked` is recorded again at the end
+ * of the metrics pass and `side` then runs the centred pass, while the
+ * encode (and whatever the caller enqueues after it on `stream`, such as a
+ * decode of the stream) runs on `stream`.  The profile
  * result is complete when both streams have reached the end of this call's
  * work: join them (wait on `side`) before apax_profile_read or another
  * profile in d_ws.  side == stream, or side without forked: APAX_E_INVALID.

@@ -246,9 +246,12 @@ uint64_t ws_cj_off(const HG& h) { return ws_ssum_off(h) + al256(4 * (((uint64_t)
 uint64_t ws_part_off(const HG& h) { return ws_cj_off(h) + al256(4 * (uint64_t)h.g.nblocks); }
 // adaptive rate: the controller's maps and states after the per-block codes
 uint64_t adapt_need(const HG& h) { return h.mode == APAX_ADAPTIVE_RATE ? adapt_bytes(h.g.nblocks) : 0; }
-uint64_t ws_need(const HG& h) { return ws_part_off(h) + std::max(partial_bytes(h), adapt_need(h)); }
+// two partial-record regions: a profile with a side stream runs its curve
+// pass beside the metrics pass, each with its own records
+uint64_t ws_need(const HG& h) { return ws_part_off(h) + std::max(2 * al256(partial_bytes(h)), adapt_need(h)); }
 
 void* partials_ptr(void* ws, const HG& h) { return (uint8_t*)ws + ws_part_off(h); }
+void* partials2_ptr(void* ws, const HG& h) { return (uint8_t*)partials_ptr(ws, h) + al256(partial_bytes(h)); }
 int32_t* cj_ptr(void* ws, const HG& h) { return (int32_t*)((uint8_t*)ws + ws_cj_off(h)); }
 
 int hip_err(hipError_t e) { return e == hipSuccess ? APAX_OK : APAX_E_HIP; }
@@ -747,9 +750,10 @@ static int profile_setup(const void* d_x, const apax_params* p, const void* d_ws
 // point, enqueued right after the metrics pass from that pass's per-block
 // results (the encoder's own per-block search and stream choice, run there);
 // `encoded` is recorded once it is complete, before the centred and curve
-// passes.  side (optional, with the event `forked`): the centred and curve
-// passes run on `side` from the end of the metrics pass on, beside the
-// encode on `stream`.
+// passes.  side (optional, with the event `forked`): the curve pass runs on
+// `side` from the end of the histogram pass on (beside the metrics pass),
+// and the centred pass there once the metrics pass is done (beside the
+// encode on `stream`).
 static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
                            hipEvent_t* ev = nullptr, uint32_t* ran = nullptr,
                            hipEvent_t point_ready = nullptr, EncArgs* enc = nullptr,
@@ -805,7 +809,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     A.jstride = sub ? sub_stride : 1;
     A.nbe = sub ? sub_n : g.nblocks;
     A.maxcodes = maxcodes;
-    A.parts = partials_ptr(d_ws, h);
+    A.parts = (flags & 32) ? partials2_ptr(d_ws, h) : partials_ptr(d_ws, h);
     A.cj = cj_ptr(d_ws, h);
     A.hist = (flags & 1) != 0;
     A.final_code = (flags & 2) != 0;
@@ -820,7 +824,8 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     A.C.step = next;
     return hip_err(launch_profile(h.dtype, h.ndim, A, ps, pair(pass)));
   };
-  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16 };
+  // F_PARTS2: the second partial-record region (a pass beside another)
+  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16, F_PARTS2 = 32 };
 
   // whole profile, asynchronously: clear, max |x| (-> bracket), bisection
   // batches, histogram at the chosen code (-> mask, curve codes), curve
@@ -840,14 +845,30 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     }
     if ((e = run(P_FITS, rule, 0, true, 1, C_CURVE, F_HIST | F_FINAL, APAX_PASS_HIST))) return e;
     if (point_ready && hipEventRecord(point_ready, stream) != hipSuccess) return APAX_E_HIP;
+    // side stream: `side` forks here and runs the curve (its codes are set)
+    // beside the metrics pass, with its own partial records; the two
+    // passes' reduce kernels change different fields of the state and write
+    // back only those
+    auto fork = [&]() -> int {
+      if (hipEventRecord(forked, stream) != hipSuccess || hipStreamWaitEvent(side, forked, 0) != hipSuccess)
+        return APAX_E_HIP;
+      return APAX_OK;
+    };
+    if (side) {
+      if ((e = fork())) return e;
+      ps = side;
+      if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_KEEP_CURVE, F_CURVE | F_PARTS2, APAX_PASS_CURVE)))
+        return e;
+      ps = stream;
+    }
     // metrics at the operating point (fixed rate: each block's code kept
     // for the centred pass), then the encode that may follow it, the
-    // centred sums and the curve
+    // centred sums (on `side`, forked again once the means are known) and,
+    // without a side stream, the curve
     if (enc && !fr) launch_encode_reset(enc->ssum, (g.nblocks + 63) / 64, stream);
     if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC, APAX_PASS_METRICS))) return e;
     if (side) {
-      if (hipEventRecord(forked, stream) != hipSuccess || hipStreamWaitEvent(side, forked, 0) != hipSuccess)
-        return APAX_E_HIP;
+      if ((e = fork())) return e;
       ps = side;
     }
     if (enc) {
@@ -855,7 +876,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
     }
     if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL, APAX_PASS_CENTRED))) return e;
-    if ((e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_KEEP_CURVE, F_CURVE, APAX_PASS_CURVE))) return e;
+    if (!side && (e = run(P_STATS, R_QUALITY, 1, true, NCURVE, C_KEEP_CURVE, F_CURVE, APAX_PASS_CURVE))) return e;
   } else {
     if ((e = ctl(C_INIT))) return e;
     if ((e = ctl(C_MASK))) return e;

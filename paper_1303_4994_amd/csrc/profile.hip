@@ -19,23 +19,35 @@ namespace apax {
 __device__ void ctl_step(const CtlArgs& C);
 
 // The profiler state is staged in LDS for the reduce kernels, so the
-// one-thread control step runs on LDS instead of dependent global loads.
-__device__ __forceinline__ void st_copy(uint32_t* dst, const uint32_t* src) {
+// one-thread control step runs on LDS instead of dependent global loads; a
+// second copy keeps the state as read.
+__device__ __forceinline__ void st_copy(PState* dst, PState* was, const PState* src) {
   constexpr int NW = (int)(sizeof(PState) / 4);
-  for (int i = threadIdx.x; i < NW; i += blockDim.x) dst[i] = src[i];
+  const uint32_t* s = (const uint32_t*)src;
+  uint32_t* d = (uint32_t*)dst;
+  uint32_t* w = (uint32_t*)was;
+  for (int i = threadIdx.x; i < NW; i += blockDim.x) {
+    const uint32_t v = s[i];
+    d[i] = v;
+    w[i] = v;
+  }
 }
 
-// The state back from LDS, except the status and ticket words: other
-// kernels only ever change those atomically, and a write-back of the copy
-// taken at the start would undo such a change.
-__device__ __forceinline__ void st_copy_back(PState* dst, const PState* src) {
+// The words of the state this kernel changed, back from LDS.  Reduce
+// kernels of passes on two streams (the curve beside the metrics and
+// centred passes) run at the same time and change different fields, so
+// neither writes back a field it did not change; nor are the status and
+// ticket words written, which other kernels change atomically.
+__device__ __forceinline__ void st_copy_back(PState* dst, const PState* now, const PState* was) {
   constexpr int NW = (int)(sizeof(PState) / 4);
   constexpr int W0 = (int)(offsetof(PState, maxbits) / 4);
   static_assert(offsetof(PState, status) == 0 && offsetof(PState, ticket) == 4 && W0 == 2,
                 "status and ticket lead the state");
-  const uint32_t* s = (const uint32_t*)src;
+  const uint32_t* n = (const uint32_t*)now;
+  const uint32_t* w = (const uint32_t*)was;
   uint32_t* d = (uint32_t*)dst;
-  for (int i = W0 + threadIdx.x; i < NW; i += blockDim.x) d[i] = s[i];
+  for (int i = W0 + threadIdx.x; i < NW; i += blockDim.x)
+    if (n[i] != w[i]) d[i] = n[i];
 }
 
 
@@ -130,7 +142,7 @@ __global__ __launch_bounds__(256) void k_pmax(const T* __restrict__ x, uint64_t 
 __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int nparts, CtlArgs C) {
   __shared__ uint64_t s_key[4];
   __shared__ uint32_t s_nf[4];
-  __shared__ PState s_st;
+  __shared__ PState s_st, s_was;
   uint64_t k = 0;
   uint32_t f = 0;
   // the first record of every thread is loaded before the state is copied
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
   const int w0 = threadIdx.x;
   const uint64_t k0 = w0 < nparts ? parts[w0].key : 0;
   const uint32_t f0 = w0 < nparts ? parts[w0].nf : 0;
-  st_copy((uint32_t*)&s_st, (const uint32_t*)C.st);
+  st_copy(&s_st, &s_was, C.st);
   k = k0;
   f = f0;
   for (int w = w0 + blockDim.x; w < nparts; w += blockDim.x) {
@@ -174,7 +186,7 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
     ctl_step(D);
   }
   __syncthreads();
-  st_copy_back(C.st, &s_st);
+  st_copy_back(C.st, &s_st, &s_was);
 }
 
 // ---------------------------------------------------------------- block passes
@@ -183,10 +195,10 @@ __global__ __launch_bounds__(256) void k_pmax_reduce(const PMaxPart* parts, int 
 // records k, k + Lc, ... in order (U records loaded together), then a
 // butterfly inside the wave and an ordered merge of the waves.  OPK / HIST
 // name the pass, so only its fields are loaded.  The first batch is loaded
-// before the profiler state is copied into LDS (S), so both are in flight
-// together; the results are written into S.
+// before the profiler state is copied into LDS (S, and S0 as read), so both
+// are in flight together; the results are written into S.
 template <int OPK, bool HIST>
-__device__ void reduce_recs(const ProfArgs& A, PState* S) {
+__device__ void reduce_recs(const ProfArgs& A, PState* S, PState* S0) {
   constexpr int I0 = OPK == P_STATS ? 0 : (OPK == P_CURVE ? S_XX : (OPK == P_CENTER ? S_CXX : NSUM));
   constexpr int I1 = (OPK == P_STATS || OPK == P_CURVE) ? S_CXX : NSUM;
   constexpr int NS = I1 - I0;  // sums of the pass
@@ -230,7 +242,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S) {
         for (int t = 0; t < 8; t++) hv[t][u] = in ? P.hist[(int64_t)t * P.R + r0 + q] : 0;
       }
     }
-    if (copy_state) st_copy((uint32_t*)S, (const uint32_t*)A.st);
+    if (copy_state) st_copy(S, S0, A.st);
 #pragma unroll
     for (int u = 0; u < U; u++) {
 #pragma unroll
@@ -567,8 +579,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
 template <int OPK, bool HIST>
 __global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
   if (OPK == P_CENTER && A.st->centred) return;  // no centred pass ran
-  __shared__ PState s_st;
-  reduce_recs<OPK, HIST>(A, &s_st);
+  __shared__ PState s_st, s_was;
+  reduce_recs<OPK, HIST>(A, &s_st, &s_was);
   __syncthreads();
   if (threadIdx.x == 0 && A.C.step != C_NONE) {
     CtlArgs C = A.C;
@@ -576,7 +588,7 @@ __global__ __launch_bounds__(256) void k_reduce(ProfArgs A) {
     ctl_step(C);
   }
   __syncthreads();
-  st_copy_back(A.st, &s_st);
+  st_copy_back(A.st, &s_st, &s_was);
 }
 
 // ---------------------------------------------------------------- control
