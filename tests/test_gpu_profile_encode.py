@@ -115,9 +115,38 @@ def test_fused_full_field(A):
     xg = torch.from_numpy(x).to(DEV)
     p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
     ref, pref = separate(A, xg, p)
-    for side in (False, True):
+    # the side stream runs the curve beside the metrics pass (each with its
+    # own partial records) and the centred pass beside the encode: repeated,
+    # so an overlap of the two streams' records or state write-backs shows
+    for side in (False, True, True, True):
         buf, n, pf = fused(A, xg, p, side)
         assert pf == pref
+        assert n == ref.size and torch.equal(buf[:n].cpu(), torch.from_numpy(ref))
+
+
+def test_side_stream_back_to_back(A):
+    """Six fused profile-encodes of the 4096^2 fp32 field enqueued back to
+    back with the side stream (no host synchronisation between them), as a
+    pipeline runs them: every stream equals the separate encode's and the
+    profile left in the workspace equals the separate profile."""
+    x = synth.grf2d(4096, 4096)
+    xg = torch.from_numpy(x).to(DEV)
+    p = {"mode": "fixed_rate", "brick": (16, 16), "rate": 4.0}
+    ref, pref = separate(A, xg, p)
+    ws = A.workspace(xg.dtype, tuple(xg.shape), p, DEV)
+    A.apax_status_clear(ws)
+    main, s2, fk = torch.cuda.current_stream(), torch.cuda.Stream(), torch.cuda.Event()
+    outs = []
+    torch.cuda.synchronize()
+    for _ in range(6):
+        buf, nb = A.apax_profile_encode_async(xg, p, ws, stream=main, side=s2, forked=fk)
+        main.wait_stream(s2)
+        outs.append((buf, nb))
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    assert A.apax_profile_read(xg, p, ws) == pref
+    for buf, nb in outs:
+        n = int(nb.item())
         assert n == ref.size and torch.equal(buf[:n].cpu(), torch.from_numpy(ref))
 
 
