@@ -567,13 +567,20 @@ struct Blk {
     bool fit = ((mask >> 7) & 1) && H + g.B * W <= lim;
     // true once every lane's block fits (wave-uniform)
     auto done = [&]() { return __ballot(blk_ok && !fit) == 0; };
+    // every JEE position takes at least half a nibble (a pair token covers
+    // two), so H + 4 ceil((G - 1) / 2) + payload bounds a stream's size from
+    // below: where that bound exceeds lim in every block of the wave, the
+    // token count is not needed
+    const int tmin = 4 * (g.G / 2);
     auto try1 = [&](const uint32_t s[4]) {
       int32_t v[4];
       finish<DENSE>(s, v);
       int e, p;
       eps_of<DENSE>(v, e, p);
-      const int tk = token_nibbles(e);
       const uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)p), L.seg);
+      const int lb = H + tmin + 4 * (int)tot;
+      if (__ballot(blk_ok && !fit && lb <= lim) == 0) return false;  // no block of the wave can fit with it
+      const int tk = token_nibbles(e);
       fit = fit || H + 4 * tk + 4 * (int)tot <= lim;
       return done();
     };
