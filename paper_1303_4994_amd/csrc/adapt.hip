@@ -43,11 +43,9 @@ __global__ __launch_bounds__(WPG * 64) void k_adapt_table(EncArgs A, uint8_t* __
     const int c = clampc(g.alo + w, b.cf, b.cc);
     if (__ballot(b.act && c != cprev)) {  // some block of the wave needs a new evaluation
       int32_t a[4];
-      Costs C;
       int32_t best;
       b.quantize(c, false, a);
-      b.costs(g, g.mask, a, C);
-      B_::argmin(C, g.mask, best);
+      b.best_stream(g, g.mask, a, best);
       nprev = (best + 31) >> 5;
       cprev = c;
     }

@@ -552,6 +552,96 @@ struct Blk {
     C.sz[7] = ((mask >> 7) & 1) ? H + g.B * W : BIG;
   }
 
+  // The cheapest stream of `mask` and its size (`best`), exactly as costs()
+  // + argmin() (ties: the lowest id), by branch and bound: streams are
+  // formed most-likely-smallest first, two at a time, their payload sizes
+  // summed in one scan per pair, and a stream's JEE token count is taken
+  // only where its payload plus the minimum token bits (half a nibble per
+  // position) could still beat or tie, with a lower id, the best so far in
+  // some block of the wave.
+  __device__ __forceinline__ int best_stream(const Geo& g, uint32_t mask, const int32_t a[4], int32_t& best) const {
+    return dense ? best_stream_t<true>(g, mask, a, best) : best_stream_t<false>(g, mask, a, best);
+  }
+  template <bool DENSE>
+  __device__ __forceinline__ int best_stream_t(const Geo& g, uint32_t mask, const int32_t a[4], int32_t& best) const {
+    const uint32_t nd = (uint32_t)__builtin_amdgcn_readfirstlane((int)(NDMASK & mask));  // wave-uniform
+    const uint32_t A[4] = {(uint32_t)a[0], (uint32_t)a[1], (uint32_t)a[2], (uint32_t)a[3]};
+    const int tmin = 4 * (g.G / 2);
+    int bs = 7;
+    best = ((mask >> 7) & 1) ? H + g.B * W : BIG;
+    // one stream's exponent and payload width per lane
+    auto prep = [&](const uint32_t s[4], int& e, int& p) {
+      int32_t v[4];
+      finish<DENSE>(s, v);
+      eps_of<DENSE>(v, e, p);
+    };
+    // a stream whose payload bits `tot` are known: its tokens, if it can win
+    auto judge = [&](int t, int e, uint32_t tot) {
+      const int lb = H + tmin + 4 * (int)tot;
+      if (__ballot(blk_ok && (lb < best || (lb == best && t < bs))) == 0) return;
+      const int sz = H + 4 * token_nibbles(e) + 4 * (int)tot;
+      if (sz < best || (sz == best && t < bs)) {
+        best = sz;
+        bs = t;
+      }
+    };
+    // two streams (ta, tb; tb < 0: none) with one scan of their packed
+    // payload widths (each segment total <= 64 * 128 < 2^16)
+    auto pair = [&](int ta, const uint32_t sa[4], int tb, const uint32_t sb[4]) {
+      int ea, pa, eb = 0, pb = 0;
+      prep(sa, ea, pa);
+      if (tb >= 0) prep(sb, eb, pb);
+      const uint32_t tot = seg_last<LPB>(seg_scan_add<LPB>((uint32_t)pa | ((uint32_t)pb << 16)), L.seg);
+      judge(ta, ea, tot & 0xFFFFu);
+      if (tb >= 0) judge(tb, eb, tot >> 16);
+    };
+    uint32_t d[4];
+    if (nd & 6u) xdiff(A, d);
+    if (NDIM >= 2 && (nd & 0x78u)) {
+      uint32_t Q[4], R[4], RQ[4], f[4];
+      exchange(A, Q, R, RQ, (nd & 0x50u) != 0);
+#pragma unroll
+      for (int k = 0; k < 4; k++) f[k] = A[k] - Q[k];
+      if (NDIM == 3 && (nd & 0x50u)) {
+        uint32_t h[4], u[4], s6[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          h[k] = A[k] - R[k];
+          u[k] = f[k] - R[k] + RQ[k];  // dz dy a
+        }
+        xdiff(u, s6);
+        if ((nd & 0x40u) && (nd & 0x10u)) pair(6, s6, 4, h);
+        else if (nd & 0x40u) pair(6, s6, -1, s6);
+        else pair(4, h, -1, h);
+      }
+      uint32_t s5[4];
+      xdiff(f, s5);
+      if ((nd & 0x20u) && (nd & 8u)) pair(5, s5, 3, f);
+      else if (nd & 0x20u) pair(5, s5, -1, s5);
+      else if (nd & 8u) pair(3, f, -1, f);
+    }
+    if (nd & 6u) {
+      uint32_t s2[4];
+      xdiff(d, s2);
+      if ((nd & 2u) && (nd & 4u)) pair(1, d, 2, s2);
+      else if (nd & 2u) pair(1, d, -1, d);
+      else pair(2, s2, -1, s2);
+    }
+    if constexpr (NDIM == 1) {
+      if (nd & 8u) {
+        uint32_t F[4];
+        filt(g, A, F);
+        if (nd & 1u) pair(3, F, 0, A);
+        else pair(3, F, -1, F);
+      } else if (nd & 1u) {
+        pair(0, A, -1, A);
+      }
+    } else {
+      if (nd & 1u) pair(0, A, -1, A);
+    }
+    return bs;
+  }
+
   // Fixed-rate fit test (this lane's block): whether some stream of `mask`
   // codes the block in at most `lim` bits, i.e. min over the mask <= lim.
   // The streams are tried most-likely-smallest first (the verbatim size

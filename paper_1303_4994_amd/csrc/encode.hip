@@ -235,11 +235,9 @@ __global__ __launch_bounds__(WPG * 64) void k_stream_choice(EncArgs A, int32_t* 
   b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * XCH : nullptr);
   b.template load<false>((const T*)A.x, g);
   int32_t a[4];
-  Costs C;
   int32_t best;
   b.quantize(0, true, a);
-  b.costs(g, g.mask, a, C);
-  const int st = B_::argmin(C, g.mask, best);
+  const int st = b.best_stream(g, g.mask, a, best);
   if (b.blk_ok && b.L.gi == 0) best_st[b.j] = st;
 }
 

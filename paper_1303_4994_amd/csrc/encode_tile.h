@@ -133,11 +133,10 @@ __device__ __forceinline__ void analyze_block(const EncArgs& A, Blk<T, LPB, NDIM
   c = 0;
   if (mode != M_LOSSLESS) c = clampc(code0, b.cf, b.cc);
   b.quantize(c, mode == M_LOSSLESS, a);
-  Costs C;
-  b.costs(g, emask, a, C);
-  st = B_::argmin(C, emask, best);
   if (A.lag) {  // lagged choice (lossless): the previous block's best stream,
                 // or verbatim where that would code the block above verbatim size
+    Costs C;
+    b.costs(g, emask, a, C);
     st = b.j == 0 ? 0 : (b.blk_ok ? A.lag[b.j - 1] : 0);
     if constexpr (LPB == 64) st = __builtin_amdgcn_readfirstlane(st);
     best = B_::size_sel(C, st);
@@ -145,6 +144,8 @@ __device__ __forceinline__ void analyze_block(const EncArgs& A, Blk<T, LPB, NDIM
       st = 7;
       best = C.sz[7];
     }
+  } else {
+    st = b.best_stream(g, emask, a, best);
   }
   if constexpr (LPB == 64) {
     st = __builtin_amdgcn_readfirstlane(st);

@@ -418,7 +418,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     if (OP == P_CENTER && A.rule != R_QUALITY) b.template take<false>(g, cv);
     else b.take(g, cv);
     int32_t a[4];
-    Costs C;
     int32_t best;
     if (OP == P_FITS) {
       // argmin over the mask at the clamped code: fit test + stream histogram
@@ -428,8 +427,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
         if (b.fits(g, mask, a, 32 * g.budget) && b.blk_ok && b.L.gi == 0) nfit++;
         continue;
       }
-      b.costs(g, mask, a, C);
-      int s_ = B_::argmin(C, mask, best);
+      int s_ = b.best_stream(g, mask, a, best);
       if (b.blk_ok && b.L.gi == 0 && best <= 32 * g.budget) nfit++;
       if (A.hist) {
         if (b.act) wsum += (unsigned long long)b.nvalid;  // samples of the subsample
@@ -451,8 +449,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
         c = clampc(code, b.cf, b.cc);
         const uint32_t m7 = mask & 0x7Fu;
         b.quantize(c, false, a);
-        b.costs(g, m7, a, C);
-        int s_ = B_::argmin(C, m7, best);
+        int s_ = b.best_stream(g, m7, a, best);
         bool need = b.act && best > 32 * g.budget;
         if (__ballot(need)) c = b.rate_search(g, g.mask, c, s_, need);
         else have_a = true;
@@ -466,8 +463,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     if (OP == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
-        b.costs(g, mask, a, C);
-        const int s_ = B_::argmin(C, mask, best);
+        const int s_ = b.best_stream(g, mask, a, best);
         nw = (best + 31) >> 5;
         if (A.bst && b.blk_ok && b.L.gi == 0) {  // the encoder's size pass, done here
           A.bst[b.j] = (uint8_t)s_;
