@@ -125,17 +125,19 @@ struct PParts {
   uint32_t* hist;     // [8][R] blocks per chosen stream
   int64_t R;
 };
+// The fit counts come first, so a pass that writes only them (the fixed-rate
+// probes, up to MAXCODES x 2048 records) needs 4 bytes per record.
 __host__ __device__ inline PParts pparts(void* base, int64_t R) {
   PParts P;
   uint8_t* b = (uint8_t*)base;
+  P.nfit = (uint32_t*)b;
+  b += (4 * R + 7) / 8 * 8;
   P.s = (double*)b;
   b += 8 * NSUM * R;
   P.words = (uint64_t*)b;
   b += 8 * R;
   P.dmax = (uint64_t*)b;
   b += 8 * R;
-  P.nfit = (uint32_t*)b;
-  b += 4 * R;
   P.hist = (uint32_t*)b;
   P.R = R;
   return P;
@@ -171,6 +173,7 @@ struct ProfArgs {
   // ids are spread so the workgroups of every code that visit the same
   // tiles share an XCD (and its L2), which then fetches those tiles once
   int xcd_map;
+  int probe_all;              // fixed-rate probes: every code tested on each tile (k_probe_all)
   // metrics pass of a profile that encodes next (else null): each block's
   // chosen stream, and in variable-size modes its length (into the stream's
   // index) and its superblock's word sum -- the encoder's first pass

@@ -570,6 +570,74 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
   }
 }
 
+// the probe records (fit counts only) of up to MAXCODES codes x 2048
+// workgroups fit the partial region sized for 2048 + 2 MAXCODES full records
+static_assert((int64_t)MAXCODES * 2048 * 4 <= (2048 + 2 * (int64_t)MAXCODES) * PPART_BYTES, "probe records");
+
+// Bisection probes of a fixed-rate profile (the fit test alone) with every
+// code of the launch tested on a tile that is loaded and bracketed once:
+// each persistent workgroup takes tiles wgx, wgx + nwg, ... and, per tile,
+// quantizes and tests its blocks at each code in turn; the fits of code ci
+// go to record ci * nwg + wgx, the layout of the one-code-per-workgroup
+// passes, so the same reduce kernel follows.
+template <typename T, int LPB, int NDIM>
+__global__ __launch_bounds__(256) void k_probe_all(ProfArgs A) {
+  constexpr int BPW = 64 / LPB;
+  using B_ = Blk<T, LPB, NDIM>;
+  const Geo& g = A.g;
+  const PState* st = A.st;
+  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
+  __shared__ uint32_t s_fit[WPG][MAXCODES];
+  __shared__ int32_t s_code[MAXCODES];
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int nset = st->ncodes;
+  const int ncodes = nset < A.maxcodes ? nset : A.maxcodes;
+  if (threadIdx.x < MAXCODES) s_code[threadIdx.x] = st->codes[threadIdx.x];
+  if (lane < MAXCODES) s_fit[wave][lane] = 0;
+  __syncthreads();
+  const uint32_t mask = st->mask_probe;
+  const int64_t wgx = blockIdx.x;
+  auto block_of = [&](int64_t t) -> int64_t {
+    const int64_t jj = (t * WPG + wave) * BPW + lane / LPB;
+    return jj < A.nbe ? jj * A.jstride : g.nblocks;
+  };
+  uint4* xw = NDIM >= 2 ? s_xch + wave * XCH : nullptr;
+  B_ nb;
+  T nv[4];
+  nb.init(g, block_of(wgx), xw);
+  nb.fetch((const T*)A.x, g, nv);
+  for (int64_t tile = wgx; tile < A.ntiles; tile += A.nwg) {
+    B_ b = nb;
+    T cv[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) cv[k] = nv[k];
+    if (tile + A.nwg < A.ntiles) {
+      nb.init(g, block_of(tile + A.nwg), xw);
+      nb.fetch((const T*)A.x, g, nv);
+    }
+    b.take(g, cv);
+    const bool lead = b.blk_ok && b.L.gi == 0;
+#pragma unroll 1
+    for (int ci = 0; ci < ncodes; ci++) {
+      const int c = clampc(s_code[ci], b.cf, b.cc);
+      int32_t a[4];
+      b.quantize(c, false, a);
+      const bool f = b.fits(g, mask, a, 32 * g.budget);
+      const uint32_t n = (uint32_t)__popcll(__ballot(f && lead));
+      if (lane == 0) s_fit[wave][ci] += n;
+    }
+  }
+  __syncthreads();
+  const PParts P = pparts(A.parts, (int64_t)A.maxcodes * A.nwg);
+  if (threadIdx.x < ncodes) {
+    const int ci = threadIdx.x;
+    uint32_t n = 0;
+    for (int w = 0; w < WPG; w++) n += s_fit[w][ci];
+    P.nfit[(int64_t)ci * A.nwg + wgx] = n;
+  }
+}
+
 // One workgroup: fixed-order reduction of the records of the preceding
 // pass, then its control step.
 template <int OPK, bool HIST>
@@ -797,6 +865,10 @@ template <typename T, int LPB, int NDIM>
 static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
   const dim3 grid = A.xcd_map ? dim3((unsigned)(A.nwg * A.maxcodes), 1) : dim3((unsigned)A.nwg, A.maxcodes);
   const dim3 block(WPG * 64);
+  if (A.op == P_FITS && A.probe_all) {
+    hipLaunchKernelGGL((k_probe_all<T, LPB, NDIM>), dim3((unsigned)A.nwg), block, 0, s, A);
+    return hipGetLastError();
+  }
   if (A.op == P_FITS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_FITS>), grid, block, 0, s, A);
   else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CURVE>), grid, block, 0, s, A);
   else if (A.op == P_STATS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_STATS>), grid, block, 0, s, A);
@@ -827,7 +899,12 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEv
   // code, mapped onto the XCDs (the one-workgroup-per-block passes keep the
   // 2-D grid)
   A.xcd_map = 0;
-  if (!wide && A.maxcodes > 1 && A.nwg >= 8) {
+  // fixed-rate bisection probes: one workgroup per tile group for all codes
+  // (about 2048 workgroups over the tiles), each tile loaded and bracketed
+  // once
+  A.probe_all = !wide && A.op == P_FITS && !A.hist && !A.final_code && A.rule == R_RATE && A.maxcodes > 1;
+  if (A.probe_all) A.nwg = A.ntiles < 2048 ? A.ntiles : 2048;
+  else if (!wide && A.maxcodes > 1 && A.nwg >= 8) {
     A.nwg = A.nwg / 8 * 8;
     A.xcd_map = 1;
   }
