@@ -861,8 +861,53 @@ int64_t prof_wgs(int64_t ntiles, int ncodes) {
   return ntiles < w ? ntiles : w;
 }
 
+// Workgroups of `kernel` (256 threads) the whole chip holds at once, at most
+// 2048: the persistent passes launch about this many, so every SIMD runs the
+// same number of waves from start to end.
+template <void (*KERNEL)(ProfArgs)>
+static int64_t resident_wgs() {
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)KERNEL, WPG * 64, 0) != hipSuccess || n < 1)
+      n = 8;
+    return n;
+  }();
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 256;
+  const int64_t r = (int64_t)per_cu * cus;
+  return r < 2048 ? r : 2048;
+}
+
+// Persistent workgroups of a one-wave-per-block pass: a one-code pass runs
+// the resident count (every SIMD keeps the same number of waves to the end);
+// several codes share about 2048 workgroups (measured faster than the
+// resident count for the curve), in whole groups of 8 per code mapped onto
+// the XCDs; the fixed-rate probes test every code in each workgroup.
+static void plan_wgs(ProfArgs& A, int64_t resident) {
+  A.xcd_map = 0;
+  if (A.maxcodes > 1) resident = 2048;
+  if (A.probe_all) {
+    A.nwg = A.ntiles < resident ? A.ntiles : resident;
+    return;
+  }
+  int64_t per = resident / A.maxcodes;
+  if (per < 1) per = 1;
+  A.nwg = A.ntiles < per ? A.ntiles : per;
+  if (A.maxcodes > 1 && A.nwg >= 8) {
+    A.nwg = A.nwg / 8 * 8;
+    A.xcd_map = 1;
+  }
+}
+
 template <typename T, int LPB, int NDIM>
-static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
+static hipError_t launch_t(ProfArgs& A, hipStream_t s) {
+  if (A.op == P_FITS && A.probe_all) plan_wgs(A, resident_wgs<k_probe_all<T, LPB, NDIM>>());
+  else if (A.op == P_FITS) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_FITS>>());
+  else if (A.op == P_STATS && A.curve) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_CURVE>>());
+  else if (A.op == P_STATS) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_STATS>>());
+  else plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_CENTER>>());
   const dim3 grid = A.xcd_map ? dim3((unsigned)(A.nwg * A.maxcodes), 1) : dim3((unsigned)A.nwg, A.maxcodes);
   const dim3 block(WPG * 64);
   if (A.op == P_FITS && A.probe_all) {
@@ -877,14 +922,14 @@ static hipError_t launch_t(const ProfArgs& A, hipStream_t s) {
 }
 
 template <typename T, int NDIM>
-static hipError_t launch_lpb(const ProfArgs& A, hipStream_t s) {
+static hipError_t launch_lpb(ProfArgs& A, hipStream_t s) {
   if (A.g.G <= 16) return launch_t<T, 16, NDIM>(A, s);
   if (A.g.G <= 32) return launch_t<T, 32, NDIM>(A, s);
   return launch_t<T, 64, NDIM>(A, s);
 }
 
 template <typename T>
-static hipError_t launch_nd(const ProfArgs& A, int ndim, hipStream_t s) {
+static hipError_t launch_nd(ProfArgs& A, int ndim, hipStream_t s) {
   if (ndim == 1) return launch_lpb<T, 1>(A, s);
   if (ndim == 2) return launch_lpb<T, 2>(A, s);
   return launch_lpb<T, 3>(A, s);
@@ -894,20 +939,12 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEv
   // blocks of more than 64 groups, or groups of 8: one workgroup per block
   const bool wide = A.g.G > 64 || A.g.gq == 2;
   A.ntiles = wide ? A.nbe : prof_tiles(A.g, A.nbe);
+  // (the one-wave-per-block passes size their grid at launch: plan_wgs)
   A.nwg = prof_wgs(A.ntiles, A.maxcodes);
-  // several codes over the same tiles: whole groups of 8 workgroups per
-  // code, mapped onto the XCDs (the one-workgroup-per-block passes keep the
-  // 2-D grid)
   A.xcd_map = 0;
-  // fixed-rate bisection probes: one workgroup per tile group for all codes
-  // (about 2048 workgroups over the tiles), each tile loaded and bracketed
-  // once
+  // fixed-rate bisection probes: every code of the launch tested on each
+  // tile, loaded and bracketed once
   A.probe_all = !wide && A.op == P_FITS && !A.hist && !A.final_code && A.rule == R_RATE && A.maxcodes > 1;
-  if (A.probe_all) A.nwg = A.ntiles < 2048 ? A.ntiles : 2048;
-  else if (!wide && A.maxcodes > 1 && A.nwg >= 8) {
-    A.nwg = A.nwg / 8 * 8;
-    A.xcd_map = 1;
-  }
   if (A.ntiles == 0) return hipSuccess;
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
