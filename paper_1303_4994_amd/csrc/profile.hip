@@ -482,9 +482,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     for (int i = 0; i < NL; i++) t[i] = 0.0;
     const double Rq = inv_mantissa(c);
     const int eq = -(c >> 4);
+    // a sample past the edge (or of a lane without a group) is 0 and
+    // decodes to 0, so its terms of the plain sums are +0 and change nothing:
+    // the statistics passes add them unconditionally
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-      if (!(b.act && b.valid(k))) continue;
+      if (OP != P_STATS && !(b.act && b.valid(k))) continue;
       double x = b.xv(k);
       double y;
       if (A.rule == R_LOSSLESS) y = (double)a[k];
