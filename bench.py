@@ -79,6 +79,7 @@ TRAFFIC_KEYS = {  # kernel (trace name) -> key of its bytes per launch
     "apax::k_profile<float, 64, 2, 4>": "k_profile_curve",
     "apax::k_profile<float, 64, 2, 3>": "k_profile_centred",
     "apax::k_profile<float, 64, 2, 2>": "k_profile_fits",
+    "apax::k_probe_all<float, 64, 2>": "k_probe_all",
     "apax::k_pmax<float>": "k_pmax",
 }
 
@@ -193,7 +194,8 @@ def trace_summary(db_path: str, out_path: str, workloads: bool = False):
            f"# command: {TRACE_CMD}",
            f"# summary: python3 bench.py --trace-from {db_path}",
            "# durations in microseconds; per bench step: k_clear; k_pmax + k_pmax_reduce; 3 bisection probes",
-           "# k_profile<.., 2> + k_reduce<2, false>; histogram k_profile<.., 2> + k_reduce<2, true>; metrics",
+           "# k_probe_all (all 8 codes of a launch per tile) + k_reduce<2, false>; histogram k_profile<.., 2>",
+           "# + k_reduce<2, true>; metrics",
            "# k_profile<.., 1> + k_reduce<1, false>; then k_encode_blocks (the encode from the metrics",
            "# pass's per-block codes and streams) and k_decode, beside centred k_profile<.., 3> +",
            "# k_reduce<3, false> and curve k_profile<.., 4> + k_reduce<4, false> on a second stream.",
