@@ -214,9 +214,10 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
  * passes.  Then `forked` (an event the caller owns) is recorded on `stream`
  * at the end of the stream-histogram pass, `side` waits for it and runs the
  * curve pass beside the metrics pass; `forked` is recorded again at the end
- * of the metrics pass and `side` then runs the centred pass, while the
- * encode (and whatever the caller enqueues after it on `stream`, such as a
- * decode of the stream) runs on `stream`.  The profile
+ * of the metrics pass kernel and `side` then runs that pass's reduction
+ * (the means) and the centred pass, while the encode (and whatever the
+ * caller enqueues after it on `stream`, such as a decode of the stream) runs
+ * on `stream`.  The profile
  * result is complete when both streams have reached the end of this call's
  * work: join them (wait on `side`) before apax_profile_read or another
  * profile in d_ws.  side == stream, or side without forked: APAX_E_INVALID.

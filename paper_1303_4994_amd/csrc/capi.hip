@@ -822,10 +822,11 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     }
     A.C = C;
     A.C.step = next;
-    return hip_err(launch_profile(h.dtype, h.ndim, A, ps, pair(pass)));
+    // F_SPLIT: the reduce on `side`, forked after the pass kernel
+    return hip_err(launch_profile(h.dtype, h.ndim, A, ps, pair(pass), (flags & 64) ? side : nullptr, forked));
   };
   // F_PARTS2: the second partial-record region (a pass beside another)
-  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16, F_PARTS2 = 32 };
+  enum { F_HIST = 1, F_FINAL = 2, F_CURVE = 4, F_STORE = 8, F_ENC = 16, F_PARTS2 = 32, F_SPLIT = 64 };
 
   // whole profile, asynchronously: clear, max |x| (-> bracket), bisection
   // batches, histogram at the chosen code (-> mask, curve codes), curve
@@ -862,13 +863,20 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       ps = stream;
     }
     // metrics at the operating point (fixed rate: each block's code kept
-    // for the centred pass), then the encode that may follow it, the
-    // centred sums (on `side`, forked again once the means are known) and,
-    // without a side stream, the curve
+    // for the centred pass), then the encode that may follow it (it reads
+    // the per-block codes and streams the pass stored and the operating point
+    // the histogram's control step set, nothing of the metrics' reduce), the
+    // centred sums and, without a side stream, the curve.  With a side
+    // stream and an encode, `side` forks once the metrics pass kernel is
+    // done and runs its reduce (means) and the centred pass beside the
+    // encode; that reduce writes back only the state words it changed, none
+    // of which the encode reads
     if (enc && !fr) launch_encode_reset(enc->ssum, (g.nblocks + 63) / 64, stream);
-    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC, APAX_PASS_METRICS))) return e;
+    const int split = side && enc ? F_SPLIT : 0;
+    if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC | split, APAX_PASS_METRICS)))
+      return e;
     if (side) {
-      if ((e = fork())) return e;
+      if (!split && (e = fork())) return e;
       ps = side;
     }
     if (enc) {

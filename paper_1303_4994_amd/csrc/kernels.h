@@ -269,7 +269,10 @@ int64_t prof_tiles(const Geo& g, int64_t nbe);
 int64_t prof_wgs(int64_t ntiles, int ncodes);
 // ev (optional): events recorded just before and just after the pass kernel
 // (its one-workgroup reduce follows outside the pair)
-hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev = nullptr);
+// rs (with the event fork): run the pass's reduce kernel on stream rs, which
+// waits for the pass kernel on s
+hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev = nullptr,
+                          hipStream_t rs = nullptr, hipEvent_t fork = nullptr);
 // the pass kernel for blocks of more than 64 groups or groups of 8 (A.nwg set)
 hipError_t launch_wide_profile(int dtype, int ndim, const ProfArgs& A, hipStream_t s);
 hipError_t launch_pmax(int dtype, const void* x, uint64_t n, void* parts, const CtlArgs& C,

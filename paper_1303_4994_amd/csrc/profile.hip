@@ -938,7 +938,8 @@ static hipError_t launch_nd(ProfArgs& A, int ndim, hipStream_t s) {
   return launch_lpb<T, 3>(A, s);
 }
 
-hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev) {
+hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEvent_t* ev, hipStream_t rs,
+                          hipEvent_t fork) {
   // blocks of more than 64 groups, or groups of 8: one workgroup per block
   const bool wide = A.g.G > 64 || A.g.gq == 2;
   A.ntiles = wide ? A.nbe : prof_tiles(A.g, A.nbe);
@@ -961,6 +962,11 @@ hipError_t launch_profile(int dtype, int ndim, ProfArgs& A, hipStream_t s, hipEv
   }
   if (e != hipSuccess) return e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+  // the reduce on another stream, forked once the pass is done
+  if (rs) {
+    if ((e = hipEventRecord(fork, s)) != hipSuccess || (e = hipStreamWaitEvent(rs, fork, 0)) != hipSuccess) return e;
+    s = rs;
+  }
   if (A.op == P_FITS && A.hist) hipLaunchKernelGGL((k_reduce<P_FITS, true>), dim3(1), dim3(256), 0, s, A);
   else if (A.op == P_FITS) hipLaunchKernelGGL((k_reduce<P_FITS, false>), dim3(1), dim3(256), 0, s, A);
   else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_reduce<P_CURVE, false>), dim3(1), dim3(256), 0, s, A);
