@@ -869,18 +869,18 @@ int64_t prof_wgs(int64_t ntiles, int ncodes) {
 // same number of waves from start to end.
 template <void (*KERNEL)(ProfArgs)>
 static int64_t resident_wgs() {
-  static const int per_cu = [] {
-    int n = 0;
+  // (queried once per kernel, on the device current at the first launch)
+  static const int64_t r = [] {
+    int n = 0, dev = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)KERNEL, WPG * 64, 0) != hipSuccess || n < 1)
       n = 8;
-    return n;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    const int64_t t = (int64_t)n * cus;
+    return t < 2048 ? t : (int64_t)2048;
   }();
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus < 1)
-    cus = 256;
-  const int64_t r = (int64_t)per_cu * cus;
-  return r < 2048 ? r : 2048;
+  return r;
 }
 
 // Persistent workgroups of a one-wave-per-block pass: a one-code pass runs
