@@ -13,11 +13,12 @@ APAX_CODE_PROFILED), then apax_decode, enqueued with no host round trip.  The
 profile's centred and curve passes run on a second stream from the end of
 its metrics pass on, beside the encode and decode.  Inputs are resident in HBM before
 timing; steps rotate over several copies so the 256 MB Infinity Cache cannot
-serve them.  The steps are timed three ways: enqueued eagerly one after the
+serve them.  The steps are timed four ways: enqueued eagerly one after the
 other, as hipGraphs of the same enqueue sequence (one per copy), and
 pipelined (step i + 1's profile starts while step i's last profile passes
 and its decode finish on the second stream; two profile workspaces
-alternate); the step time is the fastest loop (all are reported, each
+alternate), enqueued eagerly and as graph replays on two streams; the step
+time is the fastest loop (all are reported, each
 checked: every copy decodes to the same field).  After the timed loop the last
 profile is read back and the decoded field checked against its correlation,
 and every graph replay's decode against the eager one.  Also timed, outside
@@ -644,6 +645,59 @@ def main():
         del graphs
     except RuntimeError as exc:  # capture refused: report the eager steps
         log(f"step graph not used: {exc}")
+    # the pipelined steps as hipGraphs: step i's graph (profile, encode,
+    # decode of copy i with workspace pair i mod 2) replayed on stream i mod 2,
+    # so step i + 1 runs beside step i and the host enqueues one graph per
+    # step; step i + 2 follows step i on its stream, which orders the reuse
+    # of the workspaces
+    ms_step_graph_pipelined = None
+    if graph_ok and R % 2 == 0:
+        try:
+            ws_decp = [ws_dec, A.workspace(torch.float32, x.shape, params, dev)]
+            A.apax_status_clear(ws_decp[1])
+            gstreams = [torch.cuda.Stream(), torch.cuda.Stream()]
+            pgraphs = []
+            for i in range(R):
+                k = i & 1
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    cap = torch.cuda.current_stream()
+                    A.apax_profile_encode_async(xs[i], params, wsp[k], out=bufs[i], nbytes=nbp[k], stream=cap,
+                                                side=side, forked=ev_forkp[k])
+                    A.apax_decode(bufs[i], bound, hdr=step.hdr, y=ys[i], ws=ws_decp[k], stream=cap,
+                                  clear_status=False)
+                    cap.wait_stream(side)
+                pgraphs.append(g)
+            torch.cuda.synchronize()
+
+            def replay(k):
+                with torch.cuda.stream(gstreams[k & 1]):
+                    pgraphs[k % R].replay()
+
+            for k in range(args.warmup):
+                replay(k)
+            torch.cuda.synchronize()
+            for i in range(R):
+                ys[i].zero_()
+            torch.cuda.synchronize()
+            q0 = time.perf_counter()
+            for k in range(args.steps):
+                replay(k)
+            torch.cuda.synchronize()
+            q1 = time.perf_counter()
+            assert all(A.apax_status(w) == 0 for w in wsp + ws_decp)
+            for i in range(min(R, args.steps)):
+                assert torch.equal(ys[i], y_serial), f"pipelined graph step of copy {i} differs from the serial steps"
+            ms_step_graph_pipelined = (q1 - q0) * 1e3 / args.steps
+            del pgraphs
+        except RuntimeError as exc:
+            log(f"pipelined step graphs not used: {exc}")
+    ms_step_pipelined_eager = ms_step_pipelined
+    if ms_step_graph_pipelined is not None and ms_step_graph_pipelined < ms_step_pipelined:
+        ms_step_pipelined = ms_step_graph_pipelined
+        pipelined_as_graph = True
+    else:
+        pipelined_as_graph = False
     # the step time: the faster of the two timed loops of the same steps (on
     # this runtime a graph replay does not always beat the eager enqueue of
     # the same kernels: its nodes can start later than the eager launches)
@@ -766,6 +820,9 @@ def main():
         "ms_per_step_eager": round(ms_step_eager, 4),
         "ms_per_step_graph": None if ms_step_graph is None else round(ms_step_graph, 4),
         "ms_per_step_pipelined": round(ms_step_pipelined, 4),
+        "ms_per_step_pipelined_eager": round(ms_step_pipelined_eager, 4),
+        "ms_per_step_pipelined_graphs": None if ms_step_graph_pipelined is None else round(ms_step_graph_pipelined, 4),
+        "pipelined_as_graphs": pipelined_as_graph,
         "ms_per_step_serial": round(ms_step_serial, 4),
         "step_pipelined": ms_step_pipelined <= ms_step_serial,
         "step_as_graph": graph_ok and ms_step_graph <= ms_step_eager,
