@@ -77,6 +77,7 @@ TRAFFIC_KEYS = {  # kernel (trace name) -> key of its bytes per launch
     "apax::k_encode<float, 64, 2, 4, false>": "k_encode",
     "apax::k_decode<float, 64, 2, 4>": "k_decode",
     "apax::k_profile<float, 64, 2, 1>": "k_profile_metrics",
+    "apax::k_profile<float, 64, 2, 5>": "k_profile_metrics_encode",
     "apax::k_profile<float, 64, 2, 4>": "k_profile_curve",
     "apax::k_profile<float, 64, 2, 3>": "k_profile_centred",
     "apax::k_profile<float, 64, 2, 2>": "k_profile_fits",
@@ -197,9 +198,10 @@ def trace_summary(db_path: str, out_path: str, workloads: bool = False):
            "# durations in microseconds; per bench step: k_clear; k_pmax + k_pmax_reduce; 3 bisection probes",
            "# k_probe_all (all 8 codes of a launch per tile) + k_reduce<2, false>; histogram k_profile<.., 2>",
            "# + k_reduce<2, true>; metrics",
-           "# k_profile<.., 1> + k_reduce<1, false>; then k_encode_blocks (the encode from the metrics",
-           "# pass's per-block codes and streams) and k_decode, beside centred k_profile<.., 3> +",
-           "# k_reduce<3, false> and curve k_profile<.., 4> + k_reduce<4, false> on a second stream.",
+           "# k_profile<.., 5> (k_encode_header first: the stream header), which also writes every block of",
+           "# the stream at its code and stream, then k_decode; curve k_profile<.., 4> + k_reduce<4, false>",
+           "# beside it on a second stream, then there k_reduce<1, false> (the metrics' reduction), centred",
+           "# k_profile<.., 3> + k_reduce<3, false>.",
            "# The run also times back-to-back standalone",
            "# k_encode / k_decode launches, event-bracketed profiles and the calls outside the step;",
            "# iso_avg_us is the mean over launches with no other kernel running (the per-launch figure",
@@ -730,6 +732,15 @@ def main():
         for name, v in pm.items():
             pass_runs.setdefault(name, []).append(v)
     pass_ms = {name: sum(v) / len(v) for name, v in pass_runs.items()}
+    # the step's fixed-rate metrics pass, which also writes the stream's
+    # blocks: the profile-then-encode sequence on one stream with the same
+    # events (apax_profile_encode_timed), the same bytes into the step's buffers
+    menc_runs = []
+    for k in range(reps):
+        _, pm, _, _ = A.apax_profile_encode_timed(xs[k % R], params, ws, out=bufs[k % R], nbytes=nbt)
+        menc_runs.append(pm["metrics"])
+    menc_ms = sum(menc_runs) / len(menc_runs)
+    assert int(nbt.item()) == bound
 
     # the 2-sigma S2R margin at the operating point (Sec. 4 Window 4; not part
     # of the step): the workspace holds the last timed profile of this field
@@ -800,9 +811,11 @@ def main():
         "k_encode": ("k_encode<float, 64, 2, 4, false>", enc_ms, enc_bytes),
         "k_decode": ("k_decode<float, 64, 2, 4>", dec_ms, dec_bytes),
         "k_profile_metrics": ("k_profile<float, 64, 2, 1>", pass_ms["metrics"], nbytes_in + 4 * nblocks),
+        # read the field; write the stream's blocks, each block's code (4 B) and stream (1 B)
+        "k_profile_metrics_encode": ("k_profile<float, 64, 2, 5>", menc_ms, nbytes_in + (bound - 64) + 5 * nblocks),
         "k_profile_curve": ("k_profile<float, 64, 2, 4>", pass_ms["curve"], sub_bytes),
         "k_profile_centred": ("k_profile<float, 64, 2, 3>", pass_ms["centred"], nbytes_in + 4 * nblocks),
-        "k_profile_fits": ("k_profile<float, 64, 2, 2>", sum(probes) / len(probes), sub_bytes),
+        "k_probe_all": ("k_probe_all<float, 64, 2>", sum(probes) / len(probes), sub_bytes),
         "k_pmax": ("k_pmax<float>", pass_ms["max"], nbytes_in),
     }
     dominant = max(kernels, key=lambda k: kernels[k][1])  # longest launch

@@ -247,6 +247,16 @@ enum {
 };
 int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* h_out,
                        float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream);
+/* Instrumentation for benchmarks: apax_profile_encode_async on one stream
+ * (the profile of Sec. 4, then the encode of Sec. 5-6 at its operating
+ * point into d_stream, cap bytes, *d_nbytes; the same bytes) with the pass
+ * events of apax_profile_timed.  In fixed-rate mode the metrics pass writes
+ * the stream's blocks itself, so pass_ms[APAX_PASS_METRICS] times that
+ * kernel.  Synchronous.  The lagged choice, blocks of more than 256 samples,
+ * groups of 8 and empty arrays: APAX_E_UNSUPPORTED. */
+int apax_profile_encode_timed(const void* d_x, const apax_params* p, apax_profile_result* h_out,
+                              float* pass_ms, void* d_ws, uint64_t ws_bytes, void* d_stream, uint64_t cap,
+                              uint64_t* d_nbytes, hipStream_t stream);
 
 /* Sec. 4 Window 4: the 2-sigma signal-to-residual margin of the operating
  * point of the profile that d_ws holds (run apax_profile / _async on d_x with

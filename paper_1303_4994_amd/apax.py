@@ -129,6 +129,8 @@ def _load():
     L.apax_spectral_metrics.argtypes = [vp, vp, C.c_uint32, u64, P(Spectral), vp, u64, vp]
     L.apax_signal_monitor.argtypes = [vp, C.c_uint32, u64, P(Monitor), vp, u64, vp]
     L.apax_profile_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp]
+    L.apax_profile_encode_timed.argtypes = [vp, P(Params), P(ProfileResult), P(C.c_float), vp, u64, vp, u64,
+                                            vp, vp]
     L.apax_profile_read.argtypes = [P(Params), P(ProfileResult), vp, vp]
     L.apax_encode.argtypes = [vp, P(Params), vp, u64, vp, vp, u64, vp]
     L.apax_encode_noalloc.argtypes = [vp, P(Params), vp, u64, vp, vp, vp]
@@ -313,6 +315,26 @@ def apax_profile_timed(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=N
     _check(lib.apax_profile_timed(_dev_ptr(x), C.byref(p), C.byref(r), ms, _dev_ptr(ws), ws.numel(),
                                   _stream_ptr(stream)), "apax_profile_timed")
     return profile_dict(r), {n: ms[i] for i, n in enumerate(PASS_NAMES) if ms[i] >= 0}
+
+
+def apax_profile_encode_timed(x: torch.Tensor, params: dict, ws: torch.Tensor, out=None, nbytes=None,
+                              stream=None):
+    """apax_profile_encode_async on one stream with the duration (ms) of the
+    kernel of each pass (fixed rate: the metrics pass writes the blocks);
+    returns (result dict, {pass name: ms}, stream buffer, nbytes tensor)."""
+    assert x.is_cuda and x.is_contiguous()
+    p = make_params(x.dtype, tuple(x.shape), dict(params, code=0))
+    bound = apax_encode_bound(x.dtype, tuple(x.shape), dict(params, code=0))
+    if out is None:
+        out = torch.empty(max(bound, 64), dtype=torch.uint8, device=x.device)
+    if nbytes is None:
+        nbytes = torch.zeros(1, dtype=torch.int64, device=x.device)
+    r = ProfileResult()
+    ms = (C.c_float * len(PASS_NAMES))()
+    _check(lib.apax_profile_encode_timed(_dev_ptr(x), C.byref(p), C.byref(r), ms, _dev_ptr(ws), ws.numel(),
+                                         _dev_ptr(out), out.numel(), _dev_ptr(nbytes), _stream_ptr(stream)),
+           "apax_profile_encode_timed")
+    return profile_dict(r), {n: ms[i] for i, n in enumerate(PASS_NAMES) if ms[i] >= 0}, out, nbytes
 
 
 def apax_s2r_margin(x: torch.Tensor, params: dict, ws: torch.Tensor, stream=None):

@@ -819,6 +819,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       A.bst = enc->bst;
       A.lens = enc->lens;
       A.ssum = enc->ssum;
+      if (fr) A.enc_words = enc->out_words;  // fixed rate: the pass writes the blocks too
     }
     A.C = C;
     A.C.step = next;
@@ -872,6 +873,9 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
     // encode; that reduce writes back only the state words it changed, none
     // of which the encode reads
     if (enc && !fr) launch_encode_reset(enc->ssum, (g.nblocks + 63) / 64, stream);
+    // fixed rate: the stream header now (the operating point is set), the
+    // blocks from the metrics pass itself
+    if (enc && fr && (e = hip_err(launch_encode_header(*enc, stream)))) return e;
     const int split = side && enc ? F_SPLIT : 0;
     if ((e = run(P_STATS, rule, 2, false, 1, C_MEANS, F_FINAL | F_STORE | F_ENC | split, APAX_PASS_METRICS)))
       return e;
@@ -880,7 +884,7 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       ps = side;
     }
     if (enc) {
-      if ((e = hip_err(launch_encode_profiled(h.dtype, h.ndim, *enc, cj_ptr(d_ws, h), stream)))) return e;
+      if (!fr && (e = hip_err(launch_encode_profiled(h.dtype, h.ndim, *enc, cj_ptr(d_ws, h), stream)))) return e;
       if (encoded && hipEventRecord(encoded, stream) != hipSuccess) return APAX_E_HIP;
     }
     if ((e = run(P_CENTER, rule, 2, false, 1, C_NONE, F_FINAL, APAX_PASS_CENTRED))) return e;
@@ -967,19 +971,18 @@ int apax_profile(const void* d_x, const apax_params* p, apax_profile_result* out
   return apax_profile_read(p, out, d_ws, stream);
 }
 
-int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* out,
-                       float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
-  if (!out || !pass_ms) return APAX_E_INVALID;
-  HG h;
-  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
-  if (e) return e;
+// A profile (and, with enc, the encode at its point) with HIP events around
+// each pass kernel; synchronous.
+static int profile_timed(const void* d_x, const apax_params* p, const HG& h, void* d_ws, hipStream_t stream,
+                         EncArgs* enc, apax_profile_result* out, float* pass_ms) {
+  int e = 0;
   hipEvent_t ev[2 * APAX_NPASS];
   int made = 0;
   for (; made < 2 * APAX_NPASS; made++)
     if (hipEventCreate(&ev[made]) != hipSuccess) break;
   uint32_t ran = 0;
   if (made < 2 * APAX_NPASS) e = APAX_E_HIP;
-  if (!e) e = profile_enqueue(d_x, p, h, d_ws, stream, ev, &ran);
+  if (!e) e = profile_enqueue(d_x, p, h, d_ws, stream, ev, &ran, nullptr, enc);
   if (!e) e = apax_profile_read(p, out, d_ws, stream);  // waits for the stream
   for (int i = 0; i < APAX_NPASS; i++) {
     pass_ms[i] = -1.0f;
@@ -988,6 +991,32 @@ int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_resul
   }
   for (int i = 0; i < made; i++) (void)hipEventDestroy(ev[i]);
   return e;
+}
+
+int apax_profile_timed(const void* d_x, const apax_params* p, apax_profile_result* out,
+                       float* pass_ms, void* d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!out || !pass_ms) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  return profile_timed(d_x, p, h, d_ws, stream, nullptr, out, pass_ms);
+}
+
+int apax_profile_encode_timed(const void* d_x, const apax_params* p, apax_profile_result* out, float* pass_ms,
+                              void* d_ws, uint64_t ws_bytes, void* d_stream, uint64_t cap, uint64_t* d_nbytes,
+                              hipStream_t stream) {
+  if (!out || !pass_ms) return APAX_E_INVALID;
+  HG h;
+  int e = profile_setup(d_x, p, d_ws, ws_bytes, h);
+  if (e) return e;
+  if (!d_stream || !d_nbytes || ((uintptr_t)d_stream & 15)) return APAX_E_INVALID;
+  if (cap < bound_of(h)) return APAX_E_CAPACITY;
+  if (h.lagged || h.g.nblocks == 0 || h.g.G > 64 || h.g.gq == 2) return APAX_E_UNSUPPORTED;
+  apax_params q = *p;
+  q.code = 0;
+  EncArgs A;
+  enc_args(d_x, &q, h, true, d_stream, d_nbytes, d_ws, A);
+  return profile_timed(d_x, p, h, d_ws, stream, &A, out, pass_ms);
 }
 
 int apax_s2r_margin(const void* d_x, const apax_params* p, double* h_ratio, double* h_db, void* d_ws,

@@ -154,48 +154,17 @@ __global__ __launch_bounds__(WPG * 64) void k_encode_emit(EncArgs A) {
   for (int w = gi; w < nw; w += LPB) dst[w] = w < stride ? buf[w] : 0u;
 }
 
-// Fixed rate from a profile's metrics pass: every block at the code and with
-// the stream that pass recorded (the encoder's own per-block search, run
-// there), so no bracket, costing or search here; block j at j * budget words.
-template <typename T, int LPB, int NDIM>
-__global__ __launch_bounds__(WPG * 64) void k_encode_blocks(EncArgs A, const int32_t* __restrict__ cj) {
-  constexpr int BPW = 64 / LPB;
-  using B_ = Blk<T, LPB, NDIM>;
+// The stream header of a fixed-rate encode whose blocks the profile's
+// metrics pass writes (one wave; the operating point from the profile).
+__global__ __launch_bounds__(64) void k_encode_header(EncArgs A) {
   const uint32_t* hsrc =
       (const uint32_t*)((const uint8_t*)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(EncArgs, hdr));
-  extern __shared__ __align__(16) uint32_t lds[];
-  __shared__ uint4 s_xch[NDIM >= 2 ? WPG * XCH : 1];
-  const Geo& g = A.g;
-  int32_t code0;
-  uint32_t mask0;
-  profiled_point(A, g, code0, mask0);
-  const int wave = threadIdx.x >> 6;
-  const int lane = lane_id();
-  if (blockIdx.x == 0 && wave == 0) write_stream_header(A, hsrc, false);
-  B_ b;
-  b.init(g, ((int64_t)blockIdx.x * WPG + wave) * BPW + lane / LPB, NDIM >= 2 ? s_xch + wave * XCH : nullptr);
-  {
-    T xv4[4];
-    b.fetch((const T*)A.x, g, xv4);
-    b.template take<false>(g, xv4);
-  }
-  int c = b.blk_ok ? cj[b.j] : 0;
-  int st = b.blk_ok ? (int)A.bst[b.j] : 0;
-  if constexpr (LPB == 64) {
-    c = __builtin_amdgcn_readfirstlane(c);
-    st = __builtin_amdgcn_readfirstlane(st);
-  }
-  int32_t a[4];
-  b.quantize(c, false, a);
-  const int seg = b.L.seg, gi = b.L.gi;
-  const int nw = b.blk_ok ? g.budget : 0;
-  uint32_t* buf = lds + (wave * BPW + seg) * g.ldsw;
-  emit_block<T, LPB, NDIM>(g, b, c, st, mask0 & 0x7Fu, a, buf, nw);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  uint32_t* dst = A.out_words + (uint64_t)(b.blk_ok ? b.j : 0) * (uint64_t)g.budget;
-  for (int w = gi; w < nw; w += LPB) dst[w] = w < g.ldsw ? buf[w] : 0u;
+  write_stream_header(A, hsrc, false);
+}
+
+hipError_t launch_encode_header(const EncArgs& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_encode_header, dim3(1), dim3(64), 0, s, A);
+  return hipGetLastError();
 }
 
 // Fixed rate: one workgroup per tile, block j at j * budget words.  (VAR is
@@ -305,13 +274,12 @@ static hipError_t launch_t(const EncArgs& A, hipStream_t s) {
 
 template <typename T, int LPB, int NDIM>
 static hipError_t launch_profiled_t(const EncArgs& A, const int32_t* cj, hipStream_t s) {
+  (void)cj;
   constexpr int BPW = 64 / LPB;
   const size_t lds = (size_t)WPG * BPW * A.g.ldsw * 4;
   const unsigned grid = (unsigned)A.ntiles;
-  if (A.g.mode == M_RATE) {
-    hipLaunchKernelGGL((k_encode_blocks<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), lds, s, A, cj);
-    return hipGetLastError();
-  }
+  // (fixed rate: the metrics pass writes the blocks, launch_encode_header the header)
+  if (A.g.mode == M_RATE) return hipErrorInvalidValue;
   launch_encode_scan(A, (A.g.nblocks + 63) / 64, s);
   hipLaunchKernelGGL((k_encode_emit<T, LPB, NDIM>), dim3(grid), dim3(WPG * 64), lds, s, A);
   return hipGetLastError();

@@ -76,7 +76,8 @@ struct DecArgs {
   Geo g;
 };
 
-enum { P_STATS = 1, P_FITS = 2, P_CENTER = 3, P_CURVE = 4 /* P_STATS on the curve's sums only */ };
+enum { P_STATS = 1, P_FITS = 2, P_CENTER = 3, P_CURVE = 4 /* P_STATS on the curve's sums only */,
+       P_MENC = 5 /* fixed-rate P_STATS that also writes each block's encoded words */ };
 enum { R_LOSSLESS = 0, R_RATE = 1, R_QUALITY = 2 };
 enum { S_X = 0, S_Y, S_D, S_XX, S_YY, S_DD, S_DS, S_CXX, S_CYY, S_CDD, NSUM };
 constexpr int MAXCODES = 17;
@@ -180,6 +181,11 @@ struct ProfArgs {
   uint8_t* bst;
   uint16_t* lens;
   uint32_t* ssum;
+  // fixed-rate metrics pass of a profile that encodes next (else null): the
+  // stream's block area, each block's budget words written there by the pass
+  // itself (the bytes the fixed-rate encode would write at the block's code
+  // and stream)
+  uint32_t* enc_words;
   CtlArgs C;                  // control step run by the reduce kernel (C.step, C_NONE: none)
   Geo g;
 };
@@ -235,10 +241,14 @@ hipError_t launch_decode_batch(int lpb, int ndim, int wp, const BatchArgs& B, in
                                size_t lds, hipStream_t s);
 hipError_t launch_batch_reset(uint32_t* ticket, uint64_t* tile_state, int64_t n, hipStream_t s);
 hipError_t launch_encode(int dtype, int ndim, EncArgs& A, hipStream_t s);
-// the encode of a profiled array from its metrics pass's per-block results:
-// fixed rate from each block's code (cj) and stream (A.bst); variable-size
-// modes from the lengths, streams and superblock sums it left (scan + emit)
+// the encode of a profiled array in a variable-size mode from its metrics
+// pass's per-block results: the lengths, streams and superblock sums it left
+// (scan + emit).  Fixed rate: the metrics pass writes the blocks itself
+// (ProfArgs::enc_words) and launch_encode_header the header
 hipError_t launch_encode_profiled(int dtype, int ndim, EncArgs& A, const int32_t* cj, hipStream_t s);
+// the stream header (and byte count) of a fixed-rate encode whose blocks a
+// profile's metrics pass writes (ProfArgs::enc_words)
+hipError_t launch_encode_header(const EncArgs& A, hipStream_t s);
 // each block's own best stream into best[nblocks] (lossless; the lagged choice)
 hipError_t launch_stream_choice(int dtype, int ndim, const EncArgs& A, int32_t* best, hipStream_t s);
 hipError_t launch_decode(int dtype, int ndim, DecArgs& A, hipStream_t s);

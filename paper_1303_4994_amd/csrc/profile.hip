@@ -13,6 +13,7 @@
 #include "block.h"
 #include "totals.h"
 #include "kernels.h"
+#include "encode_tile.h"
 
 namespace apax {
 
@@ -321,8 +322,13 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S, PState* S0) {
 // over 1-4 byte samples are held to five waves per SIMD (a few spilled
 // values cost less than the latency the fifth wave hides).
 template <typename T, int LPB, int NDIM, int OPK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_STATS || OPK == P_CURVE) && sizeof(T) <= 4 ? 5 : 1))) void k_profile(ProfArgs A) {
-  constexpr int OP = OPK == P_CURVE ? P_STATS : OPK;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_STATS || OPK == P_CURVE || OPK == P_MENC) && sizeof(T) <= 4 ? 5 : 1))) void k_profile(ProfArgs A) {
+  constexpr int OP = (OPK == P_CURVE || OPK == P_MENC) ? P_STATS : OPK;
+  // P_MENC: the fixed-rate metrics pass also writes each block's encoded
+  // words (its code and stream are the encoder's), assembled in the
+  // dynamic LDS, one ldsw-word buffer per block of the tile
+  constexpr bool MENC = OPK == P_MENC;
+  extern __shared__ __align__(16) uint32_t enc_lds[];
   A.curve = OPK == P_CURVE;
   if (OPK == P_CURVE) A.rule = R_QUALITY;  // curve codes are fixed per block
   constexpr int BPW = 64 / LPB;
@@ -439,6 +445,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
     }
     // P_STATS / P_CENTER: operating point of the block, decoded values
     int c = 0;
+    int s_enc = 0;        // P_MENC: the block's stream
     bool have_a = false;  // a[] already holds the block quantized at c
     if (A.rule == R_QUALITY) {
       c = clampc(code, b.cf, b.cc);
@@ -457,9 +464,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_S
           A.cj[b.j] = c;
           if (A.bst) A.bst[b.j] = (uint8_t)s_;  // the encoder's choice at this block
         }
+        s_enc = s_;
       }
     }
     if (!have_a) b.quantize(c, A.rule == R_LOSSLESS, a);
+    if constexpr (MENC) {
+      // the block's budget words at code c with stream s_enc (the encoder's
+      // mask is the metrics pass's: stream-histogram mask, verbatim allowed)
+      const int nwb = b.blk_ok ? g.budget : 0;
+      uint32_t* buf = enc_lds + (wave * BPW + b.L.seg) * g.ldsw;
+      emit_block<T, LPB, NDIM>(g, b, c, s_enc, mask & 0x7Fu, a, buf, nwb);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      uint32_t* dst = A.enc_words + (uint64_t)(b.blk_ok ? b.j : 0) * (uint64_t)g.budget;
+      for (int w = b.L.gi; w < nwb; w += LPB) dst[w] = w < g.ldsw ? buf[w] : 0u;
+    }
     if (OP == P_STATS) {
       int nw;
       if (A.rule != R_RATE) {
@@ -909,6 +929,7 @@ static hipError_t launch_t(ProfArgs& A, hipStream_t s) {
   if (A.op == P_FITS && A.probe_all) plan_wgs(A, resident_wgs<k_probe_all<T, LPB, NDIM>>());
   else if (A.op == P_FITS) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_FITS>>());
   else if (A.op == P_STATS && A.curve) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_CURVE>>());
+  else if (A.op == P_STATS && A.enc_words) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_MENC>>());
   else if (A.op == P_STATS) plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_STATS>>());
   else plan_wgs(A, resident_wgs<k_profile<T, LPB, NDIM, P_CENTER>>());
   const dim3 grid = A.xcd_map ? dim3((unsigned)(A.nwg * A.maxcodes), 1) : dim3((unsigned)A.nwg, A.maxcodes);
@@ -919,6 +940,8 @@ static hipError_t launch_t(ProfArgs& A, hipStream_t s) {
   }
   if (A.op == P_FITS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_FITS>), grid, block, 0, s, A);
   else if (A.op == P_STATS && A.curve) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CURVE>), grid, block, 0, s, A);
+  else if (A.op == P_STATS && A.enc_words)
+    hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_MENC>), grid, block, (size_t)WPG * (64 / LPB) * A.g.ldsw * 4, s, A);
   else if (A.op == P_STATS) hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_STATS>), grid, block, 0, s, A);
   else hipLaunchKernelGGL((k_profile<T, LPB, NDIM, P_CENTER>), grid, block, 0, s, A);
   return hipGetLastError();

@@ -197,3 +197,33 @@ def test_side_stream_refused_when_malformed(A):
         with pytest.raises(A.ApaxError) as e:
             A.apax_profile_encode_async(xg, p, ws, stream=main, side=side, forked=fk)
         assert e.value.code == A.E_INVALID
+
+
+@pytest.mark.parametrize("name", ["f32-2d-16x16-fr", "i8-1d-B64-fr", "f64-3d-4x4x8-fq", "i16-1d-B256-lossless"])
+def test_profile_encode_timed(A, name):
+    """The instrumented sequence (events around every pass kernel, one
+    stream) writes the same profile and bytes as the separate calls; in fixed
+    rate the metrics pass, which writes the blocks, is the timed kernel."""
+    print(f"case {name}", flush=True)
+    _, dt, shape, params = next(c for c in CASES if c[0] == name)
+    params = dict(params, target_corr=0.9999)
+    x = field(dt, shape, 3)
+    xg = torch.from_numpy(x).to(DEV)
+    ref, pref = separate(A, xg, params)
+    ws = A.workspace(xg.dtype, tuple(xg.shape), params, DEV)
+    A.apax_status_clear(ws)
+    prof, ms, buf, nb = A.apax_profile_encode_timed(xg, params, ws)
+    torch.cuda.synchronize()
+    assert A.apax_status(ws) == 0
+    assert prof == pref
+    assert np.array_equal(buf[: int(nb.item())].cpu().numpy(), ref)
+    assert ms["metrics"] > 0 and ms["max"] > 0
+
+
+def test_profile_encode_timed_refuses_wide(A):
+    xg = torch.zeros((4096,), dtype=torch.float32, device=DEV)
+    p = {"mode": "fixed_rate", "brick": (1024,), "rate": 4.0}
+    ws = A.workspace(xg.dtype, tuple(xg.shape), p, DEV)
+    with pytest.raises(A.ApaxError) as ei:
+        A.apax_profile_encode_timed(xg, p, ws)
+    assert ei.value.code == A.E_UNSUPPORTED
