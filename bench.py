@@ -811,8 +811,8 @@ def main():
         "k_encode": ("k_encode<float, 64, 2, 4, false>", enc_ms, enc_bytes),
         "k_decode": ("k_decode<float, 64, 2, 4>", dec_ms, dec_bytes),
         "k_profile_metrics": ("k_profile<float, 64, 2, 1>", pass_ms["metrics"], nbytes_in + 4 * nblocks),
-        # read the field; write the stream's blocks, each block's code (4 B) and stream (1 B)
-        "k_profile_metrics_encode": ("k_profile<float, 64, 2, 5>", menc_ms, nbytes_in + (bound - 64) + 5 * nblocks),
+        # read the field; write the stream's blocks and each block's code (4 B, for the centred pass)
+        "k_profile_metrics_encode": ("k_profile<float, 64, 2, 5>", menc_ms, nbytes_in + (bound - 64) + 4 * nblocks),
         "k_profile_curve": ("k_profile<float, 64, 2, 4>", pass_ms["curve"], sub_bytes),
         "k_profile_centred": ("k_profile<float, 64, 2, 3>", pass_ms["centred"], nbytes_in + 4 * nblocks),
         "k_probe_all": ("k_probe_all<float, 64, 2>", sum(probes) / len(probes), sub_bytes),

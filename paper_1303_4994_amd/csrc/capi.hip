@@ -819,7 +819,10 @@ static int profile_enqueue(const void* d_x, const apax_params* p, const HG& h, v
       A.bst = enc->bst;
       A.lens = enc->lens;
       A.ssum = enc->ssum;
-      if (fr) A.enc_words = enc->out_words;  // fixed rate: the pass writes the blocks too
+      if (fr) {  // fixed rate: the pass writes the blocks too (no stream choice to hand over)
+        A.enc_words = enc->out_words;
+        A.bst = nullptr;
+      }
     }
     A.C = C;
     A.C.step = next;
