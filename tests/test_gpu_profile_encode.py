@@ -1,5 +1,5 @@
 """apax_profile_encode_async (the profiler feeding the encoder, Sec. 4 -> Sec. 6,
-the encode taken from the metrics pass's per-block results) against the
+in fixed rate the metrics pass writing the stream's blocks itself) against the
 separate calls: the same profile result and the same stream bytes as
 apax_profile_async followed by apax_encode with APAX_CODE_PROFILED, in every
 mode, 1-/2-/3-d, the lagged choice, an empty array and the 4096^2 fp32 field;
@@ -48,6 +48,8 @@ CASES = [
     ("i16-1d-lagged", np.int16, (20000,), {"mode": "lossless", "brick": (64,), "lagged": True}),
     ("f32-1d-filter-fr", np.float32, (64 * 300,), {"mode": "fixed_rate", "brick": (64,), "rate": 4.0,
                                                     "filter": (1, -1)}),
+    ("f64-3d-4x4x8-fr", np.float64, (9, 33, 40), {"mode": "fixed_rate", "brick": (4, 4, 8), "rate": 3.0}),
+    ("i16-2d-8x8-fr", np.int16, (90, 70), {"mode": "fixed_rate", "brick": (8, 8), "rate": 2.5}),
 ]
 
 
