@@ -848,9 +848,9 @@ def main():
                                "fixed rate 4:1, 16x16 bricks, profile + encode + decode per step",
                    "input_bytes": nbytes_in, "stream_bytes": bound, "copies_rotated": R,
                    "attenuation_arith": "f64", "stats_arith": "f64",
-                   "streams": "profile and encode on one stream (the encode from the metrics pass's "
-                              "per-block codes and streams, right after that pass); decode on a second, "
-                              "overlapping the centred and curve passes"},
+                   "streams": "profile and encode on one stream (the fixed-rate metrics pass writes the "
+                              "stream's blocks itself), the curve pass beside the metrics pass and the "
+                              "metrics reduction and centred pass beside the decode on a second"},
         "encode_GBps": round(enc_gbps, 2),
         "decode_GBps": round(dec_gbps, 2),
         "encode_pct_hbm": round(100 * enc_gbps / HBM_PEAK_GBPS, 2),

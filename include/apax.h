@@ -202,8 +202,10 @@ int apax_profile_async_point(const void* d_x, const apax_params* p, void* d_ws, 
  * d_stream / *d_nbytes.  The encode is taken from the profile's metrics pass,
  * which already runs the encoder's per-block analysis at that point (fixed
  * rate: each block's gain search; every mode: each block's stream choice
- * and size): it records each block's code and stream, and the encode only
- * quantizes, forms that stream and packs.  `encoded` (optional) is recorded
+ * and size).  Fixed rate: that pass also writes each block's words, and the
+ * stream header is written before it.  Other modes: it records each block's
+ * stream and size, and the encode only places, quantizes, forms that stream
+ * and packs.  `encoded` (optional) is recorded
  * on `stream` as soon as the stream is complete, before the profile's
  * centred and curve passes, so a decode on another stream can overlap them.
  * p->code is ignored; d_ws holds the profile as after apax_profile_async.
