@@ -322,7 +322,7 @@ __device__ void reduce_recs(const ProfArgs& A, PState* S, PState* S0) {
 // over 1-4 byte samples are held to five waves per SIMD (a few spilled
 // values cost less than the latency the fifth wave hides).
 template <typename T, int LPB, int NDIM, int OPK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((OPK == P_STATS || OPK == P_CURVE || OPK == P_MENC) && sizeof(T) <= 4 ? 5 : 1))) void k_profile(ProfArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OPK == P_CURVE && sizeof(T) <= 4 ? 6 : ((OPK == P_STATS || OPK == P_MENC) && sizeof(T) <= 4 ? 5 : 1)))) void k_profile(ProfArgs A) {
   constexpr int OP = (OPK == P_CURVE || OPK == P_MENC) ? P_STATS : OPK;
   // P_MENC: the fixed-rate metrics pass also writes each block's encoded
   // words (its code and stream are the encoder's), assembled in the
