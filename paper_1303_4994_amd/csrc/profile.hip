@@ -521,15 +521,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OPK == P_CU
           double ad = __builtin_fabs(d);
           dmax = ad > dmax ? ad : dmax;
         }
-        t[S_XX] += x * x;
-        t[S_YY] += y * y;
-        t[S_DD] += d * d;
-        t[S_DS] += d * (x + y);
+        // products fused into the adds (one rounding instead of two: the
+        // sums stay within the 1e-9 the statistics promise, at fewer
+        // instructions)
+        t[S_XX] = __builtin_fma(x, x, t[S_XX]);
+        t[S_YY] = __builtin_fma(y, y, t[S_YY]);
+        t[S_DD] = __builtin_fma(d, d, t[S_DD]);
+        t[S_DS] = __builtin_fma(d, x + y, t[S_DS]);
       } else {
         double ex = x - mx, ey = y - my, ed = d - md;
-        t[S_XX] += ex * ex;  // slots of the centred sums S_CXX, S_CYY, S_CDD
-        t[S_YY] += ey * ey;
-        t[S_DD] += ed * ed;
+        t[S_XX] = __builtin_fma(ex, ex, t[S_XX]);  // slots of the centred sums S_CXX, S_CYY, S_CDD
+        t[S_YY] = __builtin_fma(ey, ey, t[S_YY]);
+        t[S_DD] = __builtin_fma(ed, ed, t[S_DD]);
       }
     }
 #pragma unroll
